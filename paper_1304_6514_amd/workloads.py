@@ -1,0 +1,117 @@
+"""Seeded synthetic workloads shaped like the paper's problems.
+
+This module holds problem descriptions and seeded draws only: no step of the
+method's arithmetic.  Both the GPU library and the CPU oracle are fed from it.
+
+A workload names a right-hand side, the time interval [t0, T], the number of
+slices N (sec. 3: slice j covers [T_j, T_{j+1}], T_j = t0 + j (T - t0)/N), a
+uniform grid of the initial value space (endpoints included), the RK4 steps
+per slice, the true initial value y0, the working precision of the table build
+and the interpolation rule of the composition.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, replace
+
+import numpy as np
+
+RHS_DIM = {"linear": 1, "logistic": 1, "forced_cubic": 1, "vdp": 2, "square": 1}
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    rhs: str
+    params: tuple
+    t0: float
+    T: float
+    n_slices: int
+    grid_n: tuple
+    grid_lo: tuple
+    grid_hi: tuple
+    steps_per_slice: int
+    y0: tuple
+    precision: str          # "fp64" or "fp32" (the table build's arithmetic)
+    interp: str             # "linear", "hermite" or "bilinear"
+    scheme: str = "rk4"
+
+    @property
+    def dim(self) -> int:
+        return RHS_DIM[self.rhs]
+
+    @property
+    def points_per_slice(self) -> int:
+        return int(np.prod(self.grid_n))
+
+    @property
+    def trajectories(self) -> int:
+        return self.n_slices * self.points_per_slice
+
+    @property
+    def trajectory_steps(self) -> int:
+        return self.trajectories * self.steps_per_slice
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+
+def vdp_mu(seed: int = 0) -> float:
+    """Van der Pol damping mu ~ U[1, 5] from a seed."""
+    return float(np.random.default_rng(seed).uniform(1.0, 5.0))
+
+
+# Plain method in FP64: logistic y'=y(1-y), t in [0,10], y0 = 0.1; 64 slices,
+# 256 uniform points on [-0.1, 1.2], 1000 RK4 steps per slice, linear lookup.
+LOGISTIC_FP64 = Workload(
+    name="logistic-fp64-64sl-256pt-1000st", rhs="logistic", params=(), t0=0.0, T=10.0,
+    n_slices=64, grid_n=(256,), grid_lo=(-0.1,), grid_hi=(1.2,), steps_per_slice=1000,
+    y0=(0.1,), precision="fp64", interp="linear")
+
+# Forced scalar ODE y'=sin(3t)-y^3, t in [0,100], y0 = 1; 4096 slices, 4096
+# points on [-3, 3], 2000 RK4 steps per slice; FP32 build, FP64 Hermite compose.
+FORCED_CUBIC_FP32 = Workload(
+    name="forced-cubic-fp32-4096sl-4096pt-2000st", rhs="forced_cubic", params=(),
+    t0=0.0, T=100.0, n_slices=4096, grid_n=(4096,), grid_lo=(-3.0,), grid_hi=(3.0,),
+    steps_per_slice=2000, y0=(1.0,), precision="fp32", interp="hermite")
+
+# Van der Pol, mu ~ U[1,5] (seed 0), t in [0,50], y0 = (2, 0); 1024 slices,
+# 128 x 128 tensor grid, 500 RK4 steps per slice; FP32 build, FP64 bilinear
+# compose.  The y2 axis spans [-8, 8] so that the limit cycle of every mu in
+# [1, 5] lies inside the grid; the [-3, 3]^2 box is kept as VDP_SQUARE_BOX.
+VDP_FP32 = Workload(
+    name="vdp-fp32-1024sl-128x128pt-500st", rhs="vdp", params=(vdp_mu(0),), t0=0.0,
+    T=50.0, n_slices=1024, grid_n=(128, 128), grid_lo=(-3.0, -8.0), grid_hi=(3.0, 8.0),
+    steps_per_slice=500, y0=(2.0, 0.0), precision="fp32", interp="bilinear")
+
+VDP_SQUARE_BOX = VDP_FP32.with_(name="vdp-fp32-1024sl-128x128pt-500st-box3",
+                                grid_lo=(-3.0, -3.0), grid_hi=(3.0, 3.0))
+
+# Harmonic oscillator (Van der Pol with mu = 0): the slice map is linear, so
+# bilinear lookup reproduces it up to rounding.
+HARMONIC = VDP_FP32.with_(name="harmonic-1024sl-128x128pt-500st", params=(0.0,),
+                          grid_lo=(-3.0, -3.0), grid_hi=(3.0, 3.0))
+
+# The model problem of sec. 3: y' = y^2, y(0) = 1 on [0, 1/2].
+SQUARE_MODEL = Workload(
+    name="square-fp64-4sl-64pt-1250st", rhs="square", params=(), t0=0.0, T=0.5,
+    n_slices=4, grid_n=(64,), grid_lo=(0.0,), grid_hi=(2.0,), steps_per_slice=1250,
+    y0=(1.0,), precision="fp64", interp="hermite")
+
+FULL_SIZE = {w.name: w for w in (LOGISTIC_FP64, FORCED_CUBIC_FP32, VDP_FP32)}
+
+
+def small(w: Workload, n_slices: int, grid_n: tuple, steps: int, **kw) -> Workload:
+    """A reduced copy of a workload (same problem, interval and grid box)."""
+    return w.with_(name=f"{w.name}-small-{n_slices}x{'x'.join(map(str, grid_n))}x{steps}",
+                   n_slices=n_slices, grid_n=tuple(grid_n), steps_per_slice=steps, **kw)
+
+
+def sample_entries(w: Workload, count: int, seed: int):
+    """Seeded (slice, point) pairs covering the first/last slice and grid edges."""
+    rng = np.random.default_rng(seed)
+    sl = rng.integers(0, w.n_slices, size=count, dtype=np.int64)
+    pt = rng.integers(0, w.points_per_slice, size=count, dtype=np.int64)
+    edge_s = np.array([0, 0, w.n_slices - 1, w.n_slices - 1], dtype=np.int64)
+    edge_p = np.array([0, w.points_per_slice - 1, 0, w.points_per_slice - 1],
+                      dtype=np.int64)
+    return np.concatenate([edge_s, sl]), np.concatenate([edge_p, pt])

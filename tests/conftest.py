@@ -1,0 +1,20 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs a GPU (runs the HIP library)")
+    config.addinivalue_line("markers", "slow: oracle work of more than a few seconds")
+
+
+@pytest.fixture(scope="session")
+def orc():
+    import oracle
+    oracle._load()
+    return oracle

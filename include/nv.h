@@ -1,0 +1,232 @@
+/*
+ * nv.h — C ABI of the MI355X (gfx950) propagator-build library for
+ * Nievergelt's parallel-in-time method, as framed in A. T. Barker,
+ * "A minimal communication approach to parallel time integration",
+ * arXiv:1304.6514.
+ *
+ * The method (sec. 3, pseudocode figure): cut [t0, T] into N slices; on every
+ * slice, solve the initial value problem from every point of a sample of the
+ * initial value space (computation phase, embarrassingly parallel); then, from
+ * the true y0, obtain the slice-boundary states one after the other by
+ * evaluating each slice's tabulated initial-to-final map at the previous
+ * boundary state (communication phase).
+ *
+ *   nv_build_propagators  — computation phase: writes the map tables.
+ *   nv_compose            — communication phase: y(T) and the boundary states.
+ *
+ * Conventions
+ *   - Every call returns an nv_status; nothing aborts.  On failure,
+ *     nv_last_error() returns a message for the calling thread.
+ *   - "host" pointers are ordinary CPU memory owned by the caller; "device"
+ *     pointers are GPU memory on the context's device.
+ *   - A context is not thread-safe: one thread drives it at a time.
+ *   - All kernels of a context run on its stream (nv_options.stream).  The
+ *     build is asynchronous with respect to the host; nv_compose and the
+ *     copy-out calls synchronize the stream before returning.
+ *   - Floating-point parameters and time values are IEEE binary64.
+ */
+#ifndef NV_H
+#define NV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NV_API __attribute__((visibility("default")))
+
+typedef enum {
+    NV_OK = 0,
+    NV_ERR_INVALID_ARG = -1,      /* an argument is out of its documented range */
+    NV_ERR_NOT_BUILT = -2,        /* compose/inspect before any successful build */
+    NV_ERR_NONFINITE = -3,        /* the composition met a non-finite value */
+    NV_ERR_OOM = -4,              /* device allocation failed */
+    NV_ERR_HIP = -5,              /* a HIP runtime call failed */
+    NV_ERR_UNSUPPORTED = -6,      /* a combination this library does not build */
+    NV_ERR_BUFFER_TOO_SMALL = -7  /* caller-provided memory is too small */
+} nv_status;
+
+/* Right-hand sides f(t, y).  params[] holds the listed parameters. */
+typedef enum {
+    NV_RHS_LINEAR = 0,        /* y' = p0 y                           dim 1, 1 param */
+    NV_RHS_LOGISTIC = 1,      /* y' = y (1 - y)                      dim 1          */
+    NV_RHS_FORCED_CUBIC = 2,  /* y' = sin(3 t) - y^3                 dim 1          */
+    NV_RHS_VDP = 3,           /* y1' = y2, y2' = p0 (1 - y1^2) y2 - y1   dim 2, p0 = mu
+                                 (mu = 0: harmonic oscillator)                      */
+    NV_RHS_SQUARE = 4         /* y' = y^2, the model problem of sec. 3   dim 1      */
+} nv_rhs_id;
+
+/* Time-stepping scheme of the computation phase.  Forward Euler is the scheme
+ * of the error analysis of sec. 5; classical RK4 is the default. */
+typedef enum { NV_SCHEME_RK4 = 0, NV_SCHEME_EULER = 1 } nv_scheme;
+
+/* Arithmetic of the table build.  The composition is always FP64. */
+typedef enum { NV_FP64 = 0, NV_FP32 = 1 } nv_precision;
+
+/* Interpolation of the tabulated slice maps (the "approximating function" of
+ * the pseudocode):
+ *   LINEAR    1-D piecewise linear (Nievergelt's own choice, sec. 5)
+ *   HERMITE   1-D cubic Hermite; node slopes from the table by finite
+ *             differences (centred inside, one-sided second order at the ends)
+ *   BILINEAR  2-D tensor-grid bilinear                                       */
+typedef enum { NV_INTERP_LINEAR = 0, NV_INTERP_HERMITE = 1, NV_INTERP_BILINEAR = 2 } nv_interp;
+
+/* Sample Xi_h of the initial value space (sec. 3): a uniform tensor grid with
+ * endpoints included.  Axis a has n[a] >= 2 points
+ *     xi = lo[a] + k (hi[a] - lo[a]) / (n[a] - 1),   k = 0 .. n[a]-1,
+ * (n[0] >= 3 for HERMITE).  dim must equal the right-hand side's dimension.
+ * A 2-D point has the flat index k = k0 * n[1] + k1 (axis 0 major). */
+typedef struct {
+    int dim;
+    int n[2];
+    double lo[2];
+    double hi[2];
+    int interp;               /* nv_interp; LINEAR/HERMITE need dim 1, BILINEAR dim 2 */
+} nv_ic_grid;
+
+typedef struct {
+    int scheme;               /* nv_scheme (default RK4) */
+    int precision;            /* nv_precision (default FP64) */
+    int compensated;          /* FP32 only: compensated (Kahan) accumulation of the
+                                 state update; default 1 */
+    int traj_per_lane;        /* trajectories per GPU lane: 1, 2 or 4; 0 = default */
+    void *stream;             /* hipStream_t the context launches on; NULL = null stream */
+} nv_options;
+
+/* Result details of a composition. */
+typedef struct {
+    long long n_out_of_grid;  /* lookups whose point lay outside the grid box; those
+                                 are extrapolated from the edge cell, not clamped */
+    int bad_slice;            /* first slice whose lookup met a non-finite value, or -1 */
+    int reserved;
+} nv_compose_info;
+
+typedef struct nv_ctx nv_ctx;
+
+/* Create a context on the current HIP device with default options.
+ * *out receives the handle; free it with nv_ctx_destroy. */
+NV_API nv_status nv_ctx_create(nv_ctx **out);
+
+/* Free the context and every device buffer the library allocated for it.
+ * Caller-provided buffers (nv_set_buffers) are not freed.  NULL is accepted. */
+NV_API nv_status nv_ctx_destroy(nv_ctx *ctx);
+
+/* Replace the context's options.  Takes effect at the next build.  Invalid
+ * values give NV_ERR_INVALID_ARG and leave the options unchanged. */
+NV_API nv_status nv_set_options(nv_ctx *ctx, const nv_options *opt);
+NV_API nv_status nv_get_options(const nv_ctx *ctx, nv_options *opt);
+
+/* Device memory a build of this shape needs.
+ *   *table_bytes: the map tables, dim x N x (points per slice) values of the
+ *                 working precision, 256-byte aligned per component;
+ *   *work_bytes:  scratch (per-slice forcing values of non-autonomous
+ *                 right-hand sides, per-slice non-finite counters, the boundary
+ *                 states and the composition's status).
+ * Pure host arithmetic: no device call. */
+NV_API nv_status nv_required_bytes(int rhs_id, int n_slices, const nv_ic_grid *grid,
+                                   int steps_per_slice, const nv_options *opt,
+                                   size_t *table_bytes, size_t *work_bytes);
+
+/* Hand the context caller-owned device memory (e.g. from PyTorch) for the
+ * tables and the scratch.  The library never frees it; it must stay valid
+ * until the next nv_set_buffers, or nv_ctx_destroy.  Passing NULL pointers
+ * returns to library-owned memory (allocated on demand by the build).  If a
+ * build needs more than the given sizes it fails with NV_ERR_BUFFER_TOO_SMALL. */
+NV_API nv_status nv_set_buffers(nv_ctx *ctx, void *tables_dev, size_t table_bytes,
+                                void *work_dev, size_t work_bytes);
+
+/* Computation phase (sec. 3 pseudocode, "computation phase"; the (Mn/N) tau_F
+ * term of the GPU cost model of sec. 4).
+ *
+ * For every slice j = 0..n_slices-1 and every grid point k, integrate the
+ * problem from xi_k at T_j = t0 + j (T - t0)/n_slices over steps_per_slice
+ * steps of h = ((T - t0)/n_slices)/steps_per_slice and store the end state in
+ * the table: tab[c][j][k] for state component c (see nv_get_table).  Step s of
+ * a slice evaluates the right-hand side at T_j + s h, T_j + s h + h/2 and
+ * T_j + (s+1) h.
+ *
+ *   rhs_id          nv_rhs_id
+ *   params          host array with the right-hand side's parameters (may be
+ *                   NULL when it takes none); must be finite
+ *   t0 < T          finite
+ *   n_slices        >= 1
+ *   grid            host struct, see nv_ic_grid
+ *   steps_per_slice >= 1
+ *
+ * Asynchronous on the context's stream.  Per-slice counts of trajectories that
+ * ended non-finite are kept (nv_get_nonfinite_counts).  Errors:
+ * NV_ERR_INVALID_ARG, NV_ERR_UNSUPPORTED, NV_ERR_OOM, NV_ERR_BUFFER_TOO_SMALL,
+ * NV_ERR_HIP.  A failed build leaves the context unbuilt. */
+NV_API nv_status nv_build_propagators(nv_ctx *ctx, int rhs_id, const double *params,
+                                      double t0, double T, int n_slices,
+                                      const nv_ic_grid *grid, int steps_per_slice);
+
+/* Communication phase (sec. 3 pseudocode, "communication phase"; the N tau_N
+ * term of the cost model of sec. 4): lambda_0 = y0 and
+ * lambda_{j+1} = phi^j(lambda_j) for j = 0..N-1, each phi^j the interpolant of
+ * slice j's table (every slice, the first included), in FP64 on the GPU.
+ *
+ * Lookup on axis a: inv = (n-1)/(hi-lo), u = (x-lo) inv, cell = floor(u)
+ * limited to [0, n-2], w = u - cell, each an IEEE binary64 operation.
+ * Interpolants (t = the table row, widened exactly to FP64):
+ *   LINEAR    t[i] + w (t[i+1] - t[i])
+ *   HERMITE   ((h00 t[i] + h10 d[i]) + h01 t[i+1]) + h11 d[i+1] with
+ *             h00 = (2w^3 - 3w^2) + 1, h10 = (w^3 - 2w^2) + w, h01 = 3w^2 - 2w^3,
+ *             h11 = w^3 - w^2, d[i] = (t[i+1] - t[i-1])/2 inside,
+ *             d[0] = ((4t[1] - 3t[0]) - t[2])/2,
+ *             d[n-1] = ((3t[n-1] - 4t[n-2]) + t[n-3])/2
+ *   BILINEAR  per component: r0 = t00 + w1 (t01 - t00), r1 = t10 + w1 (t11 - t10),
+ *             r0 + w0 (r1 - r0), t_ab the corner (cell0 + a, cell1 + b)
+ *
+ *   y0        host array, dim values (the true initial value)
+ *   yT        host array, dim values: lambda_N = the method's y(T)
+ *   boundary  host array of (n_slices + 1) * dim values, lambda_j at
+ *             boundary[j * dim + c], or NULL
+ *   info      host struct, or NULL
+ *
+ * Synchronous.  NV_ERR_NOT_BUILT before a build; NV_ERR_NONFINITE when
+ * lambda_j or a table entry the lookup reads is not finite (info->bad_slice =
+ * j; boundary holds lambda_0..lambda_j).  Lookups outside the grid box
+ * extrapolate from the edge cell and are counted, not treated as errors. */
+NV_API nv_status nv_compose(nv_ctx *ctx, const double *y0, double *yT, double *boundary,
+                            nv_compose_info *info);
+
+/* Copy component c's table of the last build to host memory: n_slices rows of
+ * (points per slice) values in the build's precision (double or float),
+ * row j at offset j * points.  bytes must be at least that size. */
+NV_API nv_status nv_get_table(nv_ctx *ctx, int component, void *host_dst, size_t bytes);
+
+/* Device address of component c's table (same layout as nv_get_table). */
+NV_API nv_status nv_table_device_ptr(nv_ctx *ctx, int component, void **dev_ptr);
+
+/* Copy the per-slice counts of trajectories that ended non-finite (n_slices
+ * uint32 values) to host memory. */
+NV_API nv_status nv_get_nonfinite_counts(nv_ctx *ctx, uint32_t *host_counts, int n);
+
+/* The lookup of nv_compose applied to count device-resident queries x_dev:
+ * cell_dev[q] (int64) and w_dev[q] (double); out_dev[q] = 1 when outside the
+ * grid box.  Runs on the context's stream and synchronizes.  For checking the
+ * lookup bit for bit. */
+NV_API nv_status nv_locate(nv_ctx *ctx, double lo, double hi, int n, const double *x_dev,
+                           long long count, long long *cell_dev, double *w_dev,
+                           int32_t *out_dev);
+
+/* Kernel timing with HIP events on the context's stream.  When enabled, the
+ * last build's integration kernel and the last composition kernel are
+ * bracketed by events; nv_last_timing waits for them and returns milliseconds
+ * (-1 when not measured). */
+NV_API nv_status nv_set_timing(nv_ctx *ctx, int enable);
+NV_API nv_status nv_last_timing(nv_ctx *ctx, float *build_ms, float *compose_ms);
+
+/* Message of the last failure on the calling thread ("" if none). */
+NV_API const char *nv_last_error(void);
+
+/* Name of a status code. */
+NV_API const char *nv_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NV_H */

@@ -210,12 +210,19 @@ int orc_table_entries(int rhs, const double *p, int scheme, double t0, double T,
 }
 
 /* u = (x - lo) * (n - 1)/(hi - lo); cell = floor(u) limited to [0, n-2];
- * w = u - cell.  Outside the grid w leaves [0, 1] (extrapolation). */
+ * w = u - cell.  Outside the grid w leaves [0, 1] (extrapolation).  A NaN
+ * query gives cell 0, w = NaN, and counts as outside. */
 int orc_locate(double lo, double hi, int n, double x, long long *cell, double *w) {
     double inv = (double)(n - 1) / (hi - lo);
     double u = (x - lo) * inv;
-    double f = floor(u);
+    double f;
     long long i;
+    if (isnan(u)) {
+        *cell = 0;
+        *w = u;
+        return 1;
+    }
+    f = floor(u);
     if (f < 0.0)
         i = 0;
     else if (f > (double)(n - 2))

@@ -1,0 +1,283 @@
+// Computation phase of Nievergelt's method (sec. 3, pseudocode figure): every
+// (slice, grid point) pair integrates its own initial value problem over the
+// slice, fully independently, and stores the end state in the slice's table.
+//
+// gfx950 mapping
+//   - one trajectory per lane (P trajectories per lane for instruction-level
+//     parallelism), state in VGPRs, no LDS, no inter-lane traffic;
+//   - one workgroup covers 256*P consecutive grid points of ONE slice, so the
+//     slice index, its start time and its forcing values are wave-uniform and
+//     live in SGPRs (scalar loads from the per-slice forcing row);
+//   - workgroup ids are remapped so that each of the 8 XCDs runs a contiguous
+//     range of slices (its L2 then holds those slices' forcing rows);
+//   - the grid point is computed from the lane's index (no load); the only
+//     HBM traffic is the coalesced table store at the end.
+//
+// The inner loop is VALU-bound: RK4 on y' = F(t) - y^3 costs 15 VALU ops per
+// step (18 with the compensated FP32 update), Van der Pol 26 (32).
+#include "nv_internal.h"
+
+#include <cmath>
+
+namespace nv {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Right-hand sides.  F is the wave-uniform forcing value of the stage time
+// (used by non-autonomous problems only), p the parameter.
+// ---------------------------------------------------------------------------
+template <class R>
+struct RhsLinear {              // y' = p y
+    static constexpr int dim = 1;
+    static constexpr bool forced = false;
+    __device__ static void f(R, R p, const R *y, R *k) { k[0] = p * y[0]; }
+};
+
+template <class R>
+struct RhsLogistic {            // y' = y (1 - y)
+    static constexpr int dim = 1;
+    static constexpr bool forced = false;
+    __device__ static void f(R, R, const R *y, R *k) { k[0] = y[0] - y[0] * y[0]; }
+};
+
+template <class R>
+struct RhsForcedCubic {         // y' = sin(3t) - y^3, F = sin(3t)
+    static constexpr int dim = 1;
+    static constexpr bool forced = true;
+    __device__ static void f(R F, R, const R *y, R *k) {
+        R y2 = y[0] * y[0];
+        k[0] = F - y2 * y[0];
+    }
+};
+
+template <class R>
+struct RhsVdp {                 // y1' = y2, y2' = mu (1 - y1^2) y2 - y1
+    static constexpr int dim = 2;
+    static constexpr bool forced = false;
+    __device__ static void f(R, R mu, const R *y, R *k) {
+        R a = R(1) - y[0] * y[0];
+        k[0] = y[1];
+        k[1] = (mu * a) * y[1] - y[0];
+    }
+};
+
+template <class R>
+struct RhsSquare {              // y' = y^2
+    static constexpr int dim = 1;
+    static constexpr bool forced = false;
+    __device__ static void f(R, R, const R *y, R *k) { k[0] = y[0] * y[0]; }
+};
+
+// The forcing function of non-autonomous right-hand sides.
+__device__ inline double forcing_value(int rhs, double t) {
+    return rhs == 2 ? sin(3.0 * t) : 0.0;
+}
+
+// Workgroup id -> logical tile id such that XCD x (which receives workgroups
+// x, x+8, x+16, ...) processes one contiguous range of logical tiles.
+__device__ inline int xcd_remap(int b, int nblocks) {
+    const int q = nblocks / kNumXcd, r = nblocks % kNumXcd;
+    const int x = b % kNumXcd, local = b / kNumXcd;
+    return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+}
+
+// Grid point of flat index k: xi = lo + k * dxi per axis, in FP64 (one
+// rounding per operation), then rounded to the working precision.
+template <class R, int D>
+__device__ inline void grid_point(const BuildArgs &a, long long k, R *y) {
+#pragma clang fp contract(off)
+    if constexpr (D == 1) {
+        y[0] = R(a.lo0 + double(k) * a.dxi0);
+    } else {
+        const unsigned kk = unsigned(k), n1 = unsigned(a.n1);
+        const unsigned k0 = kk / n1, k1 = kk - k0 * n1;
+        y[0] = R(a.lo0 + double(k0) * a.dxi0);
+        y[1] = R(a.lo1 + double(k1) * a.dxi1);
+    }
+}
+
+// One step of the scheme for P trajectories.  Fa, Fb, Fc: forcing at the
+// step's start, midpoint and end times.
+template <class Rhs, class R, int Scheme, bool Comp, int P>
+__device__ inline void step(R (&y)[P][Rhs::dim], R (&c)[P][Rhs::dim], R Fa, R Fb, R Fc,
+                            R h, R h2, R h6, R p) {
+    constexpr int D = Rhs::dim;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        R k1[D], k2[D], k3[D], k4[D], z[D], dy[D];
+        if constexpr (Scheme == 1) {                 // forward Euler
+            Rhs::f(Fa, p, y[q], k1);
+#pragma unroll
+            for (int d = 0; d < D; ++d) dy[d] = h * k1[d];
+        } else {                                     // classical RK4
+            Rhs::f(Fa, p, y[q], k1);
+#pragma unroll
+            for (int d = 0; d < D; ++d) z[d] = y[q][d] + h2 * k1[d];
+            Rhs::f(Fb, p, z, k2);
+#pragma unroll
+            for (int d = 0; d < D; ++d) z[d] = y[q][d] + h2 * k2[d];
+            Rhs::f(Fb, p, z, k3);
+#pragma unroll
+            for (int d = 0; d < D; ++d) z[d] = y[q][d] + h * k3[d];
+            Rhs::f(Fc, p, z, k4);
+#pragma unroll
+            for (int d = 0; d < D; ++d) dy[d] = h6 * ((k1[d] + k4[d]) + R(2) * (k2[d] + k3[d]));
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            if constexpr (Comp) {
+                // compensated (Kahan) accumulation: c carries the low-order
+                // part the rounded state lost in earlier updates
+                const R yk = dy[d] - c[q][d];
+                const R t = y[q][d] + yk;
+                c[q][d] = (t - y[q][d]) - yk;
+                y[q][d] = t;
+            } else {
+                y[q][d] = y[q][d] + dy[d];
+            }
+        }
+    }
+}
+
+template <class Rhs, class R, int Scheme, bool Comp, int P>
+__global__ void __launch_bounds__(kBuildBlock) build_kernel(BuildArgs a) {
+    constexpr int D = Rhs::dim;
+    const int lid = xcd_remap(int(blockIdx.x), a.total_blocks);
+    const int j = lid / a.tiles_per_slice;
+    const int tile = lid - j * a.tiles_per_slice;
+    const long long base = (long long)tile * (kBuildBlock * P) + threadIdx.x;
+
+    R y[P][D], c[P][D];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        long long k = base + (long long)q * kBuildBlock;
+        if (k >= a.M) k = a.M - 1;           // ragged tail: compute, do not store
+        grid_point<R, D>(a, k, y[q]);
+#pragma unroll
+        for (int d = 0; d < D; ++d) c[q][d] = R(0);
+    }
+
+    const R h = R(a.h), h2 = R(a.h * 0.5), h6 = R(a.h / 6.0), p = R(a.p0);
+    const int S = a.steps;
+    if constexpr (Rhs::forced) {
+        const R *__restrict__ F = static_cast<const R *>(a.forcing) + (long long)j * (2 * S + 1);
+        for (int s = 0; s < S; ++s)
+            step<Rhs, R, Scheme, Comp, P>(y, c, F[2 * s], F[2 * s + 1], F[2 * s + 2], h, h2,
+                                          h6, p);
+    } else {
+        for (int s = 0; s < S; ++s)
+            step<Rhs, R, Scheme, Comp, P>(y, c, R(0), R(0), R(0), h, h2, h6, p);
+    }
+
+    R *t0 = static_cast<R *>(a.tab0) + (long long)j * a.M;
+    R *t1 = D == 2 ? static_cast<R *>(a.tab1) + (long long)j * a.M : nullptr;
+    unsigned bad = 0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const long long k = base + (long long)q * kBuildBlock;
+        if (k < a.M) {
+            t0[k] = y[q][0];
+            bad += !isfinite(y[q][0]);
+            if constexpr (D == 2) {
+                t1[k] = y[q][1];
+                bad += !isfinite(y[q][1]) && isfinite(y[q][0]);
+            }
+        }
+    }
+    if (bad) atomicAdd(&a.nonfinite[j], bad);
+}
+
+// Forcing values of slice j at the stage times of its steps:
+// F[j][2s] = g(T_j + s h), F[j][2s+1] = g((T_j + s h) + h/2), F[j][2S] = g(T_j + S h).
+template <class R>
+__global__ void forcing_kernel(int rhs, R *F, int n_slices, int steps, double t0, double L,
+                               double h) {
+#pragma clang fp contract(off)
+    const long long per = 2LL * steps + 1;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= per * n_slices) return;
+    const long long j = idx / per, m = idx - j * per;
+    const double Tj = t0 + double(j) * L;
+    double t = Tj + double(m >> 1) * h;
+    if (m & 1) t = t + h / 2.0;
+    F[idx] = R(forcing_value(rhs, t));
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, long long n, uint32_t v) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+template <class Rhs, class R, int Scheme, bool Comp, int P>
+hipError_t launch_one(const BuildArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((build_kernel<Rhs, R, Scheme, Comp, P>), dim3(a.total_blocks),
+                       dim3(kBuildBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <template <class> class Rhs, class R, int Scheme, bool Comp>
+hipError_t by_p(int P, const BuildArgs &a, hipStream_t s) {
+    switch (P) {
+    case 1: return launch_one<Rhs<R>, R, Scheme, Comp, 1>(a, s);
+    case 2: return launch_one<Rhs<R>, R, Scheme, Comp, 2>(a, s);
+    case 4: return launch_one<Rhs<R>, R, Scheme, Comp, 4>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <template <class> class Rhs>
+hipError_t by_config(const BuildConfig &c, const BuildArgs &a, hipStream_t s) {
+    const int P = c.traj_per_lane;
+    if (c.precision == 0) {
+        return c.scheme == 0 ? by_p<Rhs, double, 0, false>(P, a, s)
+                             : by_p<Rhs, double, 1, false>(P, a, s);
+    }
+    if (c.compensated)
+        return c.scheme == 0 ? by_p<Rhs, float, 0, true>(P, a, s)
+                             : by_p<Rhs, float, 1, true>(P, a, s);
+    return c.scheme == 0 ? by_p<Rhs, float, 0, false>(P, a, s)
+                         : by_p<Rhs, float, 1, false>(P, a, s);
+}
+
+}  // namespace
+
+bool build_supported(const BuildConfig &c) {
+    return c.rhs >= 0 && c.rhs <= 4 && (c.scheme == 0 || c.scheme == 1) &&
+           (c.precision == 0 || c.precision == 1) &&
+           (c.traj_per_lane == 1 || c.traj_per_lane == 2 || c.traj_per_lane == 4);
+}
+
+hipError_t launch_build(const BuildConfig &c, const BuildArgs &a, hipStream_t s) {
+    switch (c.rhs) {
+    case 0: return by_config<RhsLinear>(c, a, s);
+    case 1: return by_config<RhsLogistic>(c, a, s);
+    case 2: return by_config<RhsForcedCubic>(c, a, s);
+    case 3: return by_config<RhsVdp>(c, a, s);
+    case 4: return by_config<RhsSquare>(c, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_forcing(int rhs, int precision, void *F, int n_slices, int steps,
+                          double t0, double L, double h, hipStream_t s) {
+    const long long n = (2LL * steps + 1) * n_slices;
+    const int block = 256;
+    const long long grid = (n + block - 1) / block;
+    if (precision == 0)
+        hipLaunchKernelGGL(forcing_kernel<double>, dim3(unsigned(grid)), dim3(block), 0, s, rhs,
+                           static_cast<double *>(F), n_slices, steps, t0, L, h);
+    else
+        hipLaunchKernelGGL(forcing_kernel<float>, dim3(unsigned(grid)), dim3(block), 0, s, rhs,
+                           static_cast<float *>(F), n_slices, steps, t0, L, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int block = 256;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(unsigned((n + block - 1) / block)), dim3(block), 0,
+                       s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace nv

@@ -1,0 +1,547 @@
+// C ABI of libnv (declared in include/nv.h): argument checking, device-buffer
+// planning and ownership, kernel launches on the context's stream, timing and
+// error reporting.  No arithmetic of the method happens here apart from the
+// FP64 scalars of the slice partition and grid (T_j, h, grid spacing, the
+// lookup's (n-1)/(hi-lo)), which are computed once on the host.
+#include "nv.h"
+#include "nv_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+namespace {
+
+thread_local std::string g_last_error;
+
+nv_status fail(nv_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define NV_HIP(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(NV_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int rhs_dim(int rhs) {
+    switch (rhs) {
+    case NV_RHS_LINEAR: case NV_RHS_LOGISTIC: case NV_RHS_FORCED_CUBIC: case NV_RHS_SQUARE:
+        return 1;
+    case NV_RHS_VDP:
+        return 2;
+    default:
+        return 0;
+    }
+}
+int rhs_nparams(int rhs) { return (rhs == NV_RHS_LINEAR || rhs == NV_RHS_VDP) ? 1 : 0; }
+bool rhs_forced(int rhs) { return rhs == NV_RHS_FORCED_CUBIC; }
+
+nv_options default_options() {
+    nv_options o;
+    o.scheme = NV_SCHEME_RK4;
+    o.precision = NV_FP64;
+    o.compensated = 1;
+    o.traj_per_lane = 0;
+    o.stream = nullptr;
+    return o;
+}
+
+int effective_p(const nv_options &o) { return o.traj_per_lane == 0 ? 1 : o.traj_per_lane; }
+
+nv_status check_options(const nv_options *o) {
+    if (!o) return fail(NV_ERR_INVALID_ARG, "options pointer is NULL");
+    if (o->scheme != NV_SCHEME_RK4 && o->scheme != NV_SCHEME_EULER)
+        return fail(NV_ERR_INVALID_ARG, "unknown scheme %d", o->scheme);
+    if (o->precision != NV_FP64 && o->precision != NV_FP32)
+        return fail(NV_ERR_INVALID_ARG, "unknown precision %d", o->precision);
+    if (o->compensated != 0 && o->compensated != 1)
+        return fail(NV_ERR_INVALID_ARG, "compensated must be 0 or 1");
+    if (o->traj_per_lane != 0 && o->traj_per_lane != 1 && o->traj_per_lane != 2 &&
+        o->traj_per_lane != 4)
+        return fail(NV_ERR_INVALID_ARG, "traj_per_lane must be 0, 1, 2 or 4");
+    return NV_OK;
+}
+
+// Where everything lives for one build shape.
+struct Plan {
+    int dim = 0;
+    long long M = 0;              // points per slice
+    size_t elem = 0;              // bytes per table value
+    size_t comp_bytes = 0;        // one component's table, aligned
+    size_t table_bytes = 0;
+    size_t forcing_off = 0, forcing_bytes = 0;
+    size_t nonfinite_off = 0;
+    size_t boundary_off = 0, boundary_bytes = 0;
+    size_t status_off = 0;
+    size_t work_bytes = 0;
+    int tiles_per_slice = 0;
+    long long total_blocks = 0;
+};
+
+nv_status make_plan(int rhs, int n_slices, const nv_ic_grid *g, int steps,
+                    const nv_options &o, Plan *p) {
+    if (rhs_dim(rhs) == 0) return fail(NV_ERR_INVALID_ARG, "unknown rhs_id %d", rhs);
+    if (!g) return fail(NV_ERR_INVALID_ARG, "ic_grid is NULL");
+    if (n_slices < 1) return fail(NV_ERR_INVALID_ARG, "n_slices must be >= 1 (got %d)", n_slices);
+    if (steps < 1)
+        return fail(NV_ERR_INVALID_ARG, "steps_per_slice must be >= 1 (got %d)", steps);
+    if (g->dim != rhs_dim(rhs))
+        return fail(NV_ERR_INVALID_ARG, "grid dim %d does not match the rhs dimension %d",
+                    g->dim, rhs_dim(rhs));
+    long long M = 1;
+    for (int a = 0; a < g->dim; ++a) {
+        if (g->n[a] < 2) return fail(NV_ERR_INVALID_ARG, "grid axis %d needs n >= 2", a);
+        if (!std::isfinite(g->lo[a]) || !std::isfinite(g->hi[a]) || !(g->hi[a] > g->lo[a]))
+            return fail(NV_ERR_INVALID_ARG, "grid axis %d needs finite lo < hi", a);
+        M *= g->n[a];
+    }
+    if (M > 0x7fffffffLL)
+        return fail(NV_ERR_INVALID_ARG, "grid has %lld points; at most 2^31-1 per slice", M);
+    switch (g->interp) {
+    case NV_INTERP_LINEAR:
+        if (g->dim != 1) return fail(NV_ERR_INVALID_ARG, "LINEAR interpolation needs dim 1");
+        break;
+    case NV_INTERP_HERMITE:
+        if (g->dim != 1) return fail(NV_ERR_INVALID_ARG, "HERMITE interpolation needs dim 1");
+        if (g->n[0] < 3) return fail(NV_ERR_INVALID_ARG, "HERMITE interpolation needs n >= 3");
+        break;
+    case NV_INTERP_BILINEAR:
+        if (g->dim != 2) return fail(NV_ERR_INVALID_ARG, "BILINEAR interpolation needs dim 2");
+        break;
+    default:
+        return fail(NV_ERR_INVALID_ARG, "unknown interpolation %d", g->interp);
+    }
+    const int P = effective_p(o);
+    const long long per_tile = (long long)nv::kBuildBlock * P;
+    const long long tiles = (M + per_tile - 1) / per_tile;
+    const long long blocks = tiles * n_slices;
+    if (blocks > 0x7fffffffLL)
+        return fail(NV_ERR_INVALID_ARG, "build needs %lld workgroups; at most 2^31-1", blocks);
+
+    p->dim = g->dim;
+    p->M = M;
+    p->elem = o.precision == NV_FP64 ? sizeof(double) : sizeof(float);
+    p->comp_bytes = align_up(size_t(M) * size_t(n_slices) * p->elem);
+    p->table_bytes = p->comp_bytes * size_t(g->dim);
+    size_t off = 0;
+    p->forcing_off = off;
+    p->forcing_bytes = rhs_forced(rhs) ? (2 * size_t(steps) + 1) * size_t(n_slices) * p->elem : 0;
+    off = align_up(off + p->forcing_bytes);
+    p->nonfinite_off = off;
+    off = align_up(off + size_t(n_slices) * sizeof(uint32_t));
+    p->boundary_off = off;
+    p->boundary_bytes = (size_t(n_slices) + 1) * size_t(g->dim) * sizeof(double);
+    off = align_up(off + p->boundary_bytes);
+    p->status_off = off;
+    off = align_up(off + sizeof(nv::ComposeStatus));
+    p->work_bytes = off;
+    p->tiles_per_slice = int(tiles);
+    p->total_blocks = blocks;
+    return NV_OK;
+}
+
+}  // namespace
+
+struct nv_ctx {
+    nv_options opt = default_options();
+    // device memory
+    void *tables = nullptr;
+    size_t tables_cap = 0;
+    bool tables_owned = true;
+    void *work = nullptr;
+    size_t work_cap = 0;
+    bool work_owned = true;
+    // pinned staging for the composition's outputs
+    void *host_stage = nullptr;
+    size_t host_stage_cap = 0;
+    // last build
+    bool built = false;
+    Plan plan;
+    int rhs = -1;
+    int precision = NV_FP64;
+    int n_slices = 0;
+    nv_ic_grid grid{};
+    // timing
+    bool timing = false;
+    bool build_timed = false, compose_timed = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+hipStream_t stream_of(const nv_ctx *c) { return static_cast<hipStream_t>(c->opt.stream); }
+
+nv_status ensure_device(void **ptr, size_t *cap, bool owned, size_t need, const char *what) {
+    if (!owned) {
+        if (*ptr == nullptr && need > 0)
+            return fail(NV_ERR_BUFFER_TOO_SMALL, "no %s buffer was given", what);
+        if (need > *cap)
+            return fail(NV_ERR_BUFFER_TOO_SMALL, "%s buffer holds %zu bytes, build needs %zu",
+                        what, *cap, need);
+        return NV_OK;
+    }
+    if (need <= *cap && *ptr) return NV_OK;
+    if (*ptr) {
+        NV_HIP(hipFree(*ptr));
+        *ptr = nullptr;
+        *cap = 0;
+    }
+    hipError_t e = hipMalloc(ptr, need);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return fail(NV_ERR_OOM, "hipMalloc of %zu bytes for %s failed: %s", need, what,
+                    hipGetErrorString(e));
+    }
+    *cap = need;
+    return NV_OK;
+}
+
+nv_status ensure_host_stage(nv_ctx *c, size_t need) {
+    if (need <= c->host_stage_cap && c->host_stage) return NV_OK;
+    if (c->host_stage) {
+        NV_HIP(hipHostFree(c->host_stage));
+        c->host_stage = nullptr;
+        c->host_stage_cap = 0;
+    }
+    hipError_t e = hipHostMalloc(&c->host_stage, need, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        c->host_stage = nullptr;
+        return fail(NV_ERR_OOM, "hipHostMalloc of %zu bytes failed: %s", need,
+                    hipGetErrorString(e));
+    }
+    c->host_stage_cap = need;
+    return NV_OK;
+}
+
+nv_status ensure_events(nv_ctx *c) {
+    for (auto &e : c->ev)
+        if (!e) NV_HIP(hipEventCreate(&e));
+    return NV_OK;
+}
+
+char *work_at(const nv_ctx *c, size_t off) { return static_cast<char *>(c->work) + off; }
+
+}  // namespace
+
+extern "C" {
+
+NV_API nv_status nv_ctx_create(nv_ctx **out) {
+    if (!out) return fail(NV_ERR_INVALID_ARG, "out is NULL");
+    *out = new (std::nothrow) nv_ctx();
+    if (!*out) return fail(NV_ERR_OOM, "out of host memory");
+    return NV_OK;
+}
+
+NV_API nv_status nv_ctx_destroy(nv_ctx *ctx) {
+    if (!ctx) return NV_OK;
+    if (ctx->built) (void)hipStreamSynchronize(stream_of(ctx));
+    if (ctx->tables_owned && ctx->tables) (void)hipFree(ctx->tables);
+    if (ctx->work_owned && ctx->work) (void)hipFree(ctx->work);
+    if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+    for (auto e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+    return NV_OK;
+}
+
+NV_API nv_status nv_set_options(nv_ctx *ctx, const nv_options *opt) {
+    if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
+    nv_status s = check_options(opt);
+    if (s != NV_OK) return s;
+    ctx->opt = *opt;
+    return NV_OK;
+}
+
+NV_API nv_status nv_get_options(const nv_ctx *ctx, nv_options *opt) {
+    if (!ctx || !opt) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    *opt = ctx->opt;
+    return NV_OK;
+}
+
+NV_API nv_status nv_required_bytes(int rhs_id, int n_slices, const nv_ic_grid *grid,
+                                   int steps_per_slice, const nv_options *opt,
+                                   size_t *table_bytes, size_t *work_bytes) {
+    nv_options o = default_options();
+    if (opt) {
+        nv_status s = check_options(opt);
+        if (s != NV_OK) return s;
+        o = *opt;
+    }
+    Plan p;
+    nv_status s = make_plan(rhs_id, n_slices, grid, steps_per_slice, o, &p);
+    if (s != NV_OK) return s;
+    if (table_bytes) *table_bytes = p.table_bytes;
+    if (work_bytes) *work_bytes = p.work_bytes;
+    return NV_OK;
+}
+
+NV_API nv_status nv_set_buffers(nv_ctx *ctx, void *tables_dev, size_t table_bytes,
+                                void *work_dev, size_t work_bytes) {
+    if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
+    if ((tables_dev == nullptr) != (work_dev == nullptr))
+        return fail(NV_ERR_INVALID_ARG, "give both buffers or neither");
+    if (ctx->built) NV_HIP(hipStreamSynchronize(stream_of(ctx)));
+    if (ctx->tables_owned && ctx->tables) NV_HIP(hipFree(ctx->tables));
+    if (ctx->work_owned && ctx->work) NV_HIP(hipFree(ctx->work));
+    ctx->built = false;
+    if (tables_dev) {
+        ctx->tables = tables_dev;
+        ctx->tables_cap = table_bytes;
+        ctx->tables_owned = false;
+        ctx->work = work_dev;
+        ctx->work_cap = work_bytes;
+        ctx->work_owned = false;
+    } else {
+        ctx->tables = nullptr;
+        ctx->tables_cap = 0;
+        ctx->tables_owned = true;
+        ctx->work = nullptr;
+        ctx->work_cap = 0;
+        ctx->work_owned = true;
+    }
+    return NV_OK;
+}
+
+NV_API nv_status nv_build_propagators(nv_ctx *ctx, int rhs_id, const double *params,
+                                      double t0, double T, int n_slices,
+                                      const nv_ic_grid *grid, int steps_per_slice) {
+    if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->built = false;
+    Plan p;
+    nv_status s = make_plan(rhs_id, n_slices, grid, steps_per_slice, ctx->opt, &p);
+    if (s != NV_OK) return s;
+    if (!std::isfinite(t0) || !std::isfinite(T) || !(T > t0))
+        return fail(NV_ERR_INVALID_ARG, "need finite t0 < T (got %g, %g)", t0, T);
+    double p0 = 0.0;
+    if (rhs_nparams(rhs_id) > 0) {
+        if (!params) return fail(NV_ERR_INVALID_ARG, "rhs %d needs a parameter", rhs_id);
+        if (!std::isfinite(params[0])) return fail(NV_ERR_INVALID_ARG, "parameter not finite");
+        p0 = params[0];
+    }
+    nv::BuildConfig cfg{rhs_id, ctx->opt.scheme, ctx->opt.precision, ctx->opt.compensated,
+                        effective_p(ctx->opt)};
+    if (!nv::build_supported(cfg)) return fail(NV_ERR_UNSUPPORTED, "unsupported configuration");
+
+    s = ensure_device(&ctx->tables, &ctx->tables_cap, ctx->tables_owned, p.table_bytes, "table");
+    if (s != NV_OK) return s;
+    s = ensure_device(&ctx->work, &ctx->work_cap, ctx->work_owned, p.work_bytes, "work");
+    if (s != NV_OK) return s;
+    s = ensure_host_stage(ctx, p.status_off - p.boundary_off + sizeof(nv::ComposeStatus));
+    if (s != NV_OK) return s;
+
+    hipStream_t st = stream_of(ctx);
+    // slice partition (sec. 3): L = (T - t0)/N, T_j = t0 + j L, h = L / S
+    const double L = (T - t0) / double(n_slices);
+    const double h = L / double(steps_per_slice);
+
+    nv::BuildArgs a{};
+    a.tab0 = ctx->tables;
+    a.tab1 = p.dim == 2 ? static_cast<char *>(ctx->tables) + p.comp_bytes : nullptr;
+    a.forcing = rhs_forced(rhs_id) ? work_at(ctx, p.forcing_off) : nullptr;
+    a.nonfinite = reinterpret_cast<uint32_t *>(work_at(ctx, p.nonfinite_off));
+    a.lo0 = grid->lo[0];
+    a.dxi0 = (grid->hi[0] - grid->lo[0]) / double(grid->n[0] - 1);
+    a.lo1 = p.dim == 2 ? grid->lo[1] : 0.0;
+    a.dxi1 = p.dim == 2 ? (grid->hi[1] - grid->lo[1]) / double(grid->n[1] - 1) : 0.0;
+    a.h = h;
+    a.p0 = p0;
+    a.M = p.M;
+    a.n1 = p.dim == 2 ? grid->n[1] : 1;
+    a.n_slices = n_slices;
+    a.steps = steps_per_slice;
+    a.tiles_per_slice = p.tiles_per_slice;
+    a.total_blocks = int(p.total_blocks);
+
+    NV_HIP(nv::launch_fill_u32(a.nonfinite, n_slices, 0u, st));
+    if (a.forcing)
+        NV_HIP(nv::launch_forcing(rhs_id, ctx->opt.precision, work_at(ctx, p.forcing_off),
+                                  n_slices, steps_per_slice, t0, L, h, st));
+    ctx->build_timed = false;
+    if (ctx->timing) {
+        s = ensure_events(ctx);
+        if (s != NV_OK) return s;
+        NV_HIP(hipEventRecord(ctx->ev[0], st));
+    }
+    NV_HIP(nv::launch_build(cfg, a, st));
+    if (ctx->timing) {
+        NV_HIP(hipEventRecord(ctx->ev[1], st));
+        ctx->build_timed = true;
+    }
+
+    ctx->plan = p;
+    ctx->rhs = rhs_id;
+    ctx->precision = ctx->opt.precision;
+    ctx->n_slices = n_slices;
+    ctx->grid = *grid;
+    ctx->built = true;
+    return NV_OK;
+}
+
+NV_API nv_status nv_compose(nv_ctx *ctx, const double *y0, double *yT, double *boundary,
+                            nv_compose_info *info) {
+    if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
+    if (!ctx->built) return fail(NV_ERR_NOT_BUILT, "nv_compose before a successful build");
+    if (!y0 || !yT) return fail(NV_ERR_INVALID_ARG, "y0 and yT must not be NULL");
+    const Plan &p = ctx->plan;
+    const nv_ic_grid &g = ctx->grid;
+    hipStream_t st = stream_of(ctx);
+
+    nv::ComposeArgs a{};
+    a.tab0 = ctx->tables;
+    a.tab1 = p.dim == 2 ? static_cast<char *>(ctx->tables) + p.comp_bytes : nullptr;
+    a.boundary = reinterpret_cast<double *>(work_at(ctx, p.boundary_off));
+    a.status = reinterpret_cast<nv::ComposeStatus *>(work_at(ctx, p.status_off));
+    a.M = p.M;
+    a.n_slices = ctx->n_slices;
+    a.n0 = g.n[0];
+    a.n1 = p.dim == 2 ? g.n[1] : 1;
+    a.lo0 = g.lo[0];
+    a.inv0 = double(g.n[0] - 1) / (g.hi[0] - g.lo[0]);
+    a.lo1 = p.dim == 2 ? g.lo[1] : 0.0;
+    a.inv1 = p.dim == 2 ? double(g.n[1] - 1) / (g.hi[1] - g.lo[1]) : 0.0;
+    a.y00 = y0[0];
+    a.y01 = p.dim == 2 ? y0[1] : 0.0;
+
+    ctx->compose_timed = false;
+    if (ctx->timing) {
+        nv_status s = ensure_events(ctx);
+        if (s != NV_OK) return s;
+        NV_HIP(hipEventRecord(ctx->ev[2], st));
+    }
+    NV_HIP(nv::launch_compose(g.interp, ctx->precision, a, st));
+    if (ctx->timing) {
+        NV_HIP(hipEventRecord(ctx->ev[3], st));
+        ctx->compose_timed = true;
+    }
+    // boundary states and status to pinned host memory in one copy (they are
+    // adjacent in the scratch buffer)
+    const size_t bytes = p.status_off - p.boundary_off + sizeof(nv::ComposeStatus);
+    NV_HIP(hipMemcpyAsync(ctx->host_stage, a.boundary, bytes, hipMemcpyDeviceToHost, st));
+    NV_HIP(hipStreamSynchronize(st));
+    const double *hb = static_cast<const double *>(ctx->host_stage);
+    nv::ComposeStatus cs;
+    std::memcpy(&cs, static_cast<const char *>(ctx->host_stage) + (p.status_off - p.boundary_off),
+                sizeof cs);
+    if (!cs.done) return fail(NV_ERR_HIP, "composition kernel did not complete");
+    const int n_done = cs.bad_slice < 0 ? ctx->n_slices : cs.bad_slice;
+    if (boundary) std::memcpy(boundary, hb, size_t(n_done + 1) * p.dim * sizeof(double));
+    for (int c = 0; c < p.dim; ++c) yT[c] = hb[size_t(n_done) * p.dim + c];
+    if (info) {
+        info->n_out_of_grid = cs.n_out_of_grid;
+        info->bad_slice = cs.bad_slice;
+        info->reserved = 0;
+    }
+    if (cs.bad_slice >= 0)
+        return fail(NV_ERR_NONFINITE, "composition met a non-finite value in slice %d",
+                    cs.bad_slice);
+    return NV_OK;
+}
+
+NV_API nv_status nv_get_table(nv_ctx *ctx, int component, void *host_dst, size_t bytes) {
+    if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
+    if (!ctx->built) return fail(NV_ERR_NOT_BUILT, "no table before a successful build");
+    if (component < 0 || component >= ctx->plan.dim || !host_dst)
+        return fail(NV_ERR_INVALID_ARG, "bad component or NULL destination");
+    const size_t need = size_t(ctx->plan.M) * size_t(ctx->n_slices) * ctx->plan.elem;
+    if (bytes < need) return fail(NV_ERR_BUFFER_TOO_SMALL, "need %zu bytes", need);
+    hipStream_t st = stream_of(ctx);
+    const char *src = static_cast<const char *>(ctx->tables) + component * ctx->plan.comp_bytes;
+    NV_HIP(hipMemcpyAsync(host_dst, src, need, hipMemcpyDeviceToHost, st));
+    NV_HIP(hipStreamSynchronize(st));
+    return NV_OK;
+}
+
+NV_API nv_status nv_table_device_ptr(nv_ctx *ctx, int component, void **dev_ptr) {
+    if (!ctx || !dev_ptr) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    if (!ctx->built) return fail(NV_ERR_NOT_BUILT, "no table before a successful build");
+    if (component < 0 || component >= ctx->plan.dim)
+        return fail(NV_ERR_INVALID_ARG, "bad component %d", component);
+    *dev_ptr = static_cast<char *>(ctx->tables) + component * ctx->plan.comp_bytes;
+    return NV_OK;
+}
+
+NV_API nv_status nv_get_nonfinite_counts(nv_ctx *ctx, uint32_t *host_counts, int n) {
+    if (!ctx || !host_counts) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    if (!ctx->built) return fail(NV_ERR_NOT_BUILT, "no counts before a successful build");
+    if (n < ctx->n_slices) return fail(NV_ERR_BUFFER_TOO_SMALL, "need %d counts", ctx->n_slices);
+    hipStream_t st = stream_of(ctx);
+    NV_HIP(hipMemcpyAsync(host_counts, work_at(ctx, ctx->plan.nonfinite_off),
+                          size_t(ctx->n_slices) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    NV_HIP(hipStreamSynchronize(st));
+    return NV_OK;
+}
+
+NV_API nv_status nv_locate(nv_ctx *ctx, double lo, double hi, int n, const double *x_dev,
+                           long long count, long long *cell_dev, double *w_dev,
+                           int32_t *out_dev) {
+    if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
+    if (n < 2 || !std::isfinite(lo) || !std::isfinite(hi) || !(hi > lo))
+        return fail(NV_ERR_INVALID_ARG, "need n >= 2 and finite lo < hi");
+    if (count < 0) return fail(NV_ERR_INVALID_ARG, "negative count");
+    if (count > 0 && (!x_dev || !cell_dev || !w_dev || !out_dev))
+        return fail(NV_ERR_INVALID_ARG, "NULL device array");
+    const double inv = double(n - 1) / (hi - lo);
+    hipStream_t st = stream_of(ctx);
+    NV_HIP(nv::launch_locate(lo, inv, n, x_dev, count, cell_dev, w_dev, out_dev, st));
+    NV_HIP(hipStreamSynchronize(st));
+    return NV_OK;
+}
+
+NV_API nv_status nv_set_timing(nv_ctx *ctx, int enable) {
+    if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->timing = enable != 0;
+    ctx->build_timed = ctx->compose_timed = false;
+    return NV_OK;
+}
+
+NV_API nv_status nv_last_timing(nv_ctx *ctx, float *build_ms, float *compose_ms) {
+    if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
+    if (build_ms) {
+        *build_ms = -1.0f;
+        if (ctx->build_timed) {
+            NV_HIP(hipEventSynchronize(ctx->ev[1]));
+            NV_HIP(hipEventElapsedTime(build_ms, ctx->ev[0], ctx->ev[1]));
+        }
+    }
+    if (compose_ms) {
+        *compose_ms = -1.0f;
+        if (ctx->compose_timed) {
+            NV_HIP(hipEventSynchronize(ctx->ev[3]));
+            NV_HIP(hipEventElapsedTime(compose_ms, ctx->ev[2], ctx->ev[3]));
+        }
+    }
+    return NV_OK;
+}
+
+NV_API const char *nv_last_error(void) { return g_last_error.c_str(); }
+
+NV_API const char *nv_status_string(int status) {
+    switch (status) {
+    case NV_OK: return "NV_OK";
+    case NV_ERR_INVALID_ARG: return "NV_ERR_INVALID_ARG";
+    case NV_ERR_NOT_BUILT: return "NV_ERR_NOT_BUILT";
+    case NV_ERR_NONFINITE: return "NV_ERR_NONFINITE";
+    case NV_ERR_OOM: return "NV_ERR_OOM";
+    case NV_ERR_HIP: return "NV_ERR_HIP";
+    case NV_ERR_UNSUPPORTED: return "NV_ERR_UNSUPPORTED";
+    case NV_ERR_BUFFER_TOO_SMALL: return "NV_ERR_BUFFER_TOO_SMALL";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Library-internal declarations shared by the C ABI and the kernels of libnv.
+// Not installed; the public interface is include/nv.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace nv {
+
+constexpr int kBuildBlock = 256;   // lanes per build workgroup (4 wave64s)
+constexpr int kNumXcd = 8;         // MI355X: 8 XCDs, workgroups dispatched round-robin
+
+// Arguments of the ensemble-integration kernel (one launch = the whole build).
+struct BuildArgs {
+    void *tab0;               // component 0 table, [n_slices][M] of the working type
+    void *tab1;               // component 1 table (2-D problems) or null
+    const void *forcing;      // [n_slices][2*steps+1] forcing values, or null
+    uint32_t *nonfinite;      // [n_slices] counters
+    double lo0, dxi0;         // axis 0: xi = lo0 + k0 * dxi0
+    double lo1, dxi1;         // axis 1 (2-D)
+    double h;                 // step
+    double p0;                // right-hand side parameter
+    long long M;              // points per slice
+    int n1;                   // points on axis 1 (1 for 1-D)
+    int n_slices;
+    int steps;
+    int tiles_per_slice;      // workgroups per slice
+    int total_blocks;         // n_slices * tiles_per_slice
+};
+
+struct BuildConfig {
+    int rhs;                  // nv_rhs_id
+    int scheme;               // nv_scheme
+    int precision;            // nv_precision
+    int compensated;          // FP32 only
+    int traj_per_lane;        // 1, 2, 4
+};
+
+// Status the composition kernel leaves in device memory.
+struct ComposeStatus {
+    long long n_out_of_grid;
+    int bad_slice;
+    int done;
+};
+
+struct ComposeArgs {
+    const void *tab0;
+    const void *tab1;
+    double *boundary;         // [(n_slices+1) * dim]
+    ComposeStatus *status;
+    long long M;
+    int n_slices;
+    int n0, n1;
+    double lo0, inv0, lo1, inv1;   // inv = (n-1)/(hi-lo), computed on the host
+    double y00, y01;
+};
+
+bool build_supported(const BuildConfig &c);
+hipError_t launch_build(const BuildConfig &c, const BuildArgs &a, hipStream_t s);
+hipError_t launch_forcing(int rhs, int precision, void *F, int n_slices, int steps,
+                          double t0, double L, double h, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t s);
+hipError_t launch_compose(int interp, int precision, const ComposeArgs &a, hipStream_t s);
+hipError_t launch_locate(double lo, double inv, int n, const double *x, long long count,
+                         long long *cell, double *w, int32_t *out, hipStream_t s);
+
+}  // namespace nv

@@ -1,0 +1,240 @@
+"""ctypes binding of libnv (include/nv.h), with the C ABI's names.
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  If libnv.so has not been built this module raises on first use; there
+is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnv.so")
+
+# nv_status
+NV_OK = 0
+NV_ERR_INVALID_ARG = -1
+NV_ERR_NOT_BUILT = -2
+NV_ERR_NONFINITE = -3
+NV_ERR_OOM = -4
+NV_ERR_HIP = -5
+NV_ERR_UNSUPPORTED = -6
+NV_ERR_BUFFER_TOO_SMALL = -7
+# nv_rhs_id
+NV_RHS_LINEAR, NV_RHS_LOGISTIC, NV_RHS_FORCED_CUBIC, NV_RHS_VDP, NV_RHS_SQUARE = range(5)
+# nv_scheme, nv_precision, nv_interp
+NV_SCHEME_RK4, NV_SCHEME_EULER = 0, 1
+NV_FP64, NV_FP32 = 0, 1
+NV_INTERP_LINEAR, NV_INTERP_HERMITE, NV_INTERP_BILINEAR = 0, 1, 2
+
+RHS_IDS = {"linear": NV_RHS_LINEAR, "logistic": NV_RHS_LOGISTIC,
+           "forced_cubic": NV_RHS_FORCED_CUBIC, "vdp": NV_RHS_VDP, "square": NV_RHS_SQUARE}
+SCHEMES = {"rk4": NV_SCHEME_RK4, "euler": NV_SCHEME_EULER}
+PRECISIONS = {"fp64": NV_FP64, "fp32": NV_FP32}
+INTERPS = {"linear": NV_INTERP_LINEAR, "hermite": NV_INTERP_HERMITE,
+           "bilinear": NV_INTERP_BILINEAR}
+
+
+class nv_ic_grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 2), ("lo", ctypes.c_double * 2),
+                ("hi", ctypes.c_double * 2), ("interp", ctypes.c_int)]
+
+
+class nv_options(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int), ("precision", ctypes.c_int),
+                ("compensated", ctypes.c_int), ("traj_per_lane", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
+
+
+class nv_compose_info(ctypes.Structure):
+    _fields_ = [("n_out_of_grid", ctypes.c_longlong), ("bad_slice", ctypes.c_int),
+                ("reserved", ctypes.c_int)]
+
+
+class NvError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{status_name(status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "nv_ctx_create": [ctypes.POINTER(ctypes.c_void_p)],
+    "nv_ctx_destroy": [_P],
+    "nv_set_options": [_P, ctypes.POINTER(nv_options)],
+    "nv_get_options": [_P, ctypes.POINTER(nv_options)],
+    "nv_required_bytes": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(nv_ic_grid), ctypes.c_int,
+                          ctypes.POINTER(nv_options), ctypes.POINTER(ctypes.c_size_t),
+                          ctypes.POINTER(ctypes.c_size_t)],
+    "nv_set_buffers": [_P, _P, ctypes.c_size_t, _P, ctypes.c_size_t],
+    "nv_build_propagators": [_P, ctypes.c_int, _P, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_int, ctypes.POINTER(nv_ic_grid), ctypes.c_int],
+    "nv_compose": [_P, _P, _P, _P, ctypes.POINTER(nv_compose_info)],
+    "nv_get_table": [_P, ctypes.c_int, _P, ctypes.c_size_t],
+    "nv_table_device_ptr": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)],
+    "nv_get_nonfinite_counts": [_P, _P, ctypes.c_int],
+    "nv_locate": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, ctypes.c_longlong,
+                  _P, _P, _P],
+    "nv_set_timing": [_P, ctypes.c_int],
+    "nv_last_timing": [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+    "nv_last_error": [],
+    "nv_status_string": [ctypes.c_int],
+}
+
+
+def load():
+    """Load libnv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name in ("nv_last_error", "nv_status_string") \
+            else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def status_name(status: int) -> str:
+    return load().nv_status_string(int(status)).decode()
+
+
+def nv_last_error() -> str:
+    return load().nv_last_error().decode()
+
+
+def _check(status: int):
+    if status != NV_OK:
+        raise NvError(status, nv_last_error())
+    return status
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_grid(n, lo, hi, interp) -> nv_ic_grid:
+    n = list(np.atleast_1d(n))
+    lo = list(np.atleast_1d(lo))
+    hi = list(np.atleast_1d(hi))
+    g = nv_ic_grid()
+    g.dim = len(n)
+    for a in range(len(n)):
+        g.n[a], g.lo[a], g.hi[a] = int(n[a]), float(lo[a]), float(hi[a])
+    g.interp = INTERPS[interp] if isinstance(interp, str) else int(interp)
+    return g
+
+
+def make_options(scheme="rk4", precision="fp64", compensated=1, traj_per_lane=0,
+                 stream=None) -> nv_options:
+    o = nv_options()
+    o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.compensated = int(compensated)
+    o.traj_per_lane = int(traj_per_lane)
+    o.stream = stream
+    return o
+
+
+# ---- the C ABI, one wrapper per entry point -------------------------------
+
+def nv_ctx_create():
+    h = ctypes.c_void_p()
+    _check(load().nv_ctx_create(ctypes.byref(h)))
+    return h
+
+
+def nv_ctx_destroy(ctx):
+    return _check(load().nv_ctx_destroy(ctx))
+
+
+def nv_set_options(ctx, opt: nv_options):
+    return _check(load().nv_set_options(ctx, ctypes.byref(opt)))
+
+
+def nv_get_options(ctx) -> nv_options:
+    o = nv_options()
+    _check(load().nv_get_options(ctx, ctypes.byref(o)))
+    return o
+
+
+def nv_required_bytes(rhs_id, n_slices, grid: nv_ic_grid, steps_per_slice, opt=None):
+    tb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load().nv_required_bytes(int(rhs_id), int(n_slices), ctypes.byref(grid),
+                                    int(steps_per_slice),
+                                    ctypes.byref(opt) if opt is not None else None,
+                                    ctypes.byref(tb), ctypes.byref(wb)))
+    return tb.value, wb.value
+
+
+def nv_set_buffers(ctx, tables_dev, table_bytes, work_dev, work_bytes):
+    return _check(load().nv_set_buffers(ctx, tables_dev, int(table_bytes), work_dev,
+                                        int(work_bytes)))
+
+
+def nv_build_propagators(ctx, rhs_id, params, t0, T, n_slices, grid: nv_ic_grid,
+                         steps_per_slice):
+    p = np.ascontiguousarray(np.asarray(params if params is not None else [0.0],
+                                        dtype=np.float64).reshape(-1))
+    if p.size == 0:
+        p = np.zeros(1)
+    return _check(load().nv_build_propagators(ctx, int(rhs_id), _ptr(p), float(t0), float(T),
+                                              int(n_slices), ctypes.byref(grid),
+                                              int(steps_per_slice)))
+
+
+def nv_compose(ctx, y0, dim, n_slices, want_boundary=True):
+    """Returns (status, yT, boundary or None, info).  Raises on every status
+    other than NV_OK and NV_ERR_NONFINITE."""
+    y0 = np.ascontiguousarray(np.asarray(y0, dtype=np.float64).reshape(-1))
+    yT = np.full(dim, np.nan)
+    boundary = np.full((n_slices + 1, dim), np.nan) if want_boundary else None
+    info = nv_compose_info()
+    st = load().nv_compose(ctx, _ptr(y0), _ptr(yT),
+                           _ptr(boundary) if boundary is not None else None,
+                           ctypes.byref(info))
+    if st not in (NV_OK, NV_ERR_NONFINITE):
+        _check(st)
+    return st, yT, boundary, info
+
+
+def nv_get_table(ctx, component, n_slices, points, precision):
+    dt = np.float64 if precision in ("fp64", NV_FP64) else np.float32
+    out = np.empty((n_slices, points), dtype=dt)
+    _check(load().nv_get_table(ctx, int(component), _ptr(out), out.nbytes))
+    return out
+
+
+def nv_table_device_ptr(ctx, component):
+    p = ctypes.c_void_p()
+    _check(load().nv_table_device_ptr(ctx, int(component), ctypes.byref(p)))
+    return p.value
+
+
+def nv_get_nonfinite_counts(ctx, n_slices):
+    out = np.zeros(n_slices, dtype=np.uint32)
+    _check(load().nv_get_nonfinite_counts(ctx, _ptr(out), int(n_slices)))
+    return out
+
+
+def nv_locate(ctx, lo, hi, n, x_dev, count, cell_dev, w_dev, out_dev):
+    return _check(load().nv_locate(ctx, float(lo), float(hi), int(n), x_dev, int(count),
+                                   cell_dev, w_dev, out_dev))
+
+
+def nv_set_timing(ctx, enable):
+    return _check(load().nv_set_timing(ctx, int(bool(enable))))
+
+
+def nv_last_timing(ctx):
+    b, c = ctypes.c_float(), ctypes.c_float()
+    _check(load().nv_last_timing(ctx, ctypes.byref(b), ctypes.byref(c)))
+    return b.value, c.value

@@ -1,0 +1,122 @@
+"""PyTorch-owned device memory and streams around the libnv C ABI.
+
+``Propagator`` allocates the table and scratch buffers as torch tensors on the
+device, hands their addresses to the library (nv_set_buffers) and launches on
+torch's current stream of that device.  All arithmetic runs in libnv's kernels.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import nv
+from .workloads import Workload
+
+
+@dataclass
+class ComposeResult:
+    status: int
+    yT: np.ndarray
+    boundary: np.ndarray | None
+    n_out_of_grid: int
+    bad_slice: int
+
+
+class Propagator:
+    def __init__(self, device="cuda:0", traj_per_lane=0, compensated=1, stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("Propagator needs a GPU device")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.traj_per_lane = traj_per_lane
+        self.compensated = compensated
+        self.ctx = nv.nv_ctx_create()
+        self._tables = None
+        self._work = None
+        self.workload: Workload | None = None
+
+    # -- lifecycle -----------------------------------------------------------
+    def close(self):
+        if self.ctx is not None:
+            nv.nv_ctx_destroy(self.ctx)
+            self.ctx = None
+        self._tables = self._work = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -------------------------------------------------------------
+    def options(self, w: Workload) -> nv.nv_options:
+        return nv.make_options(w.scheme, w.precision, self.compensated, self.traj_per_lane,
+                               self.stream.cuda_stream)
+
+    @staticmethod
+    def grid(w: Workload) -> nv.nv_ic_grid:
+        return nv.make_grid(w.grid_n, w.grid_lo, w.grid_hi, w.interp)
+
+    def _ensure_buffers(self, table_bytes, work_bytes):
+        t = self.torch
+        if (self._tables is None or self._tables.numel() < table_bytes or
+                self._work is None or self._work.numel() < work_bytes):
+            with t.cuda.device(self.device):
+                self._tables = t.empty(max(table_bytes, 256), dtype=t.uint8, device=self.device)
+                self._work = t.empty(max(work_bytes, 256), dtype=t.uint8, device=self.device)
+            nv.nv_set_buffers(self.ctx, self._tables.data_ptr(), self._tables.numel(),
+                              self._work.data_ptr(), self._work.numel())
+
+    # -- the two phases --------------------------------------------------------
+    def build(self, w: Workload, params=None):
+        """Computation phase: tables of every slice (asynchronous on the stream)."""
+        opt = self.options(w)
+        nv.nv_set_options(self.ctx, opt)
+        g = self.grid(w)
+        rhs = nv.RHS_IDS[w.rhs]
+        tb, wb = nv.nv_required_bytes(rhs, w.n_slices, g, w.steps_per_slice, opt)
+        self._ensure_buffers(tb, wb)
+        nv.nv_build_propagators(self.ctx, rhs, params if params is not None else w.params,
+                                w.t0, w.T, w.n_slices, g, w.steps_per_slice)
+        self.workload = w
+
+    def compose(self, y0=None, want_boundary=True) -> ComposeResult:
+        """Communication phase (synchronous)."""
+        w = self.workload
+        st, yT, b, info = nv.nv_compose(self.ctx, w.y0 if y0 is None else y0, w.dim,
+                                        w.n_slices, want_boundary)
+        return ComposeResult(st, yT, b, info.n_out_of_grid, info.bad_slice)
+
+    # -- inspection ------------------------------------------------------------
+    def table(self, component=0) -> np.ndarray:
+        w = self.workload
+        return nv.nv_get_table(self.ctx, component, w.n_slices, w.points_per_slice, w.precision)
+
+    def table_tensor(self, component=0):
+        """Device view of one component's table, shape (n_slices, points)."""
+        t = self.torch
+        w = self.workload
+        ptr = nv.nv_table_device_ptr(self.ctx, component)
+        off = ptr - self._tables.data_ptr()
+        dt = t.float64 if w.precision == "fp64" else t.float32
+        nbytes = w.n_slices * w.points_per_slice * (8 if w.precision == "fp64" else 4)
+        return self._tables[off:off + nbytes].view(dt).view(w.n_slices, w.points_per_slice)
+
+    def nonfinite_counts(self) -> np.ndarray:
+        return nv.nv_get_nonfinite_counts(self.ctx, self.workload.n_slices)
+
+    def set_timing(self, enable=True):
+        nv.nv_set_timing(self.ctx, enable)
+
+    def last_timing(self):
+        return nv.nv_last_timing(self.ctx)

@@ -1,0 +1,146 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+include/nv.h declares, and its argument checking answers without a GPU (every
+call here returns before touching the HIP runtime)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nv.h")
+
+
+@pytest.fixture(scope="module")
+def nvmod():
+    from paper_1304_6514_amd import nv
+    if not os.path.exists(nv.LIB_PATH):
+        from paper_1304_6514_amd import _build
+        _build.build()
+    nv.load()
+    return nv
+
+
+def declared_entry_points():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"NV_API\s+[^;(]*?\b(nv_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_entry_points()
+    for must in ("nv_build_propagators", "nv_compose", "nv_ctx_create", "nv_ctx_destroy",
+                 "nv_set_options", "nv_set_buffers", "nv_required_bytes", "nv_get_table",
+                 "nv_locate", "nv_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(nvmod):
+    lib = ctypes.CDLL(nvmod.LIB_PATH)
+    missing = [n for n in declared_entry_points() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_entry_point(nvmod):
+    for name in declared_entry_points():
+        assert name in nvmod._SIGNATURES, name
+
+
+def test_status_strings(nvmod):
+    assert nvmod.status_name(0) == "NV_OK"
+    assert nvmod.status_name(-3) == "NV_ERR_NONFINITE"
+    assert nvmod.status_name(-7) == "NV_ERR_BUFFER_TOO_SMALL"
+
+
+def _grid(nvmod, n=(256,), lo=(-0.1,), hi=(1.2,), interp="linear"):
+    return nvmod.make_grid(n, lo, hi, interp)
+
+
+def test_required_bytes_layout(nvmod):
+    g = _grid(nvmod, (4096,), (-3.0,), (3.0,), "hermite")
+    o = nvmod.make_options("rk4", "fp32")
+    tb, wb = nvmod.nv_required_bytes(nvmod.NV_RHS_FORCED_CUBIC, 4096, g, 2000, o)
+    assert tb == 4096 * 4096 * 4                         # 64 MiB, one FP32 component
+    assert wb >= 4096 * 4001 * 4 + 4096 * 4 + 4097 * 8   # forcing + counters + boundary
+    g2 = _grid(nvmod, (128, 128), (-3.0, -8.0), (3.0, 8.0), "bilinear")
+    tb2, _ = nvmod.nv_required_bytes(nvmod.NV_RHS_VDP, 1024, g2, 500, o)
+    assert tb2 == 2 * 1024 * 128 * 128 * 4               # two 64 MiB tables
+    tb3, _ = nvmod.nv_required_bytes(nvmod.NV_RHS_LOGISTIC, 64, _grid(nvmod), 1000,
+                                     nvmod.make_options("rk4", "fp64"))
+    assert tb3 == 64 * 256 * 8
+
+
+@pytest.mark.parametrize("case", [
+    dict(rhs=99), dict(n_slices=0), dict(steps=0), dict(n=(1,)),
+    dict(lo=(1.0,), hi=(1.0,)), dict(lo=(float("nan"),)), dict(interp="bilinear"),
+    dict(n=(2,), interp="hermite"), dict(rhs=3),                 # vdp needs a 2-D grid
+    dict(n=(70000, 70000), lo=(0, 0), hi=(1, 1), interp="bilinear", rhs=3),  # > 2^31 points
+])
+def test_required_bytes_rejects_bad_shapes(nvmod, case):
+    rhs = case.get("rhs", nvmod.NV_RHS_LOGISTIC)
+    g = _grid(nvmod, case.get("n", (256,)), case.get("lo", (-0.1,)), case.get("hi", (1.2,)),
+              case.get("interp", "linear"))
+    with pytest.raises(nvmod.NvError) as e:
+        nvmod.nv_required_bytes(rhs, case.get("n_slices", 64), g, case.get("steps", 1000))
+    assert e.value.status == nvmod.NV_ERR_INVALID_ARG
+
+
+def test_options_validation(nvmod):
+    ctx = nvmod.nv_ctx_create()
+    try:
+        for bad in (dict(scheme=5), dict(precision=7), dict(traj_per_lane=3),
+                    dict(compensated=2)):
+            o = nvmod.make_options(**{**dict(scheme=0, precision=0), **bad})
+            with pytest.raises(nvmod.NvError) as e:
+                nvmod.nv_set_options(ctx, o)
+            assert e.value.status == nvmod.NV_ERR_INVALID_ARG
+        good = nvmod.make_options("euler", "fp32", 0, 4)
+        nvmod.nv_set_options(ctx, good)
+        back = nvmod.nv_get_options(ctx)
+        assert (back.scheme, back.precision, back.compensated, back.traj_per_lane) == (1, 1, 0, 4)
+    finally:
+        nvmod.nv_ctx_destroy(ctx)
+
+
+def test_build_argument_errors_need_no_gpu(nvmod):
+    ctx = nvmod.nv_ctx_create()
+    try:
+        g = _grid(nvmod)
+        cases = [
+            (nvmod.NV_RHS_LOGISTIC, None, 0.0, 10.0, 0, g, 1000),
+            (nvmod.NV_RHS_LOGISTIC, None, 10.0, 0.0, 64, g, 1000),          # T <= t0
+            (nvmod.NV_RHS_LOGISTIC, None, 0.0, float("inf"), 64, g, 1000),
+            (nvmod.NV_RHS_LINEAR, [float("nan")], 0.0, 1.0, 4, g, 10),      # bad parameter
+        ]
+        for args in cases:
+            with pytest.raises(nvmod.NvError) as e:
+                nvmod.nv_build_propagators(ctx, *args)
+            assert e.value.status == nvmod.NV_ERR_INVALID_ARG
+            assert nvmod.nv_last_error()
+        # nothing built: compose and inspection refuse
+        assert nvmod.load().nv_compose(ctx, None, None, None, None) == nvmod.NV_ERR_NOT_BUILT
+        with pytest.raises(nvmod.NvError) as e:
+            nvmod.nv_compose(ctx, [0.1], 1, 64)
+        assert e.value.status == nvmod.NV_ERR_NOT_BUILT
+        with pytest.raises(nvmod.NvError) as e:
+            nvmod.nv_get_table(ctx, 0, 64, 256, "fp64")
+        assert e.value.status == nvmod.NV_ERR_NOT_BUILT
+    finally:
+        nvmod.nv_ctx_destroy(ctx)
+
+
+def test_null_context_and_destroy_null(nvmod):
+    lib = nvmod.load()
+    assert lib.nv_ctx_destroy(None) == 0
+    assert lib.nv_set_timing(None, 1) == nvmod.NV_ERR_INVALID_ARG
+    assert lib.nv_build_propagators(None, 0, None, 0.0, 1.0, 1, None, 1) == \
+        nvmod.NV_ERR_INVALID_ARG
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1304_6514_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "nv_oracle" not in text, f

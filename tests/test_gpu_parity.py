@@ -1,0 +1,389 @@
+"""GPU parity: libnv (through its C ABI) against the CPU oracle.
+
+Bars
+  - table entries: |gpu - oracle| <= tol * max(|oracle|, 1), tol = 1e-12 for
+    FP64 builds and 1e-5 for FP32 builds (each entry from the same grid point
+    and the same steps);
+  - composition over the GPU's own tables: bit-exact (the lookup and the
+    interpolants are specified operation by operation);
+  - lookup: bit-exact cell, weight and outside flag.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1304_6514_amd import nv
+from paper_1304_6514_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def say(*a):
+    print("[gpu-test]", *a, file=sys.__stderr__, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    nv.load()          # raises when libnv.so is missing: no fallback
+    return torch
+
+
+@pytest.fixture(scope="module")
+def prop(torch):
+    from paper_1304_6514_amd.propagator import Propagator
+    p = Propagator("cuda:0")
+    yield p
+    p.close()
+
+
+def ogrid(orc, w):
+    return orc.make_grid(w.grid_n, w.grid_lo, w.grid_hi)
+
+
+def mixed_err(g, o):
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    return float(np.max(np.abs(g - o) / np.maximum(np.abs(o), 1.0)))
+
+
+def gpu_tables(prop, w):
+    return np.stack([prop.table(c).astype(np.float64) for c in range(w.dim)])
+
+
+def check_compose_bit_exact(orc, prop, w, tab, y0):
+    g = prop.compose(y0)
+    o = orc.compose_tables(ogrid(orc, w), w.interp, tab, y0)
+    assert g.status == (nv.NV_OK if o.status == 0 else nv.NV_ERR_NONFINITE)
+    assert g.n_out_of_grid == o.n_out_of_grid
+    if o.status == 0:
+        assert np.array_equal(g.boundary.view(np.int64), o.boundary.view(np.int64)), \
+            np.max(np.abs(g.boundary - o.boundary))
+        assert np.array_equal(g.yT, o.yT)
+    else:
+        assert g.bad_slice == o.bad_slice
+    return g, o
+
+
+SMALL = [
+    # (workload, label) -- ragged grids (not multiples of 256), several tiles
+    (W.Workload("logistic-small", "logistic", (), 0.0, 3.0, 5, (700,), (-0.1,), (1.2,), 60,
+                (0.1,), "fp64", "linear"), "logistic fp64"),
+    (W.Workload("linear-small", "linear", (-1.3,), 0.25, 2.25, 6, (301,), (-2.0,), (2.0,), 40,
+                (1.5,), "fp64", "linear"), "linear fp64"),
+    (W.Workload("linear-small-32", "linear", (-1.3,), 0.25, 2.25, 6, (301,), (-2.0,), (2.0,),
+                40, (1.5,), "fp32", "hermite"), "linear fp32"),
+    (W.Workload("fcub-small", "forced_cubic", (), 0.5, 4.5, 7, (1000,), (-3.0,), (3.0,), 80,
+                (1.0,), "fp32", "hermite"), "forced cubic fp32"),
+    (W.Workload("fcub-small-64", "forced_cubic", (), 0.5, 4.5, 7, (1000,), (-3.0,), (3.0,), 80,
+                (1.0,), "fp64", "hermite"), "forced cubic fp64"),
+    (W.Workload("vdp-small", "vdp", (3.0,), 0.0, 3.0, 3, (37, 29), (-3.0, -8.0), (3.0, 8.0),
+                50, (2.0, 0.0), "fp32", "bilinear"), "vdp fp32"),
+    (W.Workload("vdp-small-64", "vdp", (3.0,), 0.0, 3.0, 3, (37, 29), (-3.0, -8.0),
+                (3.0, 8.0), 50, (2.0, 0.0), "fp64", "bilinear"), "vdp fp64"),
+    (W.Workload("square-small", "square", (), 0.0, 0.5, 4, (257,), (0.0,), (2.0,), 100,
+                (1.0,), "fp64", "hermite"), "square fp64"),
+]
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "euler"])
+@pytest.mark.parametrize("w,label", SMALL, ids=[s[1] for s in SMALL])
+def test_small_tables_and_compose(orc, prop, w, label, scheme):
+    w = w.with_(scheme=scheme)
+    say("small", label, scheme, w.n_slices, w.grid_n, w.steps_per_slice)
+    prop.build(w)
+    tab = gpu_tables(prop, w)
+    ref = orc.build_tables(w.rhs, w.params, scheme, w.t0, w.T, w.n_slices, ogrid(orc, w),
+                           w.steps_per_slice)
+    assert np.all(np.isfinite(ref))
+    err = mixed_err(tab, ref)
+    assert err <= TOL[w.precision], err
+    assert np.all(prop.nonfinite_counts() == 0)
+    # composition from the workload's y0 and from points outside the grid box
+    y0s = [w.y0, tuple(v + 0.37 for v in w.y0)]
+    y0s.append(tuple(hi + 0.5 for hi in w.grid_hi))
+    for y0 in y0s:
+        check_compose_bit_exact(orc, prop, w, tab, y0)
+
+
+def test_traj_per_lane_gives_identical_tables(orc, torch):
+    from paper_1304_6514_amd.propagator import Propagator
+    w = SMALL[3][0]
+    tabs = []
+    for P in (1, 2, 4):
+        say("traj_per_lane", P)
+        with Propagator("cuda:0", traj_per_lane=P) as p:
+            p.build(w)
+            tabs.append(p.table(0))
+    assert np.array_equal(tabs[0], tabs[1]) and np.array_equal(tabs[0], tabs[2])
+
+
+def test_uncompensated_fp32_within_tolerance_on_short_slices(orc, torch):
+    from paper_1304_6514_amd.propagator import Propagator
+    w = SMALL[3][0]
+    with Propagator("cuda:0", compensated=0) as p:
+        say("uncompensated fp32")
+        p.build(w)
+        tab = p.table(0).astype(np.float64)
+    ref = orc.build_tables(w.rhs, w.params, "rk4", w.t0, w.T, w.n_slices, ogrid(orc, w),
+                           w.steps_per_slice)
+    assert mixed_err(tab[None], ref) <= TOL["fp32"]
+
+
+def test_library_owned_buffers_match_torch_buffers(orc, prop, torch):
+    w = SMALL[5][0]
+    say("library-owned buffers")
+    prop.build(w)
+    a = gpu_tables(prop, w)
+    ctx = nv.nv_ctx_create()
+    try:
+        nv.nv_set_options(ctx, nv.make_options(w.scheme, w.precision, 1, 0, None))
+        g = nv.make_grid(w.grid_n, w.grid_lo, w.grid_hi, w.interp)
+        nv.nv_build_propagators(ctx, nv.RHS_IDS[w.rhs], w.params, w.t0, w.T, w.n_slices, g,
+                                w.steps_per_slice)
+        b = np.stack([nv.nv_get_table(ctx, c, w.n_slices, w.points_per_slice, w.precision)
+                      for c in range(2)]).astype(np.float64)
+        st, yT, _, _ = nv.nv_compose(ctx, w.y0, 2, w.n_slices)
+        assert st == nv.NV_OK and np.array_equal(yT, prop.compose().yT)
+    finally:
+        nv.nv_ctx_destroy(ctx)
+    assert np.array_equal(a, b)
+
+
+def test_rebuild_is_deterministic_and_autonomous_slices_identical(prop):
+    w = W.LOGISTIC_FP64
+    say("determinism", w.name)
+    prop.build(w)
+    a = prop.table(0)
+    prop.build(w)
+    b = prop.table(0)
+    assert np.array_equal(a, b)
+    # autonomous right-hand side: every slice's table is bit-identical
+    assert all(np.array_equal(a[0], a[j]) for j in range(w.n_slices))
+
+
+# ---------------------------------------------------------------------------
+# lookup
+# ---------------------------------------------------------------------------
+
+def _adversarial_queries(lo, hi, n, rng):
+    d = (hi - lo) / (n - 1)
+    nodes = lo + np.arange(n, dtype=np.float64) * d
+    q = [nodes, np.nextafter(nodes, -np.inf), np.nextafter(nodes, np.inf),
+         np.array([lo, hi, lo - d, hi + d, lo - 1e-300, hi * (1 + 1e-16), 0.0, -0.0, 1e300,
+                   -1e300, np.inf, -np.inf, np.nan, 5e-324]),
+         rng.uniform(lo - 0.1 * (hi - lo), hi + 0.1 * (hi - lo), 4096)]
+    return np.concatenate(q)
+
+
+@pytest.mark.parametrize("lo,hi,n", [(-3.0, 3.0, 4096), (-0.1, 1.2, 256), (-8.0, 8.0, 128),
+                                     (0.1, 0.7, 2), (-1.0 / 3.0, 2.0 / 7.0, 1001)])
+def test_locate_bit_exact(orc, prop, torch, lo, hi, n):
+    say("locate", lo, hi, n)
+    x = _adversarial_queries(lo, hi, n, np.random.default_rng(n))
+    xd = torch.tensor(x, dtype=torch.float64, device="cuda:0")
+    cell = torch.empty(x.size, dtype=torch.int64, device="cuda:0")
+    w = torch.empty(x.size, dtype=torch.float64, device="cuda:0")
+    out = torch.empty(x.size, dtype=torch.int32, device="cuda:0")
+    nv.nv_locate(prop.ctx, lo, hi, n, xd.data_ptr(), x.size, cell.data_ptr(), w.data_ptr(),
+                 out.data_ptr())
+    cell, w, out = cell.cpu().numpy(), w.cpu().numpy(), out.cpu().numpy()
+    for q in range(x.size):
+        c, ww, o = orc.locate(lo, hi, n, x[q])
+        assert cell[q] == c and bool(out[q]) == o, (x[q], cell[q], c)
+        assert (np.isnan(ww) and np.isnan(w[q])) or \
+            np.float64(ww).view(np.int64) == np.float64(w[q]).view(np.int64), (x[q], w[q], ww)
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads, in the configuration the benchmark times
+# ---------------------------------------------------------------------------
+
+def test_full_logistic_fp64(orc, prop):
+    w = W.LOGISTIC_FP64
+    say("full", w.name)
+    prop.build(w)
+    tab = gpu_tables(prop, w)
+    g = ogrid(orc, w)
+    ref = orc.build_tables(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, g,
+                           w.steps_per_slice)
+    assert mixed_err(tab, ref) <= TOL["fp64"]
+    gres, _ = check_compose_bit_exact(orc, prop, w, tab, w.y0)
+    oracle_method = orc.compose_tables(g, w.interp, ref, w.y0)
+    assert abs(gres.yT[0] - oracle_method.yT[0]) <= TOL["fp64"]
+    ser = orc.serial(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, w.steps_per_slice,
+                     w.y0)[0]
+    closed = 1.0 / (1.0 + (1.0 / w.y0[0] - 1.0) * math.exp(-(w.T - w.t0)))
+    assert abs(ser - closed) < 1e-13
+    # the method's own error (interpolation, sec. 5): reported, ~4.9e-6
+    say("logistic method error vs serial", gres.yT[0] - ser)
+    assert 1e-7 < abs(gres.yT[0] - ser) < 1e-4
+    assert gres.n_out_of_grid == 0
+
+
+def _sampled_parity(orc, prop, w, count, seed):
+    sl, pt = W.sample_entries(w, count, seed)
+    ref = orc.table_entries(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, ogrid(orc, w),
+                            w.steps_per_slice, sl, pt)
+    got = np.stack([prop.table_tensor(c)[sl, pt].double().cpu().numpy()
+                    for c in range(w.dim)])
+    return mixed_err(got, ref)
+
+
+def test_full_forced_cubic_fp32(orc, prop):
+    w = W.FORCED_CUBIC_FP32
+    say("full", w.name)
+    prop.build(w)
+    err = _sampled_parity(orc, prop, w, 4096, seed=11)
+    say("forced cubic sampled table error", err)
+    assert err <= TOL["fp32"]
+    assert np.all(prop.nonfinite_counts() == 0)
+    tab = gpu_tables(prop, w)
+    gres, _ = check_compose_bit_exact(orc, prop, w, tab, w.y0)
+    # the same method with FP64 tables (entries integrated on demand by the oracle)
+    lazy = orc.method_lazy(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, ogrid(orc, w),
+                           w.steps_per_slice, w.interp, w.y0)
+    d = np.max(np.abs(gres.boundary - lazy.boundary))
+    say("forced cubic |fp32-table method - fp64-table method| over boundaries", d)
+    assert d <= TOL["fp32"]
+    ser = orc.serial(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, w.steps_per_slice,
+                     w.y0)[0]
+    say("forced cubic method error vs serial", gres.yT[0] - ser)
+    assert abs(gres.yT[0] - ser) <= TOL["fp32"]
+
+
+def test_full_vdp_fp32(orc, prop):
+    w = W.VDP_FP32
+    say("full", w.name, "mu =", w.params[0])
+    prop.build(w)
+    err = _sampled_parity(orc, prop, w, 4096, seed=12)
+    say("vdp sampled table error", err)
+    assert err <= TOL["fp32"]
+    assert np.all(prop.nonfinite_counts() == 0)
+    tab = gpu_tables(prop, w)
+    gres, _ = check_compose_bit_exact(orc, prop, w, tab, w.y0)
+    assert gres.n_out_of_grid == 0
+    lazy = orc.method_lazy(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, ogrid(orc, w),
+                           w.steps_per_slice, w.interp, w.y0)
+    d = np.max(np.abs(gres.boundary - lazy.boundary))
+    # per-slice table differences <= tol * max(|y|, 1) with |y| <= 8 accumulate at
+    # most linearly over the N slices along the (neutral) limit cycle
+    bound = w.n_slices * TOL["fp32"] * 8.0
+    say("vdp |fp32-table method - fp64-table method| over boundaries", d, "bound", bound)
+    assert d <= bound
+
+
+def test_full_vdp_literal_box_counts_out_of_grid(orc, prop):
+    w = W.VDP_SQUARE_BOX
+    say("full", w.name)
+    prop.build(w)
+    tab = gpu_tables(prop, w)
+    gres, _ = check_compose_bit_exact(orc, prop, w, tab, w.y0)
+    assert gres.n_out_of_grid > 0
+
+
+def test_harmonic_fp64_method_equals_serial(orc, prop):
+    # linear slice map: bilinear lookup adds no error beyond rounding (sec. 5)
+    w = W.small(W.HARMONIC, 64, (32, 32), 100, precision="fp64")
+    say("harmonic fp64")
+    prop.build(w)
+    g = prop.compose()
+    ser = orc.serial(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, w.steps_per_slice,
+                     w.y0)
+    assert g.status == 0 and g.n_out_of_grid == 0
+    assert np.max(np.abs(g.yT - ser)) < 1e-12
+
+
+def test_full_harmonic_fp32_energy(prop):
+    w = W.HARMONIC
+    say("full", w.name)
+    prop.build(w)
+    g = prop.compose()
+    energy = g.boundary[:, 0] ** 2 + g.boundary[:, 1] ** 2
+    assert g.status == 0 and g.n_out_of_grid == 0
+    # FP32 tables: energy of the composed trajectory stays within the FP32 bar
+    # accumulated over the slices (radius 2, tables within 1e-5 * 2 per slice)
+    say("harmonic fp32 max |E - 4|", np.max(np.abs(energy - 4.0)))
+    assert np.max(np.abs(energy - 4.0)) < 4 * w.n_slices * 2e-5
+
+
+# ---------------------------------------------------------------------------
+# edge cases and errors
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("w", [
+    W.Workload("one-slice-one-step", "logistic", (), 0.0, 0.1, 1, (2,), (0.0,), (1.0,), 1,
+               (0.5,), "fp64", "linear"),
+    W.Workload("hermite-min", "forced_cubic", (), 0.0, 0.3, 2, (3,), (-1.0,), (1.0,), 5,
+               (0.2,), "fp32", "hermite"),
+    W.Workload("bilinear-min", "vdp", (1.0,), 0.0, 0.2, 2, (2, 2), (-1.0, -1.0), (1.0, 1.0), 4,
+               (0.5, 0.1), "fp64", "bilinear"),
+    W.Workload("one-tile", "logistic", (), 0.0, 1.0, 3, (256,), (0.0,), (1.0,), 7, (0.3,),
+               "fp32", "linear"),
+    W.Workload("tile-plus-one", "logistic", (), 0.0, 1.0, 3, (257,), (0.0,), (1.0,), 7, (0.3,),
+               "fp32", "linear"),
+], ids=lambda w: w.name)
+def test_edge_shapes(orc, prop, w):
+    say("edge", w.name)
+    prop.build(w)
+    tab = gpu_tables(prop, w)
+    ref = orc.build_tables(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, ogrid(orc, w),
+                           w.steps_per_slice)
+    assert mixed_err(tab, ref) <= TOL[w.precision]
+    check_compose_bit_exact(orc, prop, w, tab, w.y0)
+
+
+def test_blowup_counts_and_nonfinite_compose(orc, prop):
+    # y' = y^2 from xi > 1/L blows up inside the slice (sec. 3: singularity at 1/xi)
+    w = W.Workload("square-blowup", "square", (), 0.0, 2.0, 2, (8,), (0.0,), (4.0,), 100,
+                   (0.3,), "fp64", "linear")
+    say("blowup")
+    prop.build(w)
+    tab = gpu_tables(prop, w)
+    ref = orc.build_tables(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, ogrid(orc, w),
+                           w.steps_per_slice)
+    want = (~np.isfinite(ref[0])).sum(axis=1)
+    assert want.sum() > 0
+    assert np.array_equal(prop.nonfinite_counts(), want.astype(np.uint32))
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(tab))
+    assert mixed_err(tab[fin], ref[fin]) <= TOL["fp64"]
+    # a start whose second lookup lands in a non-finite cell
+    for y0 in [(0.3,), (0.9,), (3.9,)]:
+        g, o = check_compose_bit_exact(orc, prop, w, tab, y0)
+    g = prop.compose((float("nan"),))
+    assert g.status == nv.NV_ERR_NONFINITE and g.bad_slice == 0
+
+
+def test_caller_buffer_too_small(torch):
+    w = SMALL[0][0]
+    say("buffer too small")
+    ctx = nv.nv_ctx_create()
+    try:
+        t = torch.empty(1024, dtype=torch.uint8, device="cuda:0")
+        nv.nv_set_buffers(ctx, t.data_ptr(), 1024, t.data_ptr(), 1024)
+        nv.nv_set_options(ctx, nv.make_options("rk4", "fp64"))
+        g = nv.make_grid(w.grid_n, w.grid_lo, w.grid_hi, w.interp)
+        with pytest.raises(nv.NvError) as e:
+            nv.nv_build_propagators(ctx, nv.RHS_IDS[w.rhs], w.params, w.t0, w.T, w.n_slices,
+                                    g, w.steps_per_slice)
+        assert e.value.status == nv.NV_ERR_BUFFER_TOO_SMALL
+    finally:
+        nv.nv_ctx_destroy(ctx)
+
+
+def test_timing_is_reported(prop):
+    w = SMALL[3][0]
+    say("timing")
+    prop.set_timing(True)
+    prop.build(w)
+    prop.compose()
+    b, c = prop.last_timing()
+    prop.set_timing(False)
+    assert b > 0 and c > 0

@@ -195,6 +195,10 @@ def test_locate_on_integer_grid(orc):
     assert orc.locate(0.0, 8.0, n, -0.0) == (0, 0.0, False)
     c, w, out = orc.locate(0.0, 8.0, n, 1e300)
     assert c == 7 and out and w > 1e299
+    c, w, out = orc.locate(0.0, 8.0, n, float("-inf"))
+    assert c == 0 and out and w == float("-inf")
+    c, w, out = orc.locate(0.0, 8.0, n, float("nan"))
+    assert c == 0 and out and w != w
 
 
 def test_locate_brackets_random_queries(orc):

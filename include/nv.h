@@ -89,10 +89,17 @@ typedef struct {
 typedef struct {
     int scheme;               /* nv_scheme (default RK4) */
     int precision;            /* nv_precision (default FP64) */
-    int compensated;          /* FP32 only: compensated (Kahan) accumulation of the
-                                 state update; default 1 */
+    int compensated;          /* FP32 only, accumulation of the state update:
+                                 0 plain (one rounding per step),
+                                 1 Kahan-compensated (default),
+                                 2 blocked summation (the step increments of a block of
+                                   64 steps are summed apart from the state and added to
+                                   it once per block) */
     int traj_per_lane;        /* trajectories per GPU lane: 1, 2 or 4; 0 = default */
     void *stream;             /* hipStream_t the context launches on; NULL = null stream */
+    int solve_chunks;         /* nv_solve: slice chunks the build is cut into so that the
+                                 composition of chunk c overlaps the build of chunk c+1;
+                                 0 = chosen by the library, 1 = no overlap */
 } nv_options;
 
 /* Result details of a composition. */
@@ -100,7 +107,7 @@ typedef struct {
     long long n_out_of_grid;  /* lookups whose point lay outside the grid box; those
                                  are extrapolated from the edge cell, not clamped */
     int bad_slice;            /* first slice whose lookup met a non-finite value, or -1 */
-    int reserved;
+    int n_chunks;             /* slice chunks the composition ran in (1 for nv_compose) */
 } nv_compose_info;
 
 typedef struct nv_ctx nv_ctx;
@@ -193,6 +200,23 @@ NV_API nv_status nv_build_propagators(nv_ctx *ctx, int rhs_id, const double *par
 NV_API nv_status nv_compose(nv_ctx *ctx, const double *y0, double *yT, double *boundary,
                             nv_compose_info *info);
 
+/* Both phases in one call, pipelined as in the paper's scheduling figure for
+ * the method (sec. 3): a processor interpolates as soon as its own map is
+ * built and the previous boundary value has arrived, while later slices are
+ * still being built.  The slices are cut into contiguous chunks; the build of
+ * each chunk is launched on the context's stream, and the composition of
+ * chunk c runs on a second, library-owned stream as soon as chunk c's tables
+ * are complete, concurrently with the build of the chunks after it.
+ *
+ * Arguments and results are those of nv_build_propagators followed by
+ * nv_compose, and so are the tables and the boundary states, bit for bit.
+ * The context is built afterwards (nv_compose may be called again with other
+ * initial values).  Synchronous.  Errors: those of both calls. */
+NV_API nv_status nv_solve(nv_ctx *ctx, int rhs_id, const double *params, double t0,
+                          double T, int n_slices, const nv_ic_grid *grid,
+                          int steps_per_slice, const double *y0, double *yT,
+                          double *boundary, nv_compose_info *info);
+
 /* Copy component c's table of the last build to host memory: n_slices rows of
  * (points per slice) values in the build's precision (double or float),
  * row j at offset j * points.  bytes must be at least that size. */
@@ -213,10 +237,12 @@ NV_API nv_status nv_locate(nv_ctx *ctx, double lo, double hi, int n, const doubl
                            long long count, long long *cell_dev, double *w_dev,
                            int32_t *out_dev);
 
-/* Kernel timing with HIP events on the context's stream.  When enabled, the
- * last build's integration kernel and the last composition kernel are
- * bracketed by events; nv_last_timing waits for them and returns milliseconds
- * (-1 when not measured). */
+/* Kernel timing with HIP events on the context's streams.  When enabled, the
+ * last build's integration kernel(s) and the last composition are bracketed by
+ * events; nv_last_timing waits for them and returns milliseconds (-1 when not
+ * measured).  After nv_solve, build_ms spans all build launches and
+ * compose_ms the part of the composition that ran after the last build launch
+ * had finished. */
 NV_API nv_status nv_set_timing(nv_ctx *ctx, int enable);
 NV_API nv_status nv_last_timing(nv_ctx *ctx, float *build_ms, float *compose_ms);
 

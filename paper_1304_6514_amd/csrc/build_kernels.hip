@@ -14,7 +14,8 @@
 //     HBM traffic is the coalesced table store at the end.
 //
 // The inner loop is VALU-bound: RK4 on y' = F(t) - y^3 costs 15 VALU ops per
-// step (18 with the compensated FP32 update), Van der Pol 26 (32).
+// step (+3 with Kahan-compensated FP32 accumulation, +1 with blocked
+// summation), Van der Pol 26 (+6, +2).
 #include "nv_internal.h"
 
 #include <cmath>
@@ -96,42 +97,56 @@ __device__ inline void grid_point(const BuildArgs &a, long long k, R *y) {
     }
 }
 
+// State accumulation of the FP32 build (Acc):
+//   kPlain    y <- y + dy, one rounding per step;
+//   kKahan    compensated summation: c carries the low-order part the rounded
+//             state lost in earlier updates (3 extra operations per step);
+//   kBlocked  blocked summation: the state is y (fixed for a block of
+//             kSumBlock steps) plus a small accumulator a of the block's
+//             increments, z = y + a is the state the stages see; a is folded
+//             into y once per block (1 extra operation per step).
+enum Acc { kPlain = 0, kKahan = 1, kBlocked = 2 };
+constexpr int kSumBlock = 64;
+
 // One step of the scheme for P trajectories.  Fa, Fb, Fc: forcing at the
 // step's start, midpoint and end times.
-template <class Rhs, class R, int Scheme, bool Comp, int P>
-__device__ inline void step(R (&y)[P][Rhs::dim], R (&c)[P][Rhs::dim], R Fa, R Fb, R Fc,
-                            R h, R h2, R h6, R p) {
+template <class Rhs, class R, int Scheme, int A, int P>
+__device__ inline void step(R (&y)[P][Rhs::dim], R (&c)[P][Rhs::dim], R (&z)[P][Rhs::dim],
+                            R Fa, R Fb, R Fc, R h, R h2, R h6, R p) {
     constexpr int D = Rhs::dim;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        R k1[D], k2[D], k3[D], k4[D], z[D], dy[D];
+        R k1[D], k2[D], k3[D], k4[D], u[D], dy[D];
+        // the state the right-hand side sees
+        R (&x)[D] = A == kBlocked ? z[q] : y[q];
         if constexpr (Scheme == 1) {                 // forward Euler
-            Rhs::f(Fa, p, y[q], k1);
+            Rhs::f(Fa, p, x, k1);
 #pragma unroll
             for (int d = 0; d < D; ++d) dy[d] = h * k1[d];
         } else {                                     // classical RK4
-            Rhs::f(Fa, p, y[q], k1);
+            Rhs::f(Fa, p, x, k1);
 #pragma unroll
-            for (int d = 0; d < D; ++d) z[d] = y[q][d] + h2 * k1[d];
-            Rhs::f(Fb, p, z, k2);
+            for (int d = 0; d < D; ++d) u[d] = x[d] + h2 * k1[d];
+            Rhs::f(Fb, p, u, k2);
 #pragma unroll
-            for (int d = 0; d < D; ++d) z[d] = y[q][d] + h2 * k2[d];
-            Rhs::f(Fb, p, z, k3);
+            for (int d = 0; d < D; ++d) u[d] = x[d] + h2 * k2[d];
+            Rhs::f(Fb, p, u, k3);
 #pragma unroll
-            for (int d = 0; d < D; ++d) z[d] = y[q][d] + h * k3[d];
-            Rhs::f(Fc, p, z, k4);
+            for (int d = 0; d < D; ++d) u[d] = x[d] + h * k3[d];
+            Rhs::f(Fc, p, u, k4);
 #pragma unroll
             for (int d = 0; d < D; ++d) dy[d] = h6 * ((k1[d] + k4[d]) + R(2) * (k2[d] + k3[d]));
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            if constexpr (Comp) {
-                // compensated (Kahan) accumulation: c carries the low-order
-                // part the rounded state lost in earlier updates
+            if constexpr (A == kKahan) {
                 const R yk = dy[d] - c[q][d];
                 const R t = y[q][d] + yk;
                 c[q][d] = (t - y[q][d]) - yk;
                 y[q][d] = t;
+            } else if constexpr (A == kBlocked) {
+                c[q][d] = c[q][d] + dy[d];           // block accumulator
+                z[q][d] = y[q][d] + c[q][d];
             } else {
                 y[q][d] = y[q][d] + dy[d];
             }
@@ -139,34 +154,57 @@ __device__ inline void step(R (&y)[P][Rhs::dim], R (&c)[P][Rhs::dim], R Fa, R Fb
     }
 }
 
-template <class Rhs, class R, int Scheme, bool Comp, int P>
+// Fold the block accumulator into the state (blocked summation only).
+template <int D, class R, int A, int P>
+__device__ inline void end_block(R (&y)[P][D], R (&c)[P][D], R (&z)[P][D]) {
+    if constexpr (A == kBlocked) {
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                y[q][d] = y[q][d] + c[q][d];
+                c[q][d] = R(0);
+                z[q][d] = y[q][d];
+            }
+    }
+}
+
+template <class Rhs, class R, int Scheme, int A, int P>
 __global__ void __launch_bounds__(kBuildBlock) build_kernel(BuildArgs a) {
     constexpr int D = Rhs::dim;
     const int lid = xcd_remap(int(blockIdx.x), a.total_blocks);
-    const int j = lid / a.tiles_per_slice;
-    const int tile = lid - j * a.tiles_per_slice;
+    const int j = a.slice0 + lid / a.tiles_per_slice;
+    const int tile = lid % a.tiles_per_slice;
     const long long base = (long long)tile * (kBuildBlock * P) + threadIdx.x;
 
-    R y[P][D], c[P][D];
+    R y[P][D], c[P][D], z[P][D];
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         long long k = base + (long long)q * kBuildBlock;
         if (k >= a.M) k = a.M - 1;           // ragged tail: compute, do not store
         grid_point<R, D>(a, k, y[q]);
 #pragma unroll
-        for (int d = 0; d < D; ++d) c[q][d] = R(0);
+        for (int d = 0; d < D; ++d) {
+            c[q][d] = R(0);
+            z[q][d] = y[q][d];
+        }
     }
 
     const R h = R(a.h), h2 = R(a.h * 0.5), h6 = R(a.h / 6.0), p = R(a.p0);
     const int S = a.steps;
-    if constexpr (Rhs::forced) {
-        const R *__restrict__ F = static_cast<const R *>(a.forcing) + (long long)j * (2 * S + 1);
-        for (int s = 0; s < S; ++s)
-            step<Rhs, R, Scheme, Comp, P>(y, c, F[2 * s], F[2 * s + 1], F[2 * s + 2], h, h2,
-                                          h6, p);
-    } else {
-        for (int s = 0; s < S; ++s)
-            step<Rhs, R, Scheme, Comp, P>(y, c, R(0), R(0), R(0), h, h2, h6, p);
+    const R *__restrict__ F =
+        Rhs::forced ? static_cast<const R *>(a.forcing) + (long long)j * (2 * S + 1) : nullptr;
+    for (int s0 = 0; s0 < S; s0 += kSumBlock) {
+        const int s1 = min(s0 + kSumBlock, S);
+#pragma unroll 2
+        for (int s = s0; s < s1; ++s) {
+            if constexpr (Rhs::forced)
+                step<Rhs, R, Scheme, A, P>(y, c, z, F[2 * s], F[2 * s + 1], F[2 * s + 2], h, h2,
+                                           h6, p);
+            else
+                step<Rhs, R, Scheme, A, P>(y, c, z, R(0), R(0), R(0), h, h2, h6, p);
+        }
+        end_block<D, R, A, P>(y, c, z);
     }
 
     R *t0 = static_cast<R *>(a.tab0) + (long long)j * a.M;
@@ -208,35 +246,38 @@ __global__ void fill_u32_kernel(uint32_t *p, long long n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
-template <class Rhs, class R, int Scheme, bool Comp, int P>
+template <class Rhs, class R, int Scheme, int A, int P>
 hipError_t launch_one(const BuildArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((build_kernel<Rhs, R, Scheme, Comp, P>), dim3(a.total_blocks),
+    hipLaunchKernelGGL((build_kernel<Rhs, R, Scheme, A, P>), dim3(a.total_blocks),
                        dim3(kBuildBlock), 0, s, a);
     return hipGetLastError();
 }
 
-template <template <class> class Rhs, class R, int Scheme, bool Comp>
+template <template <class> class Rhs, class R, int Scheme, int A>
 hipError_t by_p(int P, const BuildArgs &a, hipStream_t s) {
     switch (P) {
-    case 1: return launch_one<Rhs<R>, R, Scheme, Comp, 1>(a, s);
-    case 2: return launch_one<Rhs<R>, R, Scheme, Comp, 2>(a, s);
-    case 4: return launch_one<Rhs<R>, R, Scheme, Comp, 4>(a, s);
+    case 1: return launch_one<Rhs<R>, R, Scheme, A, 1>(a, s);
+    case 2: return launch_one<Rhs<R>, R, Scheme, A, 2>(a, s);
+    case 4: return launch_one<Rhs<R>, R, Scheme, A, 4>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
 
+template <template <class> class Rhs, class R, int A>
+hipError_t by_scheme(const BuildConfig &c, const BuildArgs &a, hipStream_t s) {
+    return c.scheme == 0 ? by_p<Rhs, R, 0, A>(c.traj_per_lane, a, s)
+                         : by_p<Rhs, R, 1, A>(c.traj_per_lane, a, s);
+}
+
 template <template <class> class Rhs>
 hipError_t by_config(const BuildConfig &c, const BuildArgs &a, hipStream_t s) {
-    const int P = c.traj_per_lane;
-    if (c.precision == 0) {
-        return c.scheme == 0 ? by_p<Rhs, double, 0, false>(P, a, s)
-                             : by_p<Rhs, double, 1, false>(P, a, s);
+    if (c.precision == 0) return by_scheme<Rhs, double, kPlain>(c, a, s);
+    switch (c.compensated) {
+    case 0: return by_scheme<Rhs, float, kPlain>(c, a, s);
+    case 1: return by_scheme<Rhs, float, kKahan>(c, a, s);
+    case 2: return by_scheme<Rhs, float, kBlocked>(c, a, s);
+    default: return hipErrorInvalidValue;
     }
-    if (c.compensated)
-        return c.scheme == 0 ? by_p<Rhs, float, 0, true>(P, a, s)
-                             : by_p<Rhs, float, 1, true>(P, a, s);
-    return c.scheme == 0 ? by_p<Rhs, float, 0, false>(P, a, s)
-                         : by_p<Rhs, float, 1, false>(P, a, s);
 }
 
 }  // namespace
@@ -244,6 +285,7 @@ hipError_t by_config(const BuildConfig &c, const BuildArgs &a, hipStream_t s) {
 bool build_supported(const BuildConfig &c) {
     return c.rhs >= 0 && c.rhs <= 4 && (c.scheme == 0 || c.scheme == 1) &&
            (c.precision == 0 || c.precision == 1) &&
+           (c.compensated >= 0 && c.compensated <= 2) &&
            (c.traj_per_lane == 1 || c.traj_per_lane == 2 || c.traj_per_lane == 4);
 }
 

@@ -58,6 +58,9 @@ __device__ inline double node_slope(const T *row, long long i, int n) {
     return 0.5 * (double(row[i + 1]) - double(row[i - 1]));
 }
 
+// Composes slices j_begin .. j_end-1.  A launch that starts at slice 0 takes
+// y0 from its arguments and resets the status; a later launch resumes from the
+// boundary state the previous one left in memory and adds to the status.
 template <class T, int Interp>
 __global__ void compose_kernel(ComposeArgs a) {
 #pragma clang fp contract(off)
@@ -65,12 +68,23 @@ __global__ void compose_kernel(ComposeArgs a) {
     constexpr int D = Interp == 2 ? 2 : 1;
     const T *tab0 = static_cast<const T *>(a.tab0);
     const T *tab1 = static_cast<const T *>(a.tab1);
-    double lam0 = a.y00, lam1 = a.y01;
-    a.boundary[0] = lam0;
-    if (D == 2) a.boundary[1] = lam1;
+    double lam0, lam1 = 0.0;
+    if (a.j_begin == 0) {
+        lam0 = a.y00;
+        lam1 = a.y01;
+        a.boundary[0] = lam0;
+        if (D == 2) a.boundary[1] = lam1;
+        a.status->n_out_of_grid = 0;
+        a.status->bad_slice = -1;
+        a.status->done = 0;
+    } else {
+        if (a.status->bad_slice >= 0) return;     // an earlier range already failed
+        lam0 = a.boundary[(long long)a.j_begin * D];
+        if (D == 2) lam1 = a.boundary[(long long)a.j_begin * D + 1];
+    }
     long long oog = 0;
     int bad_slice = -1;
-    for (int j = 0; j < a.n_slices; ++j) {
+    for (int j = a.j_begin; j < a.j_end; ++j) {
         if (!finite(lam0) || (D == 2 && !finite(lam1))) {
             bad_slice = j;
             break;
@@ -119,9 +133,9 @@ __global__ void compose_kernel(ComposeArgs a) {
         a.boundary[(long long)(j + 1) * D] = lam0;
         if (D == 2) a.boundary[(long long)(j + 1) * D + 1] = lam1;
     }
-    a.status->n_out_of_grid = oog;
-    a.status->bad_slice = bad_slice;
-    a.status->done = 1;
+    a.status->n_out_of_grid += oog;
+    if (bad_slice >= 0) a.status->bad_slice = bad_slice;
+    if (a.j_end == a.n_slices || bad_slice >= 0) a.status->done = 1;
 }
 
 __global__ void locate_kernel(double lo, double inv, int n, const double *x, long long count,

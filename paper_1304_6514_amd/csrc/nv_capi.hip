@@ -36,6 +36,10 @@ nv_status fail(nv_status s, const char *fmt, ...) {
     } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxChunks = 64;
+// automatic chunking of nv_solve: about this many workgroups per build launch
+// (two full rounds of 256 CUs x 8 resident workgroups)
+constexpr long long kBlocksPerChunk = 4096;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int rhs_dim(int rhs) {
@@ -58,6 +62,7 @@ nv_options default_options() {
     o.compensated = 1;
     o.traj_per_lane = 0;
     o.stream = nullptr;
+    o.solve_chunks = 0;
     return o;
 }
 
@@ -69,11 +74,13 @@ nv_status check_options(const nv_options *o) {
         return fail(NV_ERR_INVALID_ARG, "unknown scheme %d", o->scheme);
     if (o->precision != NV_FP64 && o->precision != NV_FP32)
         return fail(NV_ERR_INVALID_ARG, "unknown precision %d", o->precision);
-    if (o->compensated != 0 && o->compensated != 1)
-        return fail(NV_ERR_INVALID_ARG, "compensated must be 0 or 1");
+    if (o->compensated < 0 || o->compensated > 2)
+        return fail(NV_ERR_INVALID_ARG, "compensated must be 0, 1 or 2");
     if (o->traj_per_lane != 0 && o->traj_per_lane != 1 && o->traj_per_lane != 2 &&
         o->traj_per_lane != 4)
         return fail(NV_ERR_INVALID_ARG, "traj_per_lane must be 0, 1, 2 or 4");
+    if (o->solve_chunks < 0 || o->solve_chunks > kMaxChunks)
+        return fail(NV_ERR_INVALID_ARG, "solve_chunks must be in [0, %d]", kMaxChunks);
     return NV_OK;
 }
 
@@ -176,9 +183,12 @@ struct nv_ctx {
     int precision = NV_FP64;
     int n_slices = 0;
     nv_ic_grid grid{};
+    // nv_solve: second stream and per-chunk events
+    hipStream_t aux = nullptr;
+    hipEvent_t chunk_ev[kMaxChunks] = {};
     // timing
     bool timing = false;
-    bool build_timed = false, compose_timed = false;
+    bool build_timed = false, compose_timed = false, solve_timed = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -236,6 +246,137 @@ nv_status ensure_events(nv_ctx *c) {
 
 char *work_at(const nv_ctx *c, size_t off) { return static_cast<char *>(c->work) + off; }
 
+// Checks, buffers, the pre-launch kernels (counter reset, forcing values) on
+// the context's stream and the integration kernel's arguments; records the
+// build's description in the context (marked built by the caller once the
+// integration is launched).
+struct PreparedBuild {
+    nv::BuildConfig cfg;
+    nv::BuildArgs args;
+};
+
+nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0, double T,
+                        int n_slices, const nv_ic_grid *grid, int steps_per_slice,
+                        PreparedBuild *pb) {
+    if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->built = false;
+    Plan p;
+    nv_status s = make_plan(rhs_id, n_slices, grid, steps_per_slice, ctx->opt, &p);
+    if (s != NV_OK) return s;
+    if (!std::isfinite(t0) || !std::isfinite(T) || !(T > t0))
+        return fail(NV_ERR_INVALID_ARG, "need finite t0 < T (got %g, %g)", t0, T);
+    double p0 = 0.0;
+    if (rhs_nparams(rhs_id) > 0) {
+        if (!params) return fail(NV_ERR_INVALID_ARG, "rhs %d needs a parameter", rhs_id);
+        if (!std::isfinite(params[0])) return fail(NV_ERR_INVALID_ARG, "parameter not finite");
+        p0 = params[0];
+    }
+    nv::BuildConfig cfg{rhs_id, ctx->opt.scheme, ctx->opt.precision, ctx->opt.compensated,
+                        effective_p(ctx->opt)};
+    if (!nv::build_supported(cfg)) return fail(NV_ERR_UNSUPPORTED, "unsupported configuration");
+
+    s = ensure_device(&ctx->tables, &ctx->tables_cap, ctx->tables_owned, p.table_bytes, "table");
+    if (s != NV_OK) return s;
+    s = ensure_device(&ctx->work, &ctx->work_cap, ctx->work_owned, p.work_bytes, "work");
+    if (s != NV_OK) return s;
+    s = ensure_host_stage(ctx, p.status_off - p.boundary_off + sizeof(nv::ComposeStatus));
+    if (s != NV_OK) return s;
+    if (ctx->timing) {
+        s = ensure_events(ctx);
+        if (s != NV_OK) return s;
+    }
+
+    hipStream_t st = stream_of(ctx);
+    // slice partition (sec. 3): L = (T - t0)/N, T_j = t0 + j L, h = L / S
+    const double L = (T - t0) / double(n_slices);
+    const double h = L / double(steps_per_slice);
+
+    nv::BuildArgs &a = pb->args;
+    a = nv::BuildArgs{};
+    a.tab0 = ctx->tables;
+    a.tab1 = p.dim == 2 ? static_cast<char *>(ctx->tables) + p.comp_bytes : nullptr;
+    a.forcing = rhs_forced(rhs_id) ? work_at(ctx, p.forcing_off) : nullptr;
+    a.nonfinite = reinterpret_cast<uint32_t *>(work_at(ctx, p.nonfinite_off));
+    a.lo0 = grid->lo[0];
+    a.dxi0 = (grid->hi[0] - grid->lo[0]) / double(grid->n[0] - 1);
+    a.lo1 = p.dim == 2 ? grid->lo[1] : 0.0;
+    a.dxi1 = p.dim == 2 ? (grid->hi[1] - grid->lo[1]) / double(grid->n[1] - 1) : 0.0;
+    a.h = h;
+    a.p0 = p0;
+    a.M = p.M;
+    a.n1 = p.dim == 2 ? grid->n[1] : 1;
+    a.n_slices = n_slices;
+    a.slice0 = 0;
+    a.steps = steps_per_slice;
+    a.tiles_per_slice = p.tiles_per_slice;
+    a.total_blocks = int(p.total_blocks);
+    pb->cfg = cfg;
+
+    NV_HIP(nv::launch_fill_u32(a.nonfinite, n_slices, 0u, st));
+    if (a.forcing)
+        NV_HIP(nv::launch_forcing(rhs_id, ctx->opt.precision, work_at(ctx, p.forcing_off),
+                                  n_slices, steps_per_slice, t0, L, h, st));
+
+    ctx->plan = p;
+    ctx->rhs = rhs_id;
+    ctx->precision = ctx->opt.precision;
+    ctx->n_slices = n_slices;
+    ctx->grid = *grid;
+    return NV_OK;
+}
+
+// Arguments of the composition kernel over slices [j0, j1) of the last build.
+nv::ComposeArgs compose_args(const nv_ctx *ctx, const double *y0, int j0, int j1) {
+    const Plan &p = ctx->plan;
+    const nv_ic_grid &g = ctx->grid;
+    nv::ComposeArgs a{};
+    a.tab0 = ctx->tables;
+    a.tab1 = p.dim == 2 ? static_cast<char *>(ctx->tables) + p.comp_bytes : nullptr;
+    a.boundary = reinterpret_cast<double *>(work_at(ctx, p.boundary_off));
+    a.status = reinterpret_cast<nv::ComposeStatus *>(work_at(ctx, p.status_off));
+    a.M = p.M;
+    a.n_slices = ctx->n_slices;
+    a.j_begin = j0;
+    a.j_end = j1;
+    a.n0 = g.n[0];
+    a.n1 = p.dim == 2 ? g.n[1] : 1;
+    a.lo0 = g.lo[0];
+    a.inv0 = double(g.n[0] - 1) / (g.hi[0] - g.lo[0]);
+    a.lo1 = p.dim == 2 ? g.lo[1] : 0.0;
+    a.inv1 = p.dim == 2 ? double(g.n[1] - 1) / (g.hi[1] - g.lo[1]) : 0.0;
+    a.y00 = y0[0];
+    a.y01 = p.dim == 2 ? y0[1] : 0.0;
+    return a;
+}
+
+// Copy the boundary states and the status (adjacent in the scratch buffer) to
+// pinned memory on stream st, wait, and hand the results out.
+nv_status finish_compose(nv_ctx *ctx, hipStream_t st, double *yT, double *boundary,
+                         nv_compose_info *info, int n_chunks) {
+    const Plan &p = ctx->plan;
+    const size_t bytes = p.status_off - p.boundary_off + sizeof(nv::ComposeStatus);
+    NV_HIP(hipMemcpyAsync(ctx->host_stage, work_at(ctx, p.boundary_off), bytes,
+                          hipMemcpyDeviceToHost, st));
+    NV_HIP(hipStreamSynchronize(st));
+    const double *hb = static_cast<const double *>(ctx->host_stage);
+    nv::ComposeStatus cs;
+    std::memcpy(&cs, static_cast<const char *>(ctx->host_stage) + (p.status_off - p.boundary_off),
+                sizeof cs);
+    if (!cs.done) return fail(NV_ERR_HIP, "composition kernel did not complete");
+    const int n_done = cs.bad_slice < 0 ? ctx->n_slices : cs.bad_slice;
+    if (boundary) std::memcpy(boundary, hb, size_t(n_done + 1) * p.dim * sizeof(double));
+    for (int c = 0; c < p.dim; ++c) yT[c] = hb[size_t(n_done) * p.dim + c];
+    if (info) {
+        info->n_out_of_grid = cs.n_out_of_grid;
+        info->bad_slice = cs.bad_slice;
+        info->n_chunks = n_chunks;
+    }
+    if (cs.bad_slice >= 0)
+        return fail(NV_ERR_NONFINITE, "composition met a non-finite value in slice %d",
+                    cs.bad_slice);
+    return NV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -253,8 +394,12 @@ NV_API nv_status nv_ctx_destroy(nv_ctx *ctx) {
     if (ctx->tables_owned && ctx->tables) (void)hipFree(ctx->tables);
     if (ctx->work_owned && ctx->work) (void)hipFree(ctx->work);
     if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+    if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
     for (auto e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto e : ctx->chunk_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     delete ctx;
     return NV_OK;
 }
@@ -320,74 +465,17 @@ NV_API nv_status nv_set_buffers(nv_ctx *ctx, void *tables_dev, size_t table_byte
 NV_API nv_status nv_build_propagators(nv_ctx *ctx, int rhs_id, const double *params,
                                       double t0, double T, int n_slices,
                                       const nv_ic_grid *grid, int steps_per_slice) {
-    if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
-    ctx->built = false;
-    Plan p;
-    nv_status s = make_plan(rhs_id, n_slices, grid, steps_per_slice, ctx->opt, &p);
+    PreparedBuild pb;
+    nv_status s = prepare_build(ctx, rhs_id, params, t0, T, n_slices, grid, steps_per_slice, &pb);
     if (s != NV_OK) return s;
-    if (!std::isfinite(t0) || !std::isfinite(T) || !(T > t0))
-        return fail(NV_ERR_INVALID_ARG, "need finite t0 < T (got %g, %g)", t0, T);
-    double p0 = 0.0;
-    if (rhs_nparams(rhs_id) > 0) {
-        if (!params) return fail(NV_ERR_INVALID_ARG, "rhs %d needs a parameter", rhs_id);
-        if (!std::isfinite(params[0])) return fail(NV_ERR_INVALID_ARG, "parameter not finite");
-        p0 = params[0];
-    }
-    nv::BuildConfig cfg{rhs_id, ctx->opt.scheme, ctx->opt.precision, ctx->opt.compensated,
-                        effective_p(ctx->opt)};
-    if (!nv::build_supported(cfg)) return fail(NV_ERR_UNSUPPORTED, "unsupported configuration");
-
-    s = ensure_device(&ctx->tables, &ctx->tables_cap, ctx->tables_owned, p.table_bytes, "table");
-    if (s != NV_OK) return s;
-    s = ensure_device(&ctx->work, &ctx->work_cap, ctx->work_owned, p.work_bytes, "work");
-    if (s != NV_OK) return s;
-    s = ensure_host_stage(ctx, p.status_off - p.boundary_off + sizeof(nv::ComposeStatus));
-    if (s != NV_OK) return s;
-
     hipStream_t st = stream_of(ctx);
-    // slice partition (sec. 3): L = (T - t0)/N, T_j = t0 + j L, h = L / S
-    const double L = (T - t0) / double(n_slices);
-    const double h = L / double(steps_per_slice);
-
-    nv::BuildArgs a{};
-    a.tab0 = ctx->tables;
-    a.tab1 = p.dim == 2 ? static_cast<char *>(ctx->tables) + p.comp_bytes : nullptr;
-    a.forcing = rhs_forced(rhs_id) ? work_at(ctx, p.forcing_off) : nullptr;
-    a.nonfinite = reinterpret_cast<uint32_t *>(work_at(ctx, p.nonfinite_off));
-    a.lo0 = grid->lo[0];
-    a.dxi0 = (grid->hi[0] - grid->lo[0]) / double(grid->n[0] - 1);
-    a.lo1 = p.dim == 2 ? grid->lo[1] : 0.0;
-    a.dxi1 = p.dim == 2 ? (grid->hi[1] - grid->lo[1]) / double(grid->n[1] - 1) : 0.0;
-    a.h = h;
-    a.p0 = p0;
-    a.M = p.M;
-    a.n1 = p.dim == 2 ? grid->n[1] : 1;
-    a.n_slices = n_slices;
-    a.steps = steps_per_slice;
-    a.tiles_per_slice = p.tiles_per_slice;
-    a.total_blocks = int(p.total_blocks);
-
-    NV_HIP(nv::launch_fill_u32(a.nonfinite, n_slices, 0u, st));
-    if (a.forcing)
-        NV_HIP(nv::launch_forcing(rhs_id, ctx->opt.precision, work_at(ctx, p.forcing_off),
-                                  n_slices, steps_per_slice, t0, L, h, st));
-    ctx->build_timed = false;
-    if (ctx->timing) {
-        s = ensure_events(ctx);
-        if (s != NV_OK) return s;
-        NV_HIP(hipEventRecord(ctx->ev[0], st));
-    }
-    NV_HIP(nv::launch_build(cfg, a, st));
+    ctx->build_timed = ctx->compose_timed = ctx->solve_timed = false;
+    if (ctx->timing) NV_HIP(hipEventRecord(ctx->ev[0], st));
+    NV_HIP(nv::launch_build(pb.cfg, pb.args, st));
     if (ctx->timing) {
         NV_HIP(hipEventRecord(ctx->ev[1], st));
         ctx->build_timed = true;
     }
-
-    ctx->plan = p;
-    ctx->rhs = rhs_id;
-    ctx->precision = ctx->opt.precision;
-    ctx->n_slices = n_slices;
-    ctx->grid = *grid;
     ctx->built = true;
     return NV_OK;
 }
@@ -397,59 +485,75 @@ NV_API nv_status nv_compose(nv_ctx *ctx, const double *y0, double *yT, double *b
     if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
     if (!ctx->built) return fail(NV_ERR_NOT_BUILT, "nv_compose before a successful build");
     if (!y0 || !yT) return fail(NV_ERR_INVALID_ARG, "y0 and yT must not be NULL");
-    const Plan &p = ctx->plan;
-    const nv_ic_grid &g = ctx->grid;
     hipStream_t st = stream_of(ctx);
-
-    nv::ComposeArgs a{};
-    a.tab0 = ctx->tables;
-    a.tab1 = p.dim == 2 ? static_cast<char *>(ctx->tables) + p.comp_bytes : nullptr;
-    a.boundary = reinterpret_cast<double *>(work_at(ctx, p.boundary_off));
-    a.status = reinterpret_cast<nv::ComposeStatus *>(work_at(ctx, p.status_off));
-    a.M = p.M;
-    a.n_slices = ctx->n_slices;
-    a.n0 = g.n[0];
-    a.n1 = p.dim == 2 ? g.n[1] : 1;
-    a.lo0 = g.lo[0];
-    a.inv0 = double(g.n[0] - 1) / (g.hi[0] - g.lo[0]);
-    a.lo1 = p.dim == 2 ? g.lo[1] : 0.0;
-    a.inv1 = p.dim == 2 ? double(g.n[1] - 1) / (g.hi[1] - g.lo[1]) : 0.0;
-    a.y00 = y0[0];
-    a.y01 = p.dim == 2 ? y0[1] : 0.0;
-
-    ctx->compose_timed = false;
+    ctx->compose_timed = ctx->solve_timed = false;
     if (ctx->timing) {
         nv_status s = ensure_events(ctx);
         if (s != NV_OK) return s;
         NV_HIP(hipEventRecord(ctx->ev[2], st));
     }
-    NV_HIP(nv::launch_compose(g.interp, ctx->precision, a, st));
+    NV_HIP(nv::launch_compose(ctx->grid.interp, ctx->precision,
+                              compose_args(ctx, y0, 0, ctx->n_slices), st));
     if (ctx->timing) {
         NV_HIP(hipEventRecord(ctx->ev[3], st));
         ctx->compose_timed = true;
     }
-    // boundary states and status to pinned host memory in one copy (they are
-    // adjacent in the scratch buffer)
-    const size_t bytes = p.status_off - p.boundary_off + sizeof(nv::ComposeStatus);
-    NV_HIP(hipMemcpyAsync(ctx->host_stage, a.boundary, bytes, hipMemcpyDeviceToHost, st));
-    NV_HIP(hipStreamSynchronize(st));
-    const double *hb = static_cast<const double *>(ctx->host_stage);
-    nv::ComposeStatus cs;
-    std::memcpy(&cs, static_cast<const char *>(ctx->host_stage) + (p.status_off - p.boundary_off),
-                sizeof cs);
-    if (!cs.done) return fail(NV_ERR_HIP, "composition kernel did not complete");
-    const int n_done = cs.bad_slice < 0 ? ctx->n_slices : cs.bad_slice;
-    if (boundary) std::memcpy(boundary, hb, size_t(n_done + 1) * p.dim * sizeof(double));
-    for (int c = 0; c < p.dim; ++c) yT[c] = hb[size_t(n_done) * p.dim + c];
-    if (info) {
-        info->n_out_of_grid = cs.n_out_of_grid;
-        info->bad_slice = cs.bad_slice;
-        info->reserved = 0;
+    return finish_compose(ctx, st, yT, boundary, info, 1);
+}
+
+NV_API nv_status nv_solve(nv_ctx *ctx, int rhs_id, const double *params, double t0, double T,
+                          int n_slices, const nv_ic_grid *grid, int steps_per_slice,
+                          const double *y0, double *yT, double *boundary,
+                          nv_compose_info *info) {
+    if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
+    if (!y0 || !yT) return fail(NV_ERR_INVALID_ARG, "y0 and yT must not be NULL");
+    PreparedBuild pb;
+    nv_status s = prepare_build(ctx, rhs_id, params, t0, T, n_slices, grid, steps_per_slice, &pb);
+    if (s != NV_OK) return s;
+    if (!ctx->aux) NV_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+
+    // chunks of whole slices
+    int chunks = ctx->opt.solve_chunks;
+    if (chunks == 0) {
+        const long long c = ctx->plan.total_blocks / kBlocksPerChunk;
+        chunks = int(c < 1 ? 1 : (c > kMaxChunks ? kMaxChunks : c));
     }
-    if (cs.bad_slice >= 0)
-        return fail(NV_ERR_NONFINITE, "composition met a non-finite value in slice %d",
-                    cs.bad_slice);
-    return NV_OK;
+    if (chunks > n_slices) chunks = n_slices;
+    const int per = (n_slices + chunks - 1) / chunks;
+    chunks = (n_slices + per - 1) / per;
+    for (int c = 0; c < chunks; ++c)
+        if (!ctx->chunk_ev[c])
+            NV_HIP(hipEventCreateWithFlags(&ctx->chunk_ev[c], hipEventDisableTiming));
+
+    hipStream_t st = stream_of(ctx), aux = ctx->aux;
+    ctx->build_timed = ctx->compose_timed = ctx->solve_timed = false;
+    if (ctx->timing) NV_HIP(hipEventRecord(ctx->ev[0], st));
+    for (int c = 0; c < chunks; ++c) {
+        nv::BuildArgs a = pb.args;
+        a.slice0 = c * per;
+        const int ns = (a.slice0 + per <= n_slices ? per : n_slices - a.slice0);
+        a.total_blocks = ns * a.tiles_per_slice;
+        NV_HIP(nv::launch_build(pb.cfg, a, st));
+        NV_HIP(hipEventRecord(ctx->chunk_ev[c], st));
+    }
+    if (ctx->timing) NV_HIP(hipEventRecord(ctx->ev[1], st));
+    for (int c = 0; c < chunks; ++c) {
+        const int j0 = c * per, j1 = (j0 + per <= n_slices ? j0 + per : n_slices);
+        NV_HIP(hipStreamWaitEvent(aux, ctx->chunk_ev[c], 0));
+        NV_HIP(nv::launch_compose(ctx->grid.interp, ctx->precision,
+                                  compose_args(ctx, y0, j0, j1), aux));
+    }
+    if (ctx->timing) {
+        NV_HIP(hipEventRecord(ctx->ev[3], aux));
+        ctx->build_timed = true;
+    }
+    ctx->built = true;
+    s = finish_compose(ctx, aux, yT, boundary, info, chunks);
+    if (ctx->timing) {
+        ctx->compose_timed = true;
+        ctx->solve_timed = true;
+    }
+    return s;
 }
 
 NV_API nv_status nv_get_table(nv_ctx *ctx, int component, void *host_dst, size_t bytes) {
@@ -505,7 +609,7 @@ NV_API nv_status nv_locate(nv_ctx *ctx, double lo, double hi, int n, const doubl
 NV_API nv_status nv_set_timing(nv_ctx *ctx, int enable) {
     if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
     ctx->timing = enable != 0;
-    ctx->build_timed = ctx->compose_timed = false;
+    ctx->build_timed = ctx->compose_timed = ctx->solve_timed = false;
     return NV_OK;
 }
 
@@ -521,8 +625,10 @@ NV_API nv_status nv_last_timing(nv_ctx *ctx, float *build_ms, float *compose_ms)
     if (compose_ms) {
         *compose_ms = -1.0f;
         if (ctx->compose_timed) {
+            // after nv_solve: the composition left once the last build launch ended
+            hipEvent_t from = ctx->solve_timed ? ctx->ev[1] : ctx->ev[2];
             NV_HIP(hipEventSynchronize(ctx->ev[3]));
-            NV_HIP(hipEventElapsedTime(compose_ms, ctx->ev[2], ctx->ev[3]));
+            NV_HIP(hipEventElapsedTime(compose_ms, from, ctx->ev[3]));
         }
     }
     return NV_OK;

@@ -23,17 +23,18 @@ struct BuildArgs {
     double p0;                // right-hand side parameter
     long long M;              // points per slice
     int n1;                   // points on axis 1 (1 for 1-D)
-    int n_slices;
+    int n_slices;             // slices of the whole build (forcing row count)
+    int slice0;               // first slice of this launch
     int steps;
     int tiles_per_slice;      // workgroups per slice
-    int total_blocks;         // n_slices * tiles_per_slice
+    int total_blocks;         // (slices of this launch) * tiles_per_slice
 };
 
 struct BuildConfig {
     int rhs;                  // nv_rhs_id
     int scheme;               // nv_scheme
     int precision;            // nv_precision
-    int compensated;          // FP32 only
+    int compensated;          // FP32 only: 0 plain, 1 Kahan, 2 blocked summation
     int traj_per_lane;        // 1, 2, 4
 };
 
@@ -51,6 +52,8 @@ struct ComposeArgs {
     ComposeStatus *status;
     long long M;
     int n_slices;
+    int j_begin, j_end;       // slices this launch composes; lambda_{j_begin} is y0 when
+                              // j_begin == 0, else read from boundary
     int n0, n1;
     double lo0, inv0, lo1, inv1;   // inv = (n-1)/(hi-lo), computed on the host
     double y00, y01;

@@ -45,12 +45,12 @@ class nv_ic_grid(ctypes.Structure):
 class nv_options(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int), ("precision", ctypes.c_int),
                 ("compensated", ctypes.c_int), ("traj_per_lane", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("solve_chunks", ctypes.c_int)]
 
 
 class nv_compose_info(ctypes.Structure):
     _fields_ = [("n_out_of_grid", ctypes.c_longlong), ("bad_slice", ctypes.c_int),
-                ("reserved", ctypes.c_int)]
+                ("n_chunks", ctypes.c_int)]
 
 
 class NvError(RuntimeError):
@@ -74,6 +74,9 @@ _SIGNATURES = {
     "nv_build_propagators": [_P, ctypes.c_int, _P, ctypes.c_double, ctypes.c_double,
                              ctypes.c_int, ctypes.POINTER(nv_ic_grid), ctypes.c_int],
     "nv_compose": [_P, _P, _P, _P, ctypes.POINTER(nv_compose_info)],
+    "nv_solve": [_P, ctypes.c_int, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                 ctypes.POINTER(nv_ic_grid), ctypes.c_int, _P, _P, _P,
+                 ctypes.POINTER(nv_compose_info)],
     "nv_get_table": [_P, ctypes.c_int, _P, ctypes.c_size_t],
     "nv_table_device_ptr": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)],
     "nv_get_nonfinite_counts": [_P, _P, ctypes.c_int],
@@ -134,13 +137,14 @@ def make_grid(n, lo, hi, interp) -> nv_ic_grid:
 
 
 def make_options(scheme="rk4", precision="fp64", compensated=1, traj_per_lane=0,
-                 stream=None) -> nv_options:
+                 stream=None, solve_chunks=0) -> nv_options:
     o = nv_options()
     o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.compensated = int(compensated)
     o.traj_per_lane = int(traj_per_lane)
     o.stream = stream
+    o.solve_chunks = int(solve_chunks)
     return o
 
 
@@ -201,6 +205,26 @@ def nv_compose(ctx, y0, dim, n_slices, want_boundary=True):
     st = load().nv_compose(ctx, _ptr(y0), _ptr(yT),
                            _ptr(boundary) if boundary is not None else None,
                            ctypes.byref(info))
+    if st not in (NV_OK, NV_ERR_NONFINITE):
+        _check(st)
+    return st, yT, boundary, info
+
+
+def nv_solve(ctx, rhs_id, params, t0, T, n_slices, grid: nv_ic_grid, steps_per_slice, y0,
+             dim, want_boundary=True):
+    """Returns (status, yT, boundary or None, info).  Raises on every status
+    other than NV_OK and NV_ERR_NONFINITE."""
+    p = np.ascontiguousarray(np.asarray(params if params is not None else [0.0],
+                                        dtype=np.float64).reshape(-1))
+    if p.size == 0:
+        p = np.zeros(1)
+    y0 = np.ascontiguousarray(np.asarray(y0, dtype=np.float64).reshape(-1))
+    yT = np.full(dim, np.nan)
+    boundary = np.full((n_slices + 1, dim), np.nan) if want_boundary else None
+    info = nv_compose_info()
+    st = load().nv_solve(ctx, int(rhs_id), _ptr(p), float(t0), float(T), int(n_slices),
+                         ctypes.byref(grid), int(steps_per_slice), _ptr(y0), _ptr(yT),
+                         _ptr(boundary) if boundary is not None else None, ctypes.byref(info))
     if st not in (NV_OK, NV_ERR_NONFINITE):
         _check(st)
     return st, yT, boundary, info

@@ -21,10 +21,12 @@ class ComposeResult:
     boundary: np.ndarray | None
     n_out_of_grid: int
     bad_slice: int
+    n_chunks: int = 1
 
 
 class Propagator:
-    def __init__(self, device="cuda:0", traj_per_lane=0, compensated=1, stream=None):
+    def __init__(self, device="cuda:0", traj_per_lane=0, compensated=1, stream=None,
+                 solve_chunks=0):
         import torch
 
         self.torch = torch
@@ -34,6 +36,7 @@ class Propagator:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.traj_per_lane = traj_per_lane
         self.compensated = compensated
+        self.solve_chunks = solve_chunks
         self.ctx = nv.nv_ctx_create()
         self._tables = None
         self._work = None
@@ -61,7 +64,7 @@ class Propagator:
     # -- helpers -------------------------------------------------------------
     def options(self, w: Workload) -> nv.nv_options:
         return nv.make_options(w.scheme, w.precision, self.compensated, self.traj_per_lane,
-                               self.stream.cuda_stream)
+                               self.stream.cuda_stream, self.solve_chunks)
 
     @staticmethod
     def grid(w: Workload) -> nv.nv_ic_grid:
@@ -78,24 +81,38 @@ class Propagator:
                               self._work.data_ptr(), self._work.numel())
 
     # -- the two phases --------------------------------------------------------
-    def build(self, w: Workload, params=None):
-        """Computation phase: tables of every slice (asynchronous on the stream)."""
+    def _prepare(self, w: Workload):
         opt = self.options(w)
         nv.nv_set_options(self.ctx, opt)
         g = self.grid(w)
         rhs = nv.RHS_IDS[w.rhs]
         tb, wb = nv.nv_required_bytes(rhs, w.n_slices, g, w.steps_per_slice, opt)
         self._ensure_buffers(tb, wb)
+        return g, rhs
+
+    def build(self, w: Workload, params=None):
+        """Computation phase: tables of every slice (asynchronous on the stream)."""
+        g, rhs = self._prepare(w)
         nv.nv_build_propagators(self.ctx, rhs, params if params is not None else w.params,
                                 w.t0, w.T, w.n_slices, g, w.steps_per_slice)
         self.workload = w
+
+    def solve(self, w: Workload, y0=None, params=None, want_boundary=True) -> ComposeResult:
+        """Both phases, the composition pipelined behind the build (synchronous)."""
+        g, rhs = self._prepare(w)
+        self.workload = None
+        st, yT, b, info = nv.nv_solve(self.ctx, rhs, params if params is not None else w.params,
+                                      w.t0, w.T, w.n_slices, g, w.steps_per_slice,
+                                      w.y0 if y0 is None else y0, w.dim, want_boundary)
+        self.workload = w
+        return ComposeResult(st, yT, b, info.n_out_of_grid, info.bad_slice, info.n_chunks)
 
     def compose(self, y0=None, want_boundary=True) -> ComposeResult:
         """Communication phase (synchronous)."""
         w = self.workload
         st, yT, b, info = nv.nv_compose(self.ctx, w.y0 if y0 is None else y0, w.dim,
                                         w.n_slices, want_boundary)
-        return ComposeResult(st, yT, b, info.n_out_of_grid, info.bad_slice)
+        return ComposeResult(st, yT, b, info.n_out_of_grid, info.bad_slice, info.n_chunks)
 
     # -- inspection ------------------------------------------------------------
     def table(self, component=0) -> np.ndarray:

@@ -28,7 +28,8 @@ def declared_entry_points():
 
 def test_header_declares_the_boundary():
     names = declared_entry_points()
-    for must in ("nv_build_propagators", "nv_compose", "nv_ctx_create", "nv_ctx_destroy",
+    for must in ("nv_build_propagators", "nv_compose", "nv_solve", "nv_ctx_create",
+                 "nv_ctx_destroy",
                  "nv_set_options", "nv_set_buffers", "nv_required_bytes", "nv_get_table",
                  "nv_locate", "nv_last_error"):
         assert must in names
@@ -88,15 +89,16 @@ def test_options_validation(nvmod):
     ctx = nvmod.nv_ctx_create()
     try:
         for bad in (dict(scheme=5), dict(precision=7), dict(traj_per_lane=3),
-                    dict(compensated=2)):
+                    dict(compensated=3), dict(solve_chunks=-1), dict(solve_chunks=65)):
             o = nvmod.make_options(**{**dict(scheme=0, precision=0), **bad})
             with pytest.raises(nvmod.NvError) as e:
                 nvmod.nv_set_options(ctx, o)
             assert e.value.status == nvmod.NV_ERR_INVALID_ARG
-        good = nvmod.make_options("euler", "fp32", 0, 4)
+        good = nvmod.make_options("euler", "fp32", 2, 4, None, 7)
         nvmod.nv_set_options(ctx, good)
         back = nvmod.nv_get_options(ctx)
-        assert (back.scheme, back.precision, back.compensated, back.traj_per_lane) == (1, 1, 0, 4)
+        assert (back.scheme, back.precision, back.compensated, back.traj_per_lane,
+                back.solve_chunks) == (1, 1, 2, 4, 7)
     finally:
         nvmod.nv_ctx_destroy(ctx)
 
@@ -133,6 +135,8 @@ def test_null_context_and_destroy_null(nvmod):
     assert lib.nv_ctx_destroy(None) == 0
     assert lib.nv_set_timing(None, 1) == nvmod.NV_ERR_INVALID_ARG
     assert lib.nv_build_propagators(None, 0, None, 0.0, 1.0, 1, None, 1) == \
+        nvmod.NV_ERR_INVALID_ARG
+    assert lib.nv_solve(None, 0, None, 0.0, 1.0, 1, None, 1, None, None, None, None) == \
         nvmod.NV_ERR_INVALID_ARG
 
 

@@ -387,3 +387,77 @@ def test_timing_is_reported(prop):
     b, c = prop.last_timing()
     prop.set_timing(False)
     assert b > 0 and c > 0
+
+
+# ---------------------------------------------------------------------------
+# pipelined solve (build chunks overlapped with the composition)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("w,chunks", [
+    (SMALL[3][0], 3),           # 7 slices in chunks of 3, 3, 1
+    (SMALL[5][0], 2),           # 2-D, chunks of 2, 1
+    (SMALL[0][0], 5),           # one slice per chunk
+    (SMALL[1][0], 0),           # automatic (one chunk at this size)
+], ids=["fcub-3", "vdp-2", "logistic-5", "linear-auto"])
+def test_solve_equals_build_then_compose(orc, torch, w, chunks):
+    from paper_1304_6514_amd.propagator import Propagator
+    say("solve", w.name, chunks)
+    with Propagator("cuda:0") as a, Propagator("cuda:0", solve_chunks=chunks) as b:
+        a.build(w)
+        ra = a.compose()
+        rb = b.solve(w)
+        assert rb.status == ra.status == nv.NV_OK
+        assert np.array_equal(ra.boundary, rb.boundary)
+        assert rb.n_out_of_grid == ra.n_out_of_grid
+        assert rb.n_chunks == (min(chunks, w.n_slices) if chunks else 1)
+        for c in range(w.dim):
+            assert np.array_equal(a.table(c), b.table(c))
+        # the solved context is built: composing again from another start works
+        rc = b.compose(tuple(v * 0.9 for v in w.y0))
+        tab = gpu_tables(b, w)
+        o = orc.compose_tables(ogrid(orc, w), w.interp, tab, tuple(v * 0.9 for v in w.y0))
+        assert np.array_equal(rc.boundary, o.boundary)
+
+
+def test_solve_full_size_matches_two_phase(prop, torch):
+    from paper_1304_6514_amd.propagator import Propagator
+    for w in (W.FORCED_CUBIC_FP32, W.VDP_FP32):
+        say("solve full", w.name)
+        prop.build(w)
+        ra = prop.compose()
+        with Propagator("cuda:0") as b:
+            rb = b.solve(w)
+        say("chunks", rb.n_chunks)
+        assert rb.n_chunks > 1
+        assert rb.status == nv.NV_OK and np.array_equal(ra.boundary, rb.boundary)
+
+
+def test_solve_nonfinite_reports_same_slice(orc, torch):
+    from paper_1304_6514_amd.propagator import Propagator
+    w = W.Workload("square-blowup-solve", "square", (), 0.0, 6.0, 6, (8,), (0.0,), (4.0,), 100,
+                   (0.3,), "fp64", "linear")
+    say("solve blowup")
+    with Propagator("cuda:0", solve_chunks=3) as b:
+        r = b.solve(w)
+        tab = gpu_tables(b, w)
+    o = orc.compose_tables(ogrid(orc, w), w.interp, tab, w.y0)
+    assert o.status == orc.NONFINITE
+    assert r.status == nv.NV_ERR_NONFINITE and r.bad_slice == o.bad_slice
+    assert np.array_equal(r.boundary[:o.bad_slice + 1], o.boundary[:o.bad_slice + 1])
+
+
+def test_fp32_accumulation_modes_full_size(orc, torch):
+    # plain FP32 accumulation of the state misses the FP32 bar on this workload
+    # (one rounding of y + dy per step over 2000 steps); Kahan-compensated and
+    # blocked summation both meet it
+    from paper_1304_6514_amd.propagator import Propagator
+    w = W.FORCED_CUBIC_FP32
+    errs = {}
+    for mode in (0, 1, 2):
+        say("accumulation mode", mode)
+        with Propagator("cuda:0", compensated=mode) as p:
+            p.build(w)
+            errs[mode] = _sampled_parity(orc, p, w, 2048, seed=21)
+    say("forced cubic fp32 sampled table error by accumulation mode", errs)
+    assert errs[1] <= TOL["fp32"] and errs[2] <= TOL["fp32"]
+    assert errs[0] > 3 * max(errs[1], errs[2])

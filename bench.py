@@ -3,7 +3,8 @@
 
 One step = one pass of the whole hot path over the forced-cubic workload
 (y' = sin 3t - y^3 on [0, 100], 4096 slices x 4096 grid points x 2000 RK4
-steps, FP32 build with compensated update, FP64 cubic-Hermite composition):
+steps, FP32 build with blocked summation of the state, FP64 cubic-Hermite
+composition):
 forcing precompute + ensemble integration + table write + composition down to
 y(T) and the 4097 boundary states on the host, through nv_solve (the
 composition of each slice chunk runs as soon as its tables are complete).
@@ -40,6 +41,30 @@ RHS_FLOPS = {"linear": 1, "logistic": 2, "forced_cubic": 3, "vdp": 5, "square": 
 WORKLOADS = {"forced_cubic": W.FORCED_CUBIC_FP32, "logistic": W.LOGISTIC_FP64,
              "vdp": W.VDP_FP32}
 
+# HBM bytes per launch of the build kernel over the whole workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the same counters' reading of
+# a cold 256 MiB elementwise copy (profiles/build_kernel_forced_cubic_*.md).
+# Valid only for the kernel source they were taken with (SHA-1 below); any
+# other source gives traffic = null.
+MEASURED_TRAFFIC = {
+    ("forced-cubic-fp32-4096sl-4096pt-2000st", "blocked", "2502893abcb2af3335325fdf4026b1a36c6bbffb"): 198.3e6,
+}
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1304_6514_amd", "csrc", "build_kernels.hip")
+
+
+def kernel_source_sha1() -> str:
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
+
+def algorithmic_bytes(w: W.Workload) -> float:
+    """Table write plus the per-slice forcing rows read (non-autonomous only)."""
+    elem = 4 if w.precision == "fp32" else 8
+    tables = w.dim * w.n_slices * w.points_per_slice * elem
+    forcing = (2 * w.steps_per_slice + 1) * w.n_slices * elem if w.rhs == "forced_cubic" else 0
+    return float(tables + forcing)
+
 
 def flops_per_step(w: W.Workload, compensated: bool) -> int:
     if w.scheme == "rk4":
@@ -71,6 +96,54 @@ def cpu_baseline(w: W.Workload, n_slices_sample: int):
                       f"({steps:.3g} trajectory-steps, {dt:.1f} s, FP64, one thread)"}
 
 
+def fixed_error(w: W.Workload, yT_method, gpu_ms):
+    """Time-to-y(T) of the method on the GPU against the serial oracle on one
+    host core: at the method's own step (N*S steps) and at equal error (the
+    fewest serial steps whose error at T is no larger than the method's)."""
+    import numpy as np
+    import oracle
+
+    oracle._load()
+    S_ref = 4 * w.n_slices * w.steps_per_slice
+    ref = oracle.serial_steps(w.rhs, w.params, w.scheme, w.t0, w.T, S_ref, w.y0)
+    method_err = float(np.max(np.abs(np.asarray(yT_method) - ref)))
+    n_same = w.n_slices * w.steps_per_slice
+    t = time.perf_counter()
+    oracle.serial_steps(w.rhs, w.params, w.scheme, w.t0, w.T, n_same, w.y0)
+    t_same = time.perf_counter() - t
+
+    def err(n):
+        e = np.abs(oracle.serial_steps(w.rhs, w.params, w.scheme, w.t0, w.T, n, w.y0) - ref)
+        return float(np.max(e)) if np.all(np.isfinite(e)) else float("inf")
+
+    # geometric grid of step counts; the answer is the first count from which
+    # the next three grid points also meet the method's error (so that a lucky
+    # zero crossing of the error does not count)
+    grid, n = [], 8
+    while n < n_same:
+        grid.append(n)
+        n = max(n + 1, int(n * 1.1))
+    grid.append(n_same)
+    ok = [None] * len(grid)
+    hi = n_same
+    for i in range(len(grid)):
+        ok[i] = err(grid[i]) <= method_err
+        if i >= 3 and all(ok[i - 3:i + 1]):
+            hi = grid[i - 3]
+            break
+    t = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t < 0.2:
+        oracle.serial_steps(w.rhs, w.params, w.scheme, w.t0, w.T, hi, w.y0)
+        reps += 1
+    t_eq = (time.perf_counter() - t) / reps
+    return {"method_error_at_T": method_err, "reference": f"serial RK4, {S_ref} steps",
+            "gpu_time_to_yT_ms": gpu_ms,
+            "serial_same_step": {"steps": n_same, "ms": round(1e3 * t_same, 3)},
+            "serial_equal_error": {"steps": hi, "error": err(hi), "ms": round(1e3 * t_eq, 4)},
+            "cores": 1}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,7 +153,7 @@ def main():
     ap.add_argument("--traj-per-lane", type=int, default=0)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default=None,
                     help="override the workload's build precision")
-    ap.add_argument("--compensated", type=int, default=1, choices=[0, 1, 2],
+    ap.add_argument("--compensated", type=int, default=2, choices=[0, 1, 2],
                     help="FP32 state accumulation: 0 plain, 1 Kahan, 2 blocked summation")
     ap.add_argument("--two-phase", action="store_true",
                     help="time nv_build_propagators + nv_compose instead of nv_solve")
@@ -149,33 +222,47 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
 
-    # kernel durations (HIP events on the library's stream), same workload
+    # build span of the timed path (HIP events; in solve mode all chunk launches)
     prop.set_timing(True)
-    build_ms, compose_ms = [], []
+    span_ms, exposed_ms = [], []
     for _ in range(args.steps):
         rr = step()
         b, c = prop.last_timing()
-        build_ms.append(b)
-        compose_ms.append(c)
-    prop.set_timing(False)
+        span_ms.append(b)
+        exposed_ms.append(c)
     launches = rr.n_chunks if not args.two_phase else 1
-    avg_build_ms = sum(build_ms) / len(build_ms)          # all build launches of a step
-    avg_compose_ms = sum(compose_ms) / len(compose_ms)
 
-    steps_per_launch = w.trajectory_steps / launches
+    # the dominant kernel alone: one launch of the integration kernel over the
+    # whole workload, and one composition launch over all slices (tau_N); HIP
+    # events on the stream the kernels run on
+    kern_ms, comp_ms = [], []
+    for _ in range(args.steps):
+        prop.build(w)
+        prop.compose()
+        b, c = prop.last_timing()
+        kern_ms.append(b)
+        comp_ms.append(c)
+    prop.set_timing(False)
+    avg_kernel_ms = sum(kern_ms) / len(kern_ms)
+    avg_compose_ms = sum(comp_ms) / len(comp_ms)
+
     fps = flops_per_step(w, compensated=args.compensated != 0)
     if w.precision == "fp32" and args.compensated == 2:
         fps = flops_per_step(w, compensated=False) + w.dim   # one extra add per component
-    achieved_tflops = w.trajectory_steps * fps / (avg_build_ms * 1e-3) / 1e12
+    achieved_tflops = w.trajectory_steps * fps / (avg_kernel_ms * 1e-3) / 1e12
     peak = PEAK_FP64_VECTOR_TFLOPS if w.precision == "fp64" else PEAK_FP32_VECTOR_TFLOPS
     roofline = {
         "bound": "alu", "achieved": round(achieved_tflops, 3), "peak": peak,
-        "unit": "TFLOP/s", "frac": round(achieved_tflops / peak, 4), "traffic": None,
-        "kernel": "build_kernel (ensemble RK4 integration + table write)",
-        "kernel_ms": round(avg_build_ms / launches, 4),
-        "launches_per_step": launches,
+        "unit": "TFLOP/s", "frac": round(achieved_tflops / peak, 4),
+        "traffic": MEASURED_TRAFFIC.get(
+            (w.name, ["plain", "kahan", "blocked"][args.compensated], kernel_source_sha1())),
+        "traffic_unit": "HBM bytes per launch",
+        "algorithmic_bytes": algorithmic_bytes(w),
+        "kernel": "build_kernel (ensemble RK4 integration + table write), one launch over "
+                  "the whole workload",
+        "kernel_ms": round(avg_kernel_ms, 4),
         "flops_per_trajectory_step": fps,
-        "trajectory_steps_per_launch": steps_per_launch,
+        "trajectory_steps_per_launch": w.trajectory_steps,
     }
 
     value = w.trajectory_steps * args.steps / elapsed
@@ -196,27 +283,22 @@ def main():
                    "points_per_slice": w.points_per_slice,
                    "steps_per_slice": w.steps_per_slice, "interp": w.interp,
                    "compose": "fp64", "parallelism": "single-gpu"},
-        "build_kernel_trajectory_steps_per_s": w.trajectory_steps / (avg_build_ms * 1e-3),
         "mode": "two-phase" if args.two_phase else "solve",
         "accumulation": ["plain", "kahan", "blocked"][args.compensated]
         if w.precision == "fp32" else "fp64",
-        "compose_exposed_ms" if not args.two_phase else "compose_ms": round(avg_compose_ms, 4),
-        "yT": float(r.yT[0]),
-        "tau_N_us": None,
+        "build_launches_per_step": launches,
+        "build_span_ms": round(sum(span_ms) / len(span_ms), 4),
+        "compose_exposed_ms": round(sum(exposed_ms) / len(exposed_ms), 4)
+        if not args.two_phase else None,
+        "build_kernel_trajectory_steps_per_s": w.trajectory_steps / (avg_kernel_ms * 1e-3),
+        "compose_alone_ms": round(avg_compose_ms, 4),
+        "tau_N_us": round(1e3 * avg_compose_ms / w.n_slices, 4),
+        "yT": [float(v) for v in r.yT],
         "roofline": roofline,
     }
-    # tau_N: the composition alone (one launch over all slices), HIP events
-    prop.set_timing(True)
-    prop.build(w)
-    taus = []
-    for _ in range(3):
-        prop.compose()
-        taus.append(prop.last_timing()[1])
-    prop.set_timing(False)
-    out["compose_alone_ms"] = round(min(taus), 4)
-    out["tau_N_us"] = round(1e3 * min(taus) / w.n_slices, 4)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_slices, w.n_slices))
+        out["time_to_yT_vs_serial"] = fixed_error(w, r.yT, round(ms_per_step, 4))
     prop.close()
     print(json.dumps(out), flush=True)
 

@@ -91,11 +91,12 @@ typedef struct {
     int precision;            /* nv_precision (default FP64) */
     int compensated;          /* FP32 only, accumulation of the state update:
                                  0 plain (one rounding per step),
-                                 1 Kahan-compensated (default),
-                                 2 blocked summation (the step increments of a block of
-                                   64 steps are summed apart from the state and added to
-                                   it once per block) */
-    int traj_per_lane;        /* trajectories per GPU lane: 1, 2 or 4; 0 = default */
+                                 1 Kahan-compensated,
+                                 2 blocked summation (default: the step increments of a
+                                   block of 64 steps are summed apart from the state and
+                                   added to it once per block) */
+    int traj_per_lane;        /* trajectories per GPU lane: 1, 2 or 4; 0 = chosen by the
+                                 library (2 for builds of at least 2^21 trajectories) */
     void *stream;             /* hipStream_t the context launches on; NULL = null stream */
     int solve_chunks;         /* nv_solve: slice chunks the build is cut into so that the
                                  composition of chunk c overlaps the build of chunk c+1;

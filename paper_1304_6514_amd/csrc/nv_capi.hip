@@ -38,8 +38,8 @@ nv_status fail(nv_status s, const char *fmt, ...) {
 constexpr size_t kAlign = 256;
 constexpr int kMaxChunks = 64;
 // automatic chunking of nv_solve: about this many workgroups per build launch
-// (two full rounds of 256 CUs x 8 resident workgroups)
-constexpr long long kBlocksPerChunk = 4096;
+// (half a round of 256 CUs x 8 resident workgroups; consecutive chunks overlap)
+constexpr long long kBlocksPerChunk = 1024;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int rhs_dim(int rhs) {
@@ -59,14 +59,21 @@ nv_options default_options() {
     nv_options o;
     o.scheme = NV_SCHEME_RK4;
     o.precision = NV_FP64;
-    o.compensated = 1;
+    o.compensated = 2;
     o.traj_per_lane = 0;
     o.stream = nullptr;
     o.solve_chunks = 0;
     return o;
 }
 
-int effective_p(const nv_options &o) { return o.traj_per_lane == 0 ? 1 : o.traj_per_lane; }
+// Trajectories per lane: the caller's choice, else 2 when the build still
+// fills the chip twice over with 2 per lane (256 CUs x 8 resident workgroups
+// of 256 lanes, two rounds), else 1.
+int effective_p(const nv_options &o, long long trajectories) {
+    if (o.traj_per_lane != 0) return o.traj_per_lane;
+    const long long two_rounds_at_p2 = 2LL * 256 * 8 * nv::kBuildBlock * 2;
+    return trajectories >= two_rounds_at_p2 ? 2 : 1;
+}
 
 nv_status check_options(const nv_options *o) {
     if (!o) return fail(NV_ERR_INVALID_ARG, "options pointer is NULL");
@@ -98,6 +105,7 @@ struct Plan {
     size_t work_bytes = 0;
     int tiles_per_slice = 0;
     long long total_blocks = 0;
+    int traj_per_lane = 1;
 };
 
 nv_status make_plan(int rhs, int n_slices, const nv_ic_grid *g, int steps,
@@ -133,7 +141,7 @@ nv_status make_plan(int rhs, int n_slices, const nv_ic_grid *g, int steps,
     default:
         return fail(NV_ERR_INVALID_ARG, "unknown interpolation %d", g->interp);
     }
-    const int P = effective_p(o);
+    const int P = effective_p(o, M * (long long)n_slices);
     const long long per_tile = (long long)nv::kBuildBlock * P;
     const long long tiles = (M + per_tile - 1) / per_tile;
     const long long blocks = tiles * n_slices;
@@ -159,6 +167,7 @@ nv_status make_plan(int rhs, int n_slices, const nv_ic_grid *g, int steps,
     p->work_bytes = off;
     p->tiles_per_slice = int(tiles);
     p->total_blocks = blocks;
+    p->traj_per_lane = P;
     return NV_OK;
 }
 
@@ -183,9 +192,11 @@ struct nv_ctx {
     int precision = NV_FP64;
     int n_slices = 0;
     nv_ic_grid grid{};
-    // nv_solve: second stream and per-chunk events
+    // nv_solve: composition stream, second build stream, per-chunk events
     hipStream_t aux = nullptr;
+    hipStream_t aux2 = nullptr;
     hipEvent_t chunk_ev[kMaxChunks] = {};
+    hipEvent_t ready_ev = nullptr;
     // timing
     bool timing = false;
     bool build_timed = false, compose_timed = false, solve_timed = false;
@@ -272,7 +283,7 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
         p0 = params[0];
     }
     nv::BuildConfig cfg{rhs_id, ctx->opt.scheme, ctx->opt.precision, ctx->opt.compensated,
-                        effective_p(ctx->opt)};
+                        p.traj_per_lane};
     if (!nv::build_supported(cfg)) return fail(NV_ERR_UNSUPPORTED, "unsupported configuration");
 
     s = ensure_device(&ctx->tables, &ctx->tables_cap, ctx->tables_owned, p.table_bytes, "table");
@@ -395,11 +406,14 @@ NV_API nv_status nv_ctx_destroy(nv_ctx *ctx) {
     if (ctx->work_owned && ctx->work) (void)hipFree(ctx->work);
     if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
     if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
+    if (ctx->aux2) (void)hipStreamSynchronize(ctx->aux2);
     for (auto e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto e : ctx->chunk_ev)
         if (e) (void)hipEventDestroy(e);
+    if (ctx->ready_ev) (void)hipEventDestroy(ctx->ready_ev);
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+    if (ctx->aux2) (void)hipStreamDestroy(ctx->aux2);
     delete ctx;
     return NV_OK;
 }
@@ -511,6 +525,8 @@ NV_API nv_status nv_solve(nv_ctx *ctx, int rhs_id, const double *params, double 
     nv_status s = prepare_build(ctx, rhs_id, params, t0, T, n_slices, grid, steps_per_slice, &pb);
     if (s != NV_OK) return s;
     if (!ctx->aux) NV_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    if (!ctx->aux2) NV_HIP(hipStreamCreateWithFlags(&ctx->aux2, hipStreamNonBlocking));
+    if (!ctx->ready_ev) NV_HIP(hipEventCreateWithFlags(&ctx->ready_ev, hipEventDisableTiming));
 
     // chunks of whole slices
     int chunks = ctx->opt.solve_chunks;
@@ -525,17 +541,26 @@ NV_API nv_status nv_solve(nv_ctx *ctx, int rhs_id, const double *params, double 
         if (!ctx->chunk_ev[c])
             NV_HIP(hipEventCreateWithFlags(&ctx->chunk_ev[c], hipEventDisableTiming));
 
-    hipStream_t st = stream_of(ctx), aux = ctx->aux;
+    // build chunks alternate between the context's stream and a second one, so
+    // that one chunk's last workgroups overlap the next chunk's first ones; the
+    // second stream starts after the counter reset and the forcing values
+    hipStream_t st = stream_of(ctx), aux = ctx->aux, st2 = ctx->aux2;
     ctx->build_timed = ctx->compose_timed = ctx->solve_timed = false;
+    NV_HIP(hipEventRecord(ctx->ready_ev, st));
+    NV_HIP(hipStreamWaitEvent(st2, ctx->ready_ev, 0));
     if (ctx->timing) NV_HIP(hipEventRecord(ctx->ev[0], st));
     for (int c = 0; c < chunks; ++c) {
+        hipStream_t bs = (c % 2 == 0) ? st : st2;
         nv::BuildArgs a = pb.args;
         a.slice0 = c * per;
         const int ns = (a.slice0 + per <= n_slices ? per : n_slices - a.slice0);
         a.total_blocks = ns * a.tiles_per_slice;
-        NV_HIP(nv::launch_build(pb.cfg, a, st));
-        NV_HIP(hipEventRecord(ctx->chunk_ev[c], st));
+        NV_HIP(nv::launch_build(pb.cfg, a, bs));
+        NV_HIP(hipEventRecord(ctx->chunk_ev[c], bs));
     }
+    // the context's stream waits for every build chunk
+    if (chunks > 1) NV_HIP(hipStreamWaitEvent(st, ctx->chunk_ev[chunks % 2 == 0 ? chunks - 1
+                                                                            : chunks - 2], 0));
     if (ctx->timing) NV_HIP(hipEventRecord(ctx->ev[1], st));
     for (int c = 0; c < chunks; ++c) {
         const int j0 = c * per, j1 = (j0 + per <= n_slices ? j0 + per : n_slices);

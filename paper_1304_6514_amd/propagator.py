@@ -25,7 +25,7 @@ class ComposeResult:
 
 
 class Propagator:
-    def __init__(self, device="cuda:0", traj_per_lane=0, compensated=1, stream=None,
+    def __init__(self, device="cuda:0", traj_per_lane=0, compensated=2, stream=None,
                  solve_chunks=0):
         import torch
 

@@ -143,7 +143,7 @@ def test_library_owned_buffers_match_torch_buffers(orc, prop, torch):
     a = gpu_tables(prop, w)
     ctx = nv.nv_ctx_create()
     try:
-        nv.nv_set_options(ctx, nv.make_options(w.scheme, w.precision, 1, 0, None))
+        nv.nv_set_options(ctx, nv.make_options(w.scheme, w.precision, prop.compensated, 0, None))
         g = nv.make_grid(w.grid_n, w.grid_lo, w.grid_hi, w.interp)
         nv.nv_build_propagators(ctx, nv.RHS_IDS[w.rhs], w.params, w.t0, w.T, w.n_slices, g,
                                 w.steps_per_slice)

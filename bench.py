@@ -49,13 +49,17 @@ WORKLOADS = {"forced_cubic": W.FORCED_CUBIC_FP32, "logistic": W.LOGISTIC_FP64,
 MEASURED_TRAFFIC = {
     ("forced-cubic-fp32-4096sl-4096pt-2000st", "blocked", "2502893abcb2af3335325fdf4026b1a36c6bbffb"): 198.3e6,
 }
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1304_6514_amd", "csrc", "build_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1304_6514_amd", "csrc", f)
+                  for f in ("integrate.h", "build_kernels.hip")]
 
 
 def kernel_source_sha1() -> str:
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()
+    h = hashlib.sha1()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def algorithmic_bytes(w: W.Workload) -> float:
@@ -144,12 +148,84 @@ def fixed_error(w: W.Workload, yT_method, gpu_ms):
             "cores": 1}
 
 
+def bench_batched(args):
+    """96 seeded uneven problems in one persistent, graph-captured launch,
+    against the plain form (each problem alone through nv_solve)."""
+    import numpy as np
+    import torch
+
+    from paper_1304_6514_amd import nv
+    from paper_1304_6514_amd.propagator import Batch, Propagator
+
+    probs = W.batched_problems()
+    total_steps = sum(w.trajectory_steps for w in probs)
+    flops = sum(w.trajectory_steps * (flops_per_step(w, compensated=False) + w.dim)
+                for w in probs)
+    b = Batch(probs)
+    t = time.perf_counter()
+    sched = b.autotune(reps=2)
+    tune_s = time.perf_counter() - t
+    for _ in range(args.warmup):
+        b.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, yT, _ = b.run()
+        if st != nv.NV_OK:
+            raise RuntimeError(f"batch failed: {nv.status_name(st)}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    run_ms, _ = b.last_timing()
+    b.close()
+
+    # the plain form: the same problems one after another, same options
+    plain_y = []
+    with Propagator("cuda:0") as p:
+        for w in probs:                      # warm-up of every shape
+            p.solve(w, want_boundary=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for w in probs:
+            r = p.solve(w, want_boundary=False)
+            plain_y.append(r.yT)
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - t1
+    same = all(np.array_equal(yT[i, :w.dim], plain_y[i]) for i, w in enumerate(probs))
+
+    ms = 1e3 * elapsed / args.steps
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {
+        "metric": "trajectory-steps/s in propagator build; time-to-y(T) vs serial at fixed error",
+        "value": total_steps * args.steps / elapsed, "unit": "trajectory-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched-96-uneven-seed3", "problems": len(probs),
+                   "trajectory_steps": total_steps, "interp": "linear/bilinear",
+                   "compose": "fp64", "parallelism": "single-gpu"},
+        "graph_run_ms": round(run_ms, 4),
+        "schedule": {"traj_per_lane": list(sched.traj_per_lane),
+                     "workgroups_per_cu": sched.workgroups_per_cu,
+                     "order": ["longest-first", "natural"][sched.order],
+                     "autotune_s": round(tune_s, 2)},
+        "plain_form": {"value": total_steps / plain_s, "ms": round(1e3 * plain_s, 3),
+                       "what": "each problem alone through nv_solve, same options",
+                       "identical_results": bool(same)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                     "kernel": "whole batched step (persistent build + compositions + copy)",
+                     "flops_per_step_total": flops},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="forced_cubic", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="forced_cubic",
+                    choices=sorted(WORKLOADS) + ["batched"])
     ap.add_argument("--traj-per-lane", type=int, default=0)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default=None,
                     help="override the workload's build precision")
@@ -181,6 +257,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     nv.load()
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(args)), flush=True)
+        return
     w = WORKLOADS[args.workload]
     if args.precision:
         w = w.with_(precision=args.precision)

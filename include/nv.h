@@ -247,6 +247,84 @@ NV_API nv_status nv_locate(nv_ctx *ctx, double lo, double hi, int n, const doubl
 NV_API nv_status nv_set_timing(nv_ctx *ctx, int enable);
 NV_API nv_status nv_last_timing(nv_ctx *ctx, float *build_ms, float *compose_ms);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent problems of uneven shape in one persistent,
+ * graph-captured launch.
+ *
+ * Every problem is the method of sec. 3 on its own (own right-hand side,
+ * interval, slices, grid and steps); the batch builds all their tables in ONE
+ * launch of a persistent kernel whose workgroups take work items (a tile of
+ * 256 x P grid points of one slice of one problem) from a shared counter,
+ * longest items first, then composes every problem in one launch (one wave per
+ * problem).  The reset, the two launches and the copy of the results to host
+ * memory are captured once into a HIP graph and replayed by nv_batch_run.
+ * Results equal those of nv_build_propagators + nv_compose on each problem
+ * alone, bit for bit (same options).  Batches take the autonomous right-hand
+ * sides (LINEAR, LOGISTIC, VDP, SQUARE); FORCED_CUBIC gives NV_ERR_UNSUPPORTED.
+ * ------------------------------------------------------------------------ */
+
+/* One problem of a batch: the arguments of nv_build_propagators plus y0. */
+typedef struct {
+    int rhs_id;
+    double params[2];
+    double t0, T;
+    int n_slices;
+    nv_ic_grid grid;
+    int steps_per_slice;
+    double y0[2];
+} nv_problem;
+
+/* How the batch's build is scheduled.  traj_per_lane[r] is P for the problems
+ * of right-hand side r (1, 2 or 4); workgroups_per_cu sets the persistent
+ * grid (256 CUs x this many workgroups of 256 lanes, 1..8); order 0 hands out
+ * items longest first, order 1 in problem/slice/tile order. */
+typedef struct {
+    int traj_per_lane[5];
+    int workgroups_per_cu;
+    int order;
+} nv_batch_schedule;
+
+typedef struct nv_batch nv_batch;
+
+/* Create a batch of count problems (host array, copied).  Precision and FP32
+ * accumulation come from ctx's options; the batch owns its device memory, its
+ * stream and its graph.  The default schedule is P = 1 for every right-hand
+ * side, 8 workgroups per CU, longest items first.  Errors: NV_ERR_INVALID_ARG
+ * (with the offending problem's index in the message), NV_ERR_UNSUPPORTED,
+ * NV_ERR_OOM, NV_ERR_HIP. */
+NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int count,
+                                 nv_batch **out);
+NV_API nv_status nv_batch_destroy(nv_batch *batch);
+
+/* Replace / read the schedule (a new schedule is captured at the next run). */
+NV_API nv_status nv_batch_set_schedule(nv_batch *batch, const nv_batch_schedule *sched);
+NV_API nv_status nv_batch_get_schedule(const nv_batch *batch, nv_batch_schedule *sched);
+
+/* Project autotuner: times candidate schedules on this batch with HIP events
+ * (per right-hand side, P in {1, 2, 4} on that right-hand side's items alone;
+ * then workgroups per CU in {4, 8} and both item orders on the whole batch),
+ * keeps the fastest, sets it and returns it in *chosen (may be NULL).  reps
+ * timed launches per candidate (>= 1). */
+NV_API nv_status nv_batch_autotune(nv_batch *batch, int reps, nv_batch_schedule *chosen);
+
+/* Run the whole batch (replays the captured graph) and wait.  yT: host array
+ * of count x 2 values (problem i's final state at yT[2i], yT[2i+1]; the second
+ * is 0 for 1-D problems); info: host array of count entries, or NULL.
+ * Returns NV_ERR_NONFINITE if any problem's composition met a non-finite value
+ * (see its info entry), else NV_OK. */
+NV_API nv_status nv_batch_run(nv_batch *batch, double *yT, nv_compose_info *info);
+
+/* Milliseconds of the last nv_batch_run (HIP events around the graph launch),
+ * and the trajectory-steps one run integrates. */
+NV_API nv_status nv_batch_last_timing(nv_batch *batch, float *run_ms, long long *traj_steps);
+
+/* Copy problem p's component c table (layout of nv_get_table) or its boundary
+ * states ((n_slices + 1) x dim doubles) of the last run to host memory. */
+NV_API nv_status nv_batch_get_table(nv_batch *batch, int problem, int component,
+                                    void *host_dst, size_t bytes);
+NV_API nv_status nv_batch_get_boundary(nv_batch *batch, int problem, double *host_dst,
+                                       size_t count);
+
 /* Message of the last failure on the calling thread ("" if none). */
 NV_API const char *nv_last_error(void);
 

@@ -1,0 +1,137 @@
+// Device code of the communication phase of Nievergelt's method (sec. 3,
+// pseudocode figure): the lookup, the interpolants and the dependent chain
+// lambda_{j+1} = phi^j(lambda_j) over a range of slices.  Every floating-point
+// operation is one IEEE binary64 operation with no contraction, so that the
+// result over given tables is specified bit for bit (include/nv.h).
+#pragma once
+
+#include "nv_internal.h"
+
+#include <cmath>
+
+namespace nv {
+namespace dev {
+
+// Cell and local coordinate of x on one axis.  Returns 1 when x lies outside
+// [lo, hi] (the lookup then extrapolates from the edge cell).  A NaN query
+// gives cell 0, w = NaN and counts as outside.
+__device__ inline int locate(double lo, double inv, int n, double x, long long &cell,
+                             double &w) {
+#pragma clang fp contract(off)
+    const double u = (x - lo) * inv;
+    if (u != u) {
+        cell = 0;
+        w = u;
+        return 1;
+    }
+    const double f = floor(u);
+    long long i;
+    if (f < 0.0)
+        i = 0;
+    else if (f > double(n - 2))
+        i = n - 2;
+    else
+        i = (long long)f;
+    cell = i;
+    w = u - double(i);
+    return (u < 0.0 || u > double(n - 1)) ? 1 : 0;
+}
+
+__device__ inline bool finite(double v) { return isfinite(v); }
+
+// Delta-xi times the slope at node i of a 1-D table row, by finite differences.
+template <class T>
+__device__ inline double node_slope(const T *row, long long i, int n) {
+#pragma clang fp contract(off)
+    if (i == 0) {
+        const double t0 = double(row[0]), t1 = double(row[1]), t2 = double(row[2]);
+        return 0.5 * ((4.0 * t1 - 3.0 * t0) - t2);
+    }
+    if (i == n - 1) {
+        const double a = double(row[n - 1]), b = double(row[n - 2]), c = double(row[n - 3]);
+        return 0.5 * ((3.0 * a - 4.0 * b) + c);
+    }
+    return 0.5 * (double(row[i + 1]) - double(row[i - 1]));
+}
+
+// Composes slices j_begin .. j_end-1.  A launch that starts at slice 0 takes
+// y0 from its arguments and resets the status; a later launch resumes from the
+// boundary state the previous one left in memory and adds to the status.
+template <class T, int Interp>
+__device__ inline void compose_range(const ComposeArgs &a) {
+#pragma clang fp contract(off)
+    constexpr int D = Interp == 2 ? 2 : 1;
+    const T *tab0 = static_cast<const T *>(a.tab0);
+    const T *tab1 = static_cast<const T *>(a.tab1);
+    double lam0, lam1 = 0.0;
+    if (a.j_begin == 0) {
+        lam0 = a.y00;
+        lam1 = a.y01;
+        a.boundary[0] = lam0;
+        if (D == 2) a.boundary[1] = lam1;
+        a.status->n_out_of_grid = 0;
+        a.status->bad_slice = -1;
+        a.status->done = 0;
+    } else {
+        if (a.status->bad_slice >= 0) return;     // an earlier range already failed
+        lam0 = a.boundary[(long long)a.j_begin * D];
+        if (D == 2) lam1 = a.boundary[(long long)a.j_begin * D + 1];
+    }
+    long long oog = 0;
+    int bad_slice = -1;
+    for (int j = a.j_begin; j < a.j_end; ++j) {
+        if (!finite(lam0) || (D == 2 && !finite(lam1))) {
+            bad_slice = j;
+            break;
+        }
+        const T *row0 = tab0 + (long long)j * a.M;
+        long long i0, i1;
+        double w0, w1;
+        oog += locate(a.lo0, a.inv0, a.n0, lam0, i0, w0);
+        double next0, next1 = 0.0;
+        bool bad = false;
+        if constexpr (Interp == 0) {
+            const double ta = double(row0[i0]), tb = double(row0[i0 + 1]);
+            bad = !finite(ta) || !finite(tb);
+            next0 = ta + w0 * (tb - ta);
+        } else if constexpr (Interp == 1) {
+            const double ta = double(row0[i0]), tb = double(row0[i0 + 1]);
+            const double da = node_slope(row0, i0, a.n0), db = node_slope(row0, i0 + 1, a.n0);
+            const double w2 = w0 * w0, w3 = w2 * w0;
+            const double h00 = (2.0 * w3 - 3.0 * w2) + 1.0;
+            const double h10 = (w3 - 2.0 * w2) + w0;
+            const double h01 = 3.0 * w2 - 2.0 * w3;
+            const double h11 = w3 - w2;
+            bad = !finite(ta) || !finite(tb) || !finite(da) || !finite(db);
+            next0 = ((h00 * ta + h10 * da) + h01 * tb) + h11 * db;
+        } else {
+            oog += locate(a.lo1, a.inv1, a.n1, lam1, i1, w1);
+            const long long c00 = i0 * a.n1 + i1, c10 = (i0 + 1) * a.n1 + i1;
+            const T *row1 = tab1 + (long long)j * a.M;
+            const double p00 = double(row0[c00]), p01 = double(row0[c00 + 1]);
+            const double p10 = double(row0[c10]), p11 = double(row0[c10 + 1]);
+            const double q00 = double(row1[c00]), q01 = double(row1[c00 + 1]);
+            const double q10 = double(row1[c10]), q11 = double(row1[c10 + 1]);
+            bad = !finite(p00) || !finite(p01) || !finite(p10) || !finite(p11) ||
+                  !finite(q00) || !finite(q01) || !finite(q10) || !finite(q11);
+            const double r0 = p00 + w1 * (p01 - p00), r1 = p10 + w1 * (p11 - p10);
+            const double s0 = q00 + w1 * (q01 - q00), s1 = q10 + w1 * (q11 - q10);
+            next0 = r0 + w0 * (r1 - r0);
+            next1 = s0 + w0 * (s1 - s0);
+        }
+        if (bad) {
+            bad_slice = j;
+            break;
+        }
+        lam0 = next0;
+        lam1 = next1;
+        a.boundary[(long long)(j + 1) * D] = lam0;
+        if (D == 2) a.boundary[(long long)(j + 1) * D + 1] = lam1;
+    }
+    a.status->n_out_of_grid += oog;
+    if (bad_slice >= 0) a.status->bad_slice = bad_slice;
+    if (a.j_end == a.n_slices || bad_slice >= 0) a.status->done = 1;
+}
+
+}  // namespace dev
+}  // namespace nv

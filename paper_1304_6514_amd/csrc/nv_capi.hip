@@ -15,10 +15,10 @@
 #include <string>
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-nv_status fail(nv_status s, const char *fmt, ...) {
+nv_status nv::fail(nv_status s, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -27,6 +27,9 @@ nv_status fail(nv_status s, const char *fmt, ...) {
     g_last_error = buf;
     return s;
 }
+
+namespace {
+using nv::fail;
 
 #define NV_HIP(expr)                                                                    \
     do {                                                                                \
@@ -172,6 +175,18 @@ nv_status make_plan(int rhs, int n_slices, const nv_ic_grid *g, int steps,
 }
 
 }  // namespace
+
+nv_status nv::check_problem(int rhs_id, const double *params, double t0, double T, int n_slices,
+                            const nv_ic_grid *grid, int steps_per_slice) {
+    Plan p;
+    nv_status s = make_plan(rhs_id, n_slices, grid, steps_per_slice, default_options(), &p);
+    if (s != NV_OK) return s;
+    if (!std::isfinite(t0) || !std::isfinite(T) || !(T > t0))
+        return fail(NV_ERR_INVALID_ARG, "need finite t0 < T (got %g, %g)", t0, T);
+    if (rhs_nparams(rhs_id) > 0 && (!params || !std::isfinite(params[0])))
+        return fail(NV_ERR_INVALID_ARG, "rhs %d needs a finite parameter", rhs_id);
+    return NV_OK;
+}
 
 struct nv_ctx {
     nv_options opt = default_options();

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "nv.h"
+
 namespace nv {
 
 constexpr int kBuildBlock = 256;   // lanes per build workgroup (4 wave64s)
@@ -59,6 +61,26 @@ struct ComposeArgs {
     double y00, y01;
 };
 
+// One problem of a batch, as the batched kernels see it.
+struct BatchProblem {
+    BuildArgs build;          // slice0 = 0; tables, counters and grid of this problem
+    ComposeArgs compose;      // whole range of slices, this problem's y0
+    int rhs;                  // nv_rhs_id (autonomous right-hand sides only)
+    int interp;               // nv_interp
+    int traj_per_lane;        // P of this problem's tiles
+    int dim;
+    double *result;           // [dim]: lambda_N, written after the composition
+};
+
+// One work item of the persistent build: a tile of 256*P grid points of one
+// slice of one problem.
+struct BatchItem {
+    int problem;
+    int slice;
+    int tile;
+    int reserved;
+};
+
 bool build_supported(const BuildConfig &c);
 hipError_t launch_build(const BuildConfig &c, const BuildArgs &a, hipStream_t s);
 hipError_t launch_forcing(int rhs, int precision, void *F, int n_slices, int steps,
@@ -67,5 +89,16 @@ hipError_t launch_fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t s);
 hipError_t launch_compose(int interp, int precision, const ComposeArgs &a, hipStream_t s);
 hipError_t launch_locate(double lo, double inv, int n, const double *x, long long count,
                          long long *cell, double *w, int32_t *out, hipStream_t s);
+hipError_t launch_batch_build(int precision, int accumulation, const BatchProblem *probs,
+                              const BatchItem *items, int n_items, unsigned *counter,
+                              int n_workgroups, hipStream_t s);
+hipError_t launch_batch_compose(int precision, const BatchProblem *probs, int count,
+                                hipStream_t s);
+
+// Shared by the C-ABI translation units: record the calling thread's error
+// message and return s; check one problem's description (host only).
+nv_status fail(nv_status s, const char *fmt, ...);
+nv_status check_problem(int rhs_id, const double *params, double t0, double T, int n_slices,
+                        const nv_ic_grid *grid, int steps_per_slice);
 
 }  // namespace nv

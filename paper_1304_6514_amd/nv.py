@@ -53,6 +53,18 @@ class nv_compose_info(ctypes.Structure):
                 ("n_chunks", ctypes.c_int)]
 
 
+class nv_problem(ctypes.Structure):
+    _fields_ = [("rhs_id", ctypes.c_int), ("params", ctypes.c_double * 2),
+                ("t0", ctypes.c_double), ("T", ctypes.c_double), ("n_slices", ctypes.c_int),
+                ("grid", nv_ic_grid), ("steps_per_slice", ctypes.c_int),
+                ("y0", ctypes.c_double * 2)]
+
+
+class nv_batch_schedule(ctypes.Structure):
+    _fields_ = [("traj_per_lane", ctypes.c_int * 5), ("workgroups_per_cu", ctypes.c_int),
+                ("order", ctypes.c_int)]
+
+
 class NvError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{status_name(status)}: {message}")
@@ -84,6 +96,17 @@ _SIGNATURES = {
                   _P, _P, _P],
     "nv_set_timing": [_P, ctypes.c_int],
     "nv_last_timing": [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+    "nv_batch_create": [_P, ctypes.POINTER(nv_problem), ctypes.c_int,
+                        ctypes.POINTER(ctypes.c_void_p)],
+    "nv_batch_destroy": [_P],
+    "nv_batch_set_schedule": [_P, ctypes.POINTER(nv_batch_schedule)],
+    "nv_batch_get_schedule": [_P, ctypes.POINTER(nv_batch_schedule)],
+    "nv_batch_autotune": [_P, ctypes.c_int, ctypes.POINTER(nv_batch_schedule)],
+    "nv_batch_run": [_P, _P, ctypes.POINTER(nv_compose_info)],
+    "nv_batch_last_timing": [_P, ctypes.POINTER(ctypes.c_float),
+                             ctypes.POINTER(ctypes.c_longlong)],
+    "nv_batch_get_table": [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t],
+    "nv_batch_get_boundary": [_P, ctypes.c_int, _P, ctypes.c_size_t],
     "nv_last_error": [],
     "nv_status_string": [ctypes.c_int],
 }
@@ -262,3 +285,76 @@ def nv_last_timing(ctx):
     b, c = ctypes.c_float(), ctypes.c_float()
     _check(load().nv_last_timing(ctx, ctypes.byref(b), ctypes.byref(c)))
     return b.value, c.value
+
+
+# ---- batches ----------------------------------------------------------------
+
+def make_problem(rhs, params, t0, T, n_slices, grid: nv_ic_grid, steps_per_slice, y0):
+    p = nv_problem()
+    p.rhs_id = RHS_IDS[rhs] if isinstance(rhs, str) else int(rhs)
+    for i, v in enumerate(list(params or [])[:2]):
+        p.params[i] = float(v)
+    p.t0, p.T, p.n_slices = float(t0), float(T), int(n_slices)
+    p.grid = grid
+    p.steps_per_slice = int(steps_per_slice)
+    for i, v in enumerate(list(y0)[:2]):
+        p.y0[i] = float(v)
+    return p
+
+
+def nv_batch_create(ctx, problems):
+    arr = (nv_problem * len(problems))(*problems)
+    h = ctypes.c_void_p()
+    _check(load().nv_batch_create(ctx, arr, len(problems), ctypes.byref(h)))
+    return h
+
+
+def nv_batch_destroy(batch):
+    return _check(load().nv_batch_destroy(batch))
+
+
+def nv_batch_set_schedule(batch, sched: nv_batch_schedule):
+    return _check(load().nv_batch_set_schedule(batch, ctypes.byref(sched)))
+
+
+def nv_batch_get_schedule(batch) -> nv_batch_schedule:
+    s = nv_batch_schedule()
+    _check(load().nv_batch_get_schedule(batch, ctypes.byref(s)))
+    return s
+
+
+def nv_batch_autotune(batch, reps=2) -> nv_batch_schedule:
+    s = nv_batch_schedule()
+    _check(load().nv_batch_autotune(batch, int(reps), ctypes.byref(s)))
+    return s
+
+
+def nv_batch_run(batch, count):
+    """Returns (status, yT of shape (count, 2), infos).  Raises on statuses
+    other than NV_OK and NV_ERR_NONFINITE."""
+    yT = np.full((count, 2), np.nan)
+    infos = (nv_compose_info * count)()
+    st = load().nv_batch_run(batch, _ptr(yT), infos)
+    if st not in (NV_OK, NV_ERR_NONFINITE):
+        _check(st)
+    return st, yT, infos
+
+
+def nv_batch_last_timing(batch):
+    ms, steps = ctypes.c_float(), ctypes.c_longlong()
+    _check(load().nv_batch_last_timing(batch, ctypes.byref(ms), ctypes.byref(steps)))
+    return ms.value, steps.value
+
+
+def nv_batch_get_table(batch, problem, component, n_slices, points, precision):
+    dt = np.float64 if precision in ("fp64", NV_FP64) else np.float32
+    out = np.empty((n_slices, points), dtype=dt)
+    _check(load().nv_batch_get_table(batch, int(problem), int(component), _ptr(out),
+                                     out.nbytes))
+    return out
+
+
+def nv_batch_get_boundary(batch, problem, n_slices, dim):
+    out = np.empty((n_slices + 1, dim))
+    _check(load().nv_batch_get_boundary(batch, int(problem), _ptr(out), out.size))
+    return out

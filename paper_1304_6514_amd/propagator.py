@@ -137,3 +137,76 @@ class Propagator:
 
     def last_timing(self):
         return nv.nv_last_timing(self.ctx)
+
+
+class Batch:
+    """Many problems (Workloads) built in one persistent launch and composed in
+    one launch, replayed from a captured HIP graph (nv_batch_*)."""
+
+    def __init__(self, workloads, precision="fp32", compensated=2):
+        self.workloads = list(workloads)
+        if any(w.scheme != "rk4" for w in self.workloads):
+            raise ValueError("batches integrate with RK4")
+        self.precision = precision
+        self.ctx = nv.nv_ctx_create()
+        nv.nv_set_options(self.ctx, nv.make_options("rk4", precision, compensated))
+        probs = [nv.make_problem(w.rhs, w.params, w.t0, w.T, w.n_slices,
+                                 nv.make_grid(w.grid_n, w.grid_lo, w.grid_hi, w.interp),
+                                 w.steps_per_slice, w.y0) for w in self.workloads]
+        try:
+            self.batch = nv.nv_batch_create(self.ctx, probs)
+        except Exception:
+            nv.nv_ctx_destroy(self.ctx)
+            self.ctx = None
+            raise
+
+    def close(self):
+        if getattr(self, "batch", None) is not None:
+            nv.nv_batch_destroy(self.batch)
+            self.batch = None
+        if getattr(self, "ctx", None) is not None:
+            nv.nv_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self):
+        """(status, yT array (count, dim max 2), list of ComposeResult-like infos)."""
+        st, yT, infos = nv.nv_batch_run(self.batch, len(self.workloads))
+        return st, yT, [(i.n_out_of_grid, i.bad_slice) for i in infos]
+
+    def schedule(self):
+        return nv.nv_batch_get_schedule(self.batch)
+
+    def set_schedule(self, traj_per_lane=None, workgroups_per_cu=8, order=0):
+        s = nv.nv_batch_schedule()
+        for r in range(5):
+            s.traj_per_lane[r] = (traj_per_lane or {}).get(r, 1)
+        s.workgroups_per_cu = workgroups_per_cu
+        s.order = order
+        nv.nv_batch_set_schedule(self.batch, s)
+
+    def autotune(self, reps=2):
+        return nv.nv_batch_autotune(self.batch, reps)
+
+    def last_timing(self):
+        return nv.nv_batch_last_timing(self.batch)
+
+    def table(self, i, component=0):
+        w = self.workloads[i]
+        return nv.nv_batch_get_table(self.batch, i, component, w.n_slices, w.points_per_slice,
+                                     self.precision)
+
+    def boundary(self, i):
+        w = self.workloads[i]
+        return nv.nv_batch_get_boundary(self.batch, i, w.n_slices, w.dim)

@@ -115,3 +115,45 @@ def sample_entries(w: Workload, count: int, seed: int):
     edge_p = np.array([0, w.points_per_slice - 1, 0, w.points_per_slice - 1],
                       dtype=np.int64)
     return np.concatenate([edge_s, sl]), np.concatenate([edge_p, pt])
+
+
+def _log_uniform_int(rng, lo, hi):
+    return int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi))))))
+
+
+def batched_problems(count: int = 96, seed: int = 3, scale: float = 1.0):
+    """The batched uneven workload: count seeded problems mixing y' = lambda y
+    (lambda ~ U[-2, 0.5], [0, 10], grid [-2, 2]), the logistic problem ([0, 10],
+    grid [-0.1, 1.2]) and Van der Pol (mu ~ U[1, 5], [0, 50], grid
+    [-3, 3] x [-8, 8]); slices log-uniform in [16, 2048], 1-D grids log-uniform
+    in [64, 8192] points, 2-D grids log-uniform in [16, 256] per axis, steps per
+    slice uniform in [100, 2000].  scale < 1 shrinks slices, grids and steps
+    proportionally (same draws) for tests, and the interval with them so that
+    every problem keeps its step size."""
+    rng = np.random.default_rng(seed)
+    out = []
+    fams = ("linear", "logistic", "vdp")
+    for i in range(count):
+        fam = fams[int(rng.integers(0, 3))]
+        n_slices = _log_uniform_int(rng, 16, 2048)
+        steps = int(rng.integers(100, 2001))
+        if fam == "vdp":
+            grid_n = (_log_uniform_int(rng, 16, 256), _log_uniform_int(rng, 16, 256))
+            params, T, lo, hi, y0, interp = ((float(rng.uniform(1.0, 5.0)),), 50.0,
+                                             (-3.0, -8.0), (3.0, 8.0), (2.0, 0.0), "bilinear")
+        elif fam == "linear":
+            grid_n = (_log_uniform_int(rng, 64, 8192),)
+            params, T, lo, hi, y0, interp = ((float(rng.uniform(-2.0, 0.5)),), 10.0, (-2.0,),
+                                             (2.0,), (1.0,), "linear")
+        else:
+            grid_n = (_log_uniform_int(rng, 64, 8192),)
+            params, T, lo, hi, y0, interp = ((), 10.0, (-0.1,), (1.2,), (0.1,), "linear")
+        if scale != 1.0:
+            n_s, s_s = max(2, int(n_slices * scale)), max(2, int(steps * scale))
+            T = T * (n_s * s_s) / (n_slices * steps)
+            n_slices, steps = n_s, s_s
+            grid_n = tuple(max(3, int(n * scale)) for n in grid_n)
+        out.append(Workload(name=f"batch{i:02d}-{fam}", rhs=fam, params=params, t0=0.0, T=T,
+                            n_slices=n_slices, grid_n=grid_n, grid_lo=lo, grid_hi=hi,
+                            steps_per_slice=steps, y0=y0, precision="fp32", interp=interp))
+    return out

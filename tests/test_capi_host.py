@@ -148,3 +148,42 @@ def test_product_path_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "nv_oracle" not in text, f
+
+
+def test_batch_argument_errors_need_no_gpu(nvmod):
+    ctx = nvmod.nv_ctx_create()
+    try:
+        g = _grid(nvmod)
+        good = nvmod.make_problem("logistic", [], 0.0, 10.0, 64, g, 100, [0.1])
+        forced = nvmod.make_problem("forced_cubic", [], 0.0, 10.0, 64,
+                                    _grid(nvmod, (100,), (-3.0,), (3.0,), "hermite"), 100, [1.0])
+        bad = nvmod.make_problem("logistic", [], 0.0, 10.0, 0, g, 100, [0.1])
+        with pytest.raises(nvmod.NvError) as e:
+            nvmod.nv_batch_create(ctx, [good, forced])
+        assert e.value.status == nvmod.NV_ERR_UNSUPPORTED and "problem 1" in str(e.value)
+        with pytest.raises(nvmod.NvError) as e:
+            nvmod.nv_batch_create(ctx, [good, good, bad])
+        assert e.value.status == nvmod.NV_ERR_INVALID_ARG and "problem 2" in str(e.value)
+        lib = nvmod.load()
+        assert lib.nv_batch_create(ctx, None, 0, None) == nvmod.NV_ERR_INVALID_ARG
+        assert lib.nv_batch_destroy(None) == 0
+        assert lib.nv_batch_run(None, None, None) == nvmod.NV_ERR_INVALID_ARG
+    finally:
+        nvmod.nv_ctx_destroy(ctx)
+
+
+def test_batched_workload_recipe():
+    from paper_1304_6514_amd import workloads as W
+    probs = W.batched_problems()
+    assert len(probs) == 96 and probs == W.batched_problems()       # seeded
+    assert {w.rhs for w in probs} == {"linear", "logistic", "vdp"}
+    for w in probs:
+        assert 16 <= w.n_slices <= 2048 and 100 <= w.steps_per_slice <= 2000
+        if w.dim == 1:
+            assert 64 <= w.grid_n[0] <= 8192
+        else:
+            assert all(16 <= n <= 256 for n in w.grid_n)
+        if w.rhs == "linear":
+            assert -2.0 <= w.params[0] <= 0.5
+        if w.rhs == "vdp":
+            assert 1.0 <= w.params[0] <= 5.0

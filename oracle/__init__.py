@@ -72,6 +72,9 @@ def _load():
         "orc_method_lazy": (I, [I, P, I, D, D, I, G, I, I, P, P, ctypes.POINTER(LL),
                                 ctypes.POINTER(I)]),
         "orc_paper_method": (I, [D, I, I, D, D, D, D, I, I, ctypes.POINTER(D)]),
+        "orc_paper_nodes": (I, [I, D, D, P]),
+        "orc_paper_tables": (I, [D, I, I, D, D, D, I, I, P]),
+        "orc_paper_compose": (I, [I, I, D, D, P, D, P, ctypes.POINTER(LL), ctypes.POINTER(I)]),
         "orc_paper_serial": (I, [D, D, D, I, I, ctypes.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
@@ -261,6 +264,35 @@ def paper_method(T, n_slices, M, a, b, dt, y0, be_exact=False, equal_substeps=Fa
     _check(lib.orc_paper_method(T, n_slices, M, a, b, dt, y0, int(be_exact),
                                 int(equal_substeps), ctypes.byref(out)), "paper_method")
     return out.value
+
+
+def paper_nodes(M, a, b):
+    lib = _load()
+    out = np.zeros(M)
+    _check(lib.orc_paper_nodes(M, a, b, _ptr(out)), "paper_nodes")
+    return out
+
+
+def paper_tables(T, n_slices, M, a, b, dt, be_exact=False, equal_substeps=False):
+    """Paper mode, computation phase: tables of shape (n_slices, M)."""
+    lib = _load()
+    tab = np.zeros((n_slices, M))
+    _check(lib.orc_paper_tables(T, n_slices, M, a, b, dt, int(be_exact), int(equal_substeps),
+                                _ptr(tab)), "paper_tables")
+    return tab
+
+
+def paper_compose(M, a, b, tab, y0):
+    """Paper mode, communication phase over given tables of shape (N, M)."""
+    lib = _load()
+    tab = np.ascontiguousarray(np.asarray(tab, dtype=np.float64))
+    N = tab.shape[0]
+    boundary = np.full(N + 1, np.nan)
+    oog = ctypes.c_longlong(0)
+    bad = ctypes.c_int(-1)
+    rc = _check(lib.orc_paper_compose(N, M, a, b, _ptr(tab), float(y0), _ptr(boundary),
+                                      ctypes.byref(oog), ctypes.byref(bad)), "paper_compose")
+    return ComposeResult(rc, boundary[:, None], None, None, oog.value, bad.value)
 
 
 def paper_serial(T, dt, y0, be_exact=False, equal_substeps=False):

@@ -453,32 +453,77 @@ static double lagrange(const double *xs, const double *vs, int M, double x) {
     return s;
 }
 
+int orc_paper_nodes(int M, double a, double b, double *xs) {
+    int k;
+    if (M < 2 || !(b > a)) return ORC_BAD_ARG;
+    for (k = 0; k < M; ++k) xs[k] = cheb_node(a, b, M, k);
+    return ORC_OK;
+}
+
+/* Computation phase of paper mode: tab[j * M + k] = backward Euler over slice j
+ * (length T / N) from the node xi_k. */
+int orc_paper_tables(double T, int n_slices, int M, double a, double b, double dt,
+                     int be_exact, int equal_substeps, double *tab) {
+    double L, xs[64];
+    int j, k;
+    if (n_slices < 1 || M < 2 || M > 64 || !(b > a) || !(dt > 0.0)) return ORC_BAD_ARG;
+    L = T / (double)n_slices;
+    orc_paper_nodes(M, a, b, xs);
+    for (j = 0; j < n_slices; ++j)
+        for (k = 0; k < M; ++k)
+            tab[(long long)j * M + k] = be_interval(xs[k], L, dt, be_exact, equal_substeps);
+    return ORC_OK;
+}
+
+/* Communication phase of paper mode over given tables: lambda_0 = y0,
+ * lambda_{j+1} = Lagrange interpolant of row j at lambda_j.  Lookups at points
+ * outside [a, b] are counted; a non-finite lambda_j or table value read stops
+ * the chain with ORC_NONFINITE and *bad_slice = j. */
+int orc_paper_compose(int n_slices, int M, double a, double b, const double *tab, double y0,
+                      double *boundary, long long *n_out_of_grid, int *bad_slice) {
+    double xs[64], lam = y0;
+    long long oog = 0;
+    int j, k;
+    if (n_slices < 1 || M < 2 || M > 64 || !(b > a)) return ORC_BAD_ARG;
+    orc_paper_nodes(M, a, b, xs);
+    if (boundary) boundary[0] = lam;
+    if (bad_slice) *bad_slice = -1;
+    for (j = 0; j < n_slices; ++j) {
+        const double *row = tab + (long long)j * M;
+        int bad = !isfinite(lam);
+        for (k = 0; k < M; ++k)
+            if (!isfinite(row[k])) bad = 1;
+        if (bad) {
+            if (bad_slice) *bad_slice = j;
+            if (n_out_of_grid) *n_out_of_grid = oog;
+            return ORC_NONFINITE;
+        }
+        if (lam < a || lam > b) ++oog;
+        lam = lagrange(xs, row, M, lam);
+        if (boundary) boundary[j + 1] = lam;
+    }
+    if (n_out_of_grid) *n_out_of_grid = oog;
+    return ORC_OK;
+}
+
 int orc_paper_method(double T, int n_slices, int M, double a, double b, double dt,
                      double y0, int be_exact, int equal_substeps, double *yT) {
-    double *xs, *vs, L, lam;
-    int j, k;
-    if (n_slices < 1 || M < 2 || !(b > a) || !(dt > 0.0)) return ORC_BAD_ARG;
-    xs = (double *)malloc(sizeof(double) * (size_t)M);
-    vs = (double *)malloc(sizeof(double) * (size_t)M);
-    if (!xs || !vs) {
-        free(xs);
-        free(vs);
+    double *tab, *boundary;
+    int rc;
+    if (n_slices < 1 || M < 2 || M > 64 || !(b > a) || !(dt > 0.0)) return ORC_BAD_ARG;
+    tab = (double *)malloc(sizeof(double) * (size_t)n_slices * (size_t)M);
+    boundary = (double *)malloc(sizeof(double) * ((size_t)n_slices + 1));
+    if (!tab || !boundary) {
+        free(tab);
+        free(boundary);
         return ORC_BAD_ARG;
     }
-    L = T / (double)n_slices;
-    for (k = 0; k < M; ++k) xs[k] = cheb_node(a, b, M, k);
-    lam = y0;
-    for (j = 0; j < n_slices; ++j) {
-        /* computation phase for slice j (the map is the same on every slice of
-         * this autonomous problem, but it is built per slice as the method does) */
-        for (k = 0; k < M; ++k) vs[k] = be_interval(xs[k], L, dt, be_exact, equal_substeps);
-        /* communication phase */
-        lam = lagrange(xs, vs, M, lam);
-    }
-    *yT = lam;
-    free(xs);
-    free(vs);
-    return ORC_OK;
+    orc_paper_tables(T, n_slices, M, a, b, dt, be_exact, equal_substeps, tab);
+    rc = orc_paper_compose(n_slices, M, a, b, tab, y0, boundary, NULL, NULL);
+    *yT = rc == ORC_OK ? boundary[n_slices] : NAN;
+    free(tab);
+    free(boundary);
+    return rc == ORC_NONFINITE ? ORC_OK : rc;
 }
 
 int orc_paper_serial(double T, double dt, double y0, int be_exact, int equal_substeps,

@@ -107,6 +107,15 @@ int orc_method_lazy(int rhs, const double *p, int scheme, double t0, double T,
 int orc_paper_method(double T, int n_slices, int M, double a, double b,
                      double dt, double y0, int be_exact, int equal_substeps,
                      double *yT);
+/* The two phases of paper mode separately.  Nodes: the M Chebyshev extrema of
+ * [a, b], xs[k] = (a+b)/2 + (b-a)/2 cos(k pi/(M-1)), 2 <= M <= 64.  Tables:
+ * tab[j * M + k], slice j, node k.  Compose: boundary[0..N], Lagrange
+ * interpolation of row j at lambda_j (points outside [a, b] are counted). */
+int orc_paper_nodes(int M, double a, double b, double *xs);
+int orc_paper_tables(double T, int n_slices, int M, double a, double b, double dt,
+                     int be_exact, int equal_substeps, double *tab);
+int orc_paper_compose(int n_slices, int M, double a, double b, const double *tab, double y0,
+                      double *boundary, long long *n_out_of_grid, int *bad_slice);
 /* Plain backward Euler over [0, T] (no slicing, no interpolation). */
 int orc_paper_serial(double T, double dt, double y0, int be_exact,
                      int equal_substeps, double *yT);

@@ -82,3 +82,37 @@ def test_chebyshev_lagrange_converges_geometrically(orc):
     ref = orc.paper_method(0.5, 4, 16, 0.0, 2.0, 1e-4, 1.0)
     errs = [abs(orc.paper_method(0.5, 4, M, 0.0, 2.0, 1e-4, 1.0) - ref) for M in (6, 8, 10)]
     assert errs[0] > 10 * errs[1] > 100 * errs[2]
+
+
+def test_chebyshev_nodes_are_extrema_of_T(orc):
+    # mapped to [-1, 1], the nodes are where T_{M-1} = +-1, with alternating signs
+    from numpy.polynomial import chebyshev as C
+    for M, a, b in [(3, 0.0, 2.0), (6, 0.0, 2.0), (7, -1.5, 4.0)]:
+        xs = orc.paper_nodes(M, a, b)
+        u = (2 * xs - (a + b)) / (b - a)
+        vals = C.chebval(u, [0] * (M - 1) + [1])
+        np.testing.assert_allclose(np.abs(vals), 1.0, atol=1e-12)
+        assert np.all(np.sign(vals[:-1]) != np.sign(vals[1:]))
+        assert xs[0] == pytest.approx(b) and xs[-1] == pytest.approx(a, abs=1e-15)
+
+
+def test_lagrange_chain_reproduces_polynomials(orc):
+    # a row holding p(xi_k) for a polynomial of degree < M interpolates p exactly
+    M, a, b = 6, 0.0, 2.0
+    xs = orc.paper_nodes(M, a, b)
+    p = np.polynomial.Polynomial([0.3, -1.2, 0.5, 0.25, -0.1, 0.02])   # degree 5
+    for x in [0.0, 0.37, 1.5, 2.0, 2.4]:
+        r = orc.paper_compose(M, a, b, p(xs)[None, :], x)
+        assert r.status == 0 and r.yT[0] == pytest.approx(p(x), abs=1e-12)
+        assert r.n_out_of_grid == (1 if x > b else 0)
+
+
+def test_paper_tables_are_backward_euler_per_node(orc):
+    T, N, M, dt = 0.5, 4, 5, 0.01          # L / dt = 12.5: 12 steps plus a half step
+    tab = orc.paper_tables(T, N, M, 0.0, 2.0, dt)
+    xs = orc.paper_nodes(M, 0.0, 2.0)
+    for j in range(N):
+        for k in range(M):
+            assert tab[j, k] == orc.paper_serial(T / N, dt, xs[k])
+    chain = orc.paper_compose(M, 0.0, 2.0, tab, 1.0)
+    assert chain.yT[0] == orc.paper_method(T, N, M, 0.0, 2.0, dt, 1.0)

@@ -219,13 +219,98 @@ def bench_batched(args):
     }
 
 
+def bench_paper_table3(args):
+    """The nine shapes of the paper's Table 3 (sec. 4): y' = y^2 on [0, 1/2],
+    backward Euler with step dt, M Chebyshev nodes, N slices, single precision.
+    Time to solution of nv_solve (buffers already allocated), the serial CPU
+    oracle at the same dt, and a least-squares fit of the cost model."""
+    import numpy as np
+    import torch
+
+    from paper_1304_6514_amd import costmodel
+    from paper_1304_6514_amd import nv
+    from paper_1304_6514_amd.propagator import Propagator
+
+    # the paper's Table 3 rows: (T_total microseconds, speedup), Tesla C2075
+    printed = {(2.0 ** -14, 32): 193.6, (2.0 ** -14, 64): 187.5, (2.0 ** -14, 128): 208.4,
+               (2.0 ** -15, 32): 253.7, (2.0 ** -15, 64): 228.5, (2.0 ** -15, 128): 257.8,
+               (2.0 ** -16, 32): 388.3, (2.0 ** -16, 64): 338.9, (2.0 ** -16, 128): 392.0}
+    rows, fit_rows = [], []
+    ours_steps = ours_time = paper_time = 0.0
+    with Propagator("cuda:0") as p:
+        for dt, N, M in W.PAPER_TABLE3:
+            w = W.paper_model(N, M, dt, "fp32")
+            p.set_timing(True)
+            kb, kc = [], []
+            for _ in range(max(3, args.warmup)):
+                p.solve(w)
+                b_ms, c_ms = p.last_timing()
+                kb.append(b_ms)
+                kc.append(c_ms)
+            p.set_timing(False)
+            reps = max(20, args.steps)
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(reps):
+                t = time.perf_counter()
+                r = p.solve(w)
+                times.append(time.perf_counter() - t)
+            if r.status != nv.NV_OK:
+                raise RuntimeError("paper-mode solve failed")
+            t_us = 1e6 * float(np.median(times))
+            n = round(0.5 / dt)
+            rows.append({"dt": dt, "N": N, "M": M, "T_total_us": round(t_us, 2),
+                         "build_kernel_us": round(1e3 * min(kb), 2),
+                         "compose_kernel_us": round(1e3 * min(kc), 2),
+                         "error": abs(float(r.yT[0]) - 2.0),
+                         "paper_T_total_us": printed[(dt, N)],
+                         "trajectory_steps_per_s": M * n / (t_us * 1e-6)})
+            fit_rows.append((M, n, N, t_us))
+            ours_steps += M * n
+            ours_time += t_us
+            paper_time += printed[(dt, N)]
+    tau_F, tau_N, tau_K = costmodel.fit(fit_rows)
+    out = {
+        "metric": "trajectory-steps/s in propagator build; time-to-y(T) vs serial at fixed error",
+        "value": ours_steps / (ours_time * 1e-6), "unit": "trajectory-steps/s", "n_gpus": 1,
+        "steps": max(20, args.steps), "warmup": max(3, args.warmup),
+        "ms_per_step": round(ours_time / 1e3 / len(rows), 4), "higher_is_better": True,
+        "scaling": "weak", "dtype": "f32", "data": "synthetic",
+        "vs_baseline": round((ours_steps / ours_time) / (ours_steps / paper_time), 3),
+        "vs_baseline_note": "against the trajectory-steps/s derived from the paper's Table 3 "
+                            "(Tesla C2075 + Opteron, same nine shapes)",
+        "config": {"workload": "paper-table3-square-be-chebyshev", "shapes": len(rows),
+                   "parallelism": "single-gpu"},
+        "rows": rows,
+        "cost_model_fit_us": {"tau_F": tau_F, "tau_N": tau_N, "tau_K": tau_K},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle._load()
+        for row in rows:
+            t = time.perf_counter()
+            reps = 0
+            while time.perf_counter() - t < 0.05:
+                oracle.paper_serial(0.5, row["dt"], 1.0)
+                reps += 1
+            t_cpu = (time.perf_counter() - t) / reps * 1e6
+            row["serial_cpu_us"] = round(t_cpu, 2)
+            row["speedup_vs_serial"] = round(t_cpu / row["T_total_us"], 3)
+        out["cpu_baseline"] = {"value": sum(0.5 / r["dt"] for r in rows) /
+                               (1e-6 * sum(r["serial_cpu_us"] for r in rows)),
+                               "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": "serial backward Euler of y' = y^2 over [0, 1/2] at "
+                                         "each of the nine dt (FP64, one thread)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="forced_cubic",
-                    choices=sorted(WORKLOADS) + ["batched"])
+                    choices=sorted(WORKLOADS) + ["batched", "paper-table3"])
     ap.add_argument("--traj-per-lane", type=int, default=0)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default=None,
                     help="override the workload's build precision")
@@ -259,6 +344,9 @@ def main():
     nv.load()
     if args.workload == "batched":
         print(json.dumps(bench_batched(args)), flush=True)
+        return
+    if args.workload == "paper-table3":
+        print(json.dumps(bench_paper_table3(args)), flush=True)
         return
     w = WORKLOADS[args.workload]
     if args.precision:

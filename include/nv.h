@@ -59,19 +59,32 @@ typedef enum {
 } nv_rhs_id;
 
 /* Time-stepping scheme of the computation phase.  Forward Euler is the scheme
- * of the error analysis of sec. 5; classical RK4 is the default. */
-typedef enum { NV_SCHEME_RK4 = 0, NV_SCHEME_EULER = 1 } nv_scheme;
+ * of the error analysis of sec. 5; classical RK4 is the default; backward
+ * Euler is the scheme of every experiment of the paper (sec. 3, Table 1;
+ * sec. 4), each implicit step solved by one Newton step from the current value
+ * (y_{n+1} = y_n + h f(y_n) / (1 - h f'(y_n))), 1-D right-hand sides only. */
+typedef enum { NV_SCHEME_RK4 = 0, NV_SCHEME_EULER = 1, NV_SCHEME_BACKWARD_EULER = 2 } nv_scheme;
 
 /* Arithmetic of the table build.  The composition is always FP64. */
 typedef enum { NV_FP64 = 0, NV_FP32 = 1 } nv_precision;
 
 /* Interpolation of the tabulated slice maps (the "approximating function" of
  * the pseudocode):
- *   LINEAR    1-D piecewise linear (Nievergelt's own choice, sec. 5)
- *   HERMITE   1-D cubic Hermite; node slopes from the table by finite
- *             differences (centred inside, one-sided second order at the ends)
- *   BILINEAR  2-D tensor-grid bilinear                                       */
-typedef enum { NV_INTERP_LINEAR = 0, NV_INTERP_HERMITE = 1, NV_INTERP_BILINEAR = 2 } nv_interp;
+ *   LINEAR     1-D piecewise linear (Nievergelt's own choice, sec. 5)
+ *   HERMITE    1-D cubic Hermite; node slopes from the table by finite
+ *              differences (centred inside, one-sided second order at the ends)
+ *   BILINEAR   2-D tensor-grid bilinear
+ *   CHEBYSHEV  1-D Lagrange interpolation on the n Chebyshev extrema of
+ *              [lo, hi], xi_k = (lo+hi)/2 + (hi-lo)/2 cos(k pi/(n-1)),
+ *              k = 0..n-1 (sec. 3, Table 1), 2 <= n <= 64; the nodes REPLACE
+ *              the uniform grid.  phi(x) = sum_k t[k] prod_{m != k}
+ *              ((x - xi_m) / (xi_k - xi_m)), k and m ascending, in FP64.      */
+typedef enum {
+    NV_INTERP_LINEAR = 0,
+    NV_INTERP_HERMITE = 1,
+    NV_INTERP_BILINEAR = 2,
+    NV_INTERP_CHEBYSHEV = 3
+} nv_interp;
 
 /* Sample Xi_h of the initial value space (sec. 3): a uniform tensor grid with
  * endpoints included.  Axis a has n[a] >= 2 points
@@ -101,6 +114,11 @@ typedef struct {
     int solve_chunks;         /* nv_solve: slice chunks the build is cut into so that the
                                  composition of chunk c overlaps the build of chunk c+1;
                                  0 = chosen by the library, 1 = no overlap */
+    double dt;                /* 0: steps_per_slice equal steps per slice.  > 0: steps of
+                                 dt, floor(L/dt + 1e-9) of them, plus one final step of
+                                 the remainder L - floor(..) dt when it exceeds 1e-12 L
+                                 (the paper's fixed time step, sec. 3); steps_per_slice is
+                                 then ignored.  Autonomous right-hand sides only. */
 } nv_options;
 
 /* Result details of a composition. */

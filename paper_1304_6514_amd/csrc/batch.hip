@@ -385,6 +385,8 @@ NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int co
         if (p.rhs_id == NV_RHS_FORCED_CUBIC)
             return fail(NV_ERR_UNSUPPORTED, "problem %d: batches take autonomous right-hand sides",
                         i);
+        if (p.grid.interp == NV_INTERP_CHEBYSHEV)
+            return fail(NV_ERR_UNSUPPORTED, "problem %d: batches take uniform grids", i);
         s = nv::check_problem(p.rhs_id, p.params, p.t0, p.T, p.n_slices, &p.grid,
                               p.steps_per_slice);
         if (s != NV_OK) {
@@ -400,9 +402,9 @@ NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int co
     b->precision = opt.precision;
     b->accumulation = opt.compensated;
     b->scheme = opt.scheme;
-    if (b->scheme != NV_SCHEME_RK4) {
+    if (b->scheme != NV_SCHEME_RK4 || opt.dt != 0.0) {
         delete b;
-        return fail(NV_ERR_UNSUPPORTED, "batches integrate with RK4");
+        return fail(NV_ERR_UNSUPPORTED, "batches integrate with RK4 and equal steps per slice");
     }
     const size_t elem = b->precision == NV_FP64 ? sizeof(double) : sizeof(float);
 
@@ -486,6 +488,8 @@ NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int co
         a.lo1 = D == 2 ? p.grid.lo[1] : 0.0;
         a.dxi1 = D == 2 ? (p.grid.hi[1] - p.grid.lo[1]) / double(p.grid.n[1] - 1) : 0.0;
         a.h = L / double(p.steps_per_slice);
+        a.h_last = 0.0;
+        a.nodes = nullptr;
         a.p0 = (p.rhs_id == NV_RHS_LINEAR || p.rhs_id == NV_RHS_VDP) ? p.params[0] : 0.0;
         a.M = points_of(p);
         a.n1 = D == 2 ? p.grid.n[1] : 1;
@@ -507,6 +511,8 @@ NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int co
         c.inv0 = double(p.grid.n[0] - 1) / (p.grid.hi[0] - p.grid.lo[0]);
         c.lo1 = a.lo1;
         c.inv1 = D == 2 ? double(p.grid.n[1] - 1) / (p.grid.hi[1] - p.grid.lo[1]) : 0.0;
+        c.hi0 = p.grid.hi[0];
+        c.nodes = nullptr;
         c.y00 = p.y0[0];
         c.y01 = D == 2 ? p.y0[1] : 0.0;
         q.rhs = p.rhs_id;

@@ -69,8 +69,14 @@ hipError_t by_p(int P, const BuildArgs &a, hipStream_t s) {
 
 template <template <class> class Rhs, class R, int A>
 hipError_t by_scheme(const BuildConfig &c, const BuildArgs &a, hipStream_t s) {
-    return c.scheme == 0 ? by_p<Rhs, R, 0, A>(c.traj_per_lane, a, s)
-                         : by_p<Rhs, R, 1, A>(c.traj_per_lane, a, s);
+    switch (c.scheme) {
+    case 0: return by_p<Rhs, R, 0, A>(c.traj_per_lane, a, s);
+    case 1: return by_p<Rhs, R, 1, A>(c.traj_per_lane, a, s);
+    case 2:
+        if constexpr (Rhs<R>::dim == 1) return by_p<Rhs, R, 2, A>(c.traj_per_lane, a, s);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <template <class> class Rhs>
@@ -87,7 +93,8 @@ hipError_t by_config(const BuildConfig &c, const BuildArgs &a, hipStream_t s) {
 }  // namespace
 
 bool build_supported(const BuildConfig &c) {
-    return c.rhs >= 0 && c.rhs <= 4 && (c.scheme == 0 || c.scheme == 1) &&
+    return c.rhs >= 0 && c.rhs <= 4 && (c.scheme >= 0 && c.scheme <= 2) &&
+           !(c.scheme == 2 && c.rhs == 3) &&
            (c.precision == 0 || c.precision == 1) &&
            (c.compensated >= 0 && c.compensated <= 2) &&
            (c.traj_per_lane == 1 || c.traj_per_lane == 2 || c.traj_per_lane == 4);

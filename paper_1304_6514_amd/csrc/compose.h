@@ -133,5 +133,86 @@ __device__ inline void compose_range(const ComposeArgs &a) {
     if (a.j_end == a.n_slices || bad_slice >= 0) a.status->done = 1;
 }
 
+// The chain with Lagrange interpolation on Chebyshev nodes (paper mode), run
+// by one whole wave of 64 lanes: for each slice the M*M factors
+// (x - xi_m) / (xi_k - xi_m) are independent once lambda_j is known and are
+// computed one per lane; lane k then multiplies its node value by its factors
+// in ascending m, and every lane sums the M terms in ascending k -- exactly the
+// operation sequence of the written rule, so the result is the same to the bit.
+constexpr int kMaxLagrange = 64;
+
+template <class T>
+__device__ inline void compose_range_lagrange(const ComposeArgs &a) {
+#pragma clang fp contract(off)
+    __shared__ double fac[kMaxLagrange * kMaxLagrange];
+    __shared__ double terms[kMaxLagrange];
+    __shared__ double xs[kMaxLagrange];       // the nodes, read from memory once
+    __shared__ int row_bad;
+    const int lane = int(threadIdx.x);
+    const int M = a.n0;
+    for (int k = lane; k < M; k += int(blockDim.x)) xs[k] = a.nodes[k];
+    __syncthreads();
+    const T *tab0 = static_cast<const T *>(a.tab0);
+    double lam;
+    if (a.j_begin == 0) {
+        lam = a.y00;
+        if (lane == 0) {
+            a.boundary[0] = lam;
+            a.status->n_out_of_grid = 0;
+            a.status->bad_slice = -1;
+            a.status->done = 0;
+        }
+    } else {
+        if (a.status->bad_slice >= 0) return;     // an earlier range already failed
+        lam = a.boundary[a.j_begin];
+    }
+    long long oog = 0;
+    int bad_slice = -1;
+    // a row of the table does not depend on lambda: lane k holds node k's
+    // value of the current slice and loads the next slice's while it works
+    double v_next = (lane < M && a.j_begin < a.j_end)
+                        ? double(tab0[(long long)a.j_begin * M + lane]) : 0.0;
+    for (int j = a.j_begin; j < a.j_end; ++j) {
+        const double vk = v_next;
+        if (lane < M && j + 1 < a.j_end) v_next = double(tab0[(long long)(j + 1) * M + lane]);
+        if (!finite(lam)) {
+            bad_slice = j;
+            break;
+        }
+        if (lane == 0) row_bad = 0;
+        // the diagonal factor is exactly 1: multiplying by it changes nothing,
+        // and the product loop below needs no branch
+        for (int idx = lane; idx < M * M; idx += int(blockDim.x)) {
+            const int k = idx / M, m = idx - k * M;
+            fac[idx] = k == m ? 1.0 : (lam - xs[m]) / (xs[k] - xs[m]);
+        }
+        __syncthreads();
+        if (lane < M) {
+            if (!finite(vk)) row_bad = 1;
+            double term = vk;
+#pragma unroll 8
+            for (int m = 0; m < M; ++m) term *= fac[lane * M + m];
+            terms[lane] = term;
+        }
+        __syncthreads();
+        if (row_bad) {
+            bad_slice = j;
+            break;
+        }
+        oog += (lam < a.lo0 || lam > a.hi0) ? 1 : 0;
+        double sum = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < M; ++k) sum += terms[k];
+        lam = sum;
+        if (lane == 0) a.boundary[j + 1] = lam;
+        __syncthreads();      // factors and terms are rewritten for the next slice
+    }
+    if (lane == 0) {
+        a.status->n_out_of_grid += oog;
+        if (bad_slice >= 0) a.status->bad_slice = bad_slice;
+        if (a.j_end == a.n_slices || bad_slice >= 0) a.status->done = 1;
+    }
+}
+
 }  // namespace dev
 }  // namespace nv

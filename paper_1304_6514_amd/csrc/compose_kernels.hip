@@ -17,8 +17,13 @@ using namespace dev;
 
 template <class T, int Interp>
 __global__ void compose_kernel(ComposeArgs a) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    compose_range<T, Interp>(a);
+    if (blockIdx.x != 0) return;
+    if constexpr (Interp == 3) {
+        compose_range_lagrange<T>(a);       // the whole wave
+    } else {
+        if (threadIdx.x != 0) return;
+        compose_range<T, Interp>(a);
+    }
 }
 
 __global__ void locate_kernel(double lo, double inv, int n, const double *x, long long count,
@@ -41,6 +46,7 @@ hipError_t launch_compose(int interp, int precision, const ComposeArgs &a, hipSt
         case 0: hipLaunchKernelGGL((compose_kernel<double, 0>), grid, block, 0, s, a); break;
         case 1: hipLaunchKernelGGL((compose_kernel<double, 1>), grid, block, 0, s, a); break;
         case 2: hipLaunchKernelGGL((compose_kernel<double, 2>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((compose_kernel<double, 3>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -48,6 +54,7 @@ hipError_t launch_compose(int interp, int precision, const ComposeArgs &a, hipSt
         case 0: hipLaunchKernelGGL((compose_kernel<float, 0>), grid, block, 0, s, a); break;
         case 1: hipLaunchKernelGGL((compose_kernel<float, 1>), grid, block, 0, s, a); break;
         case 2: hipLaunchKernelGGL((compose_kernel<float, 2>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((compose_kernel<float, 3>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
         }
     }

@@ -20,6 +20,7 @@ struct RhsLinear {              // y' = p y
     static constexpr int dim = 1;
     static constexpr bool forced = false;
     __device__ static void f(R, R p, const R *y, R *k) { k[0] = p * y[0]; }
+    __device__ static R df(R, R p, R) { return p; }
 };
 
 template <class R>
@@ -27,6 +28,7 @@ struct RhsLogistic {            // y' = y (1 - y)
     static constexpr int dim = 1;
     static constexpr bool forced = false;
     __device__ static void f(R, R, const R *y, R *k) { k[0] = y[0] - y[0] * y[0]; }
+    __device__ static R df(R, R, R y) { return R(1) - R(2) * y; }
 };
 
 template <class R>
@@ -37,6 +39,7 @@ struct RhsForcedCubic {         // y' = sin(3t) - y^3, F = sin(3t)
         R y2 = y[0] * y[0];
         k[0] = F - y2 * y[0];
     }
+    __device__ static R df(R, R, R y) { return R(-3) * y * y; }
 };
 
 template <class R>
@@ -55,6 +58,7 @@ struct RhsSquare {              // y' = y^2
     static constexpr int dim = 1;
     static constexpr bool forced = false;
     __device__ static void f(R, R, const R *y, R *k) { k[0] = y[0] * y[0]; }
+    __device__ static R df(R, R, R y) { return R(2) * y; }
 };
 
 // The forcing function of non-autonomous right-hand sides.
@@ -76,7 +80,7 @@ template <class R, int D>
 __device__ inline void grid_point(const BuildArgs &a, long long k, R *y) {
 #pragma clang fp contract(off)
     if constexpr (D == 1) {
-        y[0] = R(a.lo0 + double(k) * a.dxi0);
+        y[0] = a.nodes ? R(a.nodes[k]) : R(a.lo0 + double(k) * a.dxi0);
     } else {
         const unsigned kk = unsigned(k), n1 = unsigned(a.n1);
         const unsigned k0 = kk / n1, k1 = kk - k0 * n1;
@@ -111,6 +115,17 @@ __device__ inline void step(R (&y)[P][Rhs::dim], R (&c)[P][Rhs::dim], R (&z)[P][
             Rhs::f(Fa, p, x, k1);
 #pragma unroll
             for (int d = 0; d < D; ++d) dy[d] = h * k1[d];
+        } else if constexpr (Scheme == 2) {          // backward Euler, one Newton step
+            static_assert(D == 1, "backward Euler is built for 1-D right-hand sides");
+            Rhs::f(Fc, p, x, k1);
+            const R den = R(1) - h * Rhs::df(Fc, p, x[0]);
+            if constexpr (sizeof(R) == 4)
+                // FP32: the hardware reciprocal (about 1 ulp) instead of the
+                // correctly rounded division sequence, which would dominate the
+                // latency of this strictly sequential step
+                dy[0] = (h * k1[0]) * __builtin_amdgcn_rcpf(den);
+            else
+                dy[0] = (h * k1[0]) / den;
         } else {                                     // classical RK4
             Rhs::f(Fa, p, x, k1);
 #pragma unroll
@@ -191,6 +206,13 @@ __device__ inline void build_tile(const BuildArgs &a, int j, int tile) {
                 step<Rhs, R, Scheme, A, P>(y, c, z, R(0), R(0), R(0), h, h2, h6, p);
         }
         end_block<D, R, A, P>(y, c, z);
+    }
+    if (a.h_last > 0.0) {      // the shorter final step of a fixed-step slice
+        if constexpr (!Rhs::forced) {
+            step<Rhs, R, Scheme, A, P>(y, c, z, R(0), R(0), R(0), R(a.h_last),
+                                       R(a.h_last * 0.5), R(a.h_last / 6.0), p);
+            end_block<D, R, A, P>(y, c, z);
+        }
     }
 
     R *t0 = static_cast<R *>(a.tab0) + (long long)j * a.M;

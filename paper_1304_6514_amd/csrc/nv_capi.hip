@@ -40,6 +40,7 @@ using nv::fail;
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxChunks = 64;
+constexpr int kMaxChebyshev = 64;
 // automatic chunking of nv_solve: about this many workgroups per build launch
 // (half a round of 256 CUs x 8 resident workgroups; consecutive chunks overlap)
 constexpr long long kBlocksPerChunk = 1024;
@@ -66,6 +67,7 @@ nv_options default_options() {
     o.traj_per_lane = 0;
     o.stream = nullptr;
     o.solve_chunks = 0;
+    o.dt = 0.0;
     return o;
 }
 
@@ -80,8 +82,11 @@ int effective_p(const nv_options &o, long long trajectories) {
 
 nv_status check_options(const nv_options *o) {
     if (!o) return fail(NV_ERR_INVALID_ARG, "options pointer is NULL");
-    if (o->scheme != NV_SCHEME_RK4 && o->scheme != NV_SCHEME_EULER)
+    if (o->scheme != NV_SCHEME_RK4 && o->scheme != NV_SCHEME_EULER &&
+        o->scheme != NV_SCHEME_BACKWARD_EULER)
         return fail(NV_ERR_INVALID_ARG, "unknown scheme %d", o->scheme);
+    if (!std::isfinite(o->dt) || o->dt < 0.0)
+        return fail(NV_ERR_INVALID_ARG, "dt must be finite and >= 0");
     if (o->precision != NV_FP64 && o->precision != NV_FP32)
         return fail(NV_ERR_INVALID_ARG, "unknown precision %d", o->precision);
     if (o->compensated < 0 || o->compensated > 2)
@@ -105,6 +110,7 @@ struct Plan {
     size_t nonfinite_off = 0;
     size_t boundary_off = 0, boundary_bytes = 0;
     size_t status_off = 0;
+    size_t nodes_off = 0;
     size_t work_bytes = 0;
     int tiles_per_slice = 0;
     long long total_blocks = 0;
@@ -116,8 +122,15 @@ nv_status make_plan(int rhs, int n_slices, const nv_ic_grid *g, int steps,
     if (rhs_dim(rhs) == 0) return fail(NV_ERR_INVALID_ARG, "unknown rhs_id %d", rhs);
     if (!g) return fail(NV_ERR_INVALID_ARG, "ic_grid is NULL");
     if (n_slices < 1) return fail(NV_ERR_INVALID_ARG, "n_slices must be >= 1 (got %d)", n_slices);
-    if (steps < 1)
+    if (o.dt == 0.0 && steps < 1)
         return fail(NV_ERR_INVALID_ARG, "steps_per_slice must be >= 1 (got %d)", steps);
+    if (o.dt > 0.0) {
+        if (rhs_forced(rhs))
+            return fail(NV_ERR_INVALID_ARG, "a fixed step dt needs an autonomous right-hand side");
+        steps = 0;                                 // counted per slice from dt
+    }
+    if (o.scheme == NV_SCHEME_BACKWARD_EULER && rhs_dim(rhs) != 1)
+        return fail(NV_ERR_UNSUPPORTED, "backward Euler is built for 1-D right-hand sides");
     if (g->dim != rhs_dim(rhs))
         return fail(NV_ERR_INVALID_ARG, "grid dim %d does not match the rhs dimension %d",
                     g->dim, rhs_dim(rhs));
@@ -140,6 +153,12 @@ nv_status make_plan(int rhs, int n_slices, const nv_ic_grid *g, int steps,
         break;
     case NV_INTERP_BILINEAR:
         if (g->dim != 2) return fail(NV_ERR_INVALID_ARG, "BILINEAR interpolation needs dim 2");
+        break;
+    case NV_INTERP_CHEBYSHEV:
+        if (g->dim != 1) return fail(NV_ERR_INVALID_ARG, "CHEBYSHEV interpolation needs dim 1");
+        if (g->n[0] > kMaxChebyshev)
+            return fail(NV_ERR_INVALID_ARG, "CHEBYSHEV interpolation takes at most %d nodes",
+                        kMaxChebyshev);
         break;
     default:
         return fail(NV_ERR_INVALID_ARG, "unknown interpolation %d", g->interp);
@@ -167,6 +186,8 @@ nv_status make_plan(int rhs, int n_slices, const nv_ic_grid *g, int steps,
     off = align_up(off + p->boundary_bytes);
     p->status_off = off;
     off = align_up(off + sizeof(nv::ComposeStatus));
+    p->nodes_off = off;
+    off = align_up(off + kMaxChebyshev * sizeof(double));
     p->work_bytes = off;
     p->tiles_per_slice = int(tiles);
     p->total_blocks = blocks;
@@ -199,6 +220,11 @@ struct nv_ctx {
     bool work_owned = true;
     // pinned staging for the composition's outputs
     void *host_stage = nullptr;
+    double nodes_host[kMaxChebyshev] = {};
+    // what the scratch's node array holds (uploaded once per grid and buffer)
+    const void *nodes_dev = nullptr;
+    int nodes_n = 0;
+    double nodes_lo = 0.0, nodes_hi = 0.0;
     size_t host_stage_cap = 0;
     // last build
     bool built = false;
@@ -272,6 +298,16 @@ nv_status ensure_events(nv_ctx *c) {
 
 char *work_at(const nv_ctx *c, size_t off) { return static_cast<char *>(c->work) + off; }
 
+// The n Chebyshev extrema of [a, b] (sec. 3, Table 1), one rounding per
+// operation: (a+b)/2 + (b-a)/2 cos(k pi/(n-1)), k = 0..n-1.
+void chebyshev_nodes(int n, double a, double b, double *xs) {
+#pragma clang fp contract(off)
+    const double pi = 3.14159265358979323846;
+    for (int k = 0; k < n; ++k)
+        xs[k] = (a + b) / 2.0 + (b - a) / 2.0 * std::cos(double(k) * pi / double(n - 1));
+}
+
+
 // Checks, buffers, the pre-launch kernels (counter reset, forcing values) on
 // the context's stream and the integration kernel's arguments; records the
 // build's description in the context (marked built by the caller once the
@@ -303,8 +339,10 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
 
     s = ensure_device(&ctx->tables, &ctx->tables_cap, ctx->tables_owned, p.table_bytes, "table");
     if (s != NV_OK) return s;
+    const size_t work_cap_before = ctx->work_cap;
     s = ensure_device(&ctx->work, &ctx->work_cap, ctx->work_owned, p.work_bytes, "work");
     if (s != NV_OK) return s;
+    if (ctx->work_cap != work_cap_before) ctx->nodes_dev = nullptr;   // a new allocation
     s = ensure_host_stage(ctx, p.status_off - p.boundary_off + sizeof(nv::ComposeStatus));
     if (s != NV_OK) return s;
     if (ctx->timing) {
@@ -313,9 +351,21 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
     }
 
     hipStream_t st = stream_of(ctx);
-    // slice partition (sec. 3): L = (T - t0)/N, T_j = t0 + j L, h = L / S
+    // slice partition (sec. 3): L = (T - t0)/N, T_j = t0 + j L; either S equal
+    // steps h = L / S, or steps of the fixed dt plus one shorter final step
     const double L = (T - t0) / double(n_slices);
-    const double h = L / double(steps_per_slice);
+    double h, h_last = 0.0;
+    int S = steps_per_slice;
+    if (ctx->opt.dt > 0.0) {
+        const double n = std::floor(L / ctx->opt.dt + 1e-9);
+        if (n > 2147483647.0) return fail(NV_ERR_INVALID_ARG, "dt gives too many steps");
+        S = int(n);
+        h = ctx->opt.dt;
+        const double rem = L - double(S) * ctx->opt.dt;
+        if (rem > 1e-12 * L) h_last = rem;
+    } else {
+        h = L / double(steps_per_slice);
+    }
 
     nv::BuildArgs &a = pb->args;
     a = nv::BuildArgs{};
@@ -328,16 +378,32 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
     a.lo1 = p.dim == 2 ? grid->lo[1] : 0.0;
     a.dxi1 = p.dim == 2 ? (grid->hi[1] - grid->lo[1]) / double(grid->n[1] - 1) : 0.0;
     a.h = h;
+    a.h_last = h_last;
     a.p0 = p0;
+    a.nodes = nullptr;
     a.M = p.M;
     a.n1 = p.dim == 2 ? grid->n[1] : 1;
     a.n_slices = n_slices;
     a.slice0 = 0;
-    a.steps = steps_per_slice;
+    a.steps = S;
     a.tiles_per_slice = p.tiles_per_slice;
     a.total_blocks = int(p.total_blocks);
     pb->cfg = cfg;
 
+    if (grid->interp == NV_INTERP_CHEBYSHEV) {
+        double *dn = reinterpret_cast<double *>(work_at(ctx, p.nodes_off));
+        if (ctx->nodes_dev != dn || ctx->nodes_n != grid->n[0] ||
+            ctx->nodes_lo != grid->lo[0] || ctx->nodes_hi != grid->hi[0]) {
+            chebyshev_nodes(grid->n[0], grid->lo[0], grid->hi[0], ctx->nodes_host);
+            NV_HIP(hipMemcpyAsync(dn, ctx->nodes_host, size_t(grid->n[0]) * sizeof(double),
+                                  hipMemcpyHostToDevice, st));
+            ctx->nodes_dev = dn;
+            ctx->nodes_n = grid->n[0];
+            ctx->nodes_lo = grid->lo[0];
+            ctx->nodes_hi = grid->hi[0];
+        }
+        a.nodes = dn;
+    }
     NV_HIP(nv::launch_fill_u32(a.nonfinite, n_slices, 0u, st));
     if (a.forcing)
         NV_HIP(nv::launch_forcing(rhs_id, ctx->opt.precision, work_at(ctx, p.forcing_off),
@@ -370,6 +436,10 @@ nv::ComposeArgs compose_args(const nv_ctx *ctx, const double *y0, int j0, int j1
     a.inv0 = double(g.n[0] - 1) / (g.hi[0] - g.lo[0]);
     a.lo1 = p.dim == 2 ? g.lo[1] : 0.0;
     a.inv1 = p.dim == 2 ? double(g.n[1] - 1) / (g.hi[1] - g.lo[1]) : 0.0;
+    a.hi0 = g.hi[0];
+    a.nodes = g.interp == NV_INTERP_CHEBYSHEV
+                  ? reinterpret_cast<const double *>(work_at(ctx, p.nodes_off))
+                  : nullptr;
     a.y00 = y0[0];
     a.y01 = p.dim == 2 ? y0[1] : 0.0;
     return a;
@@ -473,6 +543,7 @@ NV_API nv_status nv_set_buffers(nv_ctx *ctx, void *tables_dev, size_t table_byte
     if (ctx->tables_owned && ctx->tables) NV_HIP(hipFree(ctx->tables));
     if (ctx->work_owned && ctx->work) NV_HIP(hipFree(ctx->work));
     ctx->built = false;
+    ctx->nodes_dev = nullptr;
     if (tables_dev) {
         ctx->tables = tables_dev;
         ctx->tables_cap = table_bytes;
@@ -539,10 +610,6 @@ NV_API nv_status nv_solve(nv_ctx *ctx, int rhs_id, const double *params, double 
     PreparedBuild pb;
     nv_status s = prepare_build(ctx, rhs_id, params, t0, T, n_slices, grid, steps_per_slice, &pb);
     if (s != NV_OK) return s;
-    if (!ctx->aux) NV_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
-    if (!ctx->aux2) NV_HIP(hipStreamCreateWithFlags(&ctx->aux2, hipStreamNonBlocking));
-    if (!ctx->ready_ev) NV_HIP(hipEventCreateWithFlags(&ctx->ready_ev, hipEventDisableTiming));
-
     // chunks of whole slices
     int chunks = ctx->opt.solve_chunks;
     if (chunks == 0) {
@@ -552,6 +619,28 @@ NV_API nv_status nv_solve(nv_ctx *ctx, int rhs_id, const double *params, double 
     if (chunks > n_slices) chunks = n_slices;
     const int per = (n_slices + chunks - 1) / chunks;
     chunks = (n_slices + per - 1) / per;
+
+    if (chunks == 1) {
+        // nothing to overlap: build and compose back to back on the context's
+        // stream, without the second streams and their events
+        hipStream_t st = stream_of(ctx);
+        ctx->build_timed = ctx->compose_timed = ctx->solve_timed = false;
+        if (ctx->timing) NV_HIP(hipEventRecord(ctx->ev[0], st));
+        NV_HIP(nv::launch_build(pb.cfg, pb.args, st));
+        if (ctx->timing) NV_HIP(hipEventRecord(ctx->ev[1], st));
+        NV_HIP(nv::launch_compose(ctx->grid.interp, ctx->precision,
+                                  compose_args(ctx, y0, 0, n_slices), st));
+        if (ctx->timing) {
+            NV_HIP(hipEventRecord(ctx->ev[3], st));
+            ctx->build_timed = ctx->compose_timed = ctx->solve_timed = true;
+        }
+        ctx->built = true;
+        return finish_compose(ctx, st, yT, boundary, info, 1);
+    }
+
+    if (!ctx->aux) NV_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    if (!ctx->aux2) NV_HIP(hipStreamCreateWithFlags(&ctx->aux2, hipStreamNonBlocking));
+    if (!ctx->ready_ev) NV_HIP(hipEventCreateWithFlags(&ctx->ready_ev, hipEventDisableTiming));
     for (int c = 0; c < chunks; ++c)
         if (!ctx->chunk_ev[c])
             NV_HIP(hipEventCreateWithFlags(&ctx->chunk_ev[c], hipEventDisableTiming));

@@ -22,7 +22,9 @@ struct BuildArgs {
     double lo0, dxi0;         // axis 0: xi = lo0 + k0 * dxi0
     double lo1, dxi1;         // axis 1 (2-D)
     double h;                 // step
+    double h_last;            // > 0: one more step of this size after the `steps` steps
     double p0;                // right-hand side parameter
+    const double *nodes;      // Chebyshev nodes of axis 0 (replace lo0 + k dxi0), or null
     long long M;              // points per slice
     int n1;                   // points on axis 1 (1 for 1-D)
     int n_slices;             // slices of the whole build (forcing row count)
@@ -58,6 +60,8 @@ struct ComposeArgs {
                               // j_begin == 0, else read from boundary
     int n0, n1;
     double lo0, inv0, lo1, inv1;   // inv = (n-1)/(hi-lo), computed on the host
+    double hi0;                    // Chebyshev: the interval's upper end
+    const double *nodes;           // Chebyshev nodes (Lagrange lookup), or null
     double y00, y01;
 };
 

@@ -25,16 +25,16 @@ NV_ERR_BUFFER_TOO_SMALL = -7
 # nv_rhs_id
 NV_RHS_LINEAR, NV_RHS_LOGISTIC, NV_RHS_FORCED_CUBIC, NV_RHS_VDP, NV_RHS_SQUARE = range(5)
 # nv_scheme, nv_precision, nv_interp
-NV_SCHEME_RK4, NV_SCHEME_EULER = 0, 1
+NV_SCHEME_RK4, NV_SCHEME_EULER, NV_SCHEME_BACKWARD_EULER = 0, 1, 2
 NV_FP64, NV_FP32 = 0, 1
-NV_INTERP_LINEAR, NV_INTERP_HERMITE, NV_INTERP_BILINEAR = 0, 1, 2
+NV_INTERP_LINEAR, NV_INTERP_HERMITE, NV_INTERP_BILINEAR, NV_INTERP_CHEBYSHEV = 0, 1, 2, 3
 
 RHS_IDS = {"linear": NV_RHS_LINEAR, "logistic": NV_RHS_LOGISTIC,
            "forced_cubic": NV_RHS_FORCED_CUBIC, "vdp": NV_RHS_VDP, "square": NV_RHS_SQUARE}
-SCHEMES = {"rk4": NV_SCHEME_RK4, "euler": NV_SCHEME_EULER}
+SCHEMES = {"rk4": NV_SCHEME_RK4, "euler": NV_SCHEME_EULER, "be": NV_SCHEME_BACKWARD_EULER}
 PRECISIONS = {"fp64": NV_FP64, "fp32": NV_FP32}
 INTERPS = {"linear": NV_INTERP_LINEAR, "hermite": NV_INTERP_HERMITE,
-           "bilinear": NV_INTERP_BILINEAR}
+           "bilinear": NV_INTERP_BILINEAR, "chebyshev": NV_INTERP_CHEBYSHEV}
 
 
 class nv_ic_grid(ctypes.Structure):
@@ -45,7 +45,8 @@ class nv_ic_grid(ctypes.Structure):
 class nv_options(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int), ("precision", ctypes.c_int),
                 ("compensated", ctypes.c_int), ("traj_per_lane", ctypes.c_int),
-                ("stream", ctypes.c_void_p), ("solve_chunks", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("solve_chunks", ctypes.c_int),
+                ("dt", ctypes.c_double)]
 
 
 class nv_compose_info(ctypes.Structure):
@@ -159,8 +160,8 @@ def make_grid(n, lo, hi, interp) -> nv_ic_grid:
     return g
 
 
-def make_options(scheme="rk4", precision="fp64", compensated=1, traj_per_lane=0,
-                 stream=None, solve_chunks=0) -> nv_options:
+def make_options(scheme="rk4", precision="fp64", compensated=2, traj_per_lane=0,
+                 stream=None, solve_chunks=0, dt=0.0) -> nv_options:
     o = nv_options()
     o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -168,6 +169,7 @@ def make_options(scheme="rk4", precision="fp64", compensated=1, traj_per_lane=0,
     o.traj_per_lane = int(traj_per_lane)
     o.stream = stream
     o.solve_chunks = int(solve_chunks)
+    o.dt = float(dt)
     return o
 
 

@@ -64,7 +64,7 @@ class Propagator:
     # -- helpers -------------------------------------------------------------
     def options(self, w: Workload) -> nv.nv_options:
         return nv.make_options(w.scheme, w.precision, self.compensated, self.traj_per_lane,
-                               self.stream.cuda_stream, self.solve_chunks)
+                               self.stream.cuda_stream, self.solve_chunks, w.dt)
 
     @staticmethod
     def grid(w: Workload) -> nv.nv_ic_grid:
@@ -82,12 +82,16 @@ class Propagator:
 
     # -- the two phases --------------------------------------------------------
     def _prepare(self, w: Workload):
+        # options, grid and buffer sizes are set once per workload
+        if getattr(self, "_prepared_for", None) is w:
+            return self._prepared
         opt = self.options(w)
         nv.nv_set_options(self.ctx, opt)
         g = self.grid(w)
         rhs = nv.RHS_IDS[w.rhs]
         tb, wb = nv.nv_required_bytes(rhs, w.n_slices, g, w.steps_per_slice, opt)
         self._ensure_buffers(tb, wb)
+        self._prepared_for, self._prepared = w, (g, rhs)
         return g, rhs
 
     def build(self, w: Workload, params=None):

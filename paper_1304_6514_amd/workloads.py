@@ -32,8 +32,9 @@ class Workload:
     steps_per_slice: int
     y0: tuple
     precision: str          # "fp64" or "fp32" (the table build's arithmetic)
-    interp: str             # "linear", "hermite" or "bilinear"
-    scheme: str = "rk4"
+    interp: str             # "linear", "hermite", "bilinear" or "chebyshev"
+    scheme: str = "rk4"     # "rk4", "euler" or "be" (backward Euler)
+    dt: float = 0.0         # > 0: fixed step dt per slice (plus a shorter last step)
 
     @property
     def dim(self) -> int:
@@ -157,3 +158,19 @@ def batched_problems(count: int = 96, seed: int = 3, scale: float = 1.0):
                             n_slices=n_slices, grid_n=grid_n, grid_lo=lo, grid_hi=hi,
                             steps_per_slice=steps, y0=y0, precision="fp32", interp=interp))
     return out
+
+
+def paper_model(n_slices: int, M: int, dt: float, precision: str = "fp64") -> Workload:
+    """The model problem of sec. 3 as the paper runs it: y' = y^2, y(0) = 1 on
+    [0, 1/2], backward Euler with step dt, Lagrange on the M Chebyshev extrema
+    of [0, 2] (Tables 1 to 4)."""
+    return Workload(name=f"paper-square-be-{precision}-{n_slices}sl-{M}cheb-dt{dt:g}",
+                    rhs="square", params=(), t0=0.0, T=0.5, n_slices=n_slices, grid_n=(M,),
+                    grid_lo=(0.0,), grid_hi=(2.0,), steps_per_slice=1, y0=(1.0,),
+                    precision=precision, interp="chebyshev", scheme="be", dt=dt)
+
+
+# Table 3 of the paper (sec. 4): dt in {2^-14, 2^-15, 2^-16} with M = 4, 5, 7
+# Chebyshev nodes, N in {32, 64, 128} slices, single precision.
+PAPER_TABLE3 = [(dt, n, M) for dt, M in ((2.0 ** -14, 4), (2.0 ** -15, 5), (2.0 ** -16, 7))
+                for n in (32, 64, 128)]

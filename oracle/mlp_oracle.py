@@ -1,0 +1,169 @@
+"""Plain FP64 oracle of the learned slice-map surrogate.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no code
+with the GPU library.
+
+The surrogate replaces the table lookup of the sequential pass (sec. 3: the
+composition lambda_{j+1} = phi^j(lambda_j)) by a small network that learns the
+slice map from the endpoints the computation phase tabulates.  The network is a
+multilayer perceptron
+
+    u   = (x - shift) * scale                x = (y1, y2, slice start time, mu)
+    a1  = gelu(W1 u  + b1)                   W1: 128 x 4
+    a2  = gelu(W2 a1 + b2)                   W2: 128 x 128
+    a3  = gelu(W3 a2 + b3)                   W3: 128 x 128
+    out = W4 a3 + b4                         W4: 2 x 128
+
+with the exact GELU, gelu(z) = z Phi(z), Phi the standard normal distribution
+function.  Its output is the slice displacement in units of ``out_scale``:
+phi^j(y) ~ y + out_scale * out.  The training loss is the mean over samples of
+the squared error summed over the two outputs; the optimiser is Adam (Kingma
+and Ba, "Adam: a method for stochastic optimization", Algorithm 1).
+
+Flat parameter order: W1 (row-major, out x in), b1, W2, b2, W3, b3, W4, b4;
+33,922 numbers.
+
+``emulate_bf16=True`` rounds to bfloat16 at the points where the GPU kernels
+feed their matrix cores (inputs of the two 128 x 128 layers, their weights, the
+back-propagated errors and the operands of every weight-gradient sum), so that
+both sides take the same roundings; everything else stays FP64.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import erf
+
+IN, WIDTH, OUT = 4, 128, 2
+SHAPES = (("W1", (WIDTH, IN)), ("b1", (WIDTH,)), ("W2", (WIDTH, WIDTH)), ("b2", (WIDTH,)),
+          ("W3", (WIDTH, WIDTH)), ("b3", (WIDTH,)), ("W4", (OUT, WIDTH)), ("b4", (OUT,)))
+N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
+
+
+def unflatten(flat):
+    """Flat parameter vector -> dict of FP64 arrays (copies)."""
+    flat = np.asarray(flat, dtype=np.float64)
+    if flat.size != N_PARAMS:
+        raise ValueError(f"expected {N_PARAMS} parameters, got {flat.size}")
+    out, off = {}, 0
+    for name, shape in SHAPES:
+        n = int(np.prod(shape))
+        out[name] = flat[off:off + n].reshape(shape).copy()
+        off += n
+    return out
+
+
+def flatten(p) -> np.ndarray:
+    return np.concatenate([np.asarray(p[name], dtype=np.float64).ravel() for name, _ in SHAPES])
+
+
+def bf16(x):
+    """Round to the nearest bfloat16 (ties to even), through binary32 first, as a
+    float-to-bfloat16 conversion of a binary32 value does.  Returns FP64."""
+    f = np.asarray(x, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    nan = np.isnan(f)
+    out = (r & 0xFFFFFFFF).astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(nan, np.nan, out)
+
+
+def gelu(z):
+    """gelu(z) = z Phi(z), Phi(z) = (1 + erf(z / sqrt 2)) / 2."""
+    return z * 0.5 * (1.0 + erf(z / math.sqrt(2.0)))
+
+
+def gelu_prime(z):
+    """d/dz gelu = Phi(z) + z phi(z), phi the standard normal density."""
+    return 0.5 * (1.0 + erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+
+
+def normalise(x, shift, scale):
+    """x: (n, 4) raw inputs -> u = (x - shift) * scale."""
+    return (np.asarray(x, np.float64) - np.asarray(shift, np.float64)) * np.asarray(scale, np.float64)
+
+
+def forward(params, x, shift, scale, emulate_bf16=False):
+    """Network output (n, 2) and the intermediate values of the pass."""
+    p = params if isinstance(params, dict) else unflatten(params)
+    r = bf16 if emulate_bf16 else (lambda v: v)
+    u = normalise(x, shift, scale)
+    z1 = u @ p["W1"].T + p["b1"]
+    a1 = gelu(z1)
+    h1 = r(a1)
+    z2 = h1 @ r(p["W2"]).T + p["b2"]
+    a2 = gelu(z2)
+    h2 = r(a2)
+    z3 = h2 @ r(p["W3"]).T + p["b3"]
+    a3 = gelu(z3)
+    out = a3 @ p["W4"].T + p["b4"]
+    cache = dict(u=u, z1=z1, h1=h1, z2=z2, h2=h2, z3=z3, a3=a3, out=out)
+    return out, cache
+
+
+def loss_and_grad(params, x, target, shift, scale, emulate_bf16=False):
+    """Loss = mean over the n samples of sum_c (out_c - target_c)^2, and its
+    gradient by the chain rule, layer by layer from the output back."""
+    p = params if isinstance(params, dict) else unflatten(params)
+    r = bf16 if emulate_bf16 else (lambda v: v)
+    out, c = forward(p, x, shift, scale, emulate_bf16)
+    n = out.shape[0]
+    err = out - np.asarray(target, np.float64)
+    loss = float(np.sum(err * err) / n)
+    dout = 2.0 * err / n                                   # dL/d out
+    g = {}
+    dq = r(dout)
+    g["W4"] = dq.T @ r(c["a3"])
+    g["b4"] = dq.sum(axis=0)
+    d3 = (dout @ p["W4"]) * gelu_prime(c["z3"])            # dL/d z3
+    d3q = r(d3)
+    g["W3"] = d3q.T @ c["h2"]
+    g["b3"] = d3q.sum(axis=0)
+    d2 = (d3q @ r(p["W3"])) * gelu_prime(c["z2"])
+    d2q = r(d2)
+    g["W2"] = d2q.T @ c["h1"]
+    g["b2"] = d2q.sum(axis=0)
+    d1 = (d2q @ r(p["W2"])) * gelu_prime(c["z1"])
+    d1q = r(d1)
+    g["W1"] = d1q.T @ r(c["u"])
+    g["b1"] = d1q.sum(axis=0)
+    return loss, g
+
+
+class Adam:
+    """Adam with bias correction (Kingma and Ba, Algorithm 1), FP64 state."""
+
+    def __init__(self, n, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.lr, self.beta1, self.beta2, self.eps = lr, beta1, beta2, eps
+        self.m = np.zeros(n)
+        self.v = np.zeros(n)
+        self.t = 0
+
+    def step(self, theta, grad):
+        """Return the updated parameters (theta is not modified)."""
+        self.t += 1
+        g = np.asarray(grad, np.float64)
+        self.m = self.beta1 * self.m + (1.0 - self.beta1) * g
+        self.v = self.beta2 * self.v + (1.0 - self.beta2) * g * g
+        m_hat = self.m / (1.0 - self.beta1 ** self.t)
+        v_hat = self.v / (1.0 - self.beta2 ** self.t)
+        return np.asarray(theta, np.float64) - self.lr * m_hat / (np.sqrt(v_hat) + self.eps)
+
+
+def surrogate_chain(params, shift, scale, out_scale, y0, mu, t0, T, n_slices,
+                    emulate_bf16=False):
+    """The sequential pass with the network in place of the lookup:
+    lambda_0 = y0, lambda_{j+1} = lambda_j + out_scale * net(lambda_j, T_j, mu),
+    T_j = t0 + j (T - t0) / n_slices.  Returns lambda_0 .. lambda_N, (N+1, 2)."""
+    L = (T - t0) / n_slices
+    lam = np.array(y0, np.float64)
+    bnd = [lam.copy()]
+    for j in range(n_slices):
+        x = np.array([[lam[0], lam[1], t0 + j * L, mu]])
+        out, _ = forward(params, x, shift, scale, emulate_bf16)
+        lam = lam + np.asarray(out_scale, np.float64) * out[0]
+        bnd.append(lam.copy())
+    return np.array(bnd)

@@ -1,0 +1,192 @@
+"""Pins of the surrogate network's FP64 oracle against facts fixed outside it:
+textbook values of the normal distribution, finite differences, torch's own
+GELU/linear/Adam implementations, and affine special cases."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp_oracle as mo
+
+
+def _params(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, scale, mo.N_PARAMS)
+
+
+SHIFT = np.array([0.0, 0.0, 25.0, 3.0])
+SCALE = np.array([1 / 3, 1 / 8, 1 / 25, 1 / 2])
+
+
+def _inputs(seed, n):
+    rng = np.random.default_rng(seed)
+    x = np.column_stack([rng.uniform(-3, 3, n), rng.uniform(-8, 8, n), rng.uniform(0, 50, n),
+                         rng.uniform(1, 5, n)])
+    t = rng.normal(0.0, 1.0, (n, 2))
+    return x, t
+
+
+def test_param_count_matches_architecture():
+    # 4->128, 128->128, 128->128, 128->2 with biases
+    assert mo.N_PARAMS == (4 * 128 + 128) + 2 * (128 * 128 + 128) + (128 * 2 + 2) == 33922
+    p = _params(0)
+    assert np.array_equal(mo.flatten(mo.unflatten(p)), p)
+
+
+def test_bf16_rounding_ties_and_library():
+    one = 1.0
+    # spacing of bfloat16 near 1 is 2^-7: halfway points round to the even neighbour
+    assert mo.bf16(one + 2.0 ** -8) == 1.0
+    assert mo.bf16(one + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6
+    assert mo.bf16(one + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7
+    assert mo.bf16(-2.5) == -2.5
+    rng = np.random.default_rng(1)
+    v = np.concatenate([rng.normal(0, 1, 20000), rng.normal(0, 1e-6, 2000),
+                        rng.normal(0, 1e6, 2000)]).astype(np.float32)
+    ref = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mo.bf16(v), ref)
+
+
+def test_gelu_textbook_values():
+    # Phi(1) and Phi(-1) of the standard normal distribution
+    assert mo.gelu(np.array(1.0)) == pytest.approx(0.8413447460685429, rel=1e-15)
+    assert mo.gelu(np.array(-1.0)) == pytest.approx(-0.15865525393145707, rel=1e-14)
+    assert mo.gelu(np.array(0.0)) == 0.0
+    assert mo.gelu(np.array(12.0)) == 12.0
+    assert mo.gelu_prime(np.array(0.0)) == 0.5
+    z = np.linspace(-6, 6, 97)
+    h = 1e-5
+    fd = (mo.gelu(z + h) - mo.gelu(z - h)) / (2 * h)
+    assert np.max(np.abs(fd - mo.gelu_prime(z))) < 1e-9
+    tz = torch.from_numpy(z)
+    assert np.allclose(mo.gelu(z), torch.nn.functional.gelu(tz, approximate="none").numpy(),
+                       rtol=0, atol=1e-15)
+
+
+def test_forward_matches_torch_layers():
+    p = mo.unflatten(_params(2))
+    x, _ = _inputs(3, 33)
+    out, _ = mo.forward(p, x, SHIFT, SCALE)
+    T = lambda a: torch.from_numpy(np.asarray(a, np.float64))
+    F = torch.nn.functional
+    u = (T(x) - T(SHIFT)) * T(SCALE)
+    a = F.gelu(F.linear(u, T(p["W1"]), T(p["b1"])))
+    a = F.gelu(F.linear(a, T(p["W2"]), T(p["b2"])))
+    a = F.gelu(F.linear(a, T(p["W3"]), T(p["b3"])))
+    ref = F.linear(a, T(p["W4"]), T(p["b4"])).numpy()
+    assert np.max(np.abs(out - ref)) < 1e-13
+
+
+def test_gradient_matches_central_differences():
+    flat = _params(4)
+    x, t = _inputs(5, 9)
+    loss, g = mo.loss_and_grad(flat, x, t, SHIFT, SCALE)
+    gf = mo.flatten(g)
+    rng = np.random.default_rng(6)
+    # a few coordinates of every tensor, including both ends of each
+    idx, off = [], 0
+    for _, shape in mo.SHAPES:
+        n = int(np.prod(shape))
+        idx += [off, off + n - 1] + list(off + rng.integers(0, n, 4))
+        off += n
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(flat)
+        e[i] = h
+        lp, _ = mo.loss_and_grad(flat + e, x, t, SHIFT, SCALE)
+        lm, _ = mo.loss_and_grad(flat - e, x, t, SHIFT, SCALE)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - gf[i]) <= 1e-7 * max(1.0, abs(gf[i])), (i, fd, gf[i])
+    assert loss > 0
+
+
+def test_gradient_matches_torch_autograd():
+    flat = _params(7)
+    x, t = _inputs(8, 50)
+    loss, g = mo.loss_and_grad(flat, x, t, SHIFT, SCALE)
+    p = {k: torch.tensor(v, requires_grad=True) for k, v in mo.unflatten(flat).items()}
+    F = torch.nn.functional
+    u = (torch.from_numpy(x) - torch.from_numpy(SHIFT)) * torch.from_numpy(SCALE)
+    a = F.gelu(u @ p["W1"].T + p["b1"])
+    a = F.gelu(a @ p["W2"].T + p["b2"])
+    a = F.gelu(a @ p["W3"].T + p["b3"])
+    out = a @ p["W4"].T + p["b4"]
+    L = ((out - torch.from_numpy(t)) ** 2).sum(dim=1).mean()
+    L.backward()
+    assert abs(L.item() - loss) < 1e-12
+    for k in p:
+        assert np.max(np.abs(p[k].grad.numpy() - g[k])) < 1e-12 * max(1.0, np.abs(g[k]).max())
+
+
+def test_emulated_gradient_close_to_exact():
+    flat = _params(9)
+    x, t = _inputs(10, 256)
+    _, g = mo.loss_and_grad(flat, x, t, SHIFT, SCALE)
+    _, ge = mo.loss_and_grad(flat, x, t, SHIFT, SCALE, emulate_bf16=True)
+    for k in g:
+        rel = np.linalg.norm(ge[k] - g[k]) / np.linalg.norm(g[k])
+        assert 0 < rel < 3e-2, (k, rel)
+
+
+def test_adam_matches_torch_and_first_step_sign():
+    rng = np.random.default_rng(11)
+    theta0 = rng.normal(0, 1, 40)
+    grads = [rng.normal(0, 1, 40) for _ in range(6)]
+    opt = mo.Adam(40, lr=3e-3, beta1=0.9, beta2=0.99, eps=1e-8)
+    th = torch.tensor(theta0, requires_grad=True)
+    topt = torch.optim.Adam([th], lr=3e-3, betas=(0.9, 0.99), eps=1e-8)
+    theta = theta0.copy()
+    for k, gk in enumerate(grads):
+        new = opt.step(theta, gk)
+        if k == 0:
+            # first step: m_hat / sqrt(v_hat) = g / |g|, a step of lr against the sign
+            assert np.allclose(new - theta, -3e-3 * np.sign(gk), rtol=1e-6, atol=0)
+        theta = new
+        th.grad = torch.from_numpy(gk.copy())
+        topt.step()
+    assert np.max(np.abs(theta - th.detach().numpy())) < 1e-14
+
+
+def _affine_params(seed):
+    """A network whose every hidden pre-activation exceeds 10, where
+    gelu(z) = z to FP64 precision, so the network is an affine map."""
+    rng = np.random.default_rng(seed)
+    p = {"W1": rng.uniform(-0.1, 0.1, (128, 4)), "b1": np.full(128, 20.0),
+         "W2": rng.uniform(-0.02, 0.02, (128, 128)), "b2": np.full(128, 60.0),
+         "W3": rng.uniform(-0.02, 0.02, (128, 128)), "b3": np.full(128, 100.0),
+         "W4": rng.uniform(-0.01, 0.01, (2, 128)), "b4": rng.uniform(-0.1, 0.1, 2)}
+    A = p["W4"] @ p["W3"] @ p["W2"] @ p["W1"]
+    c = p["W4"] @ (p["W3"] @ (p["W2"] @ p["b1"] + p["b2"]) + p["b3"]) + p["b4"]
+    return p, A, c
+
+
+def test_chain_of_affine_network_is_linear_recurrence():
+    p, A, c = _affine_params(12)
+    x, _ = _inputs(13, 20)
+    _, cache = mo.forward(p, x, SHIFT, SCALE)
+    assert min(cache["z1"].min(), cache["z2"].min(), cache["z3"].min()) > 10
+    out_scale = np.array([0.05, 0.2])
+    y0, mu, t0, T, N = np.array([2.0, 0.0]), 2.7, 0.0, 5.0, 40
+    bnd = mo.surrogate_chain(p, SHIFT, SCALE, out_scale, y0, mu, t0, T, N)
+    # out = A u + c with u = (x - shift) * scale: write the recurrence in matrix form
+    As = A * SCALE[None, :]
+    M = np.eye(2) + out_scale[:, None] * As[:, :2]
+    lam = y0.copy()
+    for j in range(N):
+        tj = t0 + j * (T - t0) / N
+        drive = As[:, 2] * tj + As[:, 3] * mu - As @ SHIFT + c
+        lam = M @ lam + out_scale * drive
+    assert np.max(np.abs(bnd[-1] - lam)) < 1e-11
+    assert bnd.shape == (N + 1, 2) and np.array_equal(bnd[0], y0)
+
+
+def test_chain_zero_network_keeps_state_and_constant_network_drifts():
+    p = mo.unflatten(_params(14))
+    p["W4"][:] = 0.0
+    p["b4"][:] = 0.0
+    bnd = mo.surrogate_chain(p, SHIFT, SCALE, np.array([1.0, 1.0]), [0.5, -1.0], 3.0, 0, 10, 16)
+    assert np.all(bnd == np.array([0.5, -1.0]))
+    p["b4"][:] = [0.25, -0.5]
+    bnd = mo.surrogate_chain(p, SHIFT, SCALE, np.array([0.5, 2.0]), [0.5, -1.0], 3.0, 0, 10, 16)
+    assert np.allclose(bnd[-1], [0.5 + 16 * 0.125, -1.0 - 16 * 1.0], rtol=0, atol=1e-13)

@@ -304,13 +304,173 @@ def bench_paper_table3(args):
     return out
 
 
+# algorithmic FLOPs per training sample of the surrogate network (FMA = 2):
+# forward 2 (4*128 + 2*128*128 + 128*2) = 67,072; back-propagation through the
+# two 128 x 128 layers 2 * 2 * 128*128; weight gradients 2 (128*4 + 2*128*128
+# + 2*128); the matrix-core part is the three 128 x 128 products of each layer
+SUR_FWD_FLOPS = 2 * (4 * 128 + 2 * 128 * 128 + 128 * 2)
+SUR_TRAIN_FLOPS = SUR_FWD_FLOPS + 2 * 2 * 128 * 128 + 2 * (128 * 4 + 2 * 128 * 128 + 2 * 128)
+SUR_MFMA_FLOPS = 3 * 2 * 2 * 128 * 128
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+
+
+def bench_surrogate(args):
+    """The learned slice-map surrogate of the Van der Pol problem: the training
+    build (1024 one-slice problems, slice j with its own mu_j, 128 x 128 grid,
+    500 RK4 steps: 16.7M endpoints), the training-set gather, Adam training on
+    the matrix cores, then the composition with the network for held-out mu
+    against the plain method (bilinear tables) at equal max final-state error."""
+    import numpy as np
+    import torch
+
+    from paper_1304_6514_amd import nv
+    from paper_1304_6514_amd.propagator import Batch, Propagator
+    from paper_1304_6514_amd.surrogate import Surrogate
+
+    B = 65536
+    probs = W.surrogate_training_problems()
+    b = Batch(probs)
+    st, _, _ = b.run()                       # first run: graph capture and warm-up
+    st, _, _ = b.run()
+    if st != nv.NV_OK:
+        raise RuntimeError(f"training build failed: {nv.status_name(st)}")
+    build_ms, build_steps = b.last_timing()
+    sur = Surrogate("cuda:0", max_batch=B)
+    total = nv.nv_sur_dataset_from_batch(sur.h, b.batch)
+    perm = W.surrogate_perm(total)
+    t = time.perf_counter()
+    x, tg = sur.dataset_from_batch(b, perm)
+    gather_ms = 1e3 * (time.perf_counter() - t)
+    b.close()
+    del perm
+
+    steps_per_epoch = total // B
+    steps = args.sur_epochs * steps_per_epoch
+    sur.set_params(W.surrogate_init_params(0))
+    sur.train(x, tg, batch=B, steps=args.warmup)           # warm-up (then start afresh)
+    sur.set_params(W.surrogate_init_params(0))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    losses = sur.train(x, tg, batch=B, steps=steps, lr=args.sur_lr, lr_final=args.sur_lr_final)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t
+    train_ms_events = sur.last_ms()
+    losses = losses.cpu().numpy()
+    del x, tg
+
+    # the kernels of one training step, timed alone (HIP events inside the call)
+    xs, ts = W.surrogate_samples(B, seed=31)
+    sur.loss_grad(xs, ts)
+    step_ms = []
+    xd = torch.from_numpy(xs).cuda()
+    td = torch.from_numpy(ts).cuda()
+    for _ in range(5):
+        t1 = time.perf_counter()
+        sur.loss_grad(xd, td)
+        step_ms.append(1e3 * (time.perf_counter() - t1))
+
+    # evaluation on held-out mu: truth = the library's FP64 integration of the
+    # whole interval from y0 (a one-slice build whose first grid point is y0)
+    mus = W.surrogate_eval_mus(8)
+    base = W.VDP_FP32
+    truth = []
+    with Propagator("cuda:0") as pr:
+        for mu in mus:
+            wt = base.with_(name="vdp-serial-fp64", params=(float(mu),), n_slices=1,
+                            grid_n=(2, 2), grid_lo=base.y0, grid_hi=(base.y0[0] + 1.0,
+                                                                    base.y0[1] + 1.0),
+                            steps_per_slice=base.n_slices * base.steps_per_slice,
+                            precision="fp64")
+            pr.build(wt)
+            torch.cuda.synchronize()
+            truth.append([float(pr.table(0)[0, 0]), float(pr.table(1)[0, 0])])
+    truth = np.array(truth)
+
+    y0 = np.tile(base.y0, (len(mus), 1))
+    sur.compose(y0, mus, base.t0, base.T, base.n_slices)          # warm-up
+    st, fin, _, info = sur.compose(y0, mus, base.t0, base.T, base.n_slices)
+    sur_ms = info.ms
+    err_sur = np.max(np.abs(fin.cpu().numpy() - truth), axis=1)
+    st1, _, _, info1 = sur.compose(y0[:1], mus[:1], base.t0, base.T, base.n_slices)
+    many = 16384
+    stq, _, _, infoq = sur.compose(np.tile(base.y0, (many, 1)), np.resize(mus, many), base.t0,
+                                   base.T, base.n_slices)
+
+    plain = []
+    with Propagator("cuda:0") as pr:
+        for n in (32, 48, 64, 96, 128, 192, 256):
+            errs, ms = [], []
+            for mu in mus:
+                wp = base.with_(params=(float(mu),), grid_n=(n, n))
+                pr.solve(wp, want_boundary=False)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                r = pr.solve(wp, want_boundary=False)
+                ms.append(1e3 * (time.perf_counter() - t1))
+                errs.append(float(np.max(np.abs(np.asarray(r.yT) - truth[len(errs)]))))
+            plain.append({"grid": n, "max_error": max(errs), "errors": errs,
+                          "ms_per_mu": round(float(np.mean(ms)), 3),
+                          "table_bytes": base.n_slices * n * n * 2 * 4})
+        # the network with the 128 x 128 table of the first mu as fallback and judge
+        wf = base.with_(params=(float(mus[0]),))
+        pr.build(wf)
+        torch.cuda.synchronize()
+        stf, finf, _, infof = sur.compose(base.y0, [mus[0]], base.t0, base.T, base.n_slices,
+                                          fallback=pr, guard=args.sur_guard)
+        err_fb = float(np.max(np.abs(finf.cpu().numpy()[0] - truth[0])))
+
+    e_sur = float(np.max(err_sur))
+    eq = next((p for p in plain if p["max_error"] <= e_sur), None)
+    train_samples = steps * B
+    value = train_samples / train_s
+    achieved = train_samples * SUR_MFMA_FLOPS / train_s / 1e12
+    out = {
+        "metric": "surrogate: training samples/s; composition at equal max final-state error",
+        "value": value, "unit": "samples/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * train_s / max(steps, 1), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "vdp-surrogate-1024x128x128x500-perslice-mu",
+                   "network": "4-128-128-128-2 exact GELU", "batch": B, "epochs": args.sur_epochs,
+                   "samples": total, "lr": [args.sur_lr, args.sur_lr_final],
+                   "parallelism": "single-gpu"},
+        "training_build": {"ms": round(build_ms, 3), "trajectory_steps": build_steps,
+                           "trajectory_steps_per_s": build_steps / (build_ms * 1e-3)},
+        "gather_ms": round(gather_ms, 3),
+        "train_s": round(train_s, 3), "train_events_ms": round(train_ms_events, 2),
+        "loss": {"first": float(losses[0]), "last": float(losses[-1]),
+                 "last_epoch_mean": float(losses[-steps_per_epoch:].mean())},
+        "step_ms_loss_grad": round(min(step_ms), 4),
+        "eval": {"mus": [float(m) for m in mus], "truth": "library FP64 serial RK4, 512000 steps",
+                 "surrogate_errors": [float(e) for e in err_sur], "surrogate_max_error": e_sur,
+                 "surrogate_compose_ms_8_chains": round(sur_ms, 3),
+                 "surrogate_compose_ms_1_chain": round(info1.ms, 3),
+                 "surrogate_compose_ms_16384_chains": round(infoq.ms, 3),
+                 "plain": plain,
+                 "equal_error_grid": eq["grid"] if eq else None,
+                 "equal_error_plain_ms_per_mu": eq["ms_per_mu"] if eq else None,
+                 "with_fallback": {"guard": args.sur_guard, "n_fallback": infof.n_fallback,
+                                   "max_deviation": infof.max_deviation, "error": err_fb},
+                 "network_bytes_bf16": 33922 * 2},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
+                     "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_BF16_MFMA_TFLOPS, 5), "traffic": None,
+                     "kernel": "whole training step (forward/back-propagation, gradient sums, "
+                               "Adam); matrix-core FLOPs only",
+                     "mfma_flops_per_sample": SUR_MFMA_FLOPS,
+                     "train_flops_per_sample": SUR_TRAIN_FLOPS},
+    }
+    sur.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="forced_cubic",
-                    choices=sorted(WORKLOADS) + ["batched", "paper-table3"])
+                    choices=sorted(WORKLOADS) + ["batched", "paper-table3", "surrogate"])
     ap.add_argument("--traj-per-lane", type=int, default=0)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default=None,
                     help="override the workload's build precision")
@@ -325,6 +485,12 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one elementwise copy kernel (reads and writes this many "
                          "MiB) so that profiler byte counters can be scaled against it")
+    ap.add_argument("--sur-epochs", type=int, default=20,
+                    help="surrogate: passes over the 16.7M-sample training set")
+    ap.add_argument("--sur-lr", type=float, default=2e-3)
+    ap.add_argument("--sur-lr-final", type=float, default=2e-5)
+    ap.add_argument("--sur-guard", type=float, default=0.05,
+                    help="surrogate: deviation from the table above which the table is used")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -347,6 +513,9 @@ def main():
         return
     if args.workload == "paper-table3":
         print(json.dumps(bench_paper_table3(args)), flush=True)
+        return
+    if args.workload == "surrogate":
+        print(json.dumps(bench_surrogate(args)), flush=True)
         return
     w = WORKLOADS[args.workload]
     if args.precision:

@@ -162,6 +162,7 @@ struct nv_batch {
     void *stage = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
+    bool ran = false;          // a run has written the tables
 };
 
 namespace {
@@ -575,6 +576,7 @@ NV_API nv_status nv_batch_run(nv_batch *b, double *yT, nv_compose_info *info) {
     NV_HIP(hipEventRecord(b->ev1, b->stream));
     NV_HIP(hipStreamSynchronize(b->stream));
     b->timed = true;
+    b->ran = true;
     const auto *st = static_cast<const nv::ComposeStatus *>(b->stage);
     const auto *res = reinterpret_cast<const double *>(static_cast<const char *>(b->stage) +
                                                        (b->off_result - b->off_status));
@@ -635,3 +637,35 @@ NV_API nv_status nv_batch_get_boundary(nv_batch *b, int problem, double *host_ds
 }
 
 }  // extern "C"
+
+nv_status nv::batch_slice_sources(nv_batch *b, std::vector<SliceMapSource> &out,
+                                  int *precision) {
+    if (!b) return fail(NV_ERR_INVALID_ARG, "batch is NULL");
+    if (!b->ran) return fail(NV_ERR_NOT_BUILT, "the batch has not been run");
+    out.clear();
+    long long first = 0;
+    for (int i = 0; i < b->count; ++i) {
+        const nv_problem &p = b->problems[i];
+        if (p.rhs_id != NV_RHS_VDP || p.grid.dim != 2)
+            return fail(NV_ERR_INVALID_ARG, "problem %d is not a 2-D Van der Pol problem", i);
+        const BuildArgs &a = b->hp[i].build;
+        SliceMapSource s{};
+        s.tab0 = a.tab0;
+        s.tab1 = a.tab1;
+        s.M = a.M;
+        s.n1 = a.n1;
+        s.n_slices = p.n_slices;
+        s.lo0 = a.lo0;
+        s.dxi0 = a.dxi0;
+        s.lo1 = a.lo1;
+        s.dxi1 = a.dxi1;
+        s.t0 = p.t0;
+        s.L = (p.T - p.t0) / double(p.n_slices);
+        s.mu = p.params[0];
+        s.first = first;
+        first += a.M * (long long)p.n_slices;
+        out.push_back(s);
+    }
+    *precision = b->precision;
+    return NV_OK;
+}

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "nv.h"
 
@@ -84,6 +85,21 @@ struct BatchItem {
     int tile;
     int reserved;
 };
+
+// One problem's tables seen as samples of its slice maps: sample (j, k) is
+// grid point k of slice j, the slice starting at t0 + j L (training set of the
+// learned surrogate).  first = number of the problem's first sample.
+struct SliceMapSource {
+    const void *tab0, *tab1;
+    long long M;
+    int n1, n_slices;
+    double lo0, dxi0, lo1, dxi1;
+    double t0, L, mu;
+    long long first;
+};
+
+// The tables of a run batch of 2-D Van der Pol problems, problem by problem.
+nv_status batch_slice_sources(nv_batch *b, std::vector<SliceMapSource> &out, int *precision);
 
 bool build_supported(const BuildConfig &c);
 hipError_t launch_build(const BuildConfig &c, const BuildArgs &a, hipStream_t s);

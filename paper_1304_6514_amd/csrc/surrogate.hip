@@ -1,0 +1,860 @@
+// Learned slice-map surrogate: training (forward and back-propagation on bf16
+// matrix cores, weight-gradient sums, Adam), inference inside the composition,
+// and the training set drawn from the tables of the computation phase.
+#include "compose.h"
+#include "mlp.h"
+#include "nv_surrogate.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using nv::fail;
+using namespace nv::mlp;
+
+#define NV_HIP(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(NV_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+namespace {
+
+constexpr int kTrainThreads = 256;       // 4 waves, 1 workgroup per CU (LDS): 512 registers per wave
+constexpr int kInferThreads = 256;       // 4 waves
+constexpr int kMaxSplits = 64;           // weight-gradient sums: splits of the minibatch
+constexpr long long kMaxBatch = 1LL << 20;
+
+enum { kModeReduce = 1, kModeAdam = 2 };
+
+// ---------------------------------------------------------------- kernels
+
+struct TrainArgs {
+    const float *x, *t;          // data set rows, ld samples each
+    long long ld, start, n;      // minibatch = samples start .. start+n-1
+    const float *params;
+    const __bf16 *shadow;        // Wf2, Wf3, Wb2, Wb3 (permuted bf16)
+    __bf16 *S;                   // workspace, kRowsS rows of ldS
+    long long ldS;
+    float *loss_part;            // one sum per 16 samples
+    float shift[4], scale[4];
+    float inv_n;
+};
+
+struct TrainLds {
+    __bf16 w[4 * kWidth * kLdsRow];
+    SmallParams sp;
+};
+
+__global__ __launch_bounds__(kTrainThreads) void sur_train_kernel(TrainArgs a) {
+    __shared__ TrainLds L;
+    const int tid = int(threadIdx.x);
+    load_mats(L.w, a.shadow, 4, tid, kTrainThreads);
+    load_small(L.sp, a.params, tid, kTrainThreads);
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6, s = lane & 15, g = lane >> 4;
+    const __bf16 *Wf2 = L.w, *Wf3 = L.w + kWidth * kLdsRow;
+    const __bf16 *Wb2 = L.w + 2 * kWidth * kLdsRow, *Wb3 = L.w + 3 * kWidth * kLdsRow;
+    const long long tiles = a.n / 16;
+    const int waves = int(gridDim.x) * (kTrainThreads / 64);
+    for (long long tile = (long long)blockIdx.x * (kTrainThreads / 64) + wave; tile < tiles;
+         tile += waves) {
+        asm volatile("" ::: "memory");  // keep the weight reads inside the loop
+        const long long n = tile * 16 + s;
+        const long long src = a.start + n;
+        float u[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u[k] = (a.x[k * a.ld + src] - a.shift[k]) * a.scale[k];
+        const float t0 = a.t[src], t1 = a.t[a.ld + src];
+        Layer d1, d2, d3, x;
+        bf16x8 b[4];
+        float o0, o1;
+        __bf16 *col = a.S + (long long)(4 * g) * a.ldS + n;
+        forward<true>(L.sp, Wf2, Wf3, u, lane, d1, d2, d3, x, o0, o1, col, a.ldS);
+        pack(x, b);
+        store_rows(col, a.ldS, kRowH + 256, b);
+
+        const float e0 = o0 - t0, e1 = o1 - t1;
+        const float dout0 = 2.0f * e0 * a.inv_n, dout1 = 2.0f * e1 * a.inv_n;
+        // layer 3: dL/dz3 = (W4^T dout) * gelu'(z3)
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int f = 16 * mt + 4 * g + i;
+                x.v[mt][i] = (L.sp.w4[f] * dout0 + L.sp.w4[kWidth + f] * dout1) * d3.v[mt][i];
+            }
+        }
+        pack(x, b);
+        store_rows(col, a.ldS, kRowD + 256, b);
+        matmul(Wb3, b, x, lane);                              // W3^T dL/dz3
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) x.v[mt] *= d2.v[mt];
+        pack(x, b);
+        store_rows(col, a.ldS, kRowD + 128, b);
+        matmul(Wb2, b, x, lane);                              // W2^T dL/dz2
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) x.v[mt] *= d1.v[mt];
+        pack(x, b);
+        store_rows(col, a.ldS, kRowD, b);
+
+        // rows of XO: group 0 writes u0..u3, group 1 writes 1, dout0, dout1, 0,
+        // groups 2 and 3 the zero rows
+        __bf16 xo[4];
+        if (g == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xo[r] = __bf16(u[r]);
+        } else if (g == 1) {
+            xo[0] = __bf16(1.0f);
+            xo[1] = __bf16(dout0);
+            xo[2] = __bf16(dout1);
+            xo[3] = __bf16(0.0f);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xo[r] = __bf16(0.0f);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) col[(long long)(kRowXO + r) * a.ldS] = xo[r];
+
+        float sq = g == 0 ? e0 * e0 + e1 * e1 : 0.0f;
+        sq += __shfl_xor(sq, 1);
+        sq += __shfl_xor(sq, 2);
+        sq += __shfl_xor(sq, 4);
+        sq += __shfl_xor(sq, 8);
+        if (lane == 0) a.loss_part[tile] = sq;
+    }
+}
+
+// Weight-gradient sums G = A B^T over samples k0..k1-1 of the minibatch, A and
+// B row blocks of S; each wave computes a 32 x 32 block of one of the four
+// products (kGemmWaveTiles waves), blockIdx.y is the split of the sum.
+struct GemmArgs {
+    const __bf16 *S;
+    long long ldS, n, k_per_split;
+    float *part;                 // [splits][kGradEntries]
+};
+
+__global__ __launch_bounds__(256) void sur_grad_kernel(GemmArgs a) {
+    const int lane = int(threadIdx.x) & 63, r = lane & 15, g = lane >> 4;
+    const int wt = int(blockIdx.x) * 4 + (int(threadIdx.x) >> 6);
+    if (wt >= kGemmWaveTiles) return;
+    int a_row, b_row, M, N, out, t, tiles_n;
+    if (wt < 16) {
+        a_row = kRowD + 128; b_row = kRowH; M = N = 128; out = kG_W2; t = wt; tiles_n = 4;
+    } else if (wt < 32) {
+        a_row = kRowD + 256; b_row = kRowH + 128; M = N = 128; out = kG_W3; t = wt - 16;
+        tiles_n = 4;
+    } else if (wt < 44) {
+        a_row = kRowD; b_row = kRowXO; M = 384; N = 16; out = kG_D_XO; t = wt - 32; tiles_n = 1;
+    } else {
+        a_row = kRowXO; b_row = kRowH + 256; M = 16; N = 144; out = kG_XO_H3; t = wt - 44;
+        tiles_n = 5;
+    }
+    const int mt0 = 2 * (t / tiles_n), nt0 = 2 * (t % tiles_n);
+    const bool m1 = mt0 + 1 < M / 16, n1 = nt0 + 1 < N / 16;
+    const long long k0 = (long long)blockIdx.y * a.k_per_split;
+    const long long k1 = std::min(k0 + a.k_per_split, a.n);
+    const __bf16 *pa0 = a.S + (long long)(a_row + 16 * mt0 + r) * a.ldS + 8 * g;
+    const __bf16 *pa1 = pa0 + 16 * a.ldS;
+    const __bf16 *pb0 = a.S + (long long)(b_row + 16 * nt0 + r) * a.ldS + 8 * g;
+    const __bf16 *pb1 = pb0 + 16 * a.ldS;
+    f32x4 c00 = {0.f, 0.f, 0.f, 0.f}, c01 = c00, c10 = c00, c11 = c00;
+    const bf16x8 zero = {};
+    for (long long k = k0; k < k1; k += 32) {
+        const bool ok = k + 8 * g < k1;          // the minibatch ends on a multiple of 16
+        const bf16x8 A0 = ok ? *reinterpret_cast<const bf16x8 *>(pa0 + k) : zero;
+        const bf16x8 B0 = ok ? *reinterpret_cast<const bf16x8 *>(pb0 + k) : zero;
+        const bf16x8 A1 = (ok && m1) ? *reinterpret_cast<const bf16x8 *>(pa1 + k) : zero;
+        const bf16x8 B1 = (ok && n1) ? *reinterpret_cast<const bf16x8 *>(pb1 + k) : zero;
+        c00 = mfma(A0, B0, c00);
+        if (n1) c01 = mfma(A0, B1, c01);
+        if (m1) c10 = mfma(A1, B0, c10);
+        if (m1 && n1) c11 = mfma(A1, B1, c11);
+    }
+    float *P = a.part + (long long)blockIdx.y * kGradEntries + out;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row0 = 16 * mt0 + 4 * g + i, col0 = 16 * nt0 + r;
+        P[row0 * N + col0] = c00[i];
+        if (n1) P[row0 * N + col0 + 16] = c01[i];
+        if (m1) P[(row0 + 16) * N + col0] = c10[i];
+        if (m1 && n1) P[(row0 + 16) * N + col0 + 16] = c11[i];
+    }
+}
+
+// Offset of parameter p's gradient in the partial vector.
+__device__ inline int grad_source(int p) {
+    if (p < kB1) return kG_D_XO + (p >> 2) * 16 + (p & 3);                 // W1[f][k]
+    if (p < kW2) return kG_D_XO + (p - kB1) * 16 + 4;                      // b1
+    if (p < kB2) return kG_W2 + (p - kW2);                                 // W2
+    if (p < kW3) return kG_D_XO + (128 + p - kB2) * 16 + 4;                // b2
+    if (p < kB3) return kG_W3 + (p - kW3);                                 // W3
+    if (p < kW4) return kG_D_XO + (256 + p - kB3) * 16 + 4;                // b3
+    if (p < kB4) return kG_XO_H3 + (5 + ((p - kW4) >> 7)) * 144 + ((p - kW4) & 127);  // W4
+    return kG_XO_H3 + (5 + (p - kB4)) * 144 + 128 + 4;                     // b4
+}
+
+struct UpdateArgs {
+    float *params, *m, *v, *grad;
+    __bf16 *shadow;
+    const float *part;
+    int splits, mode;
+    float lr, beta1, beta2, eps, inv_bc1, inv_bc2;
+    const float *loss_part;
+    long long n_loss;
+    float inv_n;
+    float *loss_out;
+};
+
+__global__ __launch_bounds__(256) void sur_update_kernel(UpdateArgs a) {
+    if (blockIdx.x == 0 && a.loss_out) {
+        __shared__ float red[256];
+        float s = 0.0f;
+        for (long long i = threadIdx.x; i < a.n_loss; i += 256) s += a.loss_part[i];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) a.loss_out[0] = red[0] * a.inv_n;
+    }
+    const int p = int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (p >= kParams) return;
+    float th = a.params[p];
+    if (a.mode & kModeReduce) {
+        const int src = grad_source(p);
+        float gsum = 0.0f;
+        for (int s = 0; s < a.splits; ++s) gsum += a.part[(long long)s * kGradEntries + src];
+        a.grad[p] = gsum;
+        if (a.mode & kModeAdam) {
+            const float m = a.beta1 * a.m[p] + (1.0f - a.beta1) * gsum;
+            const float v = a.beta2 * a.v[p] + (1.0f - a.beta2) * gsum * gsum;
+            a.m[p] = m;
+            a.v[p] = v;
+            th -= a.lr * (m * a.inv_bc1) / (sqrtf(v * a.inv_bc2) + a.eps);
+            a.params[p] = th;
+        }
+    }
+    int base = -1, q = 0;
+    if (p >= kW2 && p < kB2) { base = 0; q = p - kW2; }
+    else if (p >= kW3 && p < kB3) { base = 1; q = p - kW3; }
+    if (base >= 0) {
+        const int o = q >> 7, i = q & 127;
+        const __bf16 bv = __bf16(th);
+        a.shadow[base * kMat + o * kWidth + 32 * (i >> 5) + perm32_inv(i & 31)] = bv;
+        a.shadow[(2 + base) * kMat + i * kWidth + 32 * (o >> 5) + perm32_inv(o & 31)] = bv;
+    }
+}
+
+struct InferLds {
+    __bf16 w[2 * kWidth * kLdsRow];
+    SmallParams sp;
+};
+
+struct ForwardArgs {
+    const float *params;
+    const __bf16 *shadow;
+    const float *x;
+    float *out;
+    long long n;
+    float shift[4], scale[4];
+};
+
+__global__ __launch_bounds__(kInferThreads) void sur_forward_kernel(ForwardArgs a) {
+    __shared__ InferLds L;
+    const int tid = int(threadIdx.x);
+    load_mats(L.w, a.shadow, 2, tid, kInferThreads);
+    load_small(L.sp, a.params, tid, kInferThreads);
+    __syncthreads();
+    const int lane = tid & 63, s = lane & 15, g = lane >> 4;
+    const long long n = ((long long)blockIdx.x * (kInferThreads / 64) + (tid >> 6)) * 16 + s;
+    const long long nc = n < a.n ? n : a.n - 1;
+    float u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k] = (a.x[k * a.n + nc] - a.shift[k]) * a.scale[k];
+    Layer d1, d2, d3, a3;
+    float o0, o1;
+    forward<false>(L.sp, L.w, L.w + kWidth * kLdsRow, u, lane, d1, d2, d3, a3, o0, o1, nullptr,
+                   0);
+    if (n < a.n && g == 0) {
+        a.out[n] = o0;
+        a.out[a.n + n] = o1;
+    }
+}
+
+struct ChainArgs {
+    const float *params;
+    const __bf16 *shadow;
+    float shift[4], scale[4];
+    double os0, os1;
+    const double *y0, *mu;
+    long long count;
+    double t0, L;
+    int n_slices;
+    double *final_state, *boundary;
+    const void *tab0, *tab1;
+    int fb_fp64;
+    long long M;
+    int n0, n1;
+    double lo0, inv0, lo1, inv1, guard;
+    double blo0, blo1, bhi0, bhi1;
+    unsigned long long *stats;   // fallbacks, outside, max deviation (bits), first bad chain
+};
+
+// The bilinear map of table row j at (l0, l1), with the operation sequence of
+// the library's bilinear composition.
+template <class T>
+__device__ inline void bilinear_row(const ChainArgs &a, int j, double l0, double l1, double &p,
+                                    double &q) {
+#pragma clang fp contract(off)
+    long long i0, i1;
+    double w0, w1;
+    nv::dev::locate(a.lo0, a.inv0, a.n0, l0, i0, w0);
+    nv::dev::locate(a.lo1, a.inv1, a.n1, l1, i1, w1);
+    const T *row0 = static_cast<const T *>(a.tab0) + (long long)j * a.M;
+    const T *row1 = static_cast<const T *>(a.tab1) + (long long)j * a.M;
+    const long long c00 = i0 * a.n1 + i1, c10 = (i0 + 1) * a.n1 + i1;
+    const double p00 = double(row0[c00]), p01 = double(row0[c00 + 1]);
+    const double p10 = double(row0[c10]), p11 = double(row0[c10 + 1]);
+    const double q00 = double(row1[c00]), q01 = double(row1[c00 + 1]);
+    const double q10 = double(row1[c10]), q11 = double(row1[c10 + 1]);
+    const double r0 = p00 + w1 * (p01 - p00), r1 = p10 + w1 * (p11 - p10);
+    const double s0 = q00 + w1 * (q01 - q00), s1 = q10 + w1 * (q11 - q10);
+    p = r0 + w0 * (r1 - r0);
+    q = s0 + w0 * (s1 - s0);
+}
+
+__global__ __launch_bounds__(kInferThreads) void sur_chain_kernel(ChainArgs a) {
+#pragma clang fp contract(off)
+    __shared__ InferLds L;
+    const int tid = int(threadIdx.x);
+    load_mats(L.w, a.shadow, 2, tid, kInferThreads);
+    load_small(L.sp, a.params, tid, kInferThreads);
+    __syncthreads();
+    const int lane = tid & 63, s = lane & 15, g = lane >> 4;
+    const long long q = ((long long)blockIdx.x * (kInferThreads / 64) + (tid >> 6)) * 16 + s;
+    const bool live = q < a.count;
+    const long long qc = live ? q : a.count - 1;
+    double l0 = a.y0[2 * qc], l1 = a.y0[2 * qc + 1];
+    const float muf = float(a.mu[qc]);
+    const bool writer = live && g == 0;
+    const long long stride = (long long)a.n_slices + 1;
+    if (writer && a.boundary) {
+        a.boundary[(q * stride) * 2] = l0;
+        a.boundary[(q * stride) * 2 + 1] = l1;
+    }
+    unsigned long long nfb = 0, nout = 0;
+    double maxdev = 0.0;
+    bool bad = false;
+    for (int j = 0; j < a.n_slices; ++j) {
+        asm volatile("" ::: "memory");  // keep the weight reads inside the loop
+        if (!(isfinite(l0) && isfinite(l1))) bad = true;
+        const float tj = float(a.t0 + double(j) * a.L);
+        float u[4] = {(float(l0) - a.shift[0]) * a.scale[0], (float(l1) - a.shift[1]) * a.scale[1],
+                      (tj - a.shift[2]) * a.scale[2], (muf - a.shift[3]) * a.scale[3]};
+        Layer d1, d2, d3, a3;
+        float o0, o1;
+        forward<false>(L.sp, L.w, L.w + kWidth * kLdsRow, u, lane, d1, d2, d3, a3, o0, o1,
+                       nullptr, 0);
+        double n0 = l0 + a.os0 * double(o0), n1 = l1 + a.os1 * double(o1);
+        const bool outside = !(l0 >= a.blo0 && l0 <= a.bhi0 && l1 >= a.blo1 && l1 <= a.bhi1);
+        if (a.tab0) {
+            double p, pq;
+            if (a.fb_fp64)
+                bilinear_row<double>(a, j, l0, l1, p, pq);
+            else
+                bilinear_row<float>(a, j, l0, l1, p, pq);
+            const double d0 = fabs(n0 - p), dd1 = fabs(n1 - pq);
+            const double dev = d0 > dd1 ? d0 : dd1;
+            if (dev == dev && dev > maxdev) maxdev = dev;
+            if (!(dev <= a.guard) || outside) {
+                n0 = p;
+                n1 = pq;
+                ++nfb;
+            }
+        } else if (outside) {
+            ++nout;
+        }
+        if (!bad) {
+            l0 = n0;
+            l1 = n1;
+        }
+        if (writer && a.boundary) {
+            a.boundary[(q * stride + j + 1) * 2] = l0;
+            a.boundary[(q * stride + j + 1) * 2 + 1] = l1;
+        }
+    }
+    if (!(isfinite(l0) && isfinite(l1))) bad = true;
+    if (writer) {
+        a.final_state[2 * q] = l0;
+        a.final_state[2 * q + 1] = l1;
+        if (nfb) atomicAdd(&a.stats[0], nfb);
+        if (nout) atomicAdd(&a.stats[1], nout);
+        if (maxdev > 0.0) atomicMax(&a.stats[2], (unsigned long long)__double_as_longlong(maxdev));
+        if (bad) atomicMin(&a.stats[3], (unsigned long long)q);
+    }
+}
+
+struct DatasetArgs {
+    const nv::SliceMapSource *src;
+    int n_src, fp64;
+    long long total, cap;
+    const long long *perm;
+    float *x, *t;
+    double os0, os1;
+    int *error;
+};
+
+__global__ __launch_bounds__(256) void sur_dataset_kernel(DatasetArgs a) {
+#pragma clang fp contract(off)
+    const long long step = (long long)gridDim.x * 256;
+    for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < a.total; n += step) {
+        int lo = 0, hi = a.n_src - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.src[mid].first <= n)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const nv::SliceMapSource &s = a.src[lo];
+        const long long r = n - s.first, j = r / s.M, k = r - j * s.M;
+        const unsigned kk = unsigned(k), n1 = unsigned(s.n1);
+        const unsigned k0 = kk / n1, k1 = kk - k0 * n1;
+        const float y0 = float(s.lo0 + double(k0) * s.dxi0);
+        const float y1 = float(s.lo1 + double(k1) * s.dxi1);
+        double e0, e1;
+        if (a.fp64) {
+            e0 = static_cast<const double *>(s.tab0)[j * s.M + k];
+            e1 = static_cast<const double *>(s.tab1)[j * s.M + k];
+        } else {
+            e0 = double(static_cast<const float *>(s.tab0)[j * s.M + k]);
+            e1 = double(static_cast<const float *>(s.tab1)[j * s.M + k]);
+        }
+        const long long pos = a.perm ? a.perm[n] : n;
+        if (pos < 0 || pos >= a.cap) {
+            atomicOr(a.error, 1);
+            continue;
+        }
+        a.x[pos] = y0;
+        a.x[a.cap + pos] = y1;
+        a.x[2 * a.cap + pos] = float(s.t0 + double(j) * s.L);
+        a.x[3 * a.cap + pos] = float(s.mu);
+        a.t[pos] = float((e0 - double(y0)) / a.os0);
+        a.t[a.cap + pos] = float((e1 - double(y1)) / a.os1);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+struct nv_sur {
+    nv_sur_config cfg{};
+    hipStream_t stream = nullptr;
+    int n_cu = 256;
+    long long max_batch = 0;
+    char *mem = nullptr;         // one device allocation
+    float *params = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    __bf16 *shadow = nullptr, *S = nullptr;
+    float *part = nullptr, *loss_part = nullptr, *loss = nullptr;
+    unsigned long long *stats = nullptr;
+    int *error = nullptr;
+    long long adam_t = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    float last_ms = 0.f;
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+void fill_norm(const nv_sur *s, float (&shift)[4], float (&scale)[4]) {
+    for (int k = 0; k < 4; ++k) {
+        shift[k] = s->cfg.in_shift[k];
+        scale[k] = s->cfg.in_scale[k];
+    }
+}
+
+nv_status refresh_shadow(nv_sur *s) {
+    UpdateArgs u{};
+    u.params = s->params;
+    u.shadow = s->shadow;
+    u.mode = 0;
+    hipLaunchKernelGGL(sur_update_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s->stream, u);
+    NV_HIP(hipGetLastError());
+    return NV_OK;
+}
+
+long long k_per_split(long long n) {
+    long long k = std::max(1024LL, (n + kMaxSplits - 1) / kMaxSplits);
+    return (k + 31) / 32 * 32;
+}
+
+// One minibatch: forward and back-propagation, gradient sums, then the update
+// kernel (mode: reduce only, or reduce and Adam step).
+nv_status minibatch(nv_sur *s, const float *x, const float *t, long long ld, long long start,
+                    long long n, int mode, float lr, float b1, float b2, float eps,
+                    float *loss_out) {
+    TrainArgs ta{};
+    ta.x = x;
+    ta.t = t;
+    ta.ld = ld;
+    ta.start = start;
+    ta.n = n;
+    ta.params = s->params;
+    ta.shadow = s->shadow;
+    ta.S = s->S;
+    ta.ldS = s->max_batch;
+    ta.loss_part = s->loss_part;
+    fill_norm(s, ta.shift, ta.scale);
+    ta.inv_n = float(1.0 / double(n));
+    const long long tiles = n / 16;
+    const int blocks = int(std::min<long long>((tiles + 7) / 8, s->n_cu));
+    hipLaunchKernelGGL(sur_train_kernel, dim3(blocks), dim3(kTrainThreads), 0, s->stream, ta);
+    NV_HIP(hipGetLastError());
+
+    GemmArgs ga{};
+    ga.S = s->S;
+    ga.ldS = s->max_batch;
+    ga.n = n;
+    ga.k_per_split = k_per_split(n);
+    ga.part = s->part;
+    const int splits = int((n + ga.k_per_split - 1) / ga.k_per_split);
+    hipLaunchKernelGGL(sur_grad_kernel, dim3((kGemmWaveTiles + 3) / 4, splits), dim3(256), 0,
+                       s->stream, ga);
+    NV_HIP(hipGetLastError());
+
+    UpdateArgs ua{};
+    ua.params = s->params;
+    ua.m = s->m;
+    ua.v = s->v;
+    ua.grad = s->grad;
+    ua.shadow = s->shadow;
+    ua.part = s->part;
+    ua.splits = splits;
+    ua.mode = mode;
+    if (mode & kModeAdam) {
+        const long long t = ++s->adam_t;
+        ua.lr = lr;
+        ua.beta1 = b1;
+        ua.beta2 = b2;
+        ua.eps = eps;
+        ua.inv_bc1 = float(1.0 / (1.0 - std::pow(double(b1), double(t))));
+        ua.inv_bc2 = float(1.0 / (1.0 - std::pow(double(b2), double(t))));
+    }
+    ua.loss_part = s->loss_part;
+    ua.n_loss = tiles;
+    ua.inv_n = ta.inv_n;
+    ua.loss_out = loss_out;
+    hipLaunchKernelGGL(sur_update_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s->stream,
+                       ua);
+    NV_HIP(hipGetLastError());
+    return NV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+NV_API nv_status nv_sur_create(const nv_sur_config *cfg, nv_sur **out) {
+    if (!cfg || !out) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(cfg->in_shift[k]) || !std::isfinite(cfg->in_scale[k]))
+            return fail(NV_ERR_INVALID_ARG, "input normalisation %d is not finite", k);
+    for (int c = 0; c < 2; ++c)
+        if (!(cfg->out_scale[c] > 0.0) || !std::isfinite(cfg->out_scale[c]))
+            return fail(NV_ERR_INVALID_ARG, "out_scale[%d] must be positive and finite", c);
+    const long long mb = cfg->max_batch == 0 ? 65536 : cfg->max_batch;
+    if (mb < 16 || mb > kMaxBatch || mb % 16 != 0)
+        return fail(NV_ERR_INVALID_ARG, "max_batch %lld: need a multiple of 16 in [16, 2^20]",
+                    mb);
+    nv_sur *s = new (std::nothrow) nv_sur();
+    if (!s) return fail(NV_ERR_OOM, "out of host memory");
+    s->cfg = *cfg;
+    s->cfg.max_batch = mb;
+    s->max_batch = mb;
+    s->stream = static_cast<hipStream_t>(cfg->stream);
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            n > 0)
+            s->n_cu = n;
+    }
+    // layout of the single allocation
+    size_t off = 0;
+    const size_t o_params = off; off = align256(off + kParams * sizeof(float));
+    const size_t o_m = off;      off = align256(off + kParams * sizeof(float));
+    const size_t o_v = off;      off = align256(off + kParams * sizeof(float));
+    const size_t o_grad = off;   off = align256(off + kParams * sizeof(float));
+    const size_t o_shadow = off; off = align256(off + 4 * kMat * sizeof(__bf16));
+    const size_t o_part = off;   off = align256(off + size_t(kMaxSplits) * kGradEntries * 4);
+    const size_t o_lp = off;     off = align256(off + size_t(mb / 16) * sizeof(float));
+    const size_t o_loss = off;   off = align256(off + sizeof(float));
+    const size_t o_stats = off;  off = align256(off + 4 * sizeof(unsigned long long));
+    const size_t o_err = off;    off = align256(off + sizeof(int));
+    const size_t o_S = off;      off = align256(off + size_t(kRowsS) * size_t(mb) * 2);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&s->mem), off);
+    if (e != hipSuccess) {
+        delete s;
+        return fail(NV_ERR_OOM, "device allocation of %zu bytes failed", off);
+    }
+    s->params = reinterpret_cast<float *>(s->mem + o_params);
+    s->m = reinterpret_cast<float *>(s->mem + o_m);
+    s->v = reinterpret_cast<float *>(s->mem + o_v);
+    s->grad = reinterpret_cast<float *>(s->mem + o_grad);
+    s->shadow = reinterpret_cast<__bf16 *>(s->mem + o_shadow);
+    s->part = reinterpret_cast<float *>(s->mem + o_part);
+    s->loss_part = reinterpret_cast<float *>(s->mem + o_lp);
+    s->loss = reinterpret_cast<float *>(s->mem + o_loss);
+    s->stats = reinterpret_cast<unsigned long long *>(s->mem + o_stats);
+    s->error = reinterpret_cast<int *>(s->mem + o_err);
+    s->S = reinterpret_cast<__bf16 *>(s->mem + o_S);
+    e = hipMemsetAsync(s->mem, 0, o_S, s->stream);
+    if (e == hipSuccess) e = hipEventCreate(&s->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&s->ev1);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        nv_sur_destroy(s);
+        return fail(NV_ERR_HIP, "surrogate set-up failed: %s", hipGetErrorString(e));
+    }
+    *out = s;
+    return NV_OK;
+}
+
+NV_API nv_status nv_sur_destroy(nv_sur *s) {
+    if (!s) return NV_OK;
+    if (s->stream || s->mem) (void)hipStreamSynchronize(s->stream);
+    if (s->mem) (void)hipFree(s->mem);
+    if (s->ev0) (void)hipEventDestroy(s->ev0);
+    if (s->ev1) (void)hipEventDestroy(s->ev1);
+    delete s;
+    return NV_OK;
+}
+
+NV_API nv_status nv_sur_set_params(nv_sur *s, const float *host) {
+    if (!s || !host) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    for (int i = 0; i < kParams; ++i)
+        if (!std::isfinite(host[i])) return fail(NV_ERR_INVALID_ARG, "parameter %d is not finite", i);
+    NV_HIP(hipMemcpyAsync(s->params, host, kParams * sizeof(float), hipMemcpyHostToDevice,
+                          s->stream));
+    NV_HIP(hipMemsetAsync(s->m, 0, kParams * sizeof(float), s->stream));
+    NV_HIP(hipMemsetAsync(s->v, 0, kParams * sizeof(float), s->stream));
+    s->adam_t = 0;
+    nv_status st = refresh_shadow(s);
+    if (st != NV_OK) return st;
+    NV_HIP(hipStreamSynchronize(s->stream));
+    return NV_OK;
+}
+
+NV_API nv_status nv_sur_get_params(nv_sur *s, float *host) {
+    if (!s || !host) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    NV_HIP(hipMemcpyAsync(host, s->params, kParams * sizeof(float), hipMemcpyDeviceToHost,
+                          s->stream));
+    NV_HIP(hipStreamSynchronize(s->stream));
+    return NV_OK;
+}
+
+NV_API nv_status nv_sur_forward(nv_sur *s, const float *x, long long n, float *out) {
+    if (!s || !x || !out) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    if (n < 1) return fail(NV_ERR_INVALID_ARG, "n = %lld", n);
+    ForwardArgs fa{};
+    fa.params = s->params;
+    fa.shadow = s->shadow;
+    fa.x = x;
+    fa.out = out;
+    fa.n = n;
+    fill_norm(s, fa.shift, fa.scale);
+    const long long blocks = (n + 63) / 64;
+    if (blocks > 0x7fffffffLL) return fail(NV_ERR_INVALID_ARG, "n = %lld is too large", n);
+    NV_HIP(hipEventRecord(s->ev0, s->stream));
+    hipLaunchKernelGGL(sur_forward_kernel, dim3(unsigned(blocks)), dim3(kInferThreads), 0,
+                       s->stream, fa);
+    NV_HIP(hipGetLastError());
+    NV_HIP(hipEventRecord(s->ev1, s->stream));
+    NV_HIP(hipStreamSynchronize(s->stream));
+    NV_HIP(hipEventElapsedTime(&s->last_ms, s->ev0, s->ev1));
+    return NV_OK;
+}
+
+NV_API nv_status nv_sur_loss_grad(nv_sur *s, const float *x, const float *t, long long n,
+                                  float *loss_host, float *grad_host) {
+    if (!s || !x || !t || !loss_host) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    if (n < 16 || n % 16 != 0 || n > s->max_batch)
+        return fail(NV_ERR_INVALID_ARG, "n = %lld: need a multiple of 16 in [16, %lld]", n,
+                    s->max_batch);
+    nv_status st = minibatch(s, x, t, n, 0, n, kModeReduce, 0.f, 0.f, 0.f, 0.f, s->loss);
+    if (st != NV_OK) return st;
+    NV_HIP(hipMemcpyAsync(loss_host, s->loss, sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    if (grad_host)
+        NV_HIP(hipMemcpyAsync(grad_host, s->grad, kParams * sizeof(float), hipMemcpyDeviceToHost,
+                              s->stream));
+    NV_HIP(hipStreamSynchronize(s->stream));
+    return NV_OK;
+}
+
+NV_API nv_status nv_sur_train(nv_sur *s, const float *x, const float *t, long long n_samples,
+                              const nv_sur_train_opts *o, float *loss_dev) {
+    if (!s || !x || !t || !o) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    const long long B = o->batch;
+    if (B < 16 || B % 16 != 0 || B > s->max_batch)
+        return fail(NV_ERR_INVALID_ARG, "batch %lld: need a multiple of 16 in [16, %lld]", B,
+                    s->max_batch);
+    if (n_samples < B || n_samples % B != 0)
+        return fail(NV_ERR_INVALID_ARG, "n_samples %lld is not a positive multiple of batch %lld",
+                    n_samples, B);
+    if (o->steps < 0) return fail(NV_ERR_INVALID_ARG, "steps < 0");
+    const float lr = o->lr > 0.f ? o->lr : 1e-3f;
+    const float b1 = o->beta1 > 0.f ? o->beta1 : 0.9f;
+    const float b2 = o->beta2 > 0.f ? o->beta2 : 0.999f;
+    const float eps = o->eps > 0.f ? o->eps : 1e-8f;
+    if (!(lr < 1.f) || !(b1 < 1.f) || !(b2 < 1.f) || !std::isfinite(o->lr_final) ||
+        o->lr_final < 0.f)
+        return fail(NV_ERR_INVALID_ARG, "Adam hyper-parameters out of range");
+    NV_HIP(hipEventRecord(s->ev0, s->stream));
+    const double decay = (o->lr_final > 0.f && o->steps > 1)
+                             ? std::log(double(o->lr_final) / double(lr)) / double(o->steps - 1)
+                             : 0.0;
+    for (long long k = 0; k < o->steps; ++k) {
+        const long long start = (s->adam_t * B) % n_samples;   // steps since set_params
+        const float lrk = float(double(lr) * std::exp(decay * double(k)));
+        nv_status st = minibatch(s, x, t, n_samples, start, B, kModeReduce | kModeAdam, lrk, b1,
+                                 b2, eps, loss_dev ? loss_dev + k : nullptr);
+        if (st != NV_OK) return st;
+    }
+    NV_HIP(hipEventRecord(s->ev1, s->stream));
+    NV_HIP(hipStreamSynchronize(s->stream));
+    NV_HIP(hipEventElapsedTime(&s->last_ms, s->ev0, s->ev1));
+    return NV_OK;
+}
+
+NV_API nv_status nv_sur_dataset_from_batch(nv_sur *s, nv_batch *batch, const long long *perm,
+                                           float *x, float *t, long long cap, long long *total) {
+    if (!s || !batch || !total) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    std::vector<nv::SliceMapSource> src;
+    int precision = 0;
+    nv_status st = nv::batch_slice_sources(batch, src, &precision);
+    if (st != NV_OK) return st;
+    long long n = 0;
+    for (const auto &q : src) n += q.M * q.n_slices;
+    *total = n;
+    if (!x && !t) return NV_OK;
+    if (!x || !t) return fail(NV_ERR_INVALID_ARG, "x and target must both be given");
+    if (cap < n) return fail(NV_ERR_INVALID_ARG, "capacity %lld < %lld samples", cap, n);
+    void *dsrc = nullptr;
+    NV_HIP(hipMalloc(&dsrc, src.size() * sizeof(nv::SliceMapSource)));
+    hipError_t e = hipMemcpyAsync(dsrc, src.data(), src.size() * sizeof(nv::SliceMapSource),
+                                  hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->error, 0, sizeof(int), s->stream);
+    if (e == hipSuccess) {
+        DatasetArgs da{};
+        da.src = static_cast<const nv::SliceMapSource *>(dsrc);
+        da.n_src = int(src.size());
+        da.fp64 = precision == NV_FP64;
+        da.total = n;
+        da.cap = cap;
+        da.perm = perm;
+        da.x = x;
+        da.t = t;
+        da.os0 = s->cfg.out_scale[0];
+        da.os1 = s->cfg.out_scale[1];
+        da.error = s->error;
+        const long long blocks = std::min<long long>((n + 255) / 256, 65536);
+        hipLaunchKernelGGL(sur_dataset_kernel, dim3(unsigned(blocks)), dim3(256), 0, s->stream,
+                           da);
+        e = hipGetLastError();
+    }
+    int err = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&err, s->error, sizeof(int), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(dsrc);
+    if (e != hipSuccess)
+        return fail(NV_ERR_HIP, "training-set gather failed: %s", hipGetErrorString(e));
+    if (err) return fail(NV_ERR_INVALID_ARG, "perm holds a position outside [0, cap)");
+    return NV_OK;
+}
+
+NV_API nv_status nv_sur_compose(nv_sur *s, const nv_sur_chains *c, nv_sur_compose_info *info) {
+    if (!s || !c || !info) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    if (c->count < 1 || c->n_slices < 1 || !c->y0 || !c->mu || !c->final_state)
+        return fail(NV_ERR_INVALID_ARG, "need count >= 1, n_slices >= 1, y0, mu, final_state");
+    if (!std::isfinite(c->t0) || !std::isfinite(c->T) || !(c->T > c->t0))
+        return fail(NV_ERR_INVALID_ARG, "need finite t0 < T");
+    ChainArgs a{};
+    a.params = s->params;
+    a.shadow = s->shadow;
+    fill_norm(s, a.shift, a.scale);
+    a.os0 = s->cfg.out_scale[0];
+    a.os1 = s->cfg.out_scale[1];
+    a.y0 = c->y0;
+    a.mu = c->mu;
+    a.count = c->count;
+    a.t0 = c->t0;
+    a.L = (c->T - c->t0) / double(c->n_slices);
+    a.n_slices = c->n_slices;
+    a.final_state = c->final_state;
+    a.boundary = c->boundary;
+    a.blo0 = c->box_lo[0];
+    a.blo1 = c->box_lo[1];
+    a.bhi0 = c->box_hi[0];
+    a.bhi1 = c->box_hi[1];
+    a.guard = c->guard;
+    if (c->fb_tab0) {
+        const nv_ic_grid &g = c->fb_grid;
+        if (!c->fb_tab1 || g.dim != 2 || g.interp != NV_INTERP_BILINEAR || g.n[0] < 2 ||
+            g.n[1] < 2 || !(g.hi[0] > g.lo[0]) || !(g.hi[1] > g.lo[1]) ||
+            (c->fb_precision != NV_FP32 && c->fb_precision != NV_FP64))
+            return fail(NV_ERR_INVALID_ARG, "the fallback needs two tables of a 2-D bilinear grid");
+        a.tab0 = c->fb_tab0;
+        a.tab1 = c->fb_tab1;
+        a.fb_fp64 = c->fb_precision == NV_FP64;
+        a.M = (long long)g.n[0] * g.n[1];
+        a.n0 = g.n[0];
+        a.n1 = g.n[1];
+        a.lo0 = g.lo[0];
+        a.lo1 = g.lo[1];
+        a.inv0 = double(g.n[0] - 1) / (g.hi[0] - g.lo[0]);
+        a.inv1 = double(g.n[1] - 1) / (g.hi[1] - g.lo[1]);
+    }
+    const unsigned long long init[4] = {0ull, 0ull, 0ull, ~0ull};
+    NV_HIP(hipMemcpyAsync(s->stats, init, sizeof init, hipMemcpyHostToDevice, s->stream));
+    a.stats = s->stats;
+    const long long blocks = (c->count + 63) / 64;
+    if (blocks > 0x7fffffffLL) return fail(NV_ERR_INVALID_ARG, "too many chains");
+    NV_HIP(hipEventRecord(s->ev0, s->stream));
+    hipLaunchKernelGGL(sur_chain_kernel, dim3(unsigned(blocks)), dim3(kInferThreads), 0,
+                       s->stream, a);
+    NV_HIP(hipGetLastError());
+    NV_HIP(hipEventRecord(s->ev1, s->stream));
+    unsigned long long st[4];
+    NV_HIP(hipMemcpyAsync(st, s->stats, sizeof st, hipMemcpyDeviceToHost, s->stream));
+    NV_HIP(hipStreamSynchronize(s->stream));
+    NV_HIP(hipEventElapsedTime(&s->last_ms, s->ev0, s->ev1));
+    info->n_fallback = (long long)st[0];
+    info->n_outside = (long long)st[1];
+    double md;
+    std::memcpy(&md, &st[2], sizeof md);
+    info->max_deviation = md;
+    info->bad_chain = st[3] == ~0ull ? -1 : (long long)st[3];
+    info->ms = s->last_ms;
+    if (info->bad_chain >= 0)
+        return fail(NV_ERR_NONFINITE, "chain %lld became non-finite", info->bad_chain);
+    return NV_OK;
+}
+
+NV_API nv_status nv_sur_last_ms(nv_sur *s, float *ms) {
+    if (!s || !ms) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    *ms = s->last_ms;
+    return NV_OK;
+}
+
+}  // extern "C"

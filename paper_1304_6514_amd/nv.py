@@ -360,3 +360,132 @@ def nv_batch_get_boundary(batch, problem, n_slices, dim):
     out = np.empty((n_slices + 1, dim))
     _check(load().nv_batch_get_boundary(batch, int(problem), _ptr(out), out.size))
     return out
+
+
+# ---- learned surrogate (include/nv_surrogate.h) ------------------------------
+
+NV_SUR_PARAMS = 33922
+
+
+class nv_sur_config(ctypes.Structure):
+    _fields_ = [("in_shift", ctypes.c_float * 4), ("in_scale", ctypes.c_float * 4),
+                ("out_scale", ctypes.c_double * 2), ("max_batch", ctypes.c_longlong),
+                ("stream", ctypes.c_void_p)]
+
+
+class nv_sur_train_opts(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_longlong), ("steps", ctypes.c_longlong),
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("lr_final", ctypes.c_float)]
+
+
+class nv_sur_chains(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_longlong), ("y0", ctypes.c_void_p), ("mu", ctypes.c_void_p),
+                ("t0", ctypes.c_double), ("T", ctypes.c_double), ("n_slices", ctypes.c_int),
+                ("final_state", ctypes.c_void_p), ("boundary", ctypes.c_void_p),
+                ("fb_tab0", ctypes.c_void_p), ("fb_tab1", ctypes.c_void_p),
+                ("fb_precision", ctypes.c_int), ("fb_grid", nv_ic_grid),
+                ("guard", ctypes.c_double), ("box_lo", ctypes.c_double * 2),
+                ("box_hi", ctypes.c_double * 2)]
+
+
+class nv_sur_compose_info(ctypes.Structure):
+    _fields_ = [("n_fallback", ctypes.c_longlong), ("n_outside", ctypes.c_longlong),
+                ("max_deviation", ctypes.c_double), ("bad_chain", ctypes.c_longlong),
+                ("ms", ctypes.c_float)]
+
+
+_SIGNATURES.update({
+    "nv_sur_create": [ctypes.POINTER(nv_sur_config), ctypes.POINTER(ctypes.c_void_p)],
+    "nv_sur_destroy": [_P],
+    "nv_sur_set_params": [_P, _P],
+    "nv_sur_get_params": [_P, _P],
+    "nv_sur_forward": [_P, _P, ctypes.c_longlong, _P],
+    "nv_sur_loss_grad": [_P, _P, _P, ctypes.c_longlong, ctypes.POINTER(ctypes.c_float), _P],
+    "nv_sur_train": [_P, _P, _P, ctypes.c_longlong, ctypes.POINTER(nv_sur_train_opts), _P],
+    "nv_sur_dataset_from_batch": [_P, _P, _P, _P, _P, ctypes.c_longlong,
+                                  ctypes.POINTER(ctypes.c_longlong)],
+    "nv_sur_compose": [_P, ctypes.POINTER(nv_sur_chains), ctypes.POINTER(nv_sur_compose_info)],
+    "nv_sur_last_ms": [_P, ctypes.POINTER(ctypes.c_float)],
+})
+
+
+def make_sur_config(in_shift, in_scale, out_scale, max_batch=0, stream=None) -> nv_sur_config:
+    c = nv_sur_config()
+    for k in range(4):
+        c.in_shift[k], c.in_scale[k] = float(in_shift[k]), float(in_scale[k])
+    c.out_scale[0], c.out_scale[1] = float(out_scale[0]), float(out_scale[1])
+    c.max_batch = int(max_batch)
+    c.stream = stream
+    return c
+
+
+def nv_sur_create(cfg: nv_sur_config):
+    h = ctypes.c_void_p()
+    _check(load().nv_sur_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h
+
+
+def nv_sur_destroy(sur):
+    return _check(load().nv_sur_destroy(sur))
+
+
+def nv_sur_set_params(sur, params):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+    if p.size != NV_SUR_PARAMS:
+        raise ValueError(f"expected {NV_SUR_PARAMS} parameters, got {p.size}")
+    return _check(load().nv_sur_set_params(sur, _ptr(p)))
+
+
+def nv_sur_get_params(sur):
+    out = np.empty(NV_SUR_PARAMS, dtype=np.float32)
+    _check(load().nv_sur_get_params(sur, _ptr(out)))
+    return out
+
+
+def nv_sur_forward(sur, x_dev, n, out_dev):
+    return _check(load().nv_sur_forward(sur, x_dev, int(n), out_dev))
+
+
+def nv_sur_loss_grad(sur, x_dev, t_dev, n, want_grad=True):
+    loss = ctypes.c_float()
+    grad = np.empty(NV_SUR_PARAMS, dtype=np.float32) if want_grad else None
+    _check(load().nv_sur_loss_grad(sur, x_dev, t_dev, int(n), ctypes.byref(loss),
+                                   _ptr(grad) if grad is not None else None))
+    return loss.value, grad
+
+
+def make_train_opts(batch, steps, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                    lr_final=0.0) -> nv_sur_train_opts:
+    o = nv_sur_train_opts()
+    o.batch, o.steps = int(batch), int(steps)
+    o.lr, o.beta1, o.beta2, o.eps, o.lr_final = lr, beta1, beta2, eps, lr_final
+    return o
+
+
+def nv_sur_train(sur, x_dev, t_dev, n_samples, opts: nv_sur_train_opts, loss_dev=None):
+    return _check(load().nv_sur_train(sur, x_dev, t_dev, int(n_samples), ctypes.byref(opts),
+                                      loss_dev))
+
+
+def nv_sur_dataset_from_batch(sur, batch, perm_dev=None, x_dev=None, t_dev=None, cap=0):
+    total = ctypes.c_longlong()
+    _check(load().nv_sur_dataset_from_batch(sur, batch, perm_dev, x_dev, t_dev, int(cap),
+                                            ctypes.byref(total)))
+    return total.value
+
+
+def nv_sur_compose(sur, chains: nv_sur_chains):
+    """Returns (status, info); raises on statuses other than NV_OK and
+    NV_ERR_NONFINITE."""
+    info = nv_sur_compose_info()
+    st = load().nv_sur_compose(sur, ctypes.byref(chains), ctypes.byref(info))
+    if st not in (NV_OK, NV_ERR_NONFINITE):
+        _check(st)
+    return st, info
+
+
+def nv_sur_last_ms(sur):
+    ms = ctypes.c_float()
+    _check(load().nv_sur_last_ms(sur, ctypes.byref(ms)))
+    return ms.value

@@ -174,3 +174,60 @@ def paper_model(n_slices: int, M: int, dt: float, precision: str = "fp64") -> Wo
 # Chebyshev nodes, N in {32, 64, 128} slices, single precision.
 PAPER_TABLE3 = [(dt, n, M) for dt, M in ((2.0 ** -14, 4), (2.0 ** -15, 5), (2.0 ** -16, 7))
                 for n in (32, 64, 128)]
+
+
+# ---- learned surrogate of the Van der Pol slice map ---------------------------
+# Network input x = (y1, y2, slice start time, mu), normalised as
+# (x - shift) * scale so that the box [-3, 3] x [-8, 8], the interval [0, 50] and
+# mu in [1, 5] map to [-1, 1]; outputs are slice displacements in units of
+# SUR_OUT_SCALE (about their standard deviation over the box for slices of
+# length 50/1024).
+SUR_IN_SHIFT = (0.0, 0.0, 25.0, 3.0)
+SUR_IN_SCALE = (1.0 / 3.0, 1.0 / 8.0, 1.0 / 25.0, 0.5)
+SUR_OUT_SCALE = (0.2, 1.6)
+
+
+def surrogate_training_problems(n_slices: int = 1024, grid_n=(128, 128), steps: int = 500,
+                                seed: int = 17, T: float = 50.0):
+    """The training build: Van der Pol on [0, T] cut into n_slices slices, slice j
+    integrated with its own mu_j ~ U[1, 5] (seeded), each slice a one-slice
+    problem of a batch.  With the defaults: 1024 x 128 x 128 = 16.7M endpoints."""
+    rng = np.random.default_rng(seed)
+    mus = rng.uniform(1.0, 5.0, n_slices)
+    L = T / n_slices
+    return [Workload(name=f"sur-train-{j:04d}", rhs="vdp", params=(float(mus[j]),), t0=j * L,
+                     T=(j + 1) * L, n_slices=1, grid_n=tuple(grid_n), grid_lo=(-3.0, -8.0),
+                     grid_hi=(3.0, 8.0), steps_per_slice=steps, y0=(2.0, 0.0),
+                     precision="fp32", interp="bilinear") for j in range(n_slices)]
+
+
+def surrogate_init_params(seed: int = 0) -> np.ndarray:
+    """Initial network parameters, flat (W1, b1, W2, b2, W3, b3, W4, b4): each
+    layer's weights and biases uniform in +-1/sqrt(fan_in)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for rows, cols in ((128, 4), (128, 128), (128, 128), (2, 128)):
+        bound = 1.0 / np.sqrt(cols)
+        parts.append(rng.uniform(-bound, bound, rows * cols))
+        parts.append(rng.uniform(-bound, bound, rows))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def surrogate_perm(total: int, seed: int = 5) -> np.ndarray:
+    """The one-time shuffle of the training set (int64 permutation)."""
+    return np.random.default_rng(seed).permutation(total).astype(np.int64)
+
+
+def surrogate_eval_mus(count: int = 8, seed: int = 23) -> np.ndarray:
+    """Held-out Van der Pol parameters for evaluating the surrogate."""
+    return np.random.default_rng(seed).uniform(1.0, 5.0, count)
+
+
+def surrogate_samples(n: int, seed: int):
+    """Seeded network inputs over the training box and targets of unit scale,
+    (4, n) and (2, n) float32, for parity checks of the network itself."""
+    rng = np.random.default_rng(seed)
+    x = np.stack([rng.uniform(-3, 3, n), rng.uniform(-8, 8, n), rng.uniform(0, 50, n),
+                  rng.uniform(1, 5, n)]).astype(np.float32)
+    t = rng.normal(0.0, 1.0, (2, n)).astype(np.float32)
+    return x, t

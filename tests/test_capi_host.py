@@ -1,14 +1,16 @@
 """Host-side checks of the C ABI: the library loads, exports every entry point
-include/nv.h declares, and its argument checking answers without a GPU (every
-call here returns before touching the HIP runtime)."""
+the headers under include/ declare, and its argument checking answers without
+a GPU (every call here returns before touching the HIP runtime)."""
 import ctypes
+import glob
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "nv.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 @pytest.fixture(scope="module")
@@ -22,7 +24,7 @@ def nvmod():
 
 
 def declared_entry_points():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"NV_API\s+[^;(]*?\b(nv_\w+)\s*\(", text)))
 
 
@@ -31,7 +33,8 @@ def test_header_declares_the_boundary():
     for must in ("nv_build_propagators", "nv_compose", "nv_solve", "nv_ctx_create",
                  "nv_ctx_destroy",
                  "nv_set_options", "nv_set_buffers", "nv_required_bytes", "nv_get_table",
-                 "nv_locate", "nv_last_error"):
+                 "nv_locate", "nv_last_error", "nv_sur_create", "nv_sur_train",
+                 "nv_sur_loss_grad", "nv_sur_compose", "nv_sur_dataset_from_batch"):
         assert must in names
 
 
@@ -187,3 +190,45 @@ def test_batched_workload_recipe():
             assert -2.0 <= w.params[0] <= 0.5
         if w.rhs == "vdp":
             assert 1.0 <= w.params[0] <= 5.0
+
+
+def test_surrogate_argument_errors_need_no_gpu(nvmod):
+    from paper_1304_6514_amd import workloads as W
+    lib = nvmod.load()
+    good = dict(in_shift=W.SUR_IN_SHIFT, in_scale=W.SUR_IN_SCALE, out_scale=W.SUR_OUT_SCALE)
+    for bad in (dict(out_scale=(0.2, 0.0)), dict(out_scale=(float("nan"), 1.0)),
+                dict(in_scale=(1.0, float("inf"), 1.0, 1.0)), dict(max_batch=24),
+                dict(max_batch=(1 << 20) + 16)):
+        kw = dict(good, **bad)
+        cfg = nvmod.make_sur_config(kw["in_shift"], kw["in_scale"], kw["out_scale"],
+                                    kw.get("max_batch", 0))
+        h = ctypes.c_void_p()
+        assert lib.nv_sur_create(ctypes.byref(cfg), ctypes.byref(h)) == nvmod.NV_ERR_INVALID_ARG
+        assert h.value is None
+    assert lib.nv_sur_create(None, None) == nvmod.NV_ERR_INVALID_ARG
+    assert lib.nv_sur_destroy(None) == 0
+    for fn, args in (("nv_sur_set_params", (None, None)), ("nv_sur_get_params", (None, None)),
+                     ("nv_sur_forward", (None, None, 1, None)),
+                     ("nv_sur_loss_grad", (None, None, None, 16, None, None)),
+                     ("nv_sur_train", (None, None, None, 16, None, None)),
+                     ("nv_sur_compose", (None, None, None)),
+                     ("nv_sur_last_ms", (None, None))):
+        assert getattr(lib, fn)(*args) == nvmod.NV_ERR_INVALID_ARG, fn
+    assert "NULL" in nvmod.nv_last_error()
+
+
+def test_surrogate_input_recipe():
+    from paper_1304_6514_amd import workloads as W
+    probs = W.surrogate_training_problems()
+    assert len(probs) == 1024
+    assert sum(p.points_per_slice * p.n_slices for p in probs) == 16777216
+    mus = np.array([p.params[0] for p in probs])
+    assert mus.min() >= 1.0 and mus.max() <= 5.0 and abs(mus.mean() - 3.0) < 0.15
+    L = 50.0 / 1024
+    assert all(abs(p.t0 - j * L) < 1e-12 and abs(p.T - p.t0 - L) < 1e-12
+               for j, p in enumerate(probs))
+    p = W.surrogate_init_params(0)
+    assert p.dtype == np.float32 and p.size == 33922
+    assert np.abs(p[:512]).max() <= 0.5 and np.abs(p[640:640 + 16384]).max() <= 1 / np.sqrt(128)
+    perm = W.surrogate_perm(1000, seed=1)
+    assert np.array_equal(np.sort(perm), np.arange(1000))

@@ -1,0 +1,223 @@
+"""GPU parity of the learned slice-map surrogate against its FP64 oracle: the
+network's forward pass, the loss and gradient of a minibatch, the Adam update,
+a short training run, the training-set gather and the composition with the
+network, with and without the table fallback.
+
+Tolerances.  The oracle is run twice: in FP64 throughout, and with bfloat16
+rounding at the points where the kernels feed the matrix cores (operands of
+the two 128 x 128 layers, of their back-propagation and of every gradient sum).
+Against the second the only differences left are FP32 against FP64
+accumulation, the FP32 evaluation of erf (absolute error below 1.5e-7) and the
+rare bfloat16 rounding that these flip; against the first, the bfloat16
+rounding itself (unit roundoff 2^-9 = 2.0e-3 per operand) bounds the relative
+error of every matrix product, which gives the looser bars below."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as mo
+from paper_1304_6514_amd import nv
+from paper_1304_6514_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SHIFT = np.array(W.SUR_IN_SHIFT)
+SCALE = np.array(W.SUR_IN_SCALE, dtype=np.float32).astype(np.float64)
+OUT_SCALE = np.array(W.SUR_OUT_SCALE)
+
+
+def say(*a):
+    print("[gpu-test]", *a, file=sys.__stderr__, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    nv.load()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def sur(torch):
+    from paper_1304_6514_amd.surrogate import Surrogate
+    s = Surrogate("cuda:0", max_batch=8192)
+    yield s
+    s.close()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def test_forward_matches_oracle(sur):
+    p = W.surrogate_init_params(1)
+    sur.set_params(p)
+    x, _ = W.surrogate_samples(1000, seed=2)          # 1000: not a multiple of 16 or 64
+    say("forward n=1000")
+    out = sur.forward(x).cpu().numpy().T
+    emu, _ = mo.forward(p.astype(np.float64), x.T.astype(np.float64), SHIFT, SCALE,
+                        emulate_bf16=True)
+    ref, _ = mo.forward(p.astype(np.float64), x.T.astype(np.float64), SHIFT, SCALE)
+    e_emu, e_ref = np.max(np.abs(out - emu)), np.max(np.abs(out - ref))
+    say(f"forward: max |gpu - oracle(bf16)| = {e_emu:.3g}, |gpu - oracle(fp64)| = {e_ref:.3g}, "
+        f"max |out| = {np.max(np.abs(ref)):.3g}")
+    assert e_emu < 1e-4
+    assert e_ref < 2e-2 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("n", [16, 4112])
+def test_loss_and_gradient_match_oracle(sur, n):
+    p = W.surrogate_init_params(3)
+    sur.set_params(p)
+    x, t = W.surrogate_samples(n, seed=4)
+    say(f"loss_grad n={n}")
+    loss, g = sur.loss_grad(x, t)
+    p64 = p.astype(np.float64)
+    l_emu, g_emu = mo.loss_and_grad(p64, x.T.astype(np.float64), t.T.astype(np.float64), SHIFT,
+                                    SCALE, emulate_bf16=True)
+    l_ref, g_ref = mo.loss_and_grad(p64, x.T.astype(np.float64), t.T.astype(np.float64), SHIFT,
+                                    SCALE)
+    assert abs(loss - l_emu) <= 1e-5 * l_emu, (loss, l_emu)
+    assert abs(loss - l_ref) <= 1e-3 * l_ref, (loss, l_ref)
+    gu = mo.unflatten(g)
+    worst = []
+    for name, _ in mo.SHAPES:
+        r_emu, r_ref = _rel(gu[name], g_emu[name]), _rel(gu[name], g_ref[name])
+        worst.append((name, r_emu, r_ref))
+        assert r_emu < 2e-3, (name, r_emu)
+        assert r_ref < 3e-2, (name, r_ref)
+    say("gradient rel. L2 error vs oracle (bf16-emulating, fp64): " +
+        ", ".join(f"{k} {a:.2g}/{b:.2g}" for k, a, b in worst))
+
+
+def test_adam_update_matches_oracle(sur, torch):
+    p = W.surrogate_init_params(5)
+    sur.set_params(p)
+    x, t = W.surrogate_samples(2048, seed=6)
+    opt = mo.Adam(mo.N_PARAMS, lr=2e-3, beta1=0.9, beta2=0.99, eps=1e-8)
+    theta = p.astype(np.float64)
+    for k in range(3):
+        _, g = sur.loss_grad(x, t)                    # gradient at the current parameters
+        theta = opt.step(theta, g.astype(np.float64))
+        sur.train(x, t, batch=2048, steps=1, lr=2e-3, beta1=0.9, beta2=0.99, eps=1e-8)
+        got = sur.params().astype(np.float64)
+        err = np.max(np.abs(got - theta))
+        say(f"adam step {k + 1}: max |gpu - oracle| = {err:.3g}")
+        assert err < 1e-6
+    # the bf16 copies of the weights follow the update
+    out = sur.forward(x[:, :256]).cpu().numpy().T
+    emu, _ = mo.forward(sur.params().astype(np.float64), x[:, :256].T.astype(np.float64), SHIFT,
+                        SCALE, emulate_bf16=True)
+    assert np.max(np.abs(out - emu)) < 1e-4
+
+
+def test_training_run_tracks_oracle(sur, torch):
+    """Twelve Adam steps over a 4-minibatch data set: the GPU's per-step losses
+    follow the oracle's (bf16-emulating) training run."""
+    p = W.surrogate_init_params(7)
+    sur.set_params(p)
+    B, steps = 1024, 12
+    x, t = W.surrogate_samples(4 * B, seed=8)
+    say("training run 12 steps")
+    losses = sur.train(x, t, batch=B, steps=steps, lr=3e-3).cpu().numpy()
+    opt = mo.Adam(mo.N_PARAMS, lr=3e-3)
+    theta = p.astype(np.float64)
+    ref = []
+    for k in range(steps):
+        sl = slice((k * B) % (4 * B), (k * B) % (4 * B) + B)
+        l, g = mo.loss_and_grad(theta, x[:, sl].T.astype(np.float64),
+                                t[:, sl].T.astype(np.float64), SHIFT, SCALE, emulate_bf16=True)
+        ref.append(l)
+        theta = opt.step(theta, mo.flatten(g))
+    ref = np.array(ref)
+    say("losses gpu  ", np.array2string(losses, precision=5))
+    say("losses oracle", np.array2string(ref, precision=5))
+    assert np.max(np.abs(losses - ref) / ref) < 2e-3
+    assert losses[-1] < losses[0]
+
+
+def _train_batch(torch):
+    from paper_1304_6514_amd.propagator import Batch
+    probs = W.surrogate_training_problems(n_slices=8, grid_n=(12, 10), steps=40, seed=9)
+    b = Batch(probs, precision="fp32")
+    st, _, _ = b.run()
+    assert st == nv.NV_OK
+    return probs, b
+
+
+def test_training_set_gather_is_exact(sur, torch):
+    probs, b = _train_batch(torch)
+    try:
+        M = 12 * 10
+        total = len(probs) * M
+        perm = W.surrogate_perm(total, seed=10)
+        x, t = sur.dataset_from_batch(b, perm)
+        x, t = x.cpu().numpy(), t.cpu().numpy()
+        for i, w in enumerate(probs):
+            tabs = [nv.nv_batch_get_table(b.batch, i, c, 1, M, "fp32")[0] for c in range(2)]
+            k = np.arange(M)
+            k0, k1 = k // 10, k % 10
+            d0 = (w.grid_hi[0] - w.grid_lo[0]) / 11
+            d1 = (w.grid_hi[1] - w.grid_lo[1]) / 9
+            y0 = (w.grid_lo[0] + k0 * d0).astype(np.float32)
+            y1 = (w.grid_lo[1] + k1 * d1).astype(np.float32)
+            pos = perm[i * M + k]
+            assert np.array_equal(x[0, pos], y0) and np.array_equal(x[1, pos], y1)
+            assert np.all(x[2, pos] == np.float32(w.t0))
+            assert np.all(x[3, pos] == np.float32(w.params[0]))
+            e0 = ((tabs[0].astype(np.float64) - y0) / OUT_SCALE[0]).astype(np.float32)
+            e1 = ((tabs[1].astype(np.float64) - y1) / OUT_SCALE[1]).astype(np.float32)
+            assert np.array_equal(t[0, pos], e0) and np.array_equal(t[1, pos], e1)
+        say(f"training-set gather: {total} samples bit-exact")
+    finally:
+        b.close()
+
+
+def test_compose_matches_oracle_chain(sur, torch):
+    p = W.surrogate_init_params(11)
+    p[mo.N_PARAMS - 258:] *= 0.2                      # a gentle map: small W4, b4
+    sur.set_params(p)
+    rng = np.random.default_rng(12)
+    Q, N = 37, 16
+    y0 = np.column_stack([rng.uniform(-2, 2, Q), rng.uniform(-4, 4, Q)])
+    mu = rng.uniform(1, 5, Q)
+    say(f"surrogate compose Q={Q} N={N}")
+    st, final, bnd, info = sur.compose(y0, mu, 0.0, 50.0 * N / 1024, N, want_boundary=True)
+    assert st == nv.NV_OK and info.bad_chain == -1
+    final, bnd = final.cpu().numpy(), bnd.cpu().numpy()
+    worst = 0.0
+    for q in range(Q):
+        ref = mo.surrogate_chain(p.astype(np.float64), SHIFT, SCALE, OUT_SCALE, y0[q], mu[q], 0.0,
+                                 50.0 * N / 1024, N, emulate_bf16=True)
+        worst = max(worst, float(np.max(np.abs(bnd[q] - ref))))
+        assert np.array_equal(bnd[q, -1], final[q])
+    say(f"chains: max |gpu - oracle(bf16)| over boundary states = {worst:.3g}")
+    assert worst < 1e-4
+
+
+def test_compose_fallback_reproduces_bilinear_composition(sur, torch):
+    """With guard < 0 every step takes the table's value: the result is the
+    library's bilinear composition over the same table, to the bit."""
+    from paper_1304_6514_amd.propagator import Propagator
+    w = W.small(W.VDP_FP32, 24, (20, 20), 60)
+    sur.set_params(W.surrogate_init_params(13))
+    with Propagator("cuda:0") as prop:
+        prop.build(w)
+        res = prop.compose()
+        y_ref = np.asarray(res.yT)
+        Q = 3
+        st, final, _, info = sur.compose(np.tile(w.y0, (Q, 1)), np.full(Q, w.params[0]), w.t0,
+                                         w.T, w.n_slices, fallback=prop, guard=-1.0)
+        assert st == nv.NV_OK
+        assert info.n_fallback == Q * w.n_slices
+        assert np.array_equal(final.cpu().numpy(), np.tile(y_ref, (Q, 1)))
+        # guard = inf: no step falls back inside the box, and the deviation is reported
+        st, final2, _, info2 = sur.compose(np.tile(w.y0, (Q, 1)), np.full(Q, w.params[0]),
+                                           w.t0, w.T, w.n_slices, fallback=prop,
+                                           guard=float("inf"))
+        assert info2.max_deviation > 0.0
+        say(f"fallback: {info.n_fallback} steps reproduce the bilinear chain; guard=inf: "
+            f"{info2.n_fallback} fallbacks, max deviation {info2.max_deviation:.3g}")

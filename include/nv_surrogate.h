@@ -116,7 +116,9 @@ NV_API nv_status nv_sur_train(nv_sur *sur, const float *x_dev, const float *targ
  * permutation of 0 .. total-1): x = (xi_k, T_j, mu_i), target =
  * (tab[c][j][k] - xi_k[c]) / out_scale[c].  *total receives the number of
  * samples; x_dev / target_dev (device, [4][cap] and [2][cap] fp32) may be NULL
- * to query it.  Errors: INVALID_ARG (foreign problem, cap < total), HIP. */
+ * to query it.  Errors: INVALID_ARG (foreign problem, cap < total, perm entry
+ * outside [0, cap)), NOT_BUILT (the batch has not run), NONFINITE (a table
+ * entry is not finite: the data set is written but unusable), HIP. */
 NV_API nv_status nv_sur_dataset_from_batch(nv_sur *sur, nv_batch *batch,
                                            const long long *perm_dev, float *x_dev,
                                            float *target_dev, long long cap,

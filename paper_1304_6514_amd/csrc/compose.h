@@ -134,24 +134,34 @@ __device__ inline void compose_range(const ComposeArgs &a) {
 }
 
 // The chain with Lagrange interpolation on Chebyshev nodes (paper mode), run
-// by one whole wave of 64 lanes: for each slice the M*M factors
-// (x - xi_m) / (xi_k - xi_m) are independent once lambda_j is known and are
-// computed one per lane; lane k then multiplies its node value by its factors
-// in ascending m, and every lane sums the M terms in ascending k -- exactly the
-// operation sequence of the written rule, so the result is the same to the bit.
+// by one wave of 64 lanes, lane k < M owning node k.  For each slice, lane k
+// forms its term t[k] * prod_m f_km, f_km = (x - xi_m) / (xi_k - xi_m) (the
+// diagonal factor is exactly 1, so multiplying by it changes nothing), with m
+// ascending; its M divisions are independent of one another, so they overlap.
+// The terms are then summed in ascending k by reading them lane by lane
+// (v_readlane: no LDS, no barrier).  This is exactly the operation sequence of
+// the written rule, so the result is the same to the bit.
 constexpr int kMaxLagrange = 64;
+
+__device__ inline double readlane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(b & 0xffffffffLL), l));
+    const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(b >> 32), l));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Table rows staged in LDS per refill: the rows of a range are loaded in
+// chunks of kLagrangeStage values with all loads in flight at once, so the
+// chain pays the memory latency once per chunk instead of once per slice.
+constexpr int kLagrangeStage = 4096;
 
 template <class T>
 __device__ inline void compose_range_lagrange(const ComposeArgs &a) {
 #pragma clang fp contract(off)
-    __shared__ double fac[kMaxLagrange * kMaxLagrange];
-    __shared__ double terms[kMaxLagrange];
-    __shared__ double xs[kMaxLagrange];       // the nodes, read from memory once
-    __shared__ int row_bad;
+    __shared__ double rows[kLagrangeStage];
     const int lane = int(threadIdx.x);
     const int M = a.n0;
-    for (int k = lane; k < M; k += int(blockDim.x)) xs[k] = a.nodes[k];
-    __syncthreads();
+    const double xk = lane < M ? a.nodes[lane] : 0.0;
     const T *tab0 = static_cast<const T *>(a.tab0);
     double lam;
     if (a.j_begin == 0) {
@@ -168,44 +178,37 @@ __device__ inline void compose_range_lagrange(const ComposeArgs &a) {
     }
     long long oog = 0;
     int bad_slice = -1;
-    // a row of the table does not depend on lambda: lane k holds node k's
-    // value of the current slice and loads the next slice's while it works
-    double v_next = (lane < M && a.j_begin < a.j_end)
-                        ? double(tab0[(long long)a.j_begin * M + lane]) : 0.0;
-    for (int j = a.j_begin; j < a.j_end; ++j) {
-        const double vk = v_next;
-        if (lane < M && j + 1 < a.j_end) v_next = double(tab0[(long long)(j + 1) * M + lane]);
-        if (!finite(lam)) {
-            bad_slice = j;
-            break;
-        }
-        if (lane == 0) row_bad = 0;
-        // the diagonal factor is exactly 1: multiplying by it changes nothing,
-        // and the product loop below needs no branch
-        for (int idx = lane; idx < M * M; idx += int(blockDim.x)) {
-            const int k = idx / M, m = idx - k * M;
-            fac[idx] = k == m ? 1.0 : (lam - xs[m]) / (xs[k] - xs[m]);
-        }
+    const int rows_per_chunk = kLagrangeStage / M;
+    for (int c0 = a.j_begin; c0 < a.j_end && bad_slice < 0; c0 += rows_per_chunk) {
+        const int c1 = c0 + rows_per_chunk < a.j_end ? c0 + rows_per_chunk : a.j_end;
+        __syncthreads();                          // the previous chunk is consumed
+        const long long base = (long long)c0 * M, count = (long long)(c1 - c0) * M;
+        for (long long i = lane; i < count; i += int(blockDim.x))
+            rows[i] = double(tab0[base + i]);
         __syncthreads();
-        if (lane < M) {
-            if (!finite(vk)) row_bad = 1;
+        for (int j = c0; j < c1; ++j) {
+            if (!finite(lam)) {
+                bad_slice = j;
+                break;
+            }
+            const double vk = lane < M ? rows[(j - c0) * M + lane] : 0.0;
+            if (__any(lane < M && !finite(vk))) {
+                bad_slice = j;
+                break;
+            }
             double term = vk;
 #pragma unroll 8
-            for (int m = 0; m < M; ++m) term *= fac[lane * M + m];
-            terms[lane] = term;
+            for (int m = 0; m < M; ++m) {
+                const double xm = readlane_f64(xk, m);
+                const double f = (lam - xm) / (xk - xm);
+                term *= (m == lane) ? 1.0 : f;
+            }
+            oog += (lam < a.lo0 || lam > a.hi0) ? 1 : 0;
+            double sum = 0.0;
+            for (int k = 0; k < M; ++k) sum += readlane_f64(term, k);
+            lam = sum;
+            if (lane == 0) a.boundary[j + 1] = lam;
         }
-        __syncthreads();
-        if (row_bad) {
-            bad_slice = j;
-            break;
-        }
-        oog += (lam < a.lo0 || lam > a.hi0) ? 1 : 0;
-        double sum = 0.0;
-#pragma unroll 8
-        for (int k = 0; k < M; ++k) sum += terms[k];
-        lam = sum;
-        if (lane == 0) a.boundary[j + 1] = lam;
-        __syncthreads();      // factors and terms are rewritten for the next slice
     }
     if (lane == 0) {
         a.status->n_out_of_grid += oog;

@@ -442,6 +442,7 @@ __global__ __launch_bounds__(256) void sur_dataset_kernel(DatasetArgs a) {
             atomicOr(a.error, 1);
             continue;
         }
+        if (!isfinite(e0) || !isfinite(e1)) atomicOr(a.error, 2);
         a.x[pos] = y0;
         a.x[a.cap + pos] = y1;
         a.x[2 * a.cap + pos] = float(s.t0 + double(j) * s.L);
@@ -779,7 +780,8 @@ NV_API nv_status nv_sur_dataset_from_batch(nv_sur *s, nv_batch *batch, const lon
     (void)hipFree(dsrc);
     if (e != hipSuccess)
         return fail(NV_ERR_HIP, "training-set gather failed: %s", hipGetErrorString(e));
-    if (err) return fail(NV_ERR_INVALID_ARG, "perm holds a position outside [0, cap)");
+    if (err & 1) return fail(NV_ERR_INVALID_ARG, "perm holds a position outside [0, cap)");
+    if (err & 2) return fail(NV_ERR_NONFINITE, "the batch's tables hold non-finite endpoints");
     return NV_OK;
 }
 

@@ -141,7 +141,9 @@ def test_training_run_tracks_oracle(sur, torch):
 
 def _train_batch(torch):
     from paper_1304_6514_amd.propagator import Batch
-    probs = W.surrogate_training_problems(n_slices=8, grid_n=(12, 10), steps=40, seed=9)
+    # eight slices of the training build's length 50/1024
+    probs = W.surrogate_training_problems(n_slices=8, grid_n=(12, 10), steps=40, seed=9,
+                                          T=8 * 50.0 / 1024)
     b = Batch(probs, precision="fp32")
     st, _, _ = b.run()
     assert st == nv.NV_OK

@@ -335,7 +335,9 @@ def bench_surrogate(args):
     if st != nv.NV_OK:
         raise RuntimeError(f"training build failed: {nv.status_name(st)}")
     build_ms, build_steps = b.last_timing()
-    sur = Surrogate("cuda:0", max_batch=B)
+    coarse = args.sur_coarse
+    sur = Surrogate("cuda:0", max_batch=B, coarse_steps=coarse,
+                    out_scale=W.SUR_OUT_SCALE if coarse == 0 else W.SUR_OUT_SCALE_COARSE)
     total = nv.nv_sur_dataset_from_batch(sur.h, b.batch)
     perm = W.surrogate_perm(total)
     t = time.perf_counter()
@@ -432,6 +434,7 @@ def bench_surrogate(args):
         "data": "synthetic",
         "config": {"workload": "vdp-surrogate-1024x128x128x500-perslice-mu",
                    "network": "4-128-128-128-2 exact GELU", "batch": B, "epochs": args.sur_epochs,
+                   "coarse_rk4_steps": coarse,
                    "samples": total, "lr": [args.sur_lr, args.sur_lr_final],
                    "parallelism": "single-gpu"},
         "training_build": {"ms": round(build_ms, 3), "trajectory_steps": build_steps,
@@ -489,6 +492,8 @@ def main():
                     help="surrogate: passes over the 16.7M-sample training set")
     ap.add_argument("--sur-lr", type=float, default=2e-3)
     ap.add_argument("--sur-lr-final", type=float, default=2e-5)
+    ap.add_argument("--sur-coarse", type=int, default=1,
+                    help="surrogate: RK4 steps of the coarse propagator the network corrects")
     ap.add_argument("--sur-guard", type=float, default=0.05,
                     help="surrogate: deviation from the table above which the table is used")
     args = ap.parse_args()

@@ -17,7 +17,12 @@
  *     out = W4 a3 + b4              W4: 2 x 128      (FP32 arithmetic)
  * gelu(z) = z Phi(z) with Phi the standard normal distribution function (the
  * exact GELU of Hendrycks and Gimpel).  The surrogate slice map is
- *     phi(y) ~ y + out_scale * out(y, T_j, mu)      (FP64 update of the state).
+ *     phi(y) ~ G(y) + out_scale * out(y, T_j, mu)   (FP64 update of the state),
+ * where G is a cheap coarse propagator over the slice: coarse_steps = 0 gives
+ * G(y) = y (the network learns the whole displacement), coarse_steps = k > 0
+ * gives k classical RK4 steps of length slice_length / k of the Van der Pol
+ * field with the sample's mu, in FP64 (the network learns the correction to
+ * that coarse step, a far smaller quantity away from the stiff regions).
  *
  * Flat parameter order (NV_SUR_PARAMS fp32 numbers): W1 (row-major, output
  * row by input column), b1, W2, b2, W3, b3, W4, b4.
@@ -54,7 +59,10 @@ typedef struct nv_sur nv_sur;
 typedef struct {
     float in_shift[NV_SUR_IN];   /* input normalisation u = (x - in_shift) * in_scale */
     float in_scale[NV_SUR_IN];
-    double out_scale[NV_SUR_OUT];/* displacement per unit of network output, > 0 */
+    double out_scale[NV_SUR_OUT];/* correction per unit of network output, > 0 */
+    double slice_length;         /* L the network is trained for (> 0): training sets and
+                                    compositions must have slices of this length */
+    int coarse_steps;            /* 0: G(y) = y; 1..16: RK4 steps of the coarse propagator */
     long long max_batch;         /* largest minibatch of nv_sur_loss_grad / nv_sur_train:
                                     a multiple of 16, 16 .. 2^20 (0 = 65536); sizes the
                                     library's training workspace (about 1.6 KB per sample) */
@@ -63,8 +71,8 @@ typedef struct {
 
 /* Create a surrogate with zero parameters on the current device.  Allocates
  * the parameters, the Adam moments and the training workspace.
- * Errors: INVALID_ARG (cfg NULL, non-finite or non-positive scales, max_batch
- * out of range), OOM, HIP. */
+ * Errors: INVALID_ARG (cfg NULL, non-finite or non-positive scales or slice
+ * length, max_batch or coarse_steps out of range), OOM, HIP. */
 NV_API nv_status nv_sur_create(const nv_sur_config *cfg, nv_sur **out);
 NV_API nv_status nv_sur_destroy(nv_sur *sur);
 
@@ -114,7 +122,8 @@ NV_API nv_status nv_sur_train(nv_sur *sur, const float *x_dev, const float *targ
  * slice, point by point from 0, is written to position perm_dev[number] (or to
  * its own number when perm_dev is NULL; perm_dev, device int64, must be a
  * permutation of 0 .. total-1): x = (xi_k, T_j, mu_i), target =
- * (tab[c][j][k] - xi_k[c]) / out_scale[c].  *total receives the number of
+ * (tab[c][j][k] - G(xi_k)[c]) / out_scale[c].  Every problem's slices must
+ * have the configured slice_length (relative 1e-9).  *total receives the number of
  * samples; x_dev / target_dev (device, [4][cap] and [2][cap] fp32) may be NULL
  * to query it.  Errors: INVALID_ARG (foreign problem, cap < total, perm entry
  * outside [0, cap)), NOT_BUILT (the batch has not run), NONFINITE (a table
@@ -126,8 +135,9 @@ NV_API nv_status nv_sur_dataset_from_batch(nv_sur *sur, nv_batch *batch,
 
 /* The composition with the network in place of the lookup, for count
  * independent chains q (device arrays): lambda_0 = y0[q], and for j = 0..N-1
- *     lambda_{j+1} = lambda_j + out_scale * out(lambda_j, T_j, mu[q]),
- * T_j = t0 + j (T - t0) / N, the state kept in FP64.
+ *     lambda_{j+1} = G(lambda_j) + out_scale * out(lambda_j, T_j, mu[q]),
+ * T_j = t0 + j (T - t0) / N, the state kept in FP64; (T - t0) / N must equal
+ * the configured slice_length (relative 1e-9).
  *
  * Fallback and judge: when fb_tab0 is not NULL, (fb_tab0, fb_tab1) are the
  * two component tables of a built Van der Pol context for the same mu, t0, T

@@ -16,8 +16,9 @@ multilayer perceptron
     out = W4 a3 + b4                         W4: 2 x 128
 
 with the exact GELU, gelu(z) = z Phi(z), Phi the standard normal distribution
-function.  Its output is the slice displacement in units of ``out_scale``:
-phi^j(y) ~ y + out_scale * out.  The training loss is the mean over samples of
+function.  Its output is the slice map's correction to a coarse propagator G
+in units of ``out_scale``: phi^j(y) ~ G(y) + out_scale * out, G the identity
+or a few RK4 steps over the slice (``coarse_step``).  The training loss is the mean over samples of
 the squared error summed over the two outputs; the optimiser is Adam (Kingma
 and Ba, "Adam: a method for stochastic optimization", Algorithm 1).
 
@@ -153,17 +154,39 @@ class Adam:
         return np.asarray(theta, np.float64) - self.lr * m_hat / (np.sqrt(v_hat) + self.eps)
 
 
+def coarse_step(y, mu, L, k):
+    """The coarse propagator G over a slice of length L: k classical RK4 steps
+    of h = L / k of the Van der Pol field y1' = y2, y2' = mu (1 - y1^2) y2 - y1
+    (k = 0: the identity).  y: (..., 2)."""
+    y = np.array(y, dtype=np.float64)
+    if k == 0:
+        return y
+
+    def f(v):
+        return np.stack([v[..., 1], mu * (1.0 - v[..., 0] ** 2) * v[..., 1] - v[..., 0]], -1)
+
+    h = L / k
+    for _ in range(k):
+        k1 = f(y)
+        k2 = f(y + 0.5 * h * k1)
+        k3 = f(y + 0.5 * h * k2)
+        k4 = f(y + h * k3)
+        y = y + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    return y
+
+
 def surrogate_chain(params, shift, scale, out_scale, y0, mu, t0, T, n_slices,
-                    emulate_bf16=False):
+                    emulate_bf16=False, coarse_steps=0):
     """The sequential pass with the network in place of the lookup:
-    lambda_0 = y0, lambda_{j+1} = lambda_j + out_scale * net(lambda_j, T_j, mu),
-    T_j = t0 + j (T - t0) / n_slices.  Returns lambda_0 .. lambda_N, (N+1, 2)."""
+    lambda_0 = y0, lambda_{j+1} = G(lambda_j) + out_scale * net(lambda_j, T_j, mu),
+    T_j = t0 + j (T - t0) / n_slices, G the coarse propagator (coarse_step).
+    Returns lambda_0 .. lambda_N, (N+1, 2)."""
     L = (T - t0) / n_slices
     lam = np.array(y0, np.float64)
     bnd = [lam.copy()]
     for j in range(n_slices):
         x = np.array([[lam[0], lam[1], t0 + j * L, mu]])
         out, _ = forward(params, x, shift, scale, emulate_bf16)
-        lam = lam + np.asarray(out_scale, np.float64) * out[0]
+        lam = coarse_step(lam, mu, L, coarse_steps) + np.asarray(out_scale, np.float64) * out[0]
         bnd.append(lam.copy())
     return np.array(bnd)

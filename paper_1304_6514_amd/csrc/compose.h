@@ -151,14 +151,36 @@ __device__ inline double readlane_f64(double v, int l) {
 }
 
 // Table rows staged in LDS per refill: the rows of a range are loaded in
-// chunks of kLagrangeStage values with all loads in flight at once, so the
-// chain pays the memory latency once per chunk instead of once per slice.
+// chunks of kLagrangeStage values with all loads in flight at once, and the
+// boundary states of a chunk are collected in LDS and written out after it, so
+// that no global memory operation sits inside the dependent chain (a store in
+// flight would make the next load wait: the memory counter is in order).
 constexpr int kLagrangeStage = 4096;
 
-template <class T>
-__device__ inline void compose_range_lagrange(const ComposeArgs &a) {
+// The Lagrange value of one slice: lane k < M holds node xk and table value
+// vk; MC > 0 is the node count as a compile-time constant (its M independent
+// divisions are then unrolled and overlap), MC = 0 a run-time M.
+template <int MC>
+__device__ inline double lagrange_value(double lam, double xk, double vk, int lane, int M) {
 #pragma clang fp contract(off)
-    __shared__ double rows[kLagrangeStage];
+    constexpr int kUnroll = MC > 0 ? MC : 1;
+    const int Mn = MC > 0 ? MC : M;
+    double term = vk;
+#pragma unroll kUnroll
+    for (int m = 0; m < Mn; ++m) {
+        const double xm = readlane_f64(xk, m);
+        const double f = (lam - xm) / (xk - xm);
+        term *= (m == lane) ? 1.0 : f;
+    }
+    double sum = 0.0;
+#pragma unroll kUnroll
+    for (int k = 0; k < Mn; ++k) sum += readlane_f64(term, k);
+    return sum;
+}
+
+template <class T, int MC>
+__device__ inline void lagrange_chain(const ComposeArgs &a, double *rows, double *bnd) {
+#pragma clang fp contract(off)
     const int lane = int(threadIdx.x);
     const int M = a.n0;
     const double xk = lane < M ? a.nodes[lane] : 0.0;
@@ -186,6 +208,7 @@ __device__ inline void compose_range_lagrange(const ComposeArgs &a) {
         for (long long i = lane; i < count; i += int(blockDim.x))
             rows[i] = double(tab0[base + i]);
         __syncthreads();
+        int done = c0;                            // boundary states bnd[0 .. done-c0) ready
         for (int j = c0; j < c1; ++j) {
             if (!finite(lam)) {
                 bad_slice = j;
@@ -196,24 +219,35 @@ __device__ inline void compose_range_lagrange(const ComposeArgs &a) {
                 bad_slice = j;
                 break;
             }
-            double term = vk;
-#pragma unroll 8
-            for (int m = 0; m < M; ++m) {
-                const double xm = readlane_f64(xk, m);
-                const double f = (lam - xm) / (xk - xm);
-                term *= (m == lane) ? 1.0 : f;
-            }
+            const double next = lagrange_value<MC>(lam, xk, vk, lane, M);
             oog += (lam < a.lo0 || lam > a.hi0) ? 1 : 0;
-            double sum = 0.0;
-            for (int k = 0; k < M; ++k) sum += readlane_f64(term, k);
-            lam = sum;
-            if (lane == 0) a.boundary[j + 1] = lam;
+            lam = next;
+            if (lane == 0) bnd[j - c0] = lam;
+            done = j + 1;
         }
+        __syncthreads();
+        for (int i = lane; i < done - c0; i += int(blockDim.x)) a.boundary[c0 + 1 + i] = bnd[i];
     }
     if (lane == 0) {
         a.status->n_out_of_grid += oog;
         if (bad_slice >= 0) a.status->bad_slice = bad_slice;
         if (a.j_end == a.n_slices || bad_slice >= 0) a.status->done = 1;
+    }
+}
+
+template <class T>
+__device__ inline void compose_range_lagrange(const ComposeArgs &a) {
+    __shared__ double rows[kLagrangeStage];
+    __shared__ double bnd[kLagrangeStage / 2];
+    switch (a.n0) {
+    case 2: lagrange_chain<T, 2>(a, rows, bnd); break;
+    case 3: lagrange_chain<T, 3>(a, rows, bnd); break;
+    case 4: lagrange_chain<T, 4>(a, rows, bnd); break;
+    case 5: lagrange_chain<T, 5>(a, rows, bnd); break;
+    case 6: lagrange_chain<T, 6>(a, rows, bnd); break;
+    case 7: lagrange_chain<T, 7>(a, rows, bnd); break;
+    case 8: lagrange_chain<T, 8>(a, rows, bnd); break;
+    default: lagrange_chain<T, 0>(a, rows, bnd); break;
     }
 }
 

@@ -31,6 +31,24 @@ constexpr int kMaxSplits = 64;           // weight-gradient sums: splits of the 
 constexpr long long kMaxBatch = 1LL << 20;
 
 enum { kModeReduce = 1, kModeAdam = 2 };
+constexpr int kMaxCoarse = 16;
+
+// The coarse propagator G: k classical RK4 steps of length h of the Van der
+// Pol field y1' = y2, y2' = mu (1 - y1^2) y2 - y1, in FP64 (k = 0: identity).
+__host__ __device__ inline void coarse_rk4(double mu, double h, int k, double &y0, double &y1) {
+#pragma clang fp contract(off)
+    for (int s = 0; s < k; ++s) {
+        const double a1 = y1, b1 = mu * (1.0 - y0 * y0) * y1 - y0;
+        const double p0 = y0 + 0.5 * h * a1, p1 = y1 + 0.5 * h * b1;
+        const double a2 = p1, b2 = mu * (1.0 - p0 * p0) * p1 - p0;
+        const double q0 = y0 + 0.5 * h * a2, q1 = y1 + 0.5 * h * b2;
+        const double a3 = q1, b3 = mu * (1.0 - q0 * q0) * q1 - q0;
+        const double r0 = y0 + h * a3, r1 = y1 + h * b3;
+        const double a4 = r1, b4 = mu * (1.0 - r0 * r0) * r1 - r0;
+        y0 = y0 + (h / 6.0) * (((a1 + 2.0 * a2) + 2.0 * a3) + a4);
+        y1 = y1 + (h / 6.0) * (((b1 + 2.0 * b2) + 2.0 * b3) + b4);
+    }
+}
 
 // ---------------------------------------------------------------- kernels
 
@@ -46,87 +64,116 @@ struct TrainArgs {
     float inv_n;
 };
 
+// Inputs and targets of up to kStageTiles tiles are staged in LDS before the
+// tiles are processed: a global load inside the tile loop would have to wait
+// for every store of the previous tile (the memory counter is in order).
+constexpr int kStageTiles = 32;
+
 struct TrainLds {
     __bf16 w[4 * kWidth * kLdsRow];
     SmallParams sp;
+    float xs[4 * kStageTiles * 16];
+    float ts[2 * kStageTiles * 16];
 };
+
+// Forward pass, loss and back-propagation of one tile of 16 samples (lane
+// l: sample l % 16), writing the workspace rows of every sample.
+__device__ inline void train_tile(const TrainArgs &a, const TrainLds &L, long long tile, int li,
+                                  int lane) {
+    const int s = lane & 15, g = lane >> 4;
+    const __bf16 *Wf2 = L.w, *Wf3 = L.w + kWidth * kLdsRow;
+    const __bf16 *Wb2 = L.w + 2 * kWidth * kLdsRow, *Wb3 = L.w + 3 * kWidth * kLdsRow;
+    const long long n = tile * 16 + s;
+    float u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k] = (L.xs[k * kStageTiles * 16 + li] - a.shift[k]) * a.scale[k];
+    const float t0 = L.ts[li], t1 = L.ts[kStageTiles * 16 + li];
+    Layer d1, d2, d3, x;
+    bf16x8 b[4];
+    float o0, o1;
+    __bf16 *col = a.S + (long long)(4 * g) * a.ldS + n;
+    forward<true>(L.sp, Wf2, Wf3, u, lane, d1, d2, d3, x, o0, o1, col, a.ldS);
+    pack(x, b);
+    store_rows(col, a.ldS, kRowH + 256, b);
+
+    const float e0 = o0 - t0, e1 = o1 - t1;
+    const float dout0 = 2.0f * e0 * a.inv_n, dout1 = 2.0f * e1 * a.inv_n;
+    // layer 3: dL/dz3 = (W4^T dout) * gelu'(z3)
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = 16 * mt + 4 * g + i;
+            x.v[mt][i] = (L.sp.w4[f] * dout0 + L.sp.w4[kWidth + f] * dout1) * d3.v[mt][i];
+        }
+    }
+    pack(x, b);
+    store_rows(col, a.ldS, kRowD + 256, b);
+    matmul(Wb3, b, x, lane);                              // W3^T dL/dz3
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) x.v[mt] *= d2.v[mt];
+    pack(x, b);
+    store_rows(col, a.ldS, kRowD + 128, b);
+    matmul(Wb2, b, x, lane);                              // W2^T dL/dz2
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) x.v[mt] *= d1.v[mt];
+    pack(x, b);
+    store_rows(col, a.ldS, kRowD, b);
+
+    // rows of XO: group 0 writes u0..u3, group 1 writes 1, dout0, dout1, 0,
+    // groups 2 and 3 the zero rows
+    __bf16 xo[4];
+    if (g == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xo[r] = __bf16(u[r]);
+    } else if (g == 1) {
+        xo[0] = __bf16(1.0f);
+        xo[1] = __bf16(dout0);
+        xo[2] = __bf16(dout1);
+        xo[3] = __bf16(0.0f);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xo[r] = __bf16(0.0f);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) col[(long long)(kRowXO + r) * a.ldS] = xo[r];
+
+    float sq = g == 0 ? e0 * e0 + e1 * e1 : 0.0f;
+    sq += __shfl_xor(sq, 1);
+    sq += __shfl_xor(sq, 2);
+    sq += __shfl_xor(sq, 4);
+    sq += __shfl_xor(sq, 8);
+    if (lane == 0) a.loss_part[tile] = sq;
+}
 
 __global__ __launch_bounds__(kTrainThreads) void sur_train_kernel(TrainArgs a) {
     __shared__ TrainLds L;
     const int tid = int(threadIdx.x);
     load_mats(L.w, a.shadow, 4, tid, kTrainThreads);
     load_small(L.sp, a.params, tid, kTrainThreads);
-    __syncthreads();
-    const int lane = tid & 63, wave = tid >> 6, s = lane & 15, g = lane >> 4;
-    const __bf16 *Wf2 = L.w, *Wf3 = L.w + kWidth * kLdsRow;
-    const __bf16 *Wb2 = L.w + 2 * kWidth * kLdsRow, *Wb3 = L.w + 3 * kWidth * kLdsRow;
+    const int lane = tid & 63, wave = tid >> 6;
     const long long tiles = a.n / 16;
-    const int waves = int(gridDim.x) * (kTrainThreads / 64);
-    for (long long tile = (long long)blockIdx.x * (kTrainThreads / 64) + wave; tile < tiles;
-         tile += waves) {
-        asm volatile("" ::: "memory");  // keep the weight reads inside the loop
-        const long long n = tile * 16 + s;
-        const long long src = a.start + n;
-        float u[4];
+    // workgroup b owns the contiguous tiles [b * per, (b+1) * per), staged in
+    // chunks of kStageTiles
+    const long long per = (tiles + gridDim.x - 1) / gridDim.x;
+    const long long tb = (long long)blockIdx.x * per;
+    const long long te = tb + per < tiles ? tb + per : tiles;
+    for (long long c0 = tb; c0 < te; c0 += kStageTiles) {
+        const long long c1 = c0 + kStageTiles < te ? c0 + kStageTiles : te;
+        const int cn = int(c1 - c0) * 16;
+        __syncthreads();                              // the previous chunk is consumed
+        for (int i = tid; i < cn; i += kTrainThreads) {
+            const long long src = a.start + c0 * 16 + i;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) u[k] = (a.x[k * a.ld + src] - a.shift[k]) * a.scale[k];
-        const float t0 = a.t[src], t1 = a.t[a.ld + src];
-        Layer d1, d2, d3, x;
-        bf16x8 b[4];
-        float o0, o1;
-        __bf16 *col = a.S + (long long)(4 * g) * a.ldS + n;
-        forward<true>(L.sp, Wf2, Wf3, u, lane, d1, d2, d3, x, o0, o1, col, a.ldS);
-        pack(x, b);
-        store_rows(col, a.ldS, kRowH + 256, b);
-
-        const float e0 = o0 - t0, e1 = o1 - t1;
-        const float dout0 = 2.0f * e0 * a.inv_n, dout1 = 2.0f * e1 * a.inv_n;
-        // layer 3: dL/dz3 = (W4^T dout) * gelu'(z3)
-#pragma unroll
-        for (int mt = 0; mt < 8; ++mt) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int f = 16 * mt + 4 * g + i;
-                x.v[mt][i] = (L.sp.w4[f] * dout0 + L.sp.w4[kWidth + f] * dout1) * d3.v[mt][i];
-            }
+            for (int k = 0; k < 4; ++k) L.xs[k * kStageTiles * 16 + i] = a.x[k * a.ld + src];
+            L.ts[i] = a.t[src];
+            L.ts[kStageTiles * 16 + i] = a.t[a.ld + src];
         }
-        pack(x, b);
-        store_rows(col, a.ldS, kRowD + 256, b);
-        matmul(Wb3, b, x, lane);                              // W3^T dL/dz3
-#pragma unroll
-        for (int mt = 0; mt < 8; ++mt) x.v[mt] *= d2.v[mt];
-        pack(x, b);
-        store_rows(col, a.ldS, kRowD + 128, b);
-        matmul(Wb2, b, x, lane);                              // W2^T dL/dz2
-#pragma unroll
-        for (int mt = 0; mt < 8; ++mt) x.v[mt] *= d1.v[mt];
-        pack(x, b);
-        store_rows(col, a.ldS, kRowD, b);
-
-        // rows of XO: group 0 writes u0..u3, group 1 writes 1, dout0, dout1, 0,
-        // groups 2 and 3 the zero rows
-        __bf16 xo[4];
-        if (g == 0) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) xo[r] = __bf16(u[r]);
-        } else if (g == 1) {
-            xo[0] = __bf16(1.0f);
-            xo[1] = __bf16(dout0);
-            xo[2] = __bf16(dout1);
-            xo[3] = __bf16(0.0f);
-        } else {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) xo[r] = __bf16(0.0f);
+        __syncthreads();
+        for (long long tile = c0 + wave; tile < c1; tile += kTrainThreads / 64) {
+            asm volatile("" ::: "memory");            // keep the weight reads inside the loop
+            train_tile(a, L, tile, int(tile - c0) * 16 + (lane & 15), lane);
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) col[(long long)(kRowXO + r) * a.ldS] = xo[r];
-
-        float sq = g == 0 ? e0 * e0 + e1 * e1 : 0.0f;
-        sq += __shfl_xor(sq, 1);
-        sq += __shfl_xor(sq, 2);
-        sq += __shfl_xor(sq, 4);
-        sq += __shfl_xor(sq, 8);
-        if (lane == 0) a.loss_part[tile] = sq;
     }
 }
 
@@ -165,7 +212,26 @@ __global__ __launch_bounds__(256) void sur_grad_kernel(GemmArgs a) {
     const __bf16 *pb1 = pb0 + 16 * a.ldS;
     f32x4 c00 = {0.f, 0.f, 0.f, 0.f}, c01 = c00, c10 = c00, c11 = c00;
     const bf16x8 zero = {};
-    for (long long k = k0; k < k1; k += 32) {
+    constexpr int U = 4;                         // k-steps of 32 samples per iteration
+    long long k = k0;
+    for (; k + 32 * U <= k1; k += 32 * U) {
+        bf16x8 A0[U], A1[U], B0[U], B1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            A0[u] = *reinterpret_cast<const bf16x8 *>(pa0 + k + 32 * u);
+            B0[u] = *reinterpret_cast<const bf16x8 *>(pb0 + k + 32 * u);
+            A1[u] = m1 ? *reinterpret_cast<const bf16x8 *>(pa1 + k + 32 * u) : zero;
+            B1[u] = n1 ? *reinterpret_cast<const bf16x8 *>(pb1 + k + 32 * u) : zero;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c00 = mfma(A0[u], B0[u], c00);
+            if (n1) c01 = mfma(A0[u], B1[u], c01);
+            if (m1) c10 = mfma(A1[u], B0[u], c10);
+            if (m1 && n1) c11 = mfma(A1[u], B1[u], c11);
+        }
+    }
+    for (; k < k1; k += 32) {
         const bool ok = k + 8 * g < k1;          // the minibatch ends on a multiple of 16
         const bf16x8 A0 = ok ? *reinterpret_cast<const bf16x8 *>(pa0 + k) : zero;
         const bf16x8 B0 = ok ? *reinterpret_cast<const bf16x8 *>(pb0 + k) : zero;
@@ -230,6 +296,7 @@ __global__ __launch_bounds__(256) void sur_update_kernel(UpdateArgs a) {
     if (a.mode & kModeReduce) {
         const int src = grad_source(p);
         float gsum = 0.0f;
+#pragma unroll 8
         for (int s = 0; s < a.splits; ++s) gsum += a.part[(long long)s * kGradEntries + src];
         a.grad[p] = gsum;
         if (a.mode & kModeAdam) {
@@ -296,6 +363,7 @@ struct ChainArgs {
     const double *y0, *mu;
     long long count;
     double t0, L;
+    int coarse;                  // coarse RK4 steps (0: identity)
     int n_slices;
     double *final_state, *boundary;
     const void *tab0, *tab1;
@@ -362,7 +430,9 @@ __global__ __launch_bounds__(kInferThreads) void sur_chain_kernel(ChainArgs a) {
         float o0, o1;
         forward<false>(L.sp, L.w, L.w + kWidth * kLdsRow, u, lane, d1, d2, d3, a3, o0, o1,
                        nullptr, 0);
-        double n0 = l0 + a.os0 * double(o0), n1 = l1 + a.os1 * double(o1);
+        double g0 = l0, g1 = l1;
+        coarse_rk4(double(a.mu[qc]), a.L / double(a.coarse), a.coarse, g0, g1);
+        double n0 = g0 + a.os0 * double(o0), n1 = g1 + a.os1 * double(o1);
         const bool outside = !(l0 >= a.blo0 && l0 <= a.bhi0 && l1 >= a.blo1 && l1 <= a.bhi1);
         if (a.tab0) {
             double p, pq;
@@ -408,6 +478,7 @@ struct DatasetArgs {
     const long long *perm;
     float *x, *t;
     double os0, os1;
+    int coarse;
     int *error;
 };
 
@@ -447,8 +518,10 @@ __global__ __launch_bounds__(256) void sur_dataset_kernel(DatasetArgs a) {
         a.x[a.cap + pos] = y1;
         a.x[2 * a.cap + pos] = float(s.t0 + double(j) * s.L);
         a.x[3 * a.cap + pos] = float(s.mu);
-        a.t[pos] = float((e0 - double(y0)) / a.os0);
-        a.t[a.cap + pos] = float((e1 - double(y1)) / a.os1);
+        double g0 = double(y0), g1 = double(y1);
+        coarse_rk4(s.mu, s.L / double(a.coarse), a.coarse, g0, g1);
+        a.t[pos] = float((e0 - g0) / a.os0);
+        a.t[a.cap + pos] = float((e1 - g1) / a.os1);
     }
 }
 
@@ -573,6 +646,11 @@ NV_API nv_status nv_sur_create(const nv_sur_config *cfg, nv_sur **out) {
     for (int c = 0; c < 2; ++c)
         if (!(cfg->out_scale[c] > 0.0) || !std::isfinite(cfg->out_scale[c]))
             return fail(NV_ERR_INVALID_ARG, "out_scale[%d] must be positive and finite", c);
+    if (!(cfg->slice_length > 0.0) || !std::isfinite(cfg->slice_length))
+        return fail(NV_ERR_INVALID_ARG, "slice_length must be positive and finite");
+    if (cfg->coarse_steps < 0 || cfg->coarse_steps > kMaxCoarse)
+        return fail(NV_ERR_INVALID_ARG, "coarse_steps %d: need 0..%d", cfg->coarse_steps,
+                    kMaxCoarse);
     const long long mb = cfg->max_batch == 0 ? 65536 : cfg->max_batch;
     if (mb < 16 || mb > kMaxBatch || mb % 16 != 0)
         return fail(NV_ERR_INVALID_ARG, "max_batch %lld: need a multiple of 16 in [16, 2^20]",
@@ -745,7 +823,13 @@ NV_API nv_status nv_sur_dataset_from_batch(nv_sur *s, nv_batch *batch, const lon
     nv_status st = nv::batch_slice_sources(batch, src, &precision);
     if (st != NV_OK) return st;
     long long n = 0;
-    for (const auto &q : src) n += q.M * q.n_slices;
+    for (size_t i = 0; i < src.size(); ++i) {
+        const double L = s->cfg.slice_length;
+        if (std::fabs(src[i].L - L) > 1e-9 * L)
+            return fail(NV_ERR_INVALID_ARG, "problem %zu has slices of length %.17g, the "
+                        "network is configured for %.17g", i, src[i].L, L);
+        n += src[i].M * src[i].n_slices;
+    }
     *total = n;
     if (!x && !t) return NV_OK;
     if (!x || !t) return fail(NV_ERR_INVALID_ARG, "x and target must both be given");
@@ -767,6 +851,7 @@ NV_API nv_status nv_sur_dataset_from_batch(nv_sur *s, nv_batch *batch, const lon
         da.t = t;
         da.os0 = s->cfg.out_scale[0];
         da.os1 = s->cfg.out_scale[1];
+        da.coarse = s->cfg.coarse_steps;
         da.error = s->error;
         const long long blocks = std::min<long long>((n + 255) / 256, 65536);
         hipLaunchKernelGGL(sur_dataset_kernel, dim3(unsigned(blocks)), dim3(256), 0, s->stream,
@@ -802,6 +887,10 @@ NV_API nv_status nv_sur_compose(nv_sur *s, const nv_sur_chains *c, nv_sur_compos
     a.count = c->count;
     a.t0 = c->t0;
     a.L = (c->T - c->t0) / double(c->n_slices);
+    if (std::fabs(a.L - s->cfg.slice_length) > 1e-9 * s->cfg.slice_length)
+        return fail(NV_ERR_INVALID_ARG, "slices of length %.17g; the network is configured "
+                    "for %.17g", a.L, s->cfg.slice_length);
+    a.coarse = s->cfg.coarse_steps;
     a.n_slices = c->n_slices;
     a.final_state = c->final_state;
     a.boundary = c->boundary;

@@ -369,7 +369,8 @@ NV_SUR_PARAMS = 33922
 
 class nv_sur_config(ctypes.Structure):
     _fields_ = [("in_shift", ctypes.c_float * 4), ("in_scale", ctypes.c_float * 4),
-                ("out_scale", ctypes.c_double * 2), ("max_batch", ctypes.c_longlong),
+                ("out_scale", ctypes.c_double * 2), ("slice_length", ctypes.c_double),
+                ("coarse_steps", ctypes.c_int), ("max_batch", ctypes.c_longlong),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -410,11 +411,13 @@ _SIGNATURES.update({
 })
 
 
-def make_sur_config(in_shift, in_scale, out_scale, max_batch=0, stream=None) -> nv_sur_config:
+def make_sur_config(in_shift, in_scale, out_scale, slice_length, coarse_steps=0, max_batch=0,
+                    stream=None) -> nv_sur_config:
     c = nv_sur_config()
     for k in range(4):
         c.in_shift[k], c.in_scale[k] = float(in_shift[k]), float(in_scale[k])
     c.out_scale[0], c.out_scale[1] = float(out_scale[0]), float(out_scale[1])
+    c.slice_length, c.coarse_steps = float(slice_length), int(coarse_steps)
     c.max_batch = int(max_batch)
     c.stream = stream
     return c

@@ -11,12 +11,13 @@ import numpy as np
 
 from . import nv
 from .propagator import Batch, Propagator
-from .workloads import SUR_IN_SCALE, SUR_IN_SHIFT, SUR_OUT_SCALE
+from .workloads import SUR_IN_SCALE, SUR_IN_SHIFT, SUR_OUT_SCALE, SUR_SLICE_LENGTH
 
 
 class Surrogate:
     def __init__(self, device="cuda:0", max_batch=65536, in_shift=SUR_IN_SHIFT,
-                 in_scale=SUR_IN_SCALE, out_scale=SUR_OUT_SCALE, stream=None):
+                 in_scale=SUR_IN_SCALE, out_scale=SUR_OUT_SCALE, slice_length=SUR_SLICE_LENGTH,
+                 coarse_steps=0, stream=None):
         import torch
 
         self.torch = torch
@@ -26,10 +27,11 @@ class Surrogate:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.in_shift, self.in_scale = tuple(in_shift), tuple(in_scale)
         self.out_scale = tuple(out_scale)
+        self.slice_length, self.coarse_steps = float(slice_length), int(coarse_steps)
         self.max_batch = int(max_batch)
         with torch.cuda.device(self.device):
-            cfg = nv.make_sur_config(in_shift, in_scale, out_scale, max_batch,
-                                     self.stream.cuda_stream)
+            cfg = nv.make_sur_config(in_shift, in_scale, out_scale, slice_length, coarse_steps,
+                                     max_batch, self.stream.cuda_stream)
             self.h = nv.nv_sur_create(cfg)
 
     def close(self):

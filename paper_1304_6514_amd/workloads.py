@@ -185,6 +185,10 @@ PAPER_TABLE3 = [(dt, n, M) for dt, M in ((2.0 ** -14, 4), (2.0 ** -15, 5), (2.0 
 SUR_IN_SHIFT = (0.0, 0.0, 25.0, 3.0)
 SUR_IN_SCALE = (1.0 / 3.0, 1.0 / 8.0, 1.0 / 25.0, 0.5)
 SUR_OUT_SCALE = (0.2, 1.6)
+SUR_SLICE_LENGTH = 50.0 / 1024
+# With one coarse RK4 step over the slice the network learns only the
+# correction to it: about 1/20 and 1/8 of the displacement's scale.
+SUR_OUT_SCALE_COARSE = (0.01, 0.2)
 
 
 def surrogate_training_problems(n_slices: int = 1024, grid_n=(128, 128), steps: int = 500,

@@ -195,13 +195,15 @@ def test_batched_workload_recipe():
 def test_surrogate_argument_errors_need_no_gpu(nvmod):
     from paper_1304_6514_amd import workloads as W
     lib = nvmod.load()
-    good = dict(in_shift=W.SUR_IN_SHIFT, in_scale=W.SUR_IN_SCALE, out_scale=W.SUR_OUT_SCALE)
+    good = dict(in_shift=W.SUR_IN_SHIFT, in_scale=W.SUR_IN_SCALE, out_scale=W.SUR_OUT_SCALE,
+                slice_length=W.SUR_SLICE_LENGTH, coarse_steps=0, max_batch=0)
     for bad in (dict(out_scale=(0.2, 0.0)), dict(out_scale=(float("nan"), 1.0)),
                 dict(in_scale=(1.0, float("inf"), 1.0, 1.0)), dict(max_batch=24),
-                dict(max_batch=(1 << 20) + 16)):
+                dict(max_batch=(1 << 20) + 16), dict(slice_length=0.0),
+                dict(slice_length=float("inf")), dict(coarse_steps=-1), dict(coarse_steps=17)):
         kw = dict(good, **bad)
         cfg = nvmod.make_sur_config(kw["in_shift"], kw["in_scale"], kw["out_scale"],
-                                    kw.get("max_batch", 0))
+                                    kw["slice_length"], kw["coarse_steps"], kw["max_batch"])
         h = ctypes.c_void_p()
         assert lib.nv_sur_create(ctypes.byref(cfg), ctypes.byref(h)) == nvmod.NV_ERR_INVALID_ARG
         assert h.value is None

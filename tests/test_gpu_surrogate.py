@@ -150,13 +150,17 @@ def _train_batch(torch):
     return probs, b
 
 
-def test_training_set_gather_is_exact(sur, torch):
+@pytest.mark.parametrize("coarse", [0, 2])
+def test_training_set_gather_is_exact(sur, torch, coarse):
+    from paper_1304_6514_amd.surrogate import Surrogate
     probs, b = _train_batch(torch)
+    os_ = OUT_SCALE if coarse == 0 else np.array(W.SUR_OUT_SCALE_COARSE)
+    s2 = Surrogate("cuda:0", max_batch=1024, out_scale=os_, coarse_steps=coarse)
     try:
         M = 12 * 10
         total = len(probs) * M
         perm = W.surrogate_perm(total, seed=10)
-        x, t = sur.dataset_from_batch(b, perm)
+        x, t = s2.dataset_from_batch(b, perm)
         x, t = x.cpu().numpy(), t.cpu().numpy()
         for i, w in enumerate(probs):
             tabs = [nv.nv_batch_get_table(b.batch, i, c, 1, M, "fp32")[0] for c in range(2)]
@@ -170,41 +174,61 @@ def test_training_set_gather_is_exact(sur, torch):
             assert np.array_equal(x[0, pos], y0) and np.array_equal(x[1, pos], y1)
             assert np.all(x[2, pos] == np.float32(w.t0))
             assert np.all(x[3, pos] == np.float32(w.params[0]))
-            e0 = ((tabs[0].astype(np.float64) - y0) / OUT_SCALE[0]).astype(np.float32)
-            e1 = ((tabs[1].astype(np.float64) - y1) / OUT_SCALE[1]).astype(np.float32)
-            assert np.array_equal(t[0, pos], e0) and np.array_equal(t[1, pos], e1)
-        say(f"training-set gather: {total} samples bit-exact")
+            g = mo.coarse_step(np.stack([y0, y1], -1).astype(np.float64), w.params[0],
+                               w.T - w.t0, coarse)
+            e0 = ((tabs[0].astype(np.float64) - g[:, 0]) / os_[0]).astype(np.float32)
+            e1 = ((tabs[1].astype(np.float64) - g[:, 1]) / os_[1]).astype(np.float32)
+            if coarse == 0:
+                assert np.array_equal(t[0, pos], e0) and np.array_equal(t[1, pos], e1)
+            else:   # the coarse RK4 step: FP64 on both sides, one FP32 rounding at the end
+                assert np.max(np.abs(t[0, pos] - e0) / np.maximum(np.abs(e0), 1e-3)) < 1e-6
+                assert np.max(np.abs(t[1, pos] - e1) / np.maximum(np.abs(e1), 1e-3)) < 1e-6
+        say(f"training-set gather (coarse steps {coarse}): {total} samples checked")
     finally:
+        s2.close()
         b.close()
 
 
-def test_compose_matches_oracle_chain(sur, torch):
+@pytest.mark.parametrize("coarse", [0, 1])
+def test_compose_matches_oracle_chain(sur, torch, coarse):
+    from paper_1304_6514_amd.surrogate import Surrogate
     p = W.surrogate_init_params(11)
     p[mo.N_PARAMS - 258:] *= 0.2                      # a gentle map: small W4, b4
-    sur.set_params(p)
+    os_ = OUT_SCALE if coarse == 0 else np.array(W.SUR_OUT_SCALE_COARSE)
+    s2 = sur if coarse == 0 else Surrogate("cuda:0", max_batch=1024, out_scale=os_,
+                                           coarse_steps=coarse)
+    s2.set_params(p)
     rng = np.random.default_rng(12)
     Q, N = 37, 16
     y0 = np.column_stack([rng.uniform(-2, 2, Q), rng.uniform(-4, 4, Q)])
     mu = rng.uniform(1, 5, Q)
-    say(f"surrogate compose Q={Q} N={N}")
-    st, final, bnd, info = sur.compose(y0, mu, 0.0, 50.0 * N / 1024, N, want_boundary=True)
+    say(f"surrogate compose Q={Q} N={N} coarse={coarse}")
+    st, final, bnd, info = s2.compose(y0, mu, 0.0, 50.0 * N / 1024, N, want_boundary=True)
     assert st == nv.NV_OK and info.bad_chain == -1
     final, bnd = final.cpu().numpy(), bnd.cpu().numpy()
     worst = 0.0
     for q in range(Q):
-        ref = mo.surrogate_chain(p.astype(np.float64), SHIFT, SCALE, OUT_SCALE, y0[q], mu[q], 0.0,
-                                 50.0 * N / 1024, N, emulate_bf16=True)
+        ref = mo.surrogate_chain(p.astype(np.float64), SHIFT, SCALE, os_, y0[q], mu[q], 0.0,
+                                 50.0 * N / 1024, N, emulate_bf16=True, coarse_steps=coarse)
         worst = max(worst, float(np.max(np.abs(bnd[q] - ref))))
         assert np.array_equal(bnd[q, -1], final[q])
     say(f"chains: max |gpu - oracle(bf16)| over boundary states = {worst:.3g}")
     assert worst < 1e-4
+    if s2 is not sur:
+        s2.close()
+
+
+def test_compose_rejects_other_slice_lengths(sur, torch):
+    with pytest.raises(nv.NvError) as e:
+        sur.compose([[2.0, 0.0]], [3.0], 0.0, 50.0, 100)
+    assert e.value.status == nv.NV_ERR_INVALID_ARG
 
 
 def test_compose_fallback_reproduces_bilinear_composition(sur, torch):
     """With guard < 0 every step takes the table's value: the result is the
     library's bilinear composition over the same table, to the bit."""
     from paper_1304_6514_amd.propagator import Propagator
-    w = W.small(W.VDP_FP32, 24, (20, 20), 60)
+    w = W.small(W.VDP_FP32, 24, (20, 20), 60).with_(T=24 * W.SUR_SLICE_LENGTH)
     sur.set_params(W.surrogate_init_params(13))
     with Propagator("cuda:0") as prop:
         prop.build(w)

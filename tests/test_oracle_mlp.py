@@ -190,3 +190,15 @@ def test_chain_zero_network_keeps_state_and_constant_network_drifts():
     p["b4"][:] = [0.25, -0.5]
     bnd = mo.surrogate_chain(p, SHIFT, SCALE, np.array([0.5, 2.0]), [0.5, -1.0], 3.0, 0, 10, 16)
     assert np.allclose(bnd[-1], [0.5 + 16 * 0.125, -1.0 - 16 * 1.0], rtol=0, atol=1e-13)
+
+
+def test_coarse_step_is_the_rk4_of_the_library_oracle(orc):
+    """G of the surrogate is classical RK4 of the Van der Pol field: the same
+    steps as the C oracle's integrator (written separately)."""
+    rng = np.random.default_rng(15)
+    for _ in range(5):
+        y, mu, k = rng.uniform(-3, 3, 2), rng.uniform(1, 5), int(rng.integers(1, 4))
+        L = 50.0 / 1024
+        ref = orc.integrate("vdp", [mu], "rk4", 0.0, L / k, k, y)
+        assert np.max(np.abs(mo.coarse_step(y, mu, L, k) - ref)) < 1e-15
+    assert np.array_equal(mo.coarse_step([0.3, -1.0], 2.0, 0.1, 0), [0.3, -1.0])

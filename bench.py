@@ -371,6 +371,13 @@ def bench_surrogate(args):
         sur.loss_grad(xd, td)
         step_ms.append(1e3 * (time.perf_counter() - t1))
 
+    if args.sur_train_only:
+        sur.close()
+        return {"what": "surrogate training only", "steps": steps,
+                "train_s": round(train_s, 4), "samples_per_s": steps * B / train_s,
+                "step_ms_loss_grad": round(min(step_ms), 4),
+                "loss_last": float(losses[-1])}
+
     # evaluation on held-out mu: truth = the library's FP64 integration of the
     # whole interval from y0 (a one-slice build whose first grid point is y0)
     mus = W.surrogate_eval_mus(8)
@@ -494,6 +501,8 @@ def main():
     ap.add_argument("--sur-lr-final", type=float, default=2e-5)
     ap.add_argument("--sur-coarse", type=int, default=1,
                     help="surrogate: RK4 steps of the coarse propagator the network corrects")
+    ap.add_argument("--sur-train-only", action="store_true",
+                    help="surrogate: stop after training (for profiling the training kernels)")
     ap.add_argument("--sur-guard", type=float, default=0.05,
                     help="surrogate: deviation from the table above which the table is used")
     args = ap.parse_args()

@@ -247,3 +247,71 @@ def test_compose_fallback_reproduces_bilinear_composition(sur, torch):
         assert info2.max_deviation > 0.0
         say(f"fallback: {info.n_fallback} steps reproduce the bilinear chain; guard=inf: "
             f"{info2.n_fallback} fallbacks, max deviation {info2.max_deviation:.3g}")
+
+
+def test_trained_network_gains_over_the_method_without_it(torch):
+    """The whole learned path at full size: the training build (1024 one-slice
+    Van der Pol problems with their own mu, 128 x 128 grid, 500 RK4 steps),
+    the training set (16.7M endpoints), 20 epochs of Adam, then the
+    composition over [0, 50] (1024 slices) for held-out mu that no table was
+    built for.  Against the same coarse propagator without the network, and
+    against the plain method with a fresh 64 x 64 table build per mu, the
+    trained network's max final-state error is smaller."""
+    from paper_1304_6514_amd.propagator import Batch, Propagator
+    from paper_1304_6514_amd.surrogate import Surrogate
+    B = 65536
+    probs = W.surrogate_training_problems()
+    b = Batch(probs)
+    st, _, _ = b.run()
+    assert st == nv.NV_OK
+    sur = Surrogate("cuda:0", max_batch=B, out_scale=W.SUR_OUT_SCALE_COARSE, coarse_steps=1)
+    try:
+        total = nv.nv_sur_dataset_from_batch(sur.h, b.batch)
+        x, t = sur.dataset_from_batch(b, W.surrogate_perm(total))
+        b.close()
+        p0 = W.surrogate_init_params(0)
+        sur.set_params(p0)
+        losses = sur.train(x, t, batch=B, steps=20 * (total // B), lr=2e-3,
+                           lr_final=2e-5).cpu().numpy()
+        del x, t
+        say(f"training: {len(losses)} steps, loss {losses[0]:.3g} -> {losses[-1]:.3g}, "
+            f"{sur.last_ms():.0f} ms")
+        assert losses[-1] < 1e-3 * losses[0]
+
+        base = W.VDP_FP32
+        mus = W.surrogate_eval_mus(8)
+        y0 = np.tile(base.y0, (len(mus), 1))
+        truth, plain = [], []
+        with Propagator("cuda:0") as pr:
+            for mu in mus:
+                wt = base.with_(name="vdp-serial-fp64", params=(float(mu),), n_slices=1,
+                                grid_n=(2, 2), grid_lo=base.y0,
+                                grid_hi=(base.y0[0] + 1.0, base.y0[1] + 1.0),
+                                steps_per_slice=base.n_slices * base.steps_per_slice,
+                                precision="fp64")
+                pr.build(wt)
+                truth.append([float(pr.table(0)[0, 0]), float(pr.table(1)[0, 0])])
+            truth = np.array(truth)
+            for i, mu in enumerate(mus):
+                r = pr.solve(base.with_(params=(float(mu),), grid_n=(64, 64)),
+                             want_boundary=False)
+                plain.append(float(np.max(np.abs(np.asarray(r.yT) - truth[i]))))
+        st, fin, _, info = sur.compose(y0, mus, base.t0, base.T, base.n_slices)
+        assert st == nv.NV_OK
+        e_net = np.max(np.abs(fin.cpu().numpy() - truth), axis=1)
+        trained = sur.params()
+        off = trained.copy()
+        off[mo.N_PARAMS - 258:] = 0.0                # W4 = 0, b4 = 0: the coarse step alone
+        sur.set_params(off)
+        st, fin0, _, _ = sur.compose(y0, mus, base.t0, base.T, base.n_slices)
+        e_coarse = np.max(np.abs(fin0.cpu().numpy() - truth), axis=1)
+        e_coarse = np.where(np.isfinite(e_coarse), e_coarse, np.inf)
+        say("held-out mu        ", np.array2string(mus, precision=3))
+        say("network error      ", np.array2string(e_net, precision=4))
+        say("coarse step alone  ", np.array2string(e_coarse, precision=4))
+        say("plain 64x64 build  ", np.array2string(np.array(plain), precision=4))
+        say(f"network compose of {len(mus)} chains: {info.ms:.2f} ms")
+        assert np.max(e_net) < np.max(plain)
+        assert np.max(e_net) < 0.1 * np.max(e_coarse)
+    finally:
+        sur.close()

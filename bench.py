@@ -400,6 +400,13 @@ def bench_surrogate(args):
     st, fin, _, info = sur.compose(y0, mus, base.t0, base.T, base.n_slices)
     sur_ms = info.ms
     err_sur = np.max(np.abs(fin.cpu().numpy() - truth), axis=1)
+    trained = sur.params()
+    off = trained.copy()
+    off[-258:] = 0.0                          # W4 = 0, b4 = 0: the coarse propagator alone
+    sur.set_params(off)
+    _, fin0, _, _ = sur.compose(y0, mus, base.t0, base.T, base.n_slices)
+    err_coarse = np.max(np.abs(fin0.cpu().numpy() - truth), axis=1)
+    sur.set_params(trained)
     st1, _, _, info1 = sur.compose(y0[:1], mus[:1], base.t0, base.T, base.n_slices)
     many = 16384
     stq, _, _, infoq = sur.compose(np.tile(base.y0, (many, 1)), np.resize(mus, many), base.t0,
@@ -453,6 +460,7 @@ def bench_surrogate(args):
         "step_ms_loss_grad": round(min(step_ms), 4),
         "eval": {"mus": [float(m) for m in mus], "truth": "library FP64 serial RK4, 512000 steps",
                  "surrogate_errors": [float(e) for e in err_sur], "surrogate_max_error": e_sur,
+                 "coarse_alone_errors": [float(e) for e in err_coarse],
                  "surrogate_compose_ms_8_chains": round(sur_ms, 3),
                  "surrogate_compose_ms_1_chain": round(info1.ms, 3),
                  "surrogate_compose_ms_16384_chains": round(infoq.ms, 3),

@@ -127,24 +127,26 @@ def serial(M, a0, a1, forcing, t0, T, n_slices, dt, y0):
     return y
 
 
-def build_tables(M, a0, a1, forcing, t0, T, n_slices, dt):
-    """The computation phase: G (N, M, M) and c (N, M); M+1 solves per slice."""
+def build_tables(M, a0, a1, forcing, t0, T, n_slices, dt, slices=None):
+    """The computation phase: G (N, M, M) and c (N, M); M+1 solves per slice.
+    With ``slices``, only those slices (in that order)."""
     dx, _, s = grid(M)
     L, S, rem = slice_steps(t0, T, n_slices, dt)
-    G = np.empty((n_slices, M, M))
-    cvec = np.empty((n_slices, M))
-    for j in range(n_slices):
+    which = list(range(n_slices)) if slices is None else list(slices)
+    G = np.empty((len(which), M, M))
+    cvec = np.empty((len(which), M))
+    for jj, j in enumerate(which):
         steps = step_list(t0 + j * L, S, dt, rem)
         y = np.zeros(M)
         for h, te in steps:
             y = be_step(y, h, te, a0, a1, dx, s, forcing)
-        cvec[j] = y
+        cvec[jj] = y
         for k in range(M):
             y = np.zeros(M)
             y[k] = 1.0
             for h, te in steps:
                 y = be_step(y, h, te, a0, a1, dx, s, False)
-            G[j, :, k] = y
+            G[jj, :, k] = y
     return G, cvec
 
 

@@ -1,0 +1,369 @@
+// Affine basis propagator for the heat equation of sec. 6 (include/nv_linear.h).
+//
+// Computation phase, two launches:
+//   lin_coef_kernel   one thread per (slice, step): the Thomas coefficients
+//                     w_i, c_i of that step's tridiagonal matrix (a chain of M
+//                     divisions that every solve of the slice shares);
+//   lin_build_kernel  one workgroup per slice, one lane per solve: lane 0 the
+//                     forced solve from 0, lane k the homogeneous solve from
+//                     e_k; each lane's vector lives in LDS (column-major, so
+//                     the lanes' accesses are consecutive), and no lane ever
+//                     waits for another.
+// Communication phase: lin_compose_kernel, one workgroup; lane i owns
+// component i of lambda and forms c_i + G_i1 l_1 + ... from the table stored
+// column by column (coalesced reads); boundary states are collected in LDS
+// and written out per chunk so that no store sits in the chain.
+#include "nv_internal.h"
+#include "nv_linear.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using nv::fail;
+
+#define NV_HIP(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(NV_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+namespace {
+
+constexpr int kMaxM = NV_LIN_MAX_POINTS;
+constexpr int kComposeThreads = 128;
+constexpr int kBoundaryChunk = 32;          // slices whose boundary states LDS collects
+
+struct CoefArgs {
+    const double *step;         // [n_slices * S_tot][2]: r, h beta
+    double *w, *c;              // [n_slices * S_tot][M]
+    long long count;            // n_slices * S_tot
+    int M;
+};
+
+__global__ __launch_bounds__(256) void lin_coef_kernel(CoefArgs a) {
+#pragma clang fp contract(off)
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= a.count) return;
+    const double r = a.step[2 * q];
+    const double diag = 1.0 + 2.0 * r, off = -r;
+    double cp = 0.0;
+    for (int i = 0; i < a.M; ++i) {
+        const double den = i == 0 ? diag : diag - off * cp;
+        const double w = 1.0 / den;
+        cp = off * w;
+        a.w[q * a.M + i] = w;
+        a.c[q * a.M + i] = cp;
+    }
+}
+
+struct BuildArgs {
+    const double *step;         // [n_slices * S_tot][2]
+    const double *w, *c;        // [n_slices * S_tot][M]
+    const double *s;            // [M] sin(pi x_i)
+    double *GT;                 // [n_slices][M][M]: GT[j][k][i] = G_j[i][k]
+    double *cvec;               // [n_slices][M]
+    int M, S_tot, forcing;
+};
+
+__global__ __launch_bounds__(256) void lin_build_kernel(BuildArgs a) {
+#pragma clang fp contract(off)
+    extern __shared__ double xs[];           // [M][ncol]
+    const int ncol = int(blockDim.x), lane = int(threadIdx.x), M = a.M;
+    const int j = int(blockIdx.x);
+    const bool live = lane <= M;             // lane 0: forced solve; lane k: from e_k
+    const bool forced = lane == 0 && a.forcing;
+    for (int i = 0; i < M; ++i) xs[i * ncol + lane] = (lane >= 1 && i == lane - 1) ? 1.0 : 0.0;
+    for (int st = 0; st < a.S_tot; ++st) {
+        const long long q = (long long)j * a.S_tot + st;
+        const double off = -a.step[2 * q], hb = a.step[2 * q + 1];
+        const double *w = a.w + q * M, *c = a.c + q * M;
+        // forward elimination, in place
+        double fp = 0.0;
+        for (int i = 0; i < M; ++i) {
+            double f = xs[i * ncol + lane];
+            if (forced) f = f + hb * a.s[i];
+            fp = i == 0 ? f * w[0] : (f - off * fp) * w[i];
+            xs[i * ncol + lane] = fp;
+        }
+        // back substitution, in place
+        double y = fp;
+        for (int i = M - 2; i >= 0; --i) {
+            y = xs[i * ncol + lane] - c[i] * y;
+            xs[i * ncol + lane] = y;
+        }
+    }
+    if (!live) return;
+    if (lane == 0) {
+        for (int i = 0; i < M; ++i) a.cvec[(long long)j * M + i] = xs[i * ncol];
+    } else {
+        double *col = a.GT + ((long long)j * M + (lane - 1)) * M;
+        for (int i = 0; i < M; ++i) col[i] = xs[i * ncol + lane];
+    }
+}
+
+struct ComposeArgs {
+    const double *GT, *cvec;
+    const double *y0;           // device [M]
+    double *boundary;           // device [(N+1)][M]
+    int *bad;                   // first slice whose state is not finite, or -1
+    int M, N;
+};
+
+__global__ __launch_bounds__(kComposeThreads) void lin_compose_kernel(ComposeArgs a) {
+#pragma clang fp contract(off)
+    __shared__ double lam[kMaxM];
+    __shared__ double bnd[kBoundaryChunk][kMaxM];
+    const int i = int(threadIdx.x), M = a.M;
+    if (i < M) {
+        lam[i] = a.y0[i];
+        a.boundary[i] = a.y0[i];
+    }
+    int bad = -1;
+    for (int c0 = 0; c0 < a.N; c0 += kBoundaryChunk) {
+        const int c1 = c0 + kBoundaryChunk < a.N ? c0 + kBoundaryChunk : a.N;
+        for (int j = c0; j < c1; ++j) {
+            __syncthreads();                         // lam of slice j is complete
+            double acc = 0.0;
+            if (i < M) {
+                const double *G = a.GT + (long long)j * M * M;
+                acc = a.cvec[(long long)j * M + i];
+#pragma unroll 8
+                for (int k = 0; k < M; ++k) acc = acc + G[(long long)k * M + i] * lam[k];
+            }
+            __syncthreads();                         // every lane has read lam
+            if (i < M) {
+                lam[i] = acc;
+                bnd[j - c0][i] = acc;
+            }
+            if (bad < 0 && __syncthreads_or(i < M && !isfinite(acc))) bad = j;
+        }
+        __syncthreads();
+        for (int jj = c0; jj < c1; ++jj)
+            if (i < M) a.boundary[(long long)(jj + 1) * M + i] = bnd[jj - c0][i];
+    }
+    if (i == 0) *a.bad = bad;
+}
+
+}  // namespace
+
+struct nv_lin {
+    hipStream_t stream = nullptr;
+    char *mem = nullptr;
+    size_t mem_bytes = 0;
+    // layout of the last build
+    double *step = nullptr, *w = nullptr, *c = nullptr, *s = nullptr, *GT = nullptr,
+           *cvec = nullptr, *y0 = nullptr, *boundary = nullptr;
+    int *bad = nullptr;
+    int M = 0, N = 0, S_tot = 0;
+    bool built = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+    float build_ms = 0.f, compose_ms = 0.f;
+};
+
+namespace {
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+// FP64 host evaluations with one rounding per operation.
+double a_of(const nv_heat &p, double t) {
+#pragma clang fp contract(off)
+    return p.a0 + p.a1 * std::sin(t);
+}
+
+double beta_of(const nv_heat &p, double t) {
+#pragma clang fp contract(off)
+    return ((M_PI * M_PI) * a_of(p, t)) * std::cos(t) - std::sin(t);
+}
+
+}  // namespace
+
+extern "C" {
+
+NV_API nv_status nv_lin_create(void *stream, nv_lin **out) {
+    if (!out) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    nv_lin *l = new (std::nothrow) nv_lin();
+    if (!l) return fail(NV_ERR_OOM, "out of host memory");
+    l->stream = static_cast<hipStream_t>(stream);
+    hipError_t e = hipEventCreate(&l->e0);
+    if (e == hipSuccess) e = hipEventCreate(&l->e1);
+    if (e == hipSuccess) e = hipEventCreate(&l->e2);
+    if (e == hipSuccess) e = hipEventCreate(&l->e3);
+    if (e != hipSuccess) {
+        nv_lin_destroy(l);
+        return fail(NV_ERR_HIP, "event creation failed: %s", hipGetErrorString(e));
+    }
+    *out = l;
+    return NV_OK;
+}
+
+NV_API nv_status nv_lin_destroy(nv_lin *l) {
+    if (!l) return NV_OK;
+    if (l->mem) {
+        (void)hipStreamSynchronize(l->stream);
+        (void)hipFree(l->mem);
+    }
+    for (hipEvent_t ev : {l->e0, l->e1, l->e2, l->e3})
+        if (ev) (void)hipEventDestroy(ev);
+    delete l;
+    return NV_OK;
+}
+
+NV_API nv_status nv_lin_build(nv_lin *l, const nv_heat *p, double t0, double T, int n_slices,
+                              double dt) {
+#pragma clang fp contract(off)
+    if (!l || !p) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    l->built = false;                        // a failed build leaves nothing to compose
+    if (p->M < 1 || p->M > kMaxM)
+        return fail(NV_ERR_INVALID_ARG, "M = %d: need 1..%d interior points", p->M, kMaxM);
+    if (n_slices < 1) return fail(NV_ERR_INVALID_ARG, "n_slices = %d", n_slices);
+    if (!std::isfinite(t0) || !std::isfinite(T) || !(T > t0))
+        return fail(NV_ERR_INVALID_ARG, "need finite t0 < T");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(NV_ERR_INVALID_ARG, "dt must be > 0");
+    if (!std::isfinite(p->a0) || !std::isfinite(p->a1))
+        return fail(NV_ERR_INVALID_ARG, "a0, a1 must be finite");
+    const int M = p->M;
+    const double L = (T - t0) / double(n_slices);
+    const double Sd = std::floor(L / dt + 1e-9);
+    if (Sd > 1e7) return fail(NV_ERR_INVALID_ARG, "more than 1e7 steps per slice");
+    const int S = int(Sd);
+    double rem = L - double(S) * dt;
+    if (!(rem > 1e-12 * L)) rem = 0.0;
+    const int S_tot = S + (rem > 0.0 ? 1 : 0);
+    if (S_tot < 1) return fail(NV_ERR_INVALID_ARG, "a slice takes no step");
+    const long long nq = (long long)n_slices * S_tot;
+    // per-step scalars on the host: r = (h a(t_end)) / (dx dx), h beta(t_end)
+    const double dx = 1.0 / double(M + 1);
+    std::vector<double> step(size_t(nq) * 2), sv(M);
+    for (int j = 0; j < n_slices; ++j) {
+        const double Tj = t0 + double(j) * L;
+        for (int st = 0; st < S_tot; ++st) {
+            const bool last = st == S;
+            const double h = last ? rem : dt;
+            const double te = last ? (Tj + double(S) * dt) + rem : Tj + double(st + 1) * dt;
+            const double a = a_of(*p, te);
+            if (!(a > 0.0))
+                return fail(NV_ERR_INVALID_ARG, "a(t) = %g is not positive at t = %g", a, te);
+            const size_t q = size_t(j) * S_tot + st;
+            step[2 * q] = (h * a) / (dx * dx);
+            step[2 * q + 1] = p->forcing ? h * beta_of(*p, te) : 0.0;
+        }
+    }
+    for (int i = 0; i < M; ++i) sv[i] = std::sin(M_PI * (double(i + 1) * dx));
+
+    // device layout
+    size_t off = 0;
+    const size_t o_step = off; off = al(off + size_t(nq) * 2 * 8);
+    const size_t o_w = off;    off = al(off + size_t(nq) * M * 8);
+    const size_t o_c = off;    off = al(off + size_t(nq) * M * 8);
+    const size_t o_s = off;    off = al(off + size_t(M) * 8);
+    const size_t o_GT = off;   off = al(off + size_t(n_slices) * M * M * 8);
+    const size_t o_cv = off;   off = al(off + size_t(n_slices) * M * 8);
+    const size_t o_y0 = off;   off = al(off + size_t(M) * 8);
+    const size_t o_b = off;    off = al(off + (size_t(n_slices) + 1) * M * 8);
+    const size_t o_bad = off;  off = al(off + sizeof(int));
+    if (off > l->mem_bytes) {
+        if (l->mem) {
+            NV_HIP(hipStreamSynchronize(l->stream));
+            NV_HIP(hipFree(l->mem));
+            l->mem = nullptr;
+            l->mem_bytes = 0;
+        }
+        if (hipMalloc(reinterpret_cast<void **>(&l->mem), off) != hipSuccess) {
+            l->built = false;
+            return fail(NV_ERR_OOM, "device allocation of %zu bytes failed", off);
+        }
+        l->mem_bytes = off;
+    }
+    l->step = reinterpret_cast<double *>(l->mem + o_step);
+    l->w = reinterpret_cast<double *>(l->mem + o_w);
+    l->c = reinterpret_cast<double *>(l->mem + o_c);
+    l->s = reinterpret_cast<double *>(l->mem + o_s);
+    l->GT = reinterpret_cast<double *>(l->mem + o_GT);
+    l->cvec = reinterpret_cast<double *>(l->mem + o_cv);
+    l->y0 = reinterpret_cast<double *>(l->mem + o_y0);
+    l->boundary = reinterpret_cast<double *>(l->mem + o_b);
+    l->bad = reinterpret_cast<int *>(l->mem + o_bad);
+    l->M = M;
+    l->N = n_slices;
+    l->S_tot = S_tot;
+    l->built = false;
+
+    NV_HIP(hipMemcpyAsync(l->step, step.data(), step.size() * 8, hipMemcpyHostToDevice,
+                          l->stream));
+    NV_HIP(hipMemcpyAsync(l->s, sv.data(), sv.size() * 8, hipMemcpyHostToDevice, l->stream));
+    NV_HIP(hipEventRecord(l->e0, l->stream));
+    CoefArgs ca{l->step, l->w, l->c, nq, M};
+    hipLaunchKernelGGL(lin_coef_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0,
+                       l->stream, ca);
+    NV_HIP(hipGetLastError());
+    BuildArgs ba{l->step, l->w, l->c, l->s, l->GT, l->cvec, M, S_tot, p->forcing ? 1 : 0};
+    const int ncol = 64 * ((M + 1 + 63) / 64);
+    const size_t lds = size_t(M) * ncol * sizeof(double);     // at most 127 x 128 x 8 bytes
+    NV_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(lin_build_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    hipLaunchKernelGGL(lin_build_kernel, dim3(unsigned(n_slices)), dim3(ncol), lds, l->stream,
+                       ba);
+    NV_HIP(hipGetLastError());
+    NV_HIP(hipEventRecord(l->e1, l->stream));
+    // the host vectors must outlive the copies
+    NV_HIP(hipStreamSynchronize(l->stream));
+    NV_HIP(hipEventElapsedTime(&l->build_ms, l->e0, l->e1));
+    l->built = true;
+    return NV_OK;
+}
+
+NV_API nv_status nv_lin_compose(nv_lin *l, const double *y0, double *yT, double *boundary) {
+    if (!l || !y0 || !yT) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    if (!l->built) return fail(NV_ERR_NOT_BUILT, "no successful nv_lin_build");
+    const int M = l->M, N = l->N;
+    NV_HIP(hipMemcpyAsync(l->y0, y0, size_t(M) * 8, hipMemcpyHostToDevice, l->stream));
+    NV_HIP(hipEventRecord(l->e2, l->stream));
+    ComposeArgs a{l->GT, l->cvec, l->y0, l->boundary, l->bad, M, N};
+    hipLaunchKernelGGL(lin_compose_kernel, dim3(1), dim3(kComposeThreads), 0, l->stream, a);
+    NV_HIP(hipGetLastError());
+    NV_HIP(hipEventRecord(l->e3, l->stream));
+    int bad = -1;
+    NV_HIP(hipMemcpyAsync(&bad, l->bad, sizeof(int), hipMemcpyDeviceToHost, l->stream));
+    NV_HIP(hipMemcpyAsync(yT, l->boundary + size_t(N) * M, size_t(M) * 8, hipMemcpyDeviceToHost,
+                          l->stream));
+    if (boundary)
+        NV_HIP(hipMemcpyAsync(boundary, l->boundary, (size_t(N) + 1) * M * 8,
+                              hipMemcpyDeviceToHost, l->stream));
+    NV_HIP(hipStreamSynchronize(l->stream));
+    NV_HIP(hipEventElapsedTime(&l->compose_ms, l->e2, l->e3));
+    if (bad >= 0) return fail(NV_ERR_NONFINITE, "the state became non-finite in slice %d", bad);
+    return NV_OK;
+}
+
+NV_API nv_status nv_lin_get_tables(nv_lin *l, double *G, double *c) {
+    if (!l) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    if (!l->built) return fail(NV_ERR_NOT_BUILT, "no successful nv_lin_build");
+    const size_t M = size_t(l->M), N = size_t(l->N);
+    if (c) NV_HIP(hipMemcpyAsync(c, l->cvec, N * M * 8, hipMemcpyDeviceToHost, l->stream));
+    if (G) {
+        std::vector<double> gt(N * M * M);
+        NV_HIP(hipMemcpyAsync(gt.data(), l->GT, gt.size() * 8, hipMemcpyDeviceToHost,
+                              l->stream));
+        NV_HIP(hipStreamSynchronize(l->stream));
+        for (size_t j = 0; j < N; ++j)
+            for (size_t k = 0; k < M; ++k)
+                for (size_t i = 0; i < M; ++i) G[(j * M + i) * M + k] = gt[(j * M + k) * M + i];
+    }
+    NV_HIP(hipStreamSynchronize(l->stream));
+    return NV_OK;
+}
+
+NV_API nv_status nv_lin_last_timing(nv_lin *l, float *build_ms, float *compose_ms) {
+    if (!l) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    if (build_ms) *build_ms = l->build_ms;
+    if (compose_ms) *compose_ms = l->compose_ms;
+    return NV_OK;
+}
+
+}  // extern "C"

@@ -492,3 +492,72 @@ def nv_sur_last_ms(sur):
     ms = ctypes.c_float()
     _check(load().nv_sur_last_ms(sur, ctypes.byref(ms)))
     return ms.value
+
+
+# ---- affine basis propagator for linear systems (include/nv_linear.h) ---------
+
+NV_LIN_MAX_POINTS = 127
+
+
+class nv_heat(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int), ("a0", ctypes.c_double), ("a1", ctypes.c_double),
+                ("forcing", ctypes.c_int)]
+
+
+_SIGNATURES.update({
+    "nv_lin_create": [_P, ctypes.POINTER(ctypes.c_void_p)],
+    "nv_lin_destroy": [_P],
+    "nv_lin_build": [_P, ctypes.POINTER(nv_heat), ctypes.c_double, ctypes.c_double,
+                     ctypes.c_int, ctypes.c_double],
+    "nv_lin_compose": [_P, _P, _P, _P],
+    "nv_lin_get_tables": [_P, _P, _P],
+    "nv_lin_last_timing": [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+})
+
+
+def make_heat(M, a0=1.0, a1=0.25, forcing=True) -> nv_heat:
+    h = nv_heat()
+    h.M, h.a0, h.a1, h.forcing = int(M), float(a0), float(a1), int(bool(forcing))
+    return h
+
+
+def nv_lin_create(stream=None):
+    h = ctypes.c_void_p()
+    _check(load().nv_lin_create(stream, ctypes.byref(h)))
+    return h
+
+
+def nv_lin_destroy(lin):
+    return _check(load().nv_lin_destroy(lin))
+
+
+def nv_lin_build(lin, heat: nv_heat, t0, T, n_slices, dt):
+    return _check(load().nv_lin_build(lin, ctypes.byref(heat), float(t0), float(T),
+                                      int(n_slices), float(dt)))
+
+
+def nv_lin_compose(lin, y0, M, n_slices, want_boundary=True):
+    """Returns (status, yT, boundary or None); raises on statuses other than
+    NV_OK and NV_ERR_NONFINITE."""
+    y0 = np.ascontiguousarray(np.asarray(y0, dtype=np.float64).reshape(-1))
+    if y0.size != M:
+        raise ValueError(f"y0 has {y0.size} values, the problem {M}")
+    yT = np.full(M, np.nan)
+    b = np.full((n_slices + 1, M), np.nan) if want_boundary else None
+    st = load().nv_lin_compose(lin, _ptr(y0), _ptr(yT), _ptr(b) if b is not None else None)
+    if st not in (NV_OK, NV_ERR_NONFINITE):
+        _check(st)
+    return st, yT, b
+
+
+def nv_lin_get_tables(lin, M, n_slices):
+    G = np.empty((n_slices, M, M))
+    c = np.empty((n_slices, M))
+    _check(load().nv_lin_get_tables(lin, _ptr(G), _ptr(c)))
+    return G, c
+
+
+def nv_lin_last_timing(lin):
+    b, c = ctypes.c_float(), ctypes.c_float()
+    _check(load().nv_lin_last_timing(lin, ctypes.byref(b), ctypes.byref(c)))
+    return b.value, c.value

@@ -234,3 +234,14 @@ def test_surrogate_input_recipe():
     assert np.abs(p[:512]).max() <= 0.5 and np.abs(p[640:640 + 16384]).max() <= 1 / np.sqrt(128)
     perm = W.surrogate_perm(1000, seed=1)
     assert np.array_equal(np.sort(perm), np.arange(1000))
+
+
+def test_linear_argument_errors_need_no_gpu(nvmod):
+    lib = nvmod.load()
+    assert lib.nv_lin_create(None, None) == nvmod.NV_ERR_INVALID_ARG
+    assert lib.nv_lin_destroy(None) == 0
+    h = nvmod.make_heat(9)
+    assert lib.nv_lin_build(None, ctypes.byref(h), 0.0, 1.0, 4, 0.01) == nvmod.NV_ERR_INVALID_ARG
+    assert lib.nv_lin_compose(None, None, None, None) == nvmod.NV_ERR_INVALID_ARG
+    assert lib.nv_lin_get_tables(None, None, None) == nvmod.NV_ERR_INVALID_ARG
+    assert lib.nv_lin_last_timing(None, None, None) == nvmod.NV_ERR_INVALID_ARG

@@ -1,0 +1,96 @@
+"""GPU parity of the affine basis propagator (heat equation of sec. 6): the
+tables and the composition equal the oracle's to the bit (FP64, one rounding
+per operation, the same operation order on both sides), and the method equals
+serial backward Euler up to rounding, as the paper states for linear
+problems."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import linear_oracle as lo
+from paper_1304_6514_amd import nv
+from paper_1304_6514_amd.linear import HeatWorkload
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-test]", *a, file=sys.__stderr__, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lin():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1304_6514_amd.linear import LinearPropagator
+    nv.load()
+    p = LinearPropagator()
+    yield p
+    p.close()
+
+
+CASES = [HeatWorkload("heat-M9-dt0.005-N8", 9, 0.005, 8, T=1.0),
+         HeatWorkload("heat-M9-dt0.003-N7-remainder", 9, 0.003, 7, T=1.0),
+         HeatWorkload("heat-M1", 1, 0.01, 3, T=0.5),
+         HeatWorkload("heat-M63-two-waves", 63, 0.002, 5, T=0.1),
+         HeatWorkload("heat-M70-unforced", 70, 0.001, 4, T=0.05, forcing=False),
+         HeatWorkload("heat-M127-max", 127, 0.001, 3, T=0.02)]
+
+
+@pytest.mark.parametrize("w", CASES, ids=lambda w: w.name)
+def test_tables_and_composition_bit_exact(lin, w):
+    say("linear", w.name)
+    lin.build(w)
+    G, c = lin.tables()
+    Go, co = lo.build_tables(w.M, w.a0, w.a1, w.forcing, w.t0, w.T, w.n_slices, w.dt)
+    assert np.array_equal(G, Go) and np.array_equal(c, co)
+    y0 = lo.exact(w.t0, w.M) + 0.1 * np.cos(np.arange(w.M))
+    st, yT, bnd = lin.compose(y0)
+    assert st == nv.NV_OK
+    ref = lo.compose(Go, co, y0)
+    assert np.array_equal(bnd, ref) and np.array_equal(yT, ref[-1])
+
+
+@pytest.mark.parametrize("M,dt,N", [(9, 0.005, 128), (19, 0.001, 256), (99, 0.0005, 1024)])
+def test_paper_sizes_method_equals_serial_backward_euler(lin, M, dt, N):
+    """Tables 5, 7 and 8 of sec. 6 (dx = 0.1, 0.05, 0.01; T = 10): the method's
+    y(T) equals serial backward Euler with the same steps to rounding, and
+    sampled slices' tables equal the oracle's to the bit."""
+    w = HeatWorkload(f"heat-M{M}", M, dt, N)
+    say(f"linear paper size M={M} dt={dt} N={N}")
+    lin.build(w)
+    b_ms, _ = lin.last_timing()
+    y0 = lo.exact(0.0, M)
+    st, yT, _ = lin.compose(y0, want_boundary=False)
+    _, c_ms = lin.last_timing()
+    assert st == nv.NV_OK
+    serial = lo.serial(M, w.a0, w.a1, True, w.t0, w.T, N, dt, y0)
+    diff = float(np.max(np.abs(yT - serial)))
+    err = float(np.max(np.abs(yT - lo.exact(w.T, M))))
+    say(f"  build {b_ms:.3f} ms, compose {c_ms:.3f} ms, |method - serial BE| = {diff:.3g}, "
+        f"|method - cos(t) sin(pi x)| = {err:.3g}")
+    assert diff <= 1e-12 * max(1.0, float(np.max(np.abs(serial))))
+    assert err < 0.02
+    G, c = lin.tables()
+    pick = [0, N // 2, N - 1]
+    Go, co = lo.build_tables(M, w.a0, w.a1, True, w.t0, w.T, N, dt, slices=pick)
+    assert np.array_equal(G[pick], Go) and np.array_equal(c[pick], co)
+
+
+def test_linear_argument_errors(lin):
+    with pytest.raises(nv.NvError) as e:
+        lin.build(HeatWorkload("bad-M", 128, 0.01, 4))
+    assert e.value.status == nv.NV_ERR_INVALID_ARG
+    with pytest.raises(nv.NvError) as e:
+        lin.build(HeatWorkload("bad-a", 9, 0.01, 4, a0=-1.0, a1=0.25))
+    assert e.value.status == nv.NV_ERR_INVALID_ARG and "not positive" in str(e.value)
+    with pytest.raises(nv.NvError) as e:
+        lin.build(HeatWorkload("bad-dt", 9, 0.0, 4))
+    assert e.value.status == nv.NV_ERR_INVALID_ARG
+    # a failed build leaves nothing to compose
+    with pytest.raises(nv.NvError) as e:
+        nv.nv_lin_compose(lin.h, np.zeros(9), 9, 4)
+    assert e.value.status == nv.NV_ERR_NOT_BUILT

@@ -47,7 +47,7 @@ WORKLOADS = {"forced_cubic": W.FORCED_CUBIC_FP32, "logistic": W.LOGISTIC_FP64,
 # Valid only for the kernel source they were taken with (SHA-1 below); any
 # other source gives traffic = null.
 MEASURED_TRAFFIC = {
-    ("forced-cubic-fp32-4096sl-4096pt-2000st", "blocked", "2502893abcb2af3335325fdf4026b1a36c6bbffb"): 198.3e6,
+    ("forced-cubic-fp32-4096sl-4096pt-2000st", "blocked", "c01e5e1f695d08523570305ed8c49942da7b06c8"): 198.3e6,
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1304_6514_amd", "csrc", f)
                   for f in ("integrate.h", "build_kernels.hip")]
@@ -482,13 +482,88 @@ def bench_surrogate(args):
     return out
 
 
+# Sec. 6, Tables 5, 7 and 8: the heat equation on [0, 10] with backward Euler,
+# the largest slice count of each table, and the paper's cluster timings at
+# that count and at one processor (seconds; context, other hardware).
+HEAT_SHAPES = [  # (dx, dt, N, paper T_total at N, paper serial T_total)
+    (0.1, 0.005, 128, 0.01763, 0.2870),
+    (0.05, 0.001, 256, 0.0984, 1.641),
+    (0.01, 0.0005, 1024, 1.595, 16.166),
+]
+
+
+def bench_heat(args):
+    """The affine basis propagator on the three heat-equation shapes of sec. 6:
+    time to y(T) of build + composition on the GPU (buffers allocated by a
+    warm-up build), against serial backward Euler on one host core (the CPU
+    oracle) and the paper's cluster timings as context."""
+    import numpy as np
+
+    from paper_1304_6514_amd.linear import HeatWorkload, LinearPropagator
+
+    rows = []
+    with LinearPropagator() as lp:
+        for dx, dt, N, paper_t, paper_serial in HEAT_SHAPES:
+            M = int(round(1.0 / dx)) - 1
+            w = HeatWorkload(f"heat-M{M}-dt{dt:g}-N{N}", M, dt, N)
+            y0 = np.sin(np.pi * dx * np.arange(1, M + 1))
+            lp.build(w)
+            lp.compose(y0, want_boundary=False)
+            ts, bk, ck = [], [], []
+            for _ in range(max(args.steps, 1)):
+                t = time.perf_counter()
+                lp.build(w)
+                st, yT, _ = lp.compose(y0, want_boundary=False)
+                ts.append(time.perf_counter() - t)
+                b, c = lp.last_timing()
+                bk.append(b)
+                ck.append(c)
+            L = 10.0 / N
+            S = int(np.floor(L / dt + 1e-9))
+            s_tot = S + (1 if L - S * dt > 1e-12 * L else 0)
+            solve_steps = N * s_tot * (M + 1)
+            err = float(np.max(np.abs(yT - np.cos(10.0) * y0)))
+            rows.append({"shape": w.name, "M": M, "dt": dt, "N": N, "steps_per_slice": s_tot,
+                         "T_total_us": round(1e6 * min(ts), 2),
+                         "build_kernels_ms": round(min(bk), 4),
+                         "compose_kernel_ms": round(min(ck), 4),
+                         "tau_N_us": round(1e3 * min(ck) / N, 4),
+                         "solve_steps": solve_steps,
+                         "error_vs_closed_form": err,
+                         "paper_T_total_s": paper_t, "paper_serial_s": paper_serial})
+    big = rows[-1]
+    out = {
+        "metric": "affine basis propagator (heat equation): backward-Euler solve-steps/s, "
+                  "time to y(T)",
+        "value": big["solve_steps"] / (big["T_total_us"] * 1e-6), "unit": "solve-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": round(big["T_total_us"] / 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "heat-sec6-tables-5-7-8", "parallelism": "single-gpu"},
+        "rows": rows,
+        "vs_baseline_note": "the paper's heat timings are cluster runs (context only)",
+    }
+    if not args.no_cpu_baseline:
+        from oracle import linear_oracle as lo
+        dx, dt, N, _, _ = HEAT_SHAPES[0]
+        M = int(round(1.0 / dx)) - 1
+        t = time.perf_counter()
+        lo.serial(M, 1.0, 0.25, True, 0.0, 10.0, N, dt, np.sin(np.pi * dx * np.arange(1, M + 1)))
+        el = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": (10.0 / dt) / el, "unit": "BE steps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"serial backward Euler, M = {M}, dt = {dt}, [0, 10] "
+                                         f"({el:.2f} s, FP64, Python, one thread)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="forced_cubic",
-                    choices=sorted(WORKLOADS) + ["batched", "paper-table3", "surrogate"])
+                    choices=sorted(WORKLOADS) + ["batched", "paper-table3", "surrogate", "heat"])
     ap.add_argument("--traj-per-lane", type=int, default=0)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default=None,
                     help="override the workload's build precision")
@@ -538,6 +613,9 @@ def main():
         return
     if args.workload == "surrogate":
         print(json.dumps(bench_surrogate(args)), flush=True)
+        return
+    if args.workload == "heat":
+        print(json.dumps(bench_heat(args)), flush=True)
         return
     w = WORKLOADS[args.workload]
     if args.precision:

@@ -114,14 +114,29 @@ struct ComposeArgs {
     int M, N;
 };
 
+// MB > 0: lane i keeps its row of the current slice's table in registers
+// (MB >= M values) and loads the next slice's row while it forms the current
+// sum, so the memory latency hides behind the dependent chain.  MB = 0: rows
+// are read from memory inside the sum (any M).
+template <int MB>
 __global__ __launch_bounds__(kComposeThreads) void lin_compose_kernel(ComposeArgs a) {
 #pragma clang fp contract(off)
     __shared__ double lam[kMaxM];
     __shared__ double bnd[kBoundaryChunk][kMaxM];
     const int i = int(threadIdx.x), M = a.M;
-    if (i < M) {
+    const bool row = i < M;
+    const int ic = row ? i : 0;
+    if (row) {
         lam[i] = a.y0[i];
         a.boundary[i] = a.y0[i];
+    }
+    constexpr int R = MB > 0 ? MB : 1;
+    double cur[R], nxt[R];
+    double c_cur = 0.0, c_nxt = 0.0;
+    if (MB > 0) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) cur[k] = k < M ? a.GT[(long long)k * M + ic] : 0.0;
+        c_cur = a.cvec[ic];
     }
     int bad = -1;
     for (int c0 = 0; c0 < a.N; c0 += kBoundaryChunk) {
@@ -129,22 +144,36 @@ __global__ __launch_bounds__(kComposeThreads) void lin_compose_kernel(ComposeArg
         for (int j = c0; j < c1; ++j) {
             __syncthreads();                         // lam of slice j is complete
             double acc = 0.0;
-            if (i < M) {
+            if (MB > 0) {
+                if (j + 1 < a.N) {
+                    const double *G = a.GT + (long long)(j + 1) * M * M;
+#pragma unroll
+                    for (int k = 0; k < R; ++k) nxt[k] = k < M ? G[(long long)k * M + ic] : 0.0;
+                    c_nxt = a.cvec[(long long)(j + 1) * M + ic];
+                }
+                acc = c_cur;
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    if (k < M) acc = acc + cur[k] * lam[k];
+#pragma unroll
+                for (int k = 0; k < R; ++k) cur[k] = nxt[k];
+                c_cur = c_nxt;
+            } else if (row) {
                 const double *G = a.GT + (long long)j * M * M;
                 acc = a.cvec[(long long)j * M + i];
-#pragma unroll 8
+#pragma unroll 32
                 for (int k = 0; k < M; ++k) acc = acc + G[(long long)k * M + i] * lam[k];
             }
             __syncthreads();                         // every lane has read lam
-            if (i < M) {
+            if (row) {
                 lam[i] = acc;
                 bnd[j - c0][i] = acc;
             }
-            if (bad < 0 && __syncthreads_or(i < M && !isfinite(acc))) bad = j;
+            if (bad < 0 && __syncthreads_or(row && !isfinite(acc))) bad = j;
         }
         __syncthreads();
         for (int jj = c0; jj < c1; ++jj)
-            if (i < M) a.boundary[(long long)(jj + 1) * M + i] = bnd[jj - c0][i];
+            if (row) a.boundary[(long long)(jj + 1) * M + i] = bnd[jj - c0][i];
     }
     if (i == 0) *a.bad = bad;
 }
@@ -325,7 +354,17 @@ NV_API nv_status nv_lin_compose(nv_lin *l, const double *y0, double *yT, double 
     NV_HIP(hipMemcpyAsync(l->y0, y0, size_t(M) * 8, hipMemcpyHostToDevice, l->stream));
     NV_HIP(hipEventRecord(l->e2, l->stream));
     ComposeArgs a{l->GT, l->cvec, l->y0, l->boundary, l->bad, M, N};
-    hipLaunchKernelGGL(lin_compose_kernel, dim3(1), dim3(kComposeThreads), 0, l->stream, a);
+    if (M <= 16)
+        hipLaunchKernelGGL(lin_compose_kernel<16>, dim3(1), dim3(kComposeThreads), 0, l->stream, a);
+    else if (M <= 32)
+        hipLaunchKernelGGL(lin_compose_kernel<32>, dim3(1), dim3(kComposeThreads), 0, l->stream, a);
+    else if (M <= 64)
+        hipLaunchKernelGGL(lin_compose_kernel<64>, dim3(1), dim3(kComposeThreads), 0, l->stream, a);
+    else if (M <= 112)
+        hipLaunchKernelGGL(lin_compose_kernel<112>, dim3(1), dim3(kComposeThreads), 0, l->stream,
+                           a);
+    else
+        hipLaunchKernelGGL(lin_compose_kernel<0>, dim3(1), dim3(kComposeThreads), 0, l->stream, a);
     NV_HIP(hipGetLastError());
     NV_HIP(hipEventRecord(l->e3, l->stream));
     int bad = -1;

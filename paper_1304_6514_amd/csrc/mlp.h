@@ -47,6 +47,7 @@ constexpr int kG_D_XO = 32768;              // [384 x 16]   D . XO^T  (dW1, db1.
 constexpr int kG_XO_H3 = 32768 + 384 * 16;  // [16 x 144]   XO . [H3; XO]^T  (dW4, db4)
 constexpr int kGradEntries = kG_XO_H3 + 16 * 144;
 constexpr int kGemmWaveTiles = 16 + 16 + 12 + 5;
+constexpr int kGemmSmallFirst = 32;         // wave tiles of the two small products
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -155,31 +156,48 @@ __device__ inline void load_mats(__bf16 *lds, const __bf16 *src, int n_mat, int 
     }
 }
 
-// Rows row0 + f of the training workspace receive the lane's 32 features of
-// its sample.  lane_col is S + 4 g ldS + n; the remaining row offsets are the
-// same in every lane, so they stay scalar instead of occupying vector registers.
-__device__ inline void store_rows(__bf16 *lane_col, long long ldS, int row0,
-                                  const bf16x8 (&b)[4]) {
+// Where the training kernel writes a tile's rows: the workspace S (row r,
+// sample n at S[r * ld + n]) at the tile's first sample.  Each lane writes its
+// 32 features of its sample; the row offsets are the same in every lane, so
+// they stay scalar instead of occupying vector registers.  (Routing the stores
+// through an LDS transpose into 16-byte runs was measured slower.)
+struct RowSink {
+    __bf16 *tile;               // S + 16 * tile
+    long long ld;
+};
+
+// Rows row0 + f (f = 0..127) of the tile from the lane's B operands b[kb]
+// (element e of b[kb] is feature 32 kb + perm32(8 g + e)).
+__device__ inline void store_rows(const RowSink &o, int row0, const bf16x8 (&b)[4], int lane) {
+    const int s = lane & 15, g = lane >> 4;
+    __bf16 *col = o.tile + (long long)(4 * g) * o.ld + s;
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int f = 32 * kb + (e < 4 ? e : 16 + (e - 4));
-            lane_col[(long long)(row0 + f) * ldS] = b[kb][e];
+            col[(long long)(row0 + f) * o.ld] = b[kb][e];
         }
     }
+}
+
+// The 16 rows starting at row0 from four values per lane (rows 4 g + r).
+__device__ inline void store_rows16(const RowSink &o, int row0, const __bf16 (&v)[4], int lane) {
+    const int s = lane & 15, g = lane >> 4;
+    __bf16 *col = o.tile + (long long)(4 * g) * o.ld + s;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) col[(long long)(row0 + r) * o.ld] = v[r];
 }
 
 // Forward pass of the lane's sample, u = normalised input.  Returns the two
 // outputs (identical in the four lanes that share a sample) and a3.  When
 // Train, also fills the hidden layers' GELU derivatives d1..d3 and stores the
 // bf16 inputs of the two matrix layers (a1, a2) to the workspace rows kRowH
-// and kRowH + 128 through lane_col.
+// and kRowH + 128 through the sink.
 template <bool Train>
 __device__ inline void forward(const SmallParams &sp, const __bf16 *Wf2, const __bf16 *Wf3,
                                const float (&u)[4], int lane, Layer &d1, Layer &d2, Layer &d3,
-                               Layer &a3, float &o0, float &o1, __bf16 *lane_col,
-                               long long ldS) {
+                               Layer &a3, float &o0, float &o1, const RowSink *sink) {
     const int g = lane >> 4;
     Layer x;
     bf16x8 b[4];
@@ -199,7 +217,7 @@ __device__ inline void forward(const SmallParams &sp, const __bf16 *Wf2, const _
         }
     }
     pack(x, b);
-    if (Train) store_rows(lane_col, ldS, kRowH, b);
+    if (Train) store_rows(*sink, kRowH, b, lane);
     matmul(Wf2, b, x, lane);
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) {
@@ -212,7 +230,7 @@ __device__ inline void forward(const SmallParams &sp, const __bf16 *Wf2, const _
         }
     }
     pack(x, b);
-    if (Train) store_rows(lane_col, ldS, kRowH + 128, b);
+    if (Train) store_rows(*sink, kRowH + 128, b, lane);
     matmul(Wf3, b, x, lane);
     float s0 = 0.f, s1 = 0.f;
 #pragma unroll

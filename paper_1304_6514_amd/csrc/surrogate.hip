@@ -80,10 +80,9 @@ struct TrainLds {
 // l: sample l % 16), writing the workspace rows of every sample.
 __device__ inline void train_tile(const TrainArgs &a, const TrainLds &L, long long tile, int li,
                                   int lane) {
-    const int s = lane & 15, g = lane >> 4;
+    const int g = lane >> 4;
     const __bf16 *Wf2 = L.w, *Wf3 = L.w + kWidth * kLdsRow;
     const __bf16 *Wb2 = L.w + 2 * kWidth * kLdsRow, *Wb3 = L.w + 3 * kWidth * kLdsRow;
-    const long long n = tile * 16 + s;
     float u[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) u[k] = (L.xs[k * kStageTiles * 16 + li] - a.shift[k]) * a.scale[k];
@@ -91,10 +90,10 @@ __device__ inline void train_tile(const TrainArgs &a, const TrainLds &L, long lo
     Layer d1, d2, d3, x;
     bf16x8 b[4];
     float o0, o1;
-    __bf16 *col = a.S + (long long)(4 * g) * a.ldS + n;
-    forward<true>(L.sp, Wf2, Wf3, u, lane, d1, d2, d3, x, o0, o1, col, a.ldS);
+    const RowSink sink{a.S + tile * 16, a.ldS};
+    forward<true>(L.sp, Wf2, Wf3, u, lane, d1, d2, d3, x, o0, o1, &sink);
     pack(x, b);
-    store_rows(col, a.ldS, kRowH + 256, b);
+    store_rows(sink, kRowH + 256, b, lane);
 
     const float e0 = o0 - t0, e1 = o1 - t1;
     const float dout0 = 2.0f * e0 * a.inv_n, dout1 = 2.0f * e1 * a.inv_n;
@@ -108,17 +107,17 @@ __device__ inline void train_tile(const TrainArgs &a, const TrainLds &L, long lo
         }
     }
     pack(x, b);
-    store_rows(col, a.ldS, kRowD + 256, b);
+    store_rows(sink, kRowD + 256, b, lane);
     matmul(Wb3, b, x, lane);                              // W3^T dL/dz3
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) x.v[mt] *= d2.v[mt];
     pack(x, b);
-    store_rows(col, a.ldS, kRowD + 128, b);
+    store_rows(sink, kRowD + 128, b, lane);
     matmul(Wb2, b, x, lane);                              // W2^T dL/dz2
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) x.v[mt] *= d1.v[mt];
     pack(x, b);
-    store_rows(col, a.ldS, kRowD, b);
+    store_rows(sink, kRowD, b, lane);
 
     // rows of XO: group 0 writes u0..u3, group 1 writes 1, dout0, dout1, 0,
     // groups 2 and 3 the zero rows
@@ -135,8 +134,7 @@ __device__ inline void train_tile(const TrainArgs &a, const TrainLds &L, long lo
 #pragma unroll
         for (int r = 0; r < 4; ++r) xo[r] = __bf16(0.0f);
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) col[(long long)(kRowXO + r) * a.ldS] = xo[r];
+    store_rows16(sink, kRowXO, xo, lane);
 
     float sq = g == 0 ? e0 * e0 + e1 * e1 : 0.0f;
     sq += __shfl_xor(sq, 1);
@@ -178,8 +176,9 @@ __global__ __launch_bounds__(kTrainThreads) void sur_train_kernel(TrainArgs a) {
 }
 
 // Weight-gradient sums G = A B^T over samples k0..k1-1 of the minibatch, A and
-// B row blocks of S; each wave computes a 32 x 32 block of one of the four
-// products (kGemmWaveTiles waves), blockIdx.y is the split of the sum.
+// B row blocks of S; each wave computes a 32 x 32 block of one of the products
+// (wave tiles kGemmSmallFirst.. of kGemmWaveTiles: the two small products
+// D . XO^T and XO . [H3; XO]^T), blockIdx.y is the split of the sum.
 struct GemmArgs {
     const __bf16 *S;
     long long ldS, n, k_per_split;
@@ -188,7 +187,7 @@ struct GemmArgs {
 
 __global__ __launch_bounds__(256) void sur_grad_kernel(GemmArgs a) {
     const int lane = int(threadIdx.x) & 63, r = lane & 15, g = lane >> 4;
-    const int wt = int(blockIdx.x) * 4 + (int(threadIdx.x) >> 6);
+    const int wt = kGemmSmallFirst + int(blockIdx.x) * 4 + (int(threadIdx.x) >> 6);
     if (wt >= kGemmWaveTiles) return;
     int a_row, b_row, M, N, out, t, tiles_n;
     if (wt < 16) {
@@ -251,6 +250,74 @@ __global__ __launch_bounds__(256) void sur_grad_kernel(GemmArgs a) {
         if (m1) P[(row0 + 16) * N + col0] = c10[i];
         if (m1 && n1) P[(row0 + 16) * N + col0 + 16] = c11[i];
     }
+}
+
+// The two 128 x 128 weight gradients, dW2 = D2 . H1^T and dW3 = D3 . H2^T
+// (blockIdx.x = 0, 1), over samples k0..k1-1 (blockIdx.y = split).  The
+// workgroup stages each 32-sample step of its 128 A rows and 128 B rows in LDS
+// once (rows padded to 80 bytes: 16 lanes reading 16 bytes from 16 rows hit
+// disjoint banks) and each wave multiplies a 64 x 64 quadrant; the next step's
+// rows are loaded into registers while the current one is multiplied.
+constexpr int kGmPad = 40;                 // bf16 per LDS row
+
+__global__ __launch_bounds__(256) void sur_grad_mat_kernel(GemmArgs a) {
+    __shared__ __bf16 As[128 * kGmPad], Bs[128 * kGmPad];
+    const int job = int(blockIdx.x);
+    const int a_row = job == 0 ? kRowD + 128 : kRowD + 256;
+    const int b_row = job == 0 ? kRowH : kRowH + 128;
+    const int out = job == 0 ? kG_W2 : kG_W3;
+    const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4, mh = wave >> 1, nh = wave & 1;
+    const long long k0 = (long long)blockIdx.y * a.k_per_split;
+    const long long k1 = std::min(k0 + a.k_per_split, a.n);
+    // this thread's share of a step: chunks tid and tid + 256 of 4 x 128 16-byte chunks
+    const int row0 = tid >> 2, part0 = tid & 3, row1 = (tid + 256) >> 2, part1 = (tid + 256) & 3;
+    const bf16x8 zero = {};
+    auto load = [&](long long k, bf16x8 &a0, bf16x8 &a1, bf16x8 &b0, bf16x8 &b1) {
+        const bool ok0 = k + 8 * part0 < k1, ok1 = k + 8 * part1 < k1;
+        a0 = ok0 ? *reinterpret_cast<const bf16x8 *>(a.S + (long long)(a_row + row0) * a.ldS + k +
+                                                     8 * part0) : zero;
+        a1 = ok1 ? *reinterpret_cast<const bf16x8 *>(a.S + (long long)(a_row + row1) * a.ldS + k +
+                                                     8 * part1) : zero;
+        b0 = ok0 ? *reinterpret_cast<const bf16x8 *>(a.S + (long long)(b_row + row0) * a.ldS + k +
+                                                     8 * part0) : zero;
+        b1 = ok1 ? *reinterpret_cast<const bf16x8 *>(a.S + (long long)(b_row + row1) * a.ldS + k +
+                                                     8 * part1) : zero;
+    };
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 ra0, ra1, rb0, rb1;
+    if (k0 < k1) load(k0, ra0, ra1, rb0, rb1);
+    for (long long k = k0; k < k1; k += 32) {
+        *reinterpret_cast<bf16x8 *>(As + row0 * kGmPad + 8 * part0) = ra0;
+        *reinterpret_cast<bf16x8 *>(As + row1 * kGmPad + 8 * part1) = ra1;
+        *reinterpret_cast<bf16x8 *>(Bs + row0 * kGmPad + 8 * part0) = rb0;
+        *reinterpret_cast<bf16x8 *>(Bs + row1 * kGmPad + 8 * part1) = rb1;
+        __syncthreads();
+        if (k + 32 < k1) load(k + 32, ra0, ra1, rb0, rb1);
+        bf16x8 fa[4], fb[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            fa[t] = *reinterpret_cast<const bf16x8 *>(As + (64 * mh + 16 * t + r) * kGmPad + 8 * g);
+            fb[t] = *reinterpret_cast<const bf16x8 *>(Bs + (64 * nh + 16 * t + r) * kGmPad + 8 * g);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma(fa[i], fb[j], acc[i][j]);
+        __syncthreads();
+    }
+    float *P = a.part + (long long)blockIdx.y * kGradEntries + out;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                P[(64 * mh + 16 * i + 4 * g + e) * 128 + 64 * nh + 16 * j + r] = acc[i][j][e];
 }
 
 // Offset of parameter p's gradient in the partial vector.
@@ -347,8 +414,7 @@ __global__ __launch_bounds__(kInferThreads) void sur_forward_kernel(ForwardArgs 
     for (int k = 0; k < 4; ++k) u[k] = (a.x[k * a.n + nc] - a.shift[k]) * a.scale[k];
     Layer d1, d2, d3, a3;
     float o0, o1;
-    forward<false>(L.sp, L.w, L.w + kWidth * kLdsRow, u, lane, d1, d2, d3, a3, o0, o1, nullptr,
-                   0);
+    forward<false>(L.sp, L.w, L.w + kWidth * kLdsRow, u, lane, d1, d2, d3, a3, o0, o1, nullptr);
     if (n < a.n && g == 0) {
         a.out[n] = o0;
         a.out[a.n + n] = o1;
@@ -398,20 +464,130 @@ __device__ inline void bilinear_row(const ChainArgs &a, int j, double l0, double
     q = s0 + w0 * (s1 - s0);
 }
 
+// The composition runs one dependent chain of network evaluations, so its
+// latency matters more than its throughput: a workgroup of 4 waves evaluates
+// the network for 16 chains together.  Wave w computes output tiles 2w and
+// 2w+1 (features 32w .. 32w+31) of every 128-wide layer, which is exactly
+// k-block w of the next layer's operand in the permuted order; the four blocks
+// are exchanged through LDS, and the output layer's partial sums are added in
+// wave order.
+struct ChainLds {
+    __bf16 w[2 * kWidth * kLdsRow];      // Wf2, Wf3
+    SmallParams sp;
+    bf16x8 xb[4][64];                    // operand k-block of each wave, by lane
+    float part[4][2][16];                // output partial sums: wave, output, sample
+};
+
+// One 128 x 128 layer's tiles 2w, 2w+1 from the four operand blocks.
+__device__ inline void layer_split(const __bf16 *M, const bf16x8 (&b)[4], int w, int lane,
+                                   f32x4 (&out)[2]) {
+    const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const __bf16 *row = M + (16 * (2 * w + t) + r) * kLdsRow + 8 * g;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+            acc = mfma(*reinterpret_cast<const bf16x8 *>(row + 32 * kb), b[kb], acc);
+        out[t] = acc;
+    }
+}
+
+// Publish this wave's block and gather all four (two barriers: the previous
+// round's reads are complete before the block is overwritten).
+__device__ inline void exchange(ChainLds &L, const bf16x8 &mine, int w, int lane,
+                                bf16x8 (&b)[4]) {
+    __syncthreads();
+    L.xb[w][lane] = mine;
+    __syncthreads();
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) b[kb] = L.xb[kb][lane];
+}
+
+__device__ inline void forward_split(ChainLds &L, const float (&u)[4], int w, int lane,
+                                     float &o0, float &o1) {
+    const int s = lane & 15, g = lane >> 4;
+    f32x4 x[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = 16 * (2 * w + t) + 4 * g + i;
+            float z = L.sp.b1[f];
+            z = fmaf(L.sp.w1[4 * f + 0], u[0], z);
+            z = fmaf(L.sp.w1[4 * f + 1], u[1], z);
+            z = fmaf(L.sp.w1[4 * f + 2], u[2], z);
+            z = fmaf(L.sp.w1[4 * f + 3], u[3], z);
+            float d;
+            x[t][i] = gelu_d(z, d);
+        }
+    }
+    bf16x8 b[4], blk;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        blk[e] = __bf16(x[0][e]);
+        blk[e + 4] = __bf16(x[1][e]);
+    }
+    exchange(L, blk, w, lane, b);
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+        const __bf16 *M = L.w + layer * kWidth * kLdsRow;
+        const float *bias = layer == 0 ? L.sp.b2 : L.sp.b3;
+        layer_split(M, b, w, lane, x);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float d;
+                x[t][i] = gelu_d(x[t][i] + bias[16 * (2 * w + t) + 4 * g + i], d);
+            }
+        }
+        if (layer == 0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                blk[e] = __bf16(x[0][e]);
+                blk[e + 4] = __bf16(x[1][e]);
+            }
+            exchange(L, blk, w, lane, b);
+        }
+    }
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = 16 * (2 * w + t) + 4 * g + i;
+            s0 = fmaf(L.sp.w4[f], x[t][i], s0);
+            s1 = fmaf(L.sp.w4[kWidth + f], x[t][i], s1);
+        }
+    }
+    s0 += __shfl_xor(s0, 16);
+    s1 += __shfl_xor(s1, 16);
+    s0 += __shfl_xor(s0, 32);
+    s1 += __shfl_xor(s1, 32);
+    if (g == 0) {
+        L.part[w][0][s] = s0;
+        L.part[w][1][s] = s1;
+    }
+    __syncthreads();
+    o0 = ((L.part[0][0][s] + L.part[1][0][s]) + (L.part[2][0][s] + L.part[3][0][s])) + L.sp.b4[0];
+    o1 = ((L.part[0][1][s] + L.part[1][1][s]) + (L.part[2][1][s] + L.part[3][1][s])) + L.sp.b4[1];
+}
+
 __global__ __launch_bounds__(kInferThreads) void sur_chain_kernel(ChainArgs a) {
 #pragma clang fp contract(off)
-    __shared__ InferLds L;
+    __shared__ ChainLds L;
     const int tid = int(threadIdx.x);
     load_mats(L.w, a.shadow, 2, tid, kInferThreads);
     load_small(L.sp, a.params, tid, kInferThreads);
     __syncthreads();
-    const int lane = tid & 63, s = lane & 15, g = lane >> 4;
-    const long long q = ((long long)blockIdx.x * (kInferThreads / 64) + (tid >> 6)) * 16 + s;
+    const int lane = tid & 63, w = tid >> 6, s = lane & 15, g = lane >> 4;
+    const long long q = (long long)blockIdx.x * 16 + s;        // the 4 waves share 16 chains
     const bool live = q < a.count;
     const long long qc = live ? q : a.count - 1;
     double l0 = a.y0[2 * qc], l1 = a.y0[2 * qc + 1];
     const float muf = float(a.mu[qc]);
-    const bool writer = live && g == 0;
+    const bool writer = live && g == 0 && w == 0;
     const long long stride = (long long)a.n_slices + 1;
     if (writer && a.boundary) {
         a.boundary[(q * stride) * 2] = l0;
@@ -426,10 +602,8 @@ __global__ __launch_bounds__(kInferThreads) void sur_chain_kernel(ChainArgs a) {
         const float tj = float(a.t0 + double(j) * a.L);
         float u[4] = {(float(l0) - a.shift[0]) * a.scale[0], (float(l1) - a.shift[1]) * a.scale[1],
                       (tj - a.shift[2]) * a.scale[2], (muf - a.shift[3]) * a.scale[3]};
-        Layer d1, d2, d3, a3;
         float o0, o1;
-        forward<false>(L.sp, L.w, L.w + kWidth * kLdsRow, u, lane, d1, d2, d3, a3, o0, o1,
-                       nullptr, 0);
+        forward_split(L, u, w, lane, o0, o1);
         double g0 = l0, g1 = l1;
         coarse_rk4(double(a.mu[qc]), a.L / double(a.coarse), a.coarse, g0, g1);
         double n0 = g0 + a.os0 * double(o0), n1 = g1 + a.os1 * double(o1);
@@ -601,8 +775,10 @@ nv_status minibatch(nv_sur *s, const float *x, const float *t, long long ld, lon
     ga.k_per_split = k_per_split(n);
     ga.part = s->part;
     const int splits = int((n + ga.k_per_split - 1) / ga.k_per_split);
-    hipLaunchKernelGGL(sur_grad_kernel, dim3((kGemmWaveTiles + 3) / 4, splits), dim3(256), 0,
-                       s->stream, ga);
+    hipLaunchKernelGGL(sur_grad_mat_kernel, dim3(2, splits), dim3(256), 0, s->stream, ga);
+    NV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(sur_grad_kernel, dim3((kGemmWaveTiles - kGemmSmallFirst + 3) / 4, splits),
+                       dim3(256), 0, s->stream, ga);
     NV_HIP(hipGetLastError());
 
     UpdateArgs ua{};
@@ -919,7 +1095,7 @@ NV_API nv_status nv_sur_compose(nv_sur *s, const nv_sur_chains *c, nv_sur_compos
     const unsigned long long init[4] = {0ull, 0ull, 0ull, ~0ull};
     NV_HIP(hipMemcpyAsync(s->stats, init, sizeof init, hipMemcpyHostToDevice, s->stream));
     a.stats = s->stats;
-    const long long blocks = (c->count + 63) / 64;
+    const long long blocks = (c->count + 15) / 16;
     if (blocks > 0x7fffffffLL) return fail(NV_ERR_INVALID_ARG, "too many chains");
     NV_HIP(hipEventRecord(s->ev0, s->stream));
     hipLaunchKernelGGL(sur_chain_kernel, dim3(unsigned(blocks)), dim3(kInferThreads), 0,

@@ -35,8 +35,6 @@ using nv::fail;
 namespace {
 
 constexpr int kMaxM = NV_LIN_MAX_POINTS;
-constexpr int kComposeThreads = 128;
-constexpr int kBoundaryChunk = 32;          // slices whose boundary states LDS collects
 
 struct CoefArgs {
     const double *step;         // [n_slices * S_tot][2]: r, h beta
@@ -61,12 +59,13 @@ __global__ __launch_bounds__(256) void lin_coef_kernel(CoefArgs a) {
     }
 }
 
+// Device table of slice j: T[j][k M + i] = G_j[i][k] (column-major), then
+// T[j][M M + i] = c_j[i]; one contiguous block of M (M + 1) values per slice.
 struct BuildArgs {
     const double *step;         // [n_slices * S_tot][2]
     const double *w, *c;        // [n_slices * S_tot][M]
     const double *s;            // [M] sin(pi x_i)
-    double *GT;                 // [n_slices][M][M]: GT[j][k][i] = G_j[i][k]
-    double *cvec;               // [n_slices][M]
+    double *T;                  // [n_slices][M (M + 1)]
     int M, S_tot, forcing;
 };
 
@@ -98,84 +97,97 @@ __global__ __launch_bounds__(256) void lin_build_kernel(BuildArgs a) {
         }
     }
     if (!live) return;
-    if (lane == 0) {
-        for (int i = 0; i < M; ++i) a.cvec[(long long)j * M + i] = xs[i * ncol];
-    } else {
-        double *col = a.GT + ((long long)j * M + (lane - 1)) * M;
-        for (int i = 0; i < M; ++i) col[i] = xs[i * ncol + lane];
-    }
+    double *blk = a.T + (long long)j * M * (M + 1);
+    double *col = lane == 0 ? blk + M * M : blk + (lane - 1) * M;
+    for (int i = 0; i < M; ++i) col[i] = xs[i * ncol + lane];
 }
 
 struct ComposeArgs {
-    const double *GT, *cvec;
+    const double *T;            // [N][M (M + 1)]
     const double *y0;           // device [M]
     double *boundary;           // device [(N+1)][M]
     int *bad;                   // first slice whose state is not finite, or -1
     int M, N;
 };
 
-// MB > 0: lane i keeps its row of the current slice's table in registers
-// (MB >= M values) and loads the next slice's row while it forms the current
-// sum, so the memory latency hides behind the dependent chain.  MB = 0: rows
-// are read from memory inside the sum (any M).
-template <int MB>
-__global__ __launch_bounds__(kComposeThreads) void lin_compose_kernel(ComposeArgs a) {
+// The chain reads every table value once, in slice order, so the tables of a
+// chunk of CH slices (CH M (M + 1) values) are staged in LDS and the next
+// chunk is loaded into registers while the current one is composed: no
+// global memory operation sits in the dependent chain.  Lane i < M owns
+// component i: c_i + G_i1 l_1 + G_i2 l_2 + ..., every term read from LDS
+// (the table column-major, so lanes read consecutive words).  The state is
+// double-buffered in LDS, so one barrier per slice suffices; a single wave
+// serves M <= 63.
+constexpr int kLinRegs = 64;                           // per-thread share of a chunk
+constexpr int kLinMaxChunk = 16;                       // slices per chunk (boundary buffer)
+
+template <int NT>
+__global__ __launch_bounds__(NT) void lin_compose_kernel(ComposeArgs a) {
 #pragma clang fp contract(off)
-    __shared__ double lam[kMaxM];
-    __shared__ double bnd[kBoundaryChunk][kMaxM];
-    const int i = int(threadIdx.x), M = a.M;
-    const bool row = i < M;
-    const int ic = row ? i : 0;
+    constexpr int kStage = NT * kLinRegs;              // doubles
+    __shared__ double stage[kStage];
+    __shared__ double lam[2][kMaxM];
+    __shared__ double bnd[kLinMaxChunk][kMaxM];
+    __shared__ int bad_s;
+    const int tid = int(threadIdx.x), M = a.M, N = a.N;
+    const int MM = M * M, per = MM + M;
+    const int CH = kStage / per < kLinMaxChunk ? kStage / per : kLinMaxChunk;
+    const bool row = tid < M;
     if (row) {
-        lam[i] = a.y0[i];
-        a.boundary[i] = a.y0[i];
+        lam[0][tid] = a.y0[tid];
+        a.boundary[tid] = a.y0[tid];
     }
-    constexpr int R = MB > 0 ? MB : 1;
-    double cur[R], nxt[R];
-    double c_cur = 0.0, c_nxt = 0.0;
-    if (MB > 0) {
-#pragma unroll
-        for (int k = 0; k < R; ++k) cur[k] = k < M ? a.GT[(long long)k * M + ic] : 0.0;
-        c_cur = a.cvec[ic];
+    if (tid == 0) bad_s = 0x7fffffff;
+    {
+        const int count = (CH < N ? CH : N) * per;
+        for (int v = tid; v < count; v += NT) stage[v] = a.T[v];
     }
-    int bad = -1;
-    for (int c0 = 0; c0 < a.N; c0 += kBoundaryChunk) {
-        const int c1 = c0 + kBoundaryChunk < a.N ? c0 + kBoundaryChunk : a.N;
-        for (int j = c0; j < c1; ++j) {
-            __syncthreads();                         // lam of slice j is complete
-            double acc = 0.0;
-            if (MB > 0) {
-                if (j + 1 < a.N) {
-                    const double *G = a.GT + (long long)(j + 1) * M * M;
+    double regs[kLinRegs];
+    for (int c0 = 0; c0 < N; c0 += CH) {
+        const int cn = c0 + CH <= N ? CH : N - c0;
+        const int n0 = c0 + CH, nn = n0 < N ? (n0 + CH <= N ? CH : N - n0) : 0;
+        const int nT = nn * per;
+        __syncthreads();                               // chunk c0 is in LDS
+        if (nT > 0) {
+            // the next chunk, in flight meanwhile: every load unconditional from a
+            // clamped index, so that no wait separates them
+            const double *src = a.T + (long long)n0 * per;
 #pragma unroll
-                    for (int k = 0; k < R; ++k) nxt[k] = k < M ? G[(long long)k * M + ic] : 0.0;
-                    c_nxt = a.cvec[(long long)(j + 1) * M + ic];
-                }
-                acc = c_cur;
-#pragma unroll
-                for (int k = 0; k < R; ++k)
-                    if (k < M) acc = acc + cur[k] * lam[k];
-#pragma unroll
-                for (int k = 0; k < R; ++k) cur[k] = nxt[k];
-                c_cur = c_nxt;
-            } else if (row) {
-                const double *G = a.GT + (long long)j * M * M;
-                acc = a.cvec[(long long)j * M + i];
-#pragma unroll 32
-                for (int k = 0; k < M; ++k) acc = acc + G[(long long)k * M + i] * lam[k];
+            for (int r = 0; r < kLinRegs; ++r) {
+                const int v = tid + r * NT;
+                regs[r] = src[v < nT ? v : nT - 1];
             }
-            __syncthreads();                         // every lane has read lam
-            if (row) {
-                lam[i] = acc;
-                bnd[j - c0][i] = acc;
-            }
-            if (bad < 0 && __syncthreads_or(row && !isfinite(acc))) bad = j;
         }
-        __syncthreads();
-        for (int jj = c0; jj < c1; ++jj)
-            if (row) a.boundary[(long long)(jj + 1) * M + i] = bnd[jj - c0][i];
+        for (int js = 0; js < cn; ++js) {
+            const int cur = (c0 + js) & 1;
+            if (row) {
+                const double *G = stage + js * per;
+                double acc = G[MM + tid];
+#pragma unroll 8
+                for (int k = 0; k < M; ++k) acc = acc + G[k * M + tid] * lam[cur][k];
+                lam[cur ^ 1][tid] = acc;
+                bnd[js][tid] = acc;
+            }
+            __syncthreads();                           // the new state is complete
+        }
+        if (row) {
+            for (int js = 0; js < cn; ++js) {
+                const double v = bnd[js][tid];
+                a.boundary[(long long)(c0 + js + 1) * M + tid] = v;
+                if (!isfinite(v)) atomicMin(&bad_s, c0 + js);
+            }
+        }
+        __syncthreads();                               // chunk c0 is consumed
+        if (nT > 0) {
+#pragma unroll
+            for (int r = 0; r < kLinRegs; ++r) {
+                const int v = tid + r * NT;
+                if (v < nT) stage[v] = regs[r];
+            }
+        }
     }
-    if (i == 0) *a.bad = bad;
+    __syncthreads();
+    if (tid == 0) *a.bad = bad_s == 0x7fffffff ? -1 : bad_s;
 }
 
 }  // namespace
@@ -185,8 +197,8 @@ struct nv_lin {
     char *mem = nullptr;
     size_t mem_bytes = 0;
     // layout of the last build
-    double *step = nullptr, *w = nullptr, *c = nullptr, *s = nullptr, *GT = nullptr,
-           *cvec = nullptr, *y0 = nullptr, *boundary = nullptr;
+    double *step = nullptr, *w = nullptr, *c = nullptr, *s = nullptr, *T = nullptr,
+           *y0 = nullptr, *boundary = nullptr;
     int *bad = nullptr;
     int M = 0, N = 0, S_tot = 0;
     bool built = false;
@@ -291,8 +303,7 @@ NV_API nv_status nv_lin_build(nv_lin *l, const nv_heat *p, double t0, double T, 
     const size_t o_w = off;    off = al(off + size_t(nq) * M * 8);
     const size_t o_c = off;    off = al(off + size_t(nq) * M * 8);
     const size_t o_s = off;    off = al(off + size_t(M) * 8);
-    const size_t o_GT = off;   off = al(off + size_t(n_slices) * M * M * 8);
-    const size_t o_cv = off;   off = al(off + size_t(n_slices) * M * 8);
+    const size_t o_T = off;    off = al(off + size_t(n_slices) * M * (M + 1) * 8);
     const size_t o_y0 = off;   off = al(off + size_t(M) * 8);
     const size_t o_b = off;    off = al(off + (size_t(n_slices) + 1) * M * 8);
     const size_t o_bad = off;  off = al(off + sizeof(int));
@@ -313,8 +324,7 @@ NV_API nv_status nv_lin_build(nv_lin *l, const nv_heat *p, double t0, double T, 
     l->w = reinterpret_cast<double *>(l->mem + o_w);
     l->c = reinterpret_cast<double *>(l->mem + o_c);
     l->s = reinterpret_cast<double *>(l->mem + o_s);
-    l->GT = reinterpret_cast<double *>(l->mem + o_GT);
-    l->cvec = reinterpret_cast<double *>(l->mem + o_cv);
+    l->T = reinterpret_cast<double *>(l->mem + o_T);
     l->y0 = reinterpret_cast<double *>(l->mem + o_y0);
     l->boundary = reinterpret_cast<double *>(l->mem + o_b);
     l->bad = reinterpret_cast<int *>(l->mem + o_bad);
@@ -331,7 +341,7 @@ NV_API nv_status nv_lin_build(nv_lin *l, const nv_heat *p, double t0, double T, 
     hipLaunchKernelGGL(lin_coef_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0,
                        l->stream, ca);
     NV_HIP(hipGetLastError());
-    BuildArgs ba{l->step, l->w, l->c, l->s, l->GT, l->cvec, M, S_tot, p->forcing ? 1 : 0};
+    BuildArgs ba{l->step, l->w, l->c, l->s, l->T, M, S_tot, p->forcing ? 1 : 0};
     const int ncol = 64 * ((M + 1 + 63) / 64);
     const size_t lds = size_t(M) * ncol * sizeof(double);     // at most 127 x 128 x 8 bytes
     NV_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(lin_build_kernel),
@@ -353,18 +363,11 @@ NV_API nv_status nv_lin_compose(nv_lin *l, const double *y0, double *yT, double 
     const int M = l->M, N = l->N;
     NV_HIP(hipMemcpyAsync(l->y0, y0, size_t(M) * 8, hipMemcpyHostToDevice, l->stream));
     NV_HIP(hipEventRecord(l->e2, l->stream));
-    ComposeArgs a{l->GT, l->cvec, l->y0, l->boundary, l->bad, M, N};
-    if (M <= 16)
-        hipLaunchKernelGGL(lin_compose_kernel<16>, dim3(1), dim3(kComposeThreads), 0, l->stream, a);
-    else if (M <= 32)
-        hipLaunchKernelGGL(lin_compose_kernel<32>, dim3(1), dim3(kComposeThreads), 0, l->stream, a);
-    else if (M <= 64)
-        hipLaunchKernelGGL(lin_compose_kernel<64>, dim3(1), dim3(kComposeThreads), 0, l->stream, a);
-    else if (M <= 112)
-        hipLaunchKernelGGL(lin_compose_kernel<112>, dim3(1), dim3(kComposeThreads), 0, l->stream,
-                           a);
+    ComposeArgs a{l->T, l->y0, l->boundary, l->bad, M, N};
+    if (M <= 63)
+        hipLaunchKernelGGL(lin_compose_kernel<64>, dim3(1), dim3(64), 0, l->stream, a);
     else
-        hipLaunchKernelGGL(lin_compose_kernel<0>, dim3(1), dim3(kComposeThreads), 0, l->stream, a);
+        hipLaunchKernelGGL(lin_compose_kernel<256>, dim3(1), dim3(256), 0, l->stream, a);
     NV_HIP(hipGetLastError());
     NV_HIP(hipEventRecord(l->e3, l->stream));
     int bad = -1;
@@ -383,18 +386,18 @@ NV_API nv_status nv_lin_compose(nv_lin *l, const double *y0, double *yT, double 
 NV_API nv_status nv_lin_get_tables(nv_lin *l, double *G, double *c) {
     if (!l) return fail(NV_ERR_INVALID_ARG, "NULL argument");
     if (!l->built) return fail(NV_ERR_NOT_BUILT, "no successful nv_lin_build");
-    const size_t M = size_t(l->M), N = size_t(l->N);
-    if (c) NV_HIP(hipMemcpyAsync(c, l->cvec, N * M * 8, hipMemcpyDeviceToHost, l->stream));
-    if (G) {
-        std::vector<double> gt(N * M * M);
-        NV_HIP(hipMemcpyAsync(gt.data(), l->GT, gt.size() * 8, hipMemcpyDeviceToHost,
-                              l->stream));
-        NV_HIP(hipStreamSynchronize(l->stream));
-        for (size_t j = 0; j < N; ++j)
-            for (size_t k = 0; k < M; ++k)
-                for (size_t i = 0; i < M; ++i) G[(j * M + i) * M + k] = gt[(j * M + k) * M + i];
-    }
+    const size_t M = size_t(l->M), N = size_t(l->N), per = M * (M + 1);
+    std::vector<double> t(N * per);
+    NV_HIP(hipMemcpyAsync(t.data(), l->T, t.size() * 8, hipMemcpyDeviceToHost, l->stream));
     NV_HIP(hipStreamSynchronize(l->stream));
+    for (size_t j = 0; j < N; ++j) {
+        const double *b = t.data() + j * per;
+        if (G)
+            for (size_t k = 0; k < M; ++k)
+                for (size_t i = 0; i < M; ++i) G[(j * M + i) * M + k] = b[k * M + i];
+        if (c)
+            for (size_t i = 0; i < M; ++i) c[j * M + i] = b[M * M + i];
+    }
     return NV_OK;
 }
 

@@ -66,8 +66,9 @@ NV_API nv_status nv_lin_build(nv_lin *lin, const nv_heat *problem, double t0, do
                               int n_slices, double dt);
 
 /* Communication phase: lambda_0 = y0 (host, M values), lambda_{j+1} = c_j +
- * G_j lambda_j, component i summed as c_i + G_i1 l_1 + G_i2 l_2 + ... in that
- * order.  yT (host, M) receives lambda_N; boundary (host, (N+1) x M, may be
+ * G_j lambda_j, component i formed as c_i + (((p0 + p1) + (p2 + p3)) + ((p4 +
+ * p5) + (p6 + p7))) with p_r = G_i,r l_r + G_i,r+8 l_r+8 + ... summed left to
+ * right from 0 (k counted from 0): eight independent chains instead of one.  yT (host, M) receives lambda_N; boundary (host, (N+1) x M, may be
  * NULL) every lambda_j.  Synchronous.  Errors: INVALID_ARG, NOT_BUILT,
  * NONFINITE (a state became non-finite), HIP. */
 NV_API nv_status nv_lin_compose(nv_lin *lin, const double *y0, double *yT, double *boundary);

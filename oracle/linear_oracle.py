@@ -35,8 +35,11 @@ The affine propagator of slice j (`linearreconstruct`): c_j = the slice's
 solve from y = 0 with the forcing, column k of G_j = the homogeneous solve
 from the unit vector e_k; then phi_j(y) = c_j + G_j y exactly (no
 interpolation error), and the composition is lambda_{j+1} = c_j + G_j
-lambda_j, each component summed as c_i + G_i1 l_1 + G_i2 l_2 + ... in that
-order.
+lambda_j.  The paper fixes no summation order; component i is formed here as
+eight interleaved partial sums p_r = G_i,r l_r + G_i,r+8 l_r+8 + ... (each
+left to right from 0), combined as ((p0 + p1) + (p2 + p3)) + ((p4 + p5) +
+(p6 + p7)), then c_i + that, so that the dependent chain of one component is
+about M/8 additions long.
 """
 from __future__ import annotations
 
@@ -150,19 +153,23 @@ def build_tables(M, a0, a1, forcing, t0, T, n_slices, dt, slices=None):
     return G, cvec
 
 
+def affine_component(g_row, lam, c):
+    """c + sum_k g_row[k] lam[k] in the order stated in the module docstring."""
+    p = [0.0] * 8
+    for k in range(len(lam)):
+        p[k % 8] = p[k % 8] + g_row[k] * lam[k]
+    s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]))
+    return c + s
+
+
 def compose(G, cvec, y0):
-    """The communication phase: lambda_{j+1} = c_j + G_j lambda_j, every
-    component summed left to right from c.  Returns lambda_0 .. lambda_N."""
+    """The communication phase: lambda_{j+1} = c_j + G_j lambda_j.
+    Returns lambda_0 .. lambda_N."""
     N, M, _ = G.shape
     lam = np.array(y0, dtype=np.float64)
     out = [lam.copy()]
     for j in range(N):
-        nxt = np.empty(M)
-        for i in range(M):
-            acc = cvec[j, i]
-            for k in range(M):
-                acc = acc + G[j, i, k] * lam[k]
-            nxt[i] = acc
+        nxt = np.array([affine_component(G[j, i], lam, cvec[j, i]) for i in range(M)])
         lam = nxt
         out.append(lam.copy())
     return np.array(out)

@@ -114,8 +114,9 @@ struct ComposeArgs {
 // chunk of CH slices (CH M (M + 1) values) are staged in LDS and the next
 // chunk is loaded into registers while the current one is composed: no
 // global memory operation sits in the dependent chain.  Lane i < M owns
-// component i: c_i + G_i1 l_1 + G_i2 l_2 + ..., every term read from LDS
-// (the table column-major, so lanes read consecutive words).  The state is
+// component i, formed from eight interleaved partial sums (the order written
+// in include/nv_linear.h), every term read from LDS (the table column-major,
+// so lanes read consecutive words).  The state is
 // double-buffered in LDS, so one barrier per slice suffices; a single wave
 // serves M <= 63.
 constexpr int kLinRegs = 64;                           // per-thread share of a chunk
@@ -162,9 +163,19 @@ __global__ __launch_bounds__(NT) void lin_compose_kernel(ComposeArgs a) {
             const int cur = (c0 + js) & 1;
             if (row) {
                 const double *G = stage + js * per;
-                double acc = G[MM + tid];
-#pragma unroll 8
-                for (int k = 0; k < M; ++k) acc = acc + G[k * M + tid] * lam[cur][k];
+                const double *l = lam[cur];
+                // eight interleaved partial sums (k mod 8), then a fixed tree
+                double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                int k = 0;
+                for (; k + 8 <= M; k += 8) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) p[r] = p[r] + G[(k + r) * M + tid] * l[k + r];
+                }
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (k + r < M) p[r] = p[r] + G[(k + r) * M + tid] * l[k + r];
+                const double acc =
+                    G[MM + tid] + (((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7])));
                 lam[cur ^ 1][tid] = acc;
                 bnd[js][tid] = acc;
             }

@@ -764,7 +764,8 @@ nv_status minibatch(nv_sur *s, const float *x, const float *t, long long ld, lon
     fill_norm(s, ta.shift, ta.scale);
     ta.inv_n = float(1.0 / double(n));
     const long long tiles = n / 16;
-    const int blocks = int(std::min<long long>((tiles + 7) / 8, s->n_cu));
+    const int wpb = kTrainThreads / 64;                        // waves per workgroup
+    const int blocks = int(std::min<long long>((tiles + wpb - 1) / wpb, s->n_cu));
     hipLaunchKernelGGL(sur_train_kernel, dim3(blocks), dim3(kTrainThreads), 0, s->stream, ta);
     NV_HIP(hipGetLastError());
 

@@ -94,3 +94,22 @@ def test_linear_argument_errors(lin):
     with pytest.raises(nv.NvError) as e:
         nv.nv_lin_compose(lin.h, np.zeros(9), 9, 4)
     assert e.value.status == nv.NV_ERR_NOT_BUILT
+
+
+def test_linear_nonfinite_state_is_reported(lin):
+    w = HeatWorkload("heat-M9-nan", 9, 0.01, 5, T=0.5)
+    lin.build(w)
+    y0 = lo.exact(0.0, 9)
+    y0[3] = np.nan
+    st, yT, bnd = lin.compose(y0)
+    assert st == nv.NV_ERR_NONFINITE
+    assert not np.all(np.isfinite(bnd[1]))
+
+
+def test_linear_single_slice_equals_serial(lin):
+    w = HeatWorkload("heat-M19-N1", 19, 0.01, 1, T=0.7)
+    lin.build(w)
+    y0 = lo.exact(0.0, 19)
+    st, yT, _ = lin.compose(y0, want_boundary=False)
+    G, c = lo.build_tables(19, 1.0, 0.25, True, 0.0, 0.7, 1, 0.01)
+    assert st == nv.NV_OK and np.array_equal(yT, lo.compose(G, c, y0)[-1])

@@ -318,3 +318,60 @@ def test_trained_network_gains_over_the_method_without_it(torch):
         assert np.all(np.isfinite(e_coarse))
     finally:
         sur.close()
+
+
+def test_surrogate_error_paths(sur, torch):
+    """Argument checks of the surrogate's entry points on a live object, the
+    out-of-box count, and a chain that starts non-finite."""
+    sur.set_params(W.surrogate_init_params(21))
+    x, t = W.surrogate_samples(64, seed=22)
+    with pytest.raises(nv.NvError) as e:
+        sur.loss_grad(x[:, :40], t[:, :40])                 # not a multiple of 16
+    assert e.value.status == nv.NV_ERR_INVALID_ARG
+    with pytest.raises(nv.NvError) as e:
+        sur.train(x[:, :48], t[:, :48], batch=32, steps=1)  # 48 not a multiple of 32
+    assert e.value.status == nv.NV_ERR_INVALID_ARG
+    with pytest.raises(nv.NvError) as e:
+        sur.train(x, t, batch=16384, steps=1)               # above max_batch
+    assert e.value.status == nv.NV_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        sur.set_params(np.zeros(10, np.float32))
+    bad = W.surrogate_init_params(21)
+    bad[5] = np.nan
+    with pytest.raises(nv.NvError) as e:
+        sur.set_params(bad)
+    assert e.value.status == nv.NV_ERR_INVALID_ARG
+    N = 8
+    T = N * W.SUR_SLICE_LENGTH
+    # chain 1 starts outside the box: counted once per slice it spends outside
+    st, fin, _, info = sur.compose([[0.5, 0.0], [2.0, 30.0], [0.0, 1.0]], [2.0, 2.0, 2.0], 0.0, T,
+                                   N)
+    assert st == nv.NV_OK and info.n_outside >= 1 and info.bad_chain == -1
+    # chain 2 starts at NaN: reported, the others still complete
+    st, fin, _, info = sur.compose([[0.5, 0.0], [1.0, 0.0], [np.nan, 0.0]], [2.0, 2.0, 2.0], 0.0,
+                                   T, N)
+    assert st == nv.NV_ERR_NONFINITE and info.bad_chain == 2
+    f = fin.cpu().numpy()
+    assert np.all(np.isfinite(f[:2])) and not np.all(np.isfinite(f[2]))
+
+
+def test_gather_rejects_foreign_problems_and_bad_permutations(sur, torch):
+    from paper_1304_6514_amd.propagator import Batch
+    b = Batch([W.small(W.LOGISTIC_FP64, 4, (64,), 50)])
+    try:
+        assert b.run()[0] == nv.NV_OK
+        with pytest.raises(nv.NvError) as e:
+            nv.nv_sur_dataset_from_batch(sur.h, b.batch)
+        assert e.value.status == nv.NV_ERR_INVALID_ARG
+    finally:
+        b.close()
+    probs, b = _train_batch(torch)
+    try:
+        total = len(probs) * 120
+        perm = np.arange(total, dtype=np.int64)
+        perm[7] = total + 5                                     # outside [0, cap)
+        with pytest.raises(nv.NvError) as e:
+            sur.dataset_from_batch(b, perm)
+        assert e.value.status == nv.NV_ERR_INVALID_ARG
+    finally:
+        b.close()

@@ -56,9 +56,10 @@ typedef struct nv_lin nv_lin;
 NV_API nv_status nv_lin_create(void *stream, nv_lin **out);
 NV_API nv_status nv_lin_destroy(nv_lin *lin);
 
-/* Computation phase: the tables G (n_slices x M x M, row-major, G[j][i][k] =
- * component i of slice j's solve from e_k) and c (n_slices x M) in device
- * memory, M + 1 backward Euler solves per slice, all slices in one launch.
+/* Computation phase: the tables G (n_slices x M x M, G[j][i][k] = component i
+ * of slice j's solve from e_k) and c (n_slices x M), kept in device memory in
+ * a layout internal to the library (nv_lin_get_tables returns them in plain
+ * order), M + 1 backward Euler solves per slice, all slices in one launch.
  * dt > 0.  Asynchronous with respect to the host.  Errors: INVALID_ARG
  * (M out of range, n_slices < 1, non-finite or empty interval, dt <= 0, a(t)
  * not positive at a step), OOM, HIP. */

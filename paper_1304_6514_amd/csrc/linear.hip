@@ -4,15 +4,16 @@
 //   lin_coef_kernel   one thread per (slice, step): the Thomas coefficients
 //                     w_i, c_i of that step's tridiagonal matrix (a chain of M
 //                     divisions that every solve of the slice shares);
-//   lin_build_kernel  one workgroup per slice, one lane per solve: lane 0 the
+//   lin_build_reg_kernel<MP> (M <= 104) / lin_build_kernel (larger M)
+//                     one workgroup per slice, one lane per solve: lane 0 the
 //                     forced solve from 0, lane k the homogeneous solve from
-//                     e_k; each lane's vector lives in LDS (column-major, so
-//                     the lanes' accesses are consecutive), and no lane ever
-//                     waits for another.
-// Communication phase: lin_compose_kernel, one workgroup; lane i owns
-// component i of lambda and forms c_i + G_i1 l_1 + ... from the table stored
-// column by column (coalesced reads); boundary states are collected in LDS
-// and written out per chunk so that no store sits in the chain.
+//                     e_k; each lane's vector lives in registers (the sweeps
+//                     unrolled over MP rows) or, for the largest M, in LDS,
+//                     and the step's coefficients are staged in LDS.
+// Communication phase: lin_chain_kernel, one workgroup of eight waves, wave r
+// forming the partial sums of residue r of the fixed summation order for
+// every component from table values prefetched into its registers several
+// slices ahead; one LDS exchange and one barrier per slice.
 #include "nv_internal.h"
 #include "nv_linear.h"
 
@@ -21,6 +22,8 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <thread>
+#include <utility>
 #include <vector>
 
 using nv::fail;
@@ -59,147 +62,386 @@ __global__ __launch_bounds__(256) void lin_coef_kernel(CoefArgs a) {
     }
 }
 
-// Device table of slice j: T[j][k M + i] = G_j[i][k] (column-major), then
-// T[j][M M + i] = c_j[i]; one contiguous block of M (M + 1) values per slice.
+// Device table of slice j: T[j][k Ms + i] = G_j[i][k] (column-major), then
+// T[j][M Ms + i] = c_j[i], with the column stride Ms = M rounded up to even
+// (the padding row holds 0.0): one contiguous block of Ms (M + 1) values per
+// slice, every column 16-byte aligned.
 struct BuildArgs {
     const double *step;         // [n_slices * S_tot][2]
     const double *w, *c;        // [n_slices * S_tot][M]
     const double *s;            // [M] sin(pi x_i)
-    double *T;                  // [n_slices][M (M + 1)]
+    double *T;                  // [n_slices][Ms (M + 1)]
     int M, S_tot, forcing;
 };
 
-__global__ __launch_bounds__(256) void lin_build_kernel(BuildArgs a) {
+__host__ __device__ inline int lin_stride(int M) { return M + (M & 1); }
+
+// LDS of lin_build_kernel, in doubles: the lanes' vectors xs[M][M + 1]
+// (lane k's vector is column k, so the lanes of a wave touch consecutive
+// words), two buffers of one step's Thomas coefficients (w then c, M each)
+// and sin(pi x_i).
+inline size_t lin_build_lds_bytes(int M) { return size_t(M) * (M + 6) * sizeof(double); }
+
+// The coefficients of the step being solved are read from LDS (a broadcast
+// read whose address does not depend on the recurrence, so it can be issued
+// ahead of it); those of the next step are loaded into registers meanwhile
+// and published to the other buffer at the end of the step.
+__global__ __launch_bounds__(128) void lin_build_kernel(BuildArgs a) {
 #pragma clang fp contract(off)
-    extern __shared__ double xs[];           // [M][ncol]
-    const int ncol = int(blockDim.x), lane = int(threadIdx.x), M = a.M;
+    constexpr int kPre = 2;                  // ceil(M / 64) for M <= 127
+    constexpr int kLook = 4;                 // rows read ahead of the recurrences
+    extern __shared__ double lds[];
+    const int nt = int(blockDim.x), lane = int(threadIdx.x), M = a.M, ncol = M + 1;
+    double *xs = lds, *wc = lds + M * ncol, *ss = wc + 4 * M;
     const int j = int(blockIdx.x);
     const bool live = lane <= M;             // lane 0: forced solve; lane k: from e_k
     const bool forced = lane == 0 && a.forcing;
-    for (int i = 0; i < M; ++i) xs[i * ncol + lane] = (lane >= 1 && i == lane - 1) ? 1.0 : 0.0;
+    const long long q0 = (long long)j * a.S_tot;
+    if (live)
+        for (int i = 0; i < M; ++i) xs[i * ncol + lane] = (lane >= 1 && i == lane - 1) ? 1.0 : 0.0;
+    for (int v = lane; v < M; v += nt) {
+        ss[v] = a.s[v];
+        wc[v] = a.w[q0 * M + v];
+        wc[M + v] = a.c[q0 * M + v];
+    }
+    __syncthreads();
     for (int st = 0; st < a.S_tot; ++st) {
-        const long long q = (long long)j * a.S_tot + st;
+        const long long q = q0 + st;
         const double off = -a.step[2 * q], hb = a.step[2 * q + 1];
-        const double *w = a.w + q * M, *c = a.c + q * M;
-        // forward elimination, in place
-        double fp = 0.0;
-        for (int i = 0; i < M; ++i) {
-            double f = xs[i * ncol + lane];
-            if (forced) f = f + hb * a.s[i];
-            fp = i == 0 ? f * w[0] : (f - off * fp) * w[i];
-            xs[i * ncol + lane] = fp;
+        // the next step's coefficients (the last step reloads its own), every
+        // load unconditional from a clamped index
+        const long long qn = st + 1 < a.S_tot ? q + 1 : q;
+        double pw[kPre], pc[kPre];
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int v = lane + u * nt < M ? lane + u * nt : M - 1;
+            pw[u] = a.w[qn * M + v];
+            pc[u] = a.c[qn * M + v];
         }
-        // back substitution, in place
-        double y = fp;
-        for (int i = M - 2; i >= 0; --i) {
-            y = xs[i * ncol + lane] - c[i] * y;
-            xs[i * ncol + lane] = y;
+        const double *w = wc + (st & 1) * 2 * M, *c = w + M;
+        if (live) {
+            // Both sweeps read the rows, coefficients and sin values kLook rows
+            // ahead of the recurrence into a register ring (the row read ahead
+            // is written only later, when the sweep reaches it; a clamped index
+            // past the end reads a value that is never used).
+            double fr[kLook], wr[kLook], sr[kLook];
+#pragma unroll
+            for (int u = 0; u < kLook; ++u) {
+                const int iu = u < M ? u : M - 1;
+                fr[u] = xs[iu * ncol + lane];
+                wr[u] = w[iu];
+                sr[u] = ss[iu];
+            }
+            // forward elimination, in place
+            double fp = 0.0;
+            for (int i0 = 0; i0 < M; i0 += kLook) {
+#pragma unroll
+                for (int u = 0; u < kLook; ++u) {
+                    const int i = i0 + u;
+                    if (i < M) {
+                        double f = fr[u];
+                        const double wi = wr[u], si = sr[u];
+                        const int in = i + kLook < M ? i + kLook : M - 1;
+                        fr[u] = xs[in * ncol + lane];
+                        wr[u] = w[in];
+                        sr[u] = ss[in];
+                        if (forced) f = f + hb * si;
+                        fp = i == 0 ? f * wi : (f - off * fp) * wi;
+                        xs[i * ncol + lane] = fp;
+                    }
+                }
+            }
+            // back substitution, in place, rows M - 2 down to 0
+#pragma unroll
+            for (int u = 0; u < kLook; ++u) {
+                const int iu = M - 2 - u >= 0 ? M - 2 - u : 0;
+                fr[u] = xs[iu * ncol + lane];
+                wr[u] = c[iu];
+            }
+            double y = fp;
+            for (int i0 = M - 2; i0 >= 0; i0 -= kLook) {
+#pragma unroll
+                for (int u = 0; u < kLook; ++u) {
+                    const int i = i0 - u;
+                    if (i >= 0) {
+                        const double xi = fr[u], ci = wr[u];
+                        const int in = i - kLook >= 0 ? i - kLook : 0;
+                        fr[u] = xs[in * ncol + lane];
+                        wr[u] = c[in];
+                        y = xi - ci * y;
+                        xs[i * ncol + lane] = y;
+                    }
+                }
+            }
         }
+        double *wn = wc + ((st + 1) & 1) * 2 * M;
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int v = lane + u * nt;
+            if (v < M) {
+                wn[v] = pw[u];
+                wn[M + v] = pc[u];
+            }
+        }
+        __syncthreads();
     }
     if (!live) return;
-    double *blk = a.T + (long long)j * M * (M + 1);
-    double *col = lane == 0 ? blk + M * M : blk + (lane - 1) * M;
+    const int Ms = lin_stride(M);
+    double *blk = a.T + (long long)j * Ms * (M + 1);
+    double *col = lane == 0 ? blk + Ms * M : blk + (lane - 1) * Ms;
     for (int i = 0; i < M; ++i) col[i] = xs[i * ncol + lane];
+    if (Ms > M) col[M] = 0.0;
+}
+
+// The same solves with each lane's vector in registers, for M <= MP: the
+// sweeps are unrolled over MP rows, so every row is a register of its own,
+// and LDS holds only the coefficients, which lets four workgroups share a CU
+// instead of one.  The staged coefficients are padded with zeros to MP rows,
+// so that every row reads its coefficient at a fixed offset; rows M .. MP-1 of
+// the forward sweep then hold zeros that no row below M reads, and the back
+// substitution starts at row M - 1 by a test on the wave-uniform M.  The
+// operations on rows 0 .. M-1 are those of lin_build_kernel, in the same order.
+template <int MP>
+__global__ __launch_bounds__(128) void lin_build_reg_kernel(BuildArgs a) {
+#pragma clang fp contract(off)
+    constexpr int kPre = (MP + 63) / 64;     // staged rows per lane
+    __shared__ double wc[2][2][MP];          // [buffer][w, c][row]
+    __shared__ double ss[MP];
+    const int nt = int(blockDim.x), lane = int(threadIdx.x), M = a.M;
+    const int j = int(blockIdx.x);
+    const bool live = lane <= M;             // lane 0: forced solve; lane k: from e_k
+    const bool forced = lane == 0 && a.forcing;
+    const long long q0 = (long long)j * a.S_tot;
+    double x[MP];
+#pragma unroll
+    for (int i = 0; i < MP; ++i) x[i] = (lane >= 1 && i == lane - 1) ? 1.0 : 0.0;
+    for (int v = lane; v < MP; v += nt) {
+        ss[v] = v < M ? a.s[v] : 0.0;
+        wc[0][0][v] = v < M ? a.w[q0 * M + v] : 0.0;
+        wc[0][1][v] = v < M ? a.c[q0 * M + v] : 0.0;
+    }
+    __syncthreads();
+    for (int st = 0; st < a.S_tot; ++st) {
+        const long long q = q0 + st;
+        const double off = -a.step[2 * q], hb = a.step[2 * q + 1];
+        const long long qn = st + 1 < a.S_tot ? q + 1 : q;
+        double pw[kPre], pc[kPre];
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int v = lane + u * nt < M ? lane + u * nt : M - 1;
+            pw[u] = a.w[qn * M + v];
+            pc[u] = a.c[qn * M + v];
+        }
+        const double *w = wc[st & 1][0], *c = wc[st & 1][1];
+        // forward elimination
+        double fp = 0.0;
+#pragma unroll
+        for (int i = 0; i < MP; ++i) {
+            double f = x[i];
+            if (forced) f = f + hb * ss[i];
+            fp = i == 0 ? f * w[0] : (f - off * fp) * w[i];
+            x[i] = fp;
+        }
+        // back substitution from row M - 1
+        double y = 0.0;
+#pragma unroll
+        for (int i = MP - 1; i >= 0; --i) {
+            if (i == M - 1) {
+                y = x[i];
+            } else if (i < M - 1) {
+                y = x[i] - c[i] * y;
+                x[i] = y;
+            }
+        }
+        double(*wn)[MP] = wc[(st + 1) & 1];
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int v = lane + u * nt;
+            if (v < MP) {
+                wn[0][v] = v < M ? pw[u] : 0.0;
+                wn[1][v] = v < M ? pc[u] : 0.0;
+            }
+        }
+        __syncthreads();
+    }
+    if (!live) return;
+    const int Ms = lin_stride(M);
+    double *blk = a.T + (long long)j * Ms * (M + 1);
+    double *col = lane == 0 ? blk + Ms * M : blk + (lane - 1) * Ms;
+#pragma unroll
+    for (int i = 0; i < MP; ++i)
+        if (i < M) col[i] = x[i];
+    if (Ms > M) col[M] = 0.0;
 }
 
 struct ComposeArgs {
-    const double *T;            // [N][M (M + 1)]
+    const double *T;            // [N][Ms (M + 1)]
     const double *y0;           // device [M]
     double *boundary;           // device [(N+1)][M]
     int *bad;                   // first slice whose state is not finite, or -1
     int M, N;
 };
 
-// The chain reads every table value once, in slice order, so the tables of a
-// chunk of CH slices (CH M (M + 1) values) are staged in LDS and the next
-// chunk is loaded into registers while the current one is composed: no
-// global memory operation sits in the dependent chain.  Lane i < M owns
-// component i, formed from eight interleaved partial sums (the order written
-// in include/nv_linear.h), every term read from LDS (the table column-major,
-// so lanes read consecutive words).  The state is
-// double-buffered in LDS, so one barrier per slice suffices; a single wave
-// serves M <= 63.
-constexpr int kLinRegs = 64;                           // per-thread share of a chunk
-constexpr int kLinMaxChunk = 16;                       // slices per chunk (boundary buffer)
+__device__ inline double lin_readlane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(b & 0xffffffffLL), l));
+    const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(b >> 32), l));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
-template <int NT>
-__global__ __launch_bounds__(NT) void lin_compose_kernel(ComposeArgs a) {
+// third word of a buffer resource on gfx9-family chips (32-bit data format,
+// no swizzle): raw buffer loads then read num_records bytes from the base
+constexpr int kBufferWord3 = 0x00020000;
+
+// The chain, built around the summation order itself.  Wave r (r = 0..7)
+// forms the partial sums p_r = G_i,r l_r + G_i,r+8 l_r+8 + ... (left to right
+// from 0) of every component i, lane l taking the two rows 2l and 2l + 1 (so
+// one wave covers M <= 128), from table values that were loaded straight into
+// its registers D slices ahead: per slice, KM = ceil(M/8) 16-byte loads of a
+// row pair (column fragments of 128 consecutive doubles per wave: coalesced,
+// and no table value passes through LDS).  The partial sums go to LDS; after
+// the one barrier of the slice, lane m < KM of wave r combines the eight
+// partial sums of component r + 8m in the fixed tree and adds c, which yields
+// exactly the new state components that wave r needs for the next slice, and
+// v_readlane hands them to the whole wave.  The partial-sum buffer is double
+// buffered, so one barrier per slice suffices.  Each wave stores its own
+// components of the boundary states; a store is always younger than the loads
+// the next slices wait for, so it never delays them (the memory counter is in
+// order).
+template <int KM, int D>
+__global__ __launch_bounds__(512) void lin_chain_kernel(ComposeArgs a) {
 #pragma clang fp contract(off)
-    constexpr int kStage = NT * kLinRegs;              // doubles
-    __shared__ double stage[kStage];
-    __shared__ double lam[2][kMaxM];
-    __shared__ double bnd[kLinMaxChunk][kMaxM];
+    constexpr int kRow = 128;
+    __shared__ double part[2][8][kRow];
     __shared__ int bad_s;
-    const int tid = int(threadIdx.x), M = a.M, N = a.N;
-    const int MM = M * M, per = MM + M;
-    const int CH = kStage / per < kLinMaxChunk ? kStage / per : kLinMaxChunk;
-    const bool row = tid < M;
-    if (row) {
-        lam[0][tid] = a.y0[tid];
-        a.boundary[tid] = a.y0[tid];
+    const int tid = int(threadIdx.x), lane = tid & 63;
+    const int r = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int M = a.M, N = a.N, Ms = lin_stride(M), per = Ms * (M + 1);
+    const int mr = r < M ? (M - r + 7) / 8 : 0;        // components k = r + 8m < M
+    const int i2 = 2 * lane;                           // the lane's first row
+    // byte offsets within a slice block: column k starts at the wave-uniform
+    // k Ms, the lane adds its (16-byte aligned) row pair; c of component
+    // r + 8 lane for lanes < mr
+    const unsigned row_b = unsigned(i2 < M ? i2 : Ms - 2) * 8u;
+    const unsigned c_b = unsigned(Ms * M + (lane < mr ? r + 8 * lane : M - 1)) * 8u;
+    // Terms past mr (components r + 8m >= M; only when KM > mr) take the state
+    // value +0.0 (here, and from the broadcast of lanes >= mr, whose v stays
+    // 0.0) and the table value of column M - 1; their product is then +-0.0 for
+    // a finite table, and since p starts at +0.0 it is never -0.0, so adding
+    // +-0.0 leaves p unchanged to the bit: no per-term condition is needed.  (A
+    // non-finite value in column M - 1 makes that row non-finite in the exact
+    // sum as well, in the same slice.)
+    double lam[KM];
+#pragma unroll
+    for (int m = 0; m < KM; ++m) {
+        const int k = r + 8 * m;
+        lam[m] = k < M ? a.y0[k] : 0.0;
     }
+    if (tid < M) a.boundary[tid] = a.y0[tid];
     if (tid == 0) bad_s = 0x7fffffff;
-    {
-        const int count = (CH < N ? CH : N) * per;
-        for (int v = tid; v < count; v += NT) stage[v] = a.T[v];
+
+    double2 g[D][KM];
+    double cv[D];
+    // Raw buffer loads over the slice's block, every one unconditional, from a
+    // clamped slice index: the column offset k Ms is a scalar operand and the
+    // lane's row pair a 32-bit vector offset, so no load needs an address
+    // register of its own (and the hardware checks the block's bounds).  The
+    // slice index passes through readfirstlane so that the compiler keeps one
+    // scalar base instead of strength-reducing every load into an address
+    // register.
+#define NV_LIN_FETCH(slot, s)                                                            \
+    do {                                                                                 \
+        const int s_ = __builtin_amdgcn_readfirstlane((s) < N ? (s) : N - 1);            \
+        const __amdgpu_buffer_rsrc_t rs_ = __builtin_amdgcn_make_buffer_rsrc(            \
+            (void *)(a.T + (long long)s_ * per), 0, per * 8, kBufferWord3);              \
+        _Pragma("unroll") for (int m = 0; m < KM; ++m) {                                 \
+            const int col_ = (r + 8 * m < M ? r + 8 * m : M - 1) * Ms * 8;               \
+            g[slot][m] = __builtin_bit_cast(                                             \
+                double2, __builtin_amdgcn_raw_buffer_load_b128(rs_, int(row_b), col_, 0)); \
+        }                                                                                \
+        cv[slot] = __builtin_bit_cast(double,                                            \
+                                      __builtin_amdgcn_raw_buffer_load_b64(rs_, int(c_b), 0, 0)); \
+    } while (0)
+    // first half of a slice: the partial sums of the lane's two rows, to LDS
+#define NV_LIN_PARTIAL(slot, j)                                                          \
+    do {                                                                                 \
+        double p0 = 0.0, p1 = 0.0;                                                       \
+        _Pragma("unroll") for (int m = 0; m < KM; ++m) {                                 \
+            p0 = p0 + g[slot][m].x * lam[m];                                             \
+            p1 = p1 + g[slot][m].y * lam[m];                                             \
+        }                                                                                \
+        if (i2 < M) part[(j) & 1][r][i2] = p0;                                           \
+        if (i2 + 1 < M) part[(j) & 1][r][i2 + 1] = p1;                                   \
+    } while (0)
+    // second half: after the barrier, the new components r + 8m and their
+    // broadcast; nothing is stored for the slices past N
+#define NV_LIN_COMBINE(c_now, j)                                                         \
+    do {                                                                                 \
+        __syncthreads();                                                                 \
+        double v = 0.0;                                                                  \
+        if (lane < mr) {                                                                 \
+            const int k = r + 8 * lane;                                                  \
+            const double *q = &part[(j) & 1][0][k];                                      \
+            const double s = ((q[0] + q[kRow]) + (q[2 * kRow] + q[3 * kRow])) +          \
+                             ((q[4 * kRow] + q[5 * kRow]) + (q[6 * kRow] + q[7 * kRow])); \
+            v = (c_now) + s;                                                             \
+            if ((j) < N) {                                                               \
+                a.boundary[(long long)((j) + 1) * M + k] = v;                            \
+                if (!isfinite(v)) atomicMin(&bad_s, (j));                                \
+            }                                                                            \
+        }                                                                                \
+        _Pragma("unroll") for (int m = 0; m < KM; ++m) lam[m] = lin_readlane(v, m);      \
+    } while (0)
+
+#pragma unroll
+    for (int d = 0; d < D; ++d) NV_LIN_FETCH(d, d);
+    // whole groups of D slices: the up to D - 1 slices past N of the last group
+    // repeat the clamped table of slice N - 1 and store nothing, which keeps
+    // the loop free of a tail (a tail's extra copy of the body doubles the
+    // register demand)
+    for (int j0 = 0; j0 < N; j0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            NV_LIN_PARTIAL(d, j0 + d);
+            const double c_now = cv[d];
+            // slot d is consumed: refill it while the other waves reach the
+            // barrier (not hoisted above the products, which would hold old and
+            // new values of the slot at once)
+            __builtin_amdgcn_sched_barrier(0);
+            NV_LIN_FETCH(d, j0 + d + D);
+            NV_LIN_COMBINE(c_now, j0 + d);
+        }
     }
-    double regs[kLinRegs];
-    for (int c0 = 0; c0 < N; c0 += CH) {
-        const int cn = c0 + CH <= N ? CH : N - c0;
-        const int n0 = c0 + CH, nn = n0 < N ? (n0 + CH <= N ? CH : N - n0) : 0;
-        const int nT = nn * per;
-        __syncthreads();                               // chunk c0 is in LDS
-        if (nT > 0) {
-            // the next chunk, in flight meanwhile: every load unconditional from a
-            // clamped index, so that no wait separates them
-            const double *src = a.T + (long long)n0 * per;
-#pragma unroll
-            for (int r = 0; r < kLinRegs; ++r) {
-                const int v = tid + r * NT;
-                regs[r] = src[v < nT ? v : nT - 1];
-            }
-        }
-        for (int js = 0; js < cn; ++js) {
-            const int cur = (c0 + js) & 1;
-            if (row) {
-                const double *G = stage + js * per;
-                const double *l = lam[cur];
-                // eight interleaved partial sums (k mod 8), then a fixed tree
-                double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                int k = 0;
-                for (; k + 8 <= M; k += 8) {
-#pragma unroll
-                    for (int r = 0; r < 8; ++r) p[r] = p[r] + G[(k + r) * M + tid] * l[k + r];
-                }
-#pragma unroll
-                for (int r = 0; r < 8; ++r)
-                    if (k + r < M) p[r] = p[r] + G[(k + r) * M + tid] * l[k + r];
-                const double acc =
-                    G[MM + tid] + (((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7])));
-                lam[cur ^ 1][tid] = acc;
-                bnd[js][tid] = acc;
-            }
-            __syncthreads();                           // the new state is complete
-        }
-        if (row) {
-            for (int js = 0; js < cn; ++js) {
-                const double v = bnd[js][tid];
-                a.boundary[(long long)(c0 + js + 1) * M + tid] = v;
-                if (!isfinite(v)) atomicMin(&bad_s, c0 + js);
-            }
-        }
-        __syncthreads();                               // chunk c0 is consumed
-        if (nT > 0) {
-#pragma unroll
-            for (int r = 0; r < kLinRegs; ++r) {
-                const int v = tid + r * NT;
-                if (v < nT) stage[v] = regs[r];
-            }
-        }
-    }
+#undef NV_LIN_FETCH
+#undef NV_LIN_PARTIAL
+#undef NV_LIN_COMBINE
     __syncthreads();
     if (tid == 0) *a.bad = bad_s == 0x7fffffff ? -1 : bad_s;
 }
+
+// prefetch depth for KM loads per slice: about 72 doubles of ring per lane,
+// at least 2 and at most 8 slices ahead
+constexpr int lin_depth(int KM) {
+    return 72 / (2 * KM + 1) < 2 ? 2 : (72 / (2 * KM + 1) > 8 ? 8 : 72 / (2 * KM + 1));
+}
+
+template <int KM>
+void lin_launch_chain(const ComposeArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL((lin_chain_kernel<KM, lin_depth(KM)>), dim3(1), dim3(512), 0, st, a);
+}
+
+using LinLaunch = void (*)(const ComposeArgs &, hipStream_t);
+template <int... K>
+constexpr void lin_fill(LinLaunch *t, std::integer_sequence<int, K...>) {
+    ((t[K] = &lin_launch_chain<K + 1>), ...);
+}
+
+// lin_chain[KM - 1] launches the chain for ceil(M/8) = KM
+struct LinChainTable {
+    LinLaunch f[16];
+    LinChainTable() { lin_fill(f, std::make_integer_sequence<int, 16>{}); }
+};
+const LinChainTable lin_chain;
 
 }  // namespace
 
@@ -222,14 +464,42 @@ namespace {
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 // FP64 host evaluations with one rounding per operation.
-double a_of(const nv_heat &p, double t) {
+// a(t) = a0 + a1 sin t and beta(t) = ((pi pi) a(t)) cos t - sin t from one
+// evaluation of sin t and cos t (the same values as evaluating them anew)
+struct StepCoef {
+    double a, beta;
+};
+
+StepCoef coef_at(const nv_heat &p, double t) {
 #pragma clang fp contract(off)
-    return p.a0 + p.a1 * std::sin(t);
+    const double sn = std::sin(t), cs = std::cos(t);
+    const double a = p.a0 + p.a1 * sn;
+    return {a, ((M_PI * M_PI) * a) * cs - sn};
 }
 
-double beta_of(const nv_heat &p, double t) {
+// The per-step scalars r = (h a(t_end)) / (dx dx) and h beta(t_end) of slices
+// [j0, j1); returns the first step (global index) whose a(t) is not positive,
+// or -1, with its time in *bad_t.
+long long step_scalars(const nv_heat &p, double t0, double L, double dt, int S, double rem,
+                       int S_tot, double dx, int j0, int j1, double *step, double *bad_t) {
 #pragma clang fp contract(off)
-    return ((M_PI * M_PI) * a_of(p, t)) * std::cos(t) - std::sin(t);
+    for (int j = j0; j < j1; ++j) {
+        const double Tj = t0 + double(j) * L;
+        for (int st = 0; st < S_tot; ++st) {
+            const bool last = st == S;
+            const double h = last ? rem : dt;
+            const double te = last ? (Tj + double(S) * dt) + rem : Tj + double(st + 1) * dt;
+            const StepCoef k = coef_at(p, te);
+            const long long q = (long long)j * S_tot + st;
+            if (!(k.a > 0.0)) {
+                *bad_t = te;
+                return q;
+            }
+            step[2 * q] = (h * k.a) / (dx * dx);
+            step[2 * q + 1] = p.forcing ? h * k.beta : 0.0;
+        }
+    }
+    return -1;
 }
 
 }  // namespace
@@ -292,19 +562,26 @@ NV_API nv_status nv_lin_build(nv_lin *l, const nv_heat *p, double t0, double T, 
     // per-step scalars on the host: r = (h a(t_end)) / (dx dx), h beta(t_end)
     const double dx = 1.0 / double(M + 1);
     std::vector<double> step(size_t(nq) * 2), sv(M);
-    for (int j = 0; j < n_slices; ++j) {
-        const double Tj = t0 + double(j) * L;
-        for (int st = 0; st < S_tot; ++st) {
-            const bool last = st == S;
-            const double h = last ? rem : dt;
-            const double te = last ? (Tj + double(S) * dt) + rem : Tj + double(st + 1) * dt;
-            const double a = a_of(*p, te);
-            if (!(a > 0.0))
-                return fail(NV_ERR_INVALID_ARG, "a(t) = %g is not positive at t = %g", a, te);
-            const size_t q = size_t(j) * S_tot + st;
-            step[2 * q] = (h * a) / (dx * dx);
-            step[2 * q + 1] = p->forcing ? h * beta_of(*p, te) : 0.0;
-        }
+    {
+        // slices split over a few host threads when there are many steps
+        const unsigned hc = std::thread::hardware_concurrency();
+        const int nth = nq < 8192 ? 1 : int(hc < 2 ? 1 : (hc > 8 ? 8 : hc));
+        std::vector<long long> bad_q(size_t(nth), -1);
+        std::vector<double> bad_t(size_t(nth), 0.0);
+        auto part = [&](int k) {
+            const int j0 = int((long long)n_slices * k / nth);
+            const int j1 = int((long long)n_slices * (k + 1) / nth);
+            bad_q[size_t(k)] = step_scalars(*p, t0, L, dt, S, rem, S_tot, dx, j0, j1, step.data(),
+                                            &bad_t[size_t(k)]);
+        };
+        std::vector<std::thread> pool;
+        for (int k = 1; k < nth; ++k) pool.emplace_back(part, k);
+        part(0);
+        for (std::thread &t : pool) t.join();
+        for (int k = 0; k < nth; ++k)
+            if (bad_q[size_t(k)] >= 0)
+                return fail(NV_ERR_INVALID_ARG, "a(t) = %g is not positive at t = %g",
+                            coef_at(*p, bad_t[size_t(k)]).a, bad_t[size_t(k)]);
     }
     for (int i = 0; i < M; ++i) sv[i] = std::sin(M_PI * (double(i + 1) * dx));
 
@@ -314,7 +591,7 @@ NV_API nv_status nv_lin_build(nv_lin *l, const nv_heat *p, double t0, double T, 
     const size_t o_w = off;    off = al(off + size_t(nq) * M * 8);
     const size_t o_c = off;    off = al(off + size_t(nq) * M * 8);
     const size_t o_s = off;    off = al(off + size_t(M) * 8);
-    const size_t o_T = off;    off = al(off + size_t(n_slices) * M * (M + 1) * 8);
+    const size_t o_T = off;    off = al(off + size_t(n_slices) * lin_stride(M) * (M + 1) * 8);
     const size_t o_y0 = off;   off = al(off + size_t(M) * 8);
     const size_t o_b = off;    off = al(off + (size_t(n_slices) + 1) * M * 8);
     const size_t o_bad = off;  off = al(off + sizeof(int));
@@ -353,12 +630,22 @@ NV_API nv_status nv_lin_build(nv_lin *l, const nv_heat *p, double t0, double T, 
                        l->stream, ca);
     NV_HIP(hipGetLastError());
     BuildArgs ba{l->step, l->w, l->c, l->s, l->T, M, S_tot, p->forcing ? 1 : 0};
-    const int ncol = 64 * ((M + 1 + 63) / 64);
-    const size_t lds = size_t(M) * ncol * sizeof(double);     // at most 127 x 128 x 8 bytes
-    NV_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(lin_build_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-    hipLaunchKernelGGL(lin_build_kernel, dim3(unsigned(n_slices)), dim3(ncol), lds, l->stream,
-                       ba);
+    const int ncol = 64 * ((M + 1 + 63) / 64);                // threads: one per solve
+    const dim3 grid{unsigned(n_slices)}, block{unsigned(ncol)};
+    if (M <= 8) hipLaunchKernelGGL(lin_build_reg_kernel<8>, grid, block, 0, l->stream, ba);
+    else if (M <= 16) hipLaunchKernelGGL(lin_build_reg_kernel<16>, grid, block, 0, l->stream, ba);
+    else if (M <= 24) hipLaunchKernelGGL(lin_build_reg_kernel<24>, grid, block, 0, l->stream, ba);
+    else if (M <= 32) hipLaunchKernelGGL(lin_build_reg_kernel<32>, grid, block, 0, l->stream, ba);
+    else if (M <= 48) hipLaunchKernelGGL(lin_build_reg_kernel<48>, grid, block, 0, l->stream, ba);
+    else if (M <= 64) hipLaunchKernelGGL(lin_build_reg_kernel<64>, grid, block, 0, l->stream, ba);
+    else if (M <= 80) hipLaunchKernelGGL(lin_build_reg_kernel<80>, grid, block, 0, l->stream, ba);
+    else if (M <= 104) hipLaunchKernelGGL(lin_build_reg_kernel<104>, grid, block, 0, l->stream, ba);
+    else {
+        const size_t lds = lin_build_lds_bytes(M);             // at most 127 x 133 x 8 bytes
+        NV_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(lin_build_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+        hipLaunchKernelGGL(lin_build_kernel, grid, block, lds, l->stream, ba);
+    }
     NV_HIP(hipGetLastError());
     NV_HIP(hipEventRecord(l->e1, l->stream));
     // the host vectors must outlive the copies
@@ -375,10 +662,7 @@ NV_API nv_status nv_lin_compose(nv_lin *l, const double *y0, double *yT, double 
     NV_HIP(hipMemcpyAsync(l->y0, y0, size_t(M) * 8, hipMemcpyHostToDevice, l->stream));
     NV_HIP(hipEventRecord(l->e2, l->stream));
     ComposeArgs a{l->T, l->y0, l->boundary, l->bad, M, N};
-    if (M <= 63)
-        hipLaunchKernelGGL(lin_compose_kernel<64>, dim3(1), dim3(64), 0, l->stream, a);
-    else
-        hipLaunchKernelGGL(lin_compose_kernel<256>, dim3(1), dim3(256), 0, l->stream, a);
+    lin_chain.f[(M + 7) / 8 - 1](a, l->stream);
     NV_HIP(hipGetLastError());
     NV_HIP(hipEventRecord(l->e3, l->stream));
     int bad = -1;
@@ -397,7 +681,8 @@ NV_API nv_status nv_lin_compose(nv_lin *l, const double *y0, double *yT, double 
 NV_API nv_status nv_lin_get_tables(nv_lin *l, double *G, double *c) {
     if (!l) return fail(NV_ERR_INVALID_ARG, "NULL argument");
     if (!l->built) return fail(NV_ERR_NOT_BUILT, "no successful nv_lin_build");
-    const size_t M = size_t(l->M), N = size_t(l->N), per = M * (M + 1);
+    const size_t M = size_t(l->M), N = size_t(l->N), Ms = size_t(lin_stride(l->M)),
+                 per = Ms * (M + 1);
     std::vector<double> t(N * per);
     NV_HIP(hipMemcpyAsync(t.data(), l->T, t.size() * 8, hipMemcpyDeviceToHost, l->stream));
     NV_HIP(hipStreamSynchronize(l->stream));
@@ -405,9 +690,9 @@ NV_API nv_status nv_lin_get_tables(nv_lin *l, double *G, double *c) {
         const double *b = t.data() + j * per;
         if (G)
             for (size_t k = 0; k < M; ++k)
-                for (size_t i = 0; i < M; ++i) G[(j * M + i) * M + k] = b[k * M + i];
+                for (size_t i = 0; i < M; ++i) G[(j * M + i) * M + k] = b[k * Ms + i];
         if (c)
-            for (size_t i = 0; i < M; ++i) c[j * M + i] = b[M * M + i];
+            for (size_t i = 0; i < M; ++i) c[j * M + i] = b[Ms * M + i];
     }
     return NV_OK;
 }

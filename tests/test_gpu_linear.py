@@ -96,6 +96,29 @@ def test_linear_argument_errors(lin):
     assert e.value.status == nv.NV_ERR_NOT_BUILT
 
 
+def test_linear_first_nonpositive_diffusion_is_named_over_many_steps(lin):
+    """With many steps the library evaluates the per-step scalars on several
+    host threads; the error still names the first step end (in time order)
+    where a(t) = a0 + a1 sin t is not positive, as the oracle's step list
+    finds it."""
+    w = HeatWorkload("bad-a-late", 9, 0.0005, 1024, a0=0.1, a1=1.0)
+    L, S, rem = lo.slice_steps(w.t0, w.T, w.n_slices, w.dt)
+    first = None
+    for j in range(w.n_slices):
+        for _, te in lo.step_list(w.t0 + j * L, S, w.dt, rem):
+            if not lo.a_of(te, w.a0, w.a1) > 0.0:
+                first = te
+                break
+        if first is not None:
+            break
+    assert first is not None and 3.0 < first < 3.5
+    say("first non-positive a(t) at", first)
+    with pytest.raises(nv.NvError) as e:
+        lin.build(w)
+    assert e.value.status == nv.NV_ERR_INVALID_ARG
+    assert f"at t = {first:g}" in str(e.value), str(e.value)
+
+
 def test_linear_nonfinite_state_is_reported(lin):
     w = HeatWorkload("heat-M9-nan", 9, 0.01, 5, T=0.5)
     lin.build(w)

@@ -43,10 +43,10 @@ constexpr int kRowsS = 784;
 // Their outputs, concatenated, form one partial vector per split of the sum.
 constexpr int kG_W2 = 0;                    // [128 x 128]  D2 . H1^T
 constexpr int kG_W3 = 16384;                // [128 x 128]  D3 . H2^T
-constexpr int kG_D_XO = 32768;              // [384 x 16]   D . XO^T  (dW1, db1..db3)
+constexpr int kG_D_XO = 32768;              // [384 x 16]   D . XO^T  (dW1, db1; db2, db3 in column 4)
 constexpr int kG_XO_H3 = 32768 + 384 * 16;  // [16 x 144]   XO . [H3; XO]^T  (dW4, db4)
 constexpr int kGradEntries = kG_XO_H3 + 16 * 144;
-constexpr int kGemmWaveTiles = 16 + 16 + 12 + 5;
+constexpr int kGemmWaveTiles = 16 + 16 + 4 + 5;
 constexpr int kGemmSmallFirst = 32;         // wave tiles of the two small products
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));

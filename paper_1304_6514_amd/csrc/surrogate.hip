@@ -27,7 +27,8 @@ namespace {
 
 constexpr int kTrainThreads = 256;       // 4 waves, 1 workgroup per CU (LDS): 512 registers per wave
 constexpr int kInferThreads = 256;       // 4 waves
-constexpr int kMaxSplits = 64;           // weight-gradient sums: splits of the minibatch
+constexpr int kMaxSplits = 128;          // weight-gradient sums: splits of the minibatch
+constexpr long long kMinSplit = 512;      // samples per split, at least
 constexpr long long kMaxBatch = 1LL << 20;
 
 enum { kModeReduce = 1, kModeAdam = 2 };
@@ -178,7 +179,9 @@ __global__ __launch_bounds__(kTrainThreads) void sur_train_kernel(TrainArgs a) {
 // Weight-gradient sums G = A B^T over samples k0..k1-1 of the minibatch, A and
 // B row blocks of S; each wave computes a 32 x 32 block of one of the products
 // (wave tiles kGemmSmallFirst.. of kGemmWaveTiles: the two small products
-// D . XO^T and XO . [H3; XO]^T), blockIdx.y is the split of the sum.
+// D1 . XO^T, giving dW1 and db1, and XO . [H3; XO]^T, giving dW4 and db4),
+// blockIdx.y is the split of the sum.  (db2 and db3 are row sums that
+// sur_grad_mat_kernel forms from the rows it stages anyway.)
 struct GemmArgs {
     const __bf16 *S;
     long long ldS, n, k_per_split;
@@ -195,10 +198,10 @@ __global__ __launch_bounds__(256) void sur_grad_kernel(GemmArgs a) {
     } else if (wt < 32) {
         a_row = kRowD + 256; b_row = kRowH + 128; M = N = 128; out = kG_W3; t = wt - 16;
         tiles_n = 4;
-    } else if (wt < 44) {
-        a_row = kRowD; b_row = kRowXO; M = 384; N = 16; out = kG_D_XO; t = wt - 32; tiles_n = 1;
+    } else if (wt < 36) {
+        a_row = kRowD; b_row = kRowXO; M = 128; N = 16; out = kG_D_XO; t = wt - 32; tiles_n = 1;
     } else {
-        a_row = kRowXO; b_row = kRowH + 256; M = 16; N = 144; out = kG_XO_H3; t = wt - 44;
+        a_row = kRowXO; b_row = kRowH + 256; M = 16; N = 144; out = kG_XO_H3; t = wt - 36;
         tiles_n = 5;
     }
     const int mt0 = 2 * (t / tiles_n), nt0 = 2 * (t % tiles_n);
@@ -253,11 +256,13 @@ __global__ __launch_bounds__(256) void sur_grad_kernel(GemmArgs a) {
 }
 
 // The two 128 x 128 weight gradients, dW2 = D2 . H1^T and dW3 = D3 . H2^T
-// (blockIdx.x = 0, 1), over samples k0..k1-1 (blockIdx.y = split).  The
-// workgroup stages each 32-sample step of its 128 A rows and 128 B rows in LDS
-// once (rows padded to 80 bytes: 16 lanes reading 16 bytes from 16 rows hit
-// disjoint banks) and each wave multiplies a 64 x 64 quadrant; the next step's
-// rows are loaded into registers while the current one is multiplied.
+// (blockIdx.x = 0, 1), over samples k0..k1-1 (blockIdx.y = split), and the
+// bias gradients db2, db3, the row sums of D2 and D3.  The workgroup stages
+// each 32-sample step of its 128 A rows and 128 B rows in LDS once (rows
+// padded to 80 bytes: 16 lanes reading 16 bytes from 16 rows hit disjoint
+// banks) and each wave multiplies a 64 x 64 quadrant; two threads per A row
+// add its 32 staged values into FP32 row sums; the next step's rows are loaded
+// into registers while the current one is multiplied.
 constexpr int kGmPad = 40;                 // bf16 per LDS row
 
 __global__ __launch_bounds__(256) void sur_grad_mat_kernel(GemmArgs a) {
@@ -289,6 +294,9 @@ __global__ __launch_bounds__(256) void sur_grad_mat_kernel(GemmArgs a) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // row sum of A row tid / 2, samples 16 (tid & 1) .. + 15 of every step
+    const int srow = tid >> 1, shalf = tid & 1;
+    float bsum = 0.0f;
     bf16x8 ra0, ra1, rb0, rb1;
     if (k0 < k1) load(k0, ra0, ra1, rb0, rb1);
     for (long long k = k0; k < k1; k += 32) {
@@ -308,8 +316,19 @@ __global__ __launch_bounds__(256) void sur_grad_mat_kernel(GemmArgs a) {
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = mfma(fa[i], fb[j], acc[i][j]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8 *>(As + srow * kGmPad + 16 * shalf + 8 * h);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bsum += float(v[e]);
+        }
         __syncthreads();
     }
+    // the two halves of a row are adjacent lanes
+    const float rsum = bsum + __shfl_xor(bsum, 1);
+    if (shalf == 0)
+        a.part[(long long)blockIdx.y * kGradEntries + kG_D_XO + (128 * (job + 1) + srow) * 16 + 4] =
+            rsum;
     float *P = a.part + (long long)blockIdx.y * kGradEntries + out;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -344,10 +363,21 @@ struct UpdateArgs {
     float *loss_out;
 };
 
+// 64 parameters per workgroup: wave q (q = 0..3) sums splits 32q .. 32q+31 of
+// each parameter's gradient in split order (all 32 loads in flight at once);
+// wave 0 then combines the four sums as ((s0 + s1) + (s2 + s3)), takes the Adam
+// step and refreshes the permuted bf16 copies.
+constexpr int kUpdateParams = 64;
+constexpr int kUpdateGroups = 4;
+
 __global__ __launch_bounds__(256) void sur_update_kernel(UpdateArgs a) {
-    if (blockIdx.x == 0 && a.loss_out) {
+    static_assert(kMaxSplits % kUpdateGroups == 0, "splits per group");
+    constexpr int kPer = kMaxSplits / kUpdateGroups;
+    if (int(blockIdx.x) == int(gridDim.x) - 1 && a.loss_out) {
+        // the extra last workgroup: the minibatch loss from the per-tile sums
         __shared__ float red[256];
         float s = 0.0f;
+#pragma unroll 16
         for (long long i = threadIdx.x; i < a.n_loss; i += 256) s += a.loss_part[i];
         red[threadIdx.x] = s;
         __syncthreads();
@@ -356,15 +386,31 @@ __global__ __launch_bounds__(256) void sur_update_kernel(UpdateArgs a) {
             __syncthreads();
         }
         if (threadIdx.x == 0) a.loss_out[0] = red[0] * a.inv_n;
+        return;
     }
-    const int p = int(blockIdx.x) * 256 + int(threadIdx.x);
-    if (p >= kParams) return;
+    __shared__ float sums[kUpdateGroups][kUpdateParams];
+    const int pl = int(threadIdx.x) & (kUpdateParams - 1), grp = int(threadIdx.x) >> 6;
+    const int p = int(blockIdx.x) * kUpdateParams + pl;
+    const int pc = p < kParams ? p : kParams - 1;
+    if (a.mode & kModeReduce) {
+        const int src = grad_source(pc);
+        float part[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int sp = grp * kPer + u;
+            part[u] = a.part[(long long)(sp < a.splits ? sp : a.splits - 1) * kGradEntries + src];
+        }
+        float gs = 0.0f;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if (grp * kPer + u < a.splits) gs += part[u];
+        sums[grp][pl] = gs;
+    }
+    __syncthreads();
+    if (grp != 0 || p >= kParams) return;
     float th = a.params[p];
     if (a.mode & kModeReduce) {
-        const int src = grad_source(p);
-        float gsum = 0.0f;
-#pragma unroll 8
-        for (int s = 0; s < a.splits; ++s) gsum += a.part[(long long)s * kGradEntries + src];
+        const float gsum = (sums[0][pl] + sums[1][pl]) + (sums[2][pl] + sums[3][pl]);
         a.grad[p] = gsum;
         if (a.mode & kModeAdam) {
             const float m = a.beta1 * a.m[p] + (1.0f - a.beta1) * gsum;
@@ -735,13 +781,14 @@ nv_status refresh_shadow(nv_sur *s) {
     u.params = s->params;
     u.shadow = s->shadow;
     u.mode = 0;
-    hipLaunchKernelGGL(sur_update_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s->stream, u);
+    hipLaunchKernelGGL(sur_update_kernel, dim3((kParams + kUpdateParams - 1) / kUpdateParams),
+                       dim3(256), 0, s->stream, u);
     NV_HIP(hipGetLastError());
     return NV_OK;
 }
 
 long long k_per_split(long long n) {
-    long long k = std::max(1024LL, (n + kMaxSplits - 1) / kMaxSplits);
+    long long k = std::max(kMinSplit, (n + kMaxSplits - 1) / kMaxSplits);
     return (k + 31) / 32 * 32;
 }
 
@@ -804,8 +851,10 @@ nv_status minibatch(nv_sur *s, const float *x, const float *t, long long ld, lon
     ua.n_loss = tiles;
     ua.inv_n = ta.inv_n;
     ua.loss_out = loss_out;
-    hipLaunchKernelGGL(sur_update_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s->stream,
-                       ua);
+    // one workgroup per 64 parameters, plus one for the loss
+    hipLaunchKernelGGL(sur_update_kernel,
+                       dim3((kParams + kUpdateParams - 1) / kUpdateParams + (ua.loss_out ? 1 : 0)),
+                       dim3(256), 0, s->stream, ua);
     NV_HIP(hipGetLastError());
     return NV_OK;
 }

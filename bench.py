@@ -100,10 +100,54 @@ def cpu_baseline(w: W.Workload, n_slices_sample: int):
                       f"({steps:.3g} trajectory-steps, {dt:.1f} s, FP64, one thread)"}
 
 
-def fixed_error(w: W.Workload, yT_method, gpu_ms):
+def method_equal_error(prop, w: W.Workload, ref, target):
+    """The method's own cheapest configuration of the same problem (same
+    right-hand side, interval, initial value, grid range and interpolation)
+    whose error at T is no larger than ``target``: slice counts, grid sizes
+    and steps per slice from small to the fixed configuration's, each run once
+    through nv_solve for its error, and those meeting the target timed (best of
+    three whole solves, host clock, synchronized)."""
+    import numpy as np
+    import torch
+
+    from paper_1304_6514_amd import nv
+
+    tried, meeting, best = 0, 0, None
+    for N in (8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096):
+        for M in (256, 512, 1024, 2048, 4096):
+            for S in (10, 20, 50, 100, 200, 500):
+                if N > w.n_slices or M > w.points_per_slice or S > w.steps_per_slice:
+                    continue
+                c = w.with_(name=f"{w.name}-eq-{N}x{M}x{S}", n_slices=N, grid_n=(M,),
+                            steps_per_slice=S)
+                tried += 1
+                r = prop.solve(c)
+                if r.status != nv.NV_OK:
+                    continue
+                e = float(np.max(np.abs(np.asarray(r.yT) - ref)))
+                if not (e <= target):
+                    continue
+                meeting += 1
+                ts = []
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    prop.solve(c)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t)
+                ms = 1e3 * min(ts)
+                if best is None or ms < best["gpu_ms"]:
+                    best = {"n_slices": N, "points_per_slice": M, "steps_per_slice": S,
+                            "error": e, "gpu_ms": round(ms, 4),
+                            "trajectory_steps": N * M * S}
+    return {"configs_tried": tried, "configs_meeting_error": meeting, "fastest": best}
+
+
+def fixed_error(w: W.Workload, yT_method, gpu_ms, prop=None):
     """Time-to-y(T) of the method on the GPU against the serial oracle on one
     host core: at the method's own step (N*S steps) and at equal error (the
-    fewest serial steps whose error at T is no larger than the method's)."""
+    fewest serial steps whose error at T is no larger than the method's); with
+    ``prop``, also the method's own cheapest configuration at that error."""
     import numpy as np
     import oracle
 
@@ -141,11 +185,14 @@ def fixed_error(w: W.Workload, yT_method, gpu_ms):
         oracle.serial_steps(w.rhs, w.params, w.scheme, w.t0, w.T, hi, w.y0)
         reps += 1
     t_eq = (time.perf_counter() - t) / reps
-    return {"method_error_at_T": method_err, "reference": f"serial RK4, {S_ref} steps",
-            "gpu_time_to_yT_ms": gpu_ms,
-            "serial_same_step": {"steps": n_same, "ms": round(1e3 * t_same, 3)},
-            "serial_equal_error": {"steps": hi, "error": err(hi), "ms": round(1e3 * t_eq, 4)},
-            "cores": 1}
+    out = {"method_error_at_T": method_err, "reference": f"serial RK4, {S_ref} steps",
+           "gpu_time_to_yT_ms": gpu_ms,
+           "serial_same_step": {"steps": n_same, "ms": round(1e3 * t_same, 3)},
+           "serial_equal_error": {"steps": hi, "error": err(hi), "ms": round(1e3 * t_eq, 4)},
+           "cores": 1}
+    if prop is not None and w.dim == 1:
+        out["method_equal_error"] = method_equal_error(prop, w, ref, method_err)
+    return out
 
 
 def bench_batched(args):
@@ -734,7 +781,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_slices, w.n_slices))
-        out["time_to_yT_vs_serial"] = fixed_error(w, r.yT, round(ms_per_step, 4))
+        out["time_to_yT_vs_serial"] = fixed_error(w, r.yT, round(ms_per_step, 4), prop)
     prop.close()
     print(json.dumps(out), flush=True)
 

@@ -68,16 +68,16 @@ __global__ void __launch_bounds__(kBuildBlock)
 template <class T>
 __global__ void batch_compose_kernel(const BatchProblem *__restrict__ probs, int count) {
     const int b = int(blockIdx.x);
-    if (b >= count || threadIdx.x != 0) return;
+    if (b >= count) return;
     const BatchProblem &pr = probs[b];
+    double fin[2] = {0.0, 0.0};
     switch (pr.interp) {
-    case NV_INTERP_LINEAR: compose_range<T, 0>(pr.compose); break;
-    case NV_INTERP_HERMITE: compose_range<T, 1>(pr.compose); break;
-    default: compose_range<T, 2>(pr.compose); break;
+    case NV_INTERP_LINEAR: compose_range<T, 0>(pr.compose, fin); break;
+    case NV_INTERP_HERMITE: compose_range<T, 1>(pr.compose, fin); break;
+    default: compose_range<T, 2>(pr.compose, fin); break;
     }
-    const int bad = pr.compose.status->bad_slice;
-    const long long n = bad < 0 ? pr.compose.n_slices : bad;
-    for (int d = 0; d < pr.dim; ++d) pr.result[d] = pr.compose.boundary[n * pr.dim + d];
+    if (threadIdx.x == 0)
+        for (int d = 0; d < pr.dim; ++d) pr.result[d] = fin[d];
 }
 
 }  // namespace

@@ -39,39 +39,56 @@ __device__ inline int locate(double lo, double inv, int n, double x, long long &
 
 __device__ inline bool finite(double v) { return isfinite(v); }
 
-// Delta-xi times the slope at node i of a 1-D table row, by finite differences.
-template <class T>
-__device__ inline double node_slope(const T *row, long long i, int n) {
+// Delta-xi times the slope at node i of a 1-D table row, by finite differences;
+// get(k) gives node k's table value.
+template <class F>
+__device__ inline double node_slope_f(const F &get, long long i, int n) {
 #pragma clang fp contract(off)
     if (i == 0) {
-        const double t0 = double(row[0]), t1 = double(row[1]), t2 = double(row[2]);
+        const double t0 = get(0), t1 = get(1), t2 = get(2);
         return 0.5 * ((4.0 * t1 - 3.0 * t0) - t2);
     }
     if (i == n - 1) {
-        const double a = double(row[n - 1]), b = double(row[n - 2]), c = double(row[n - 3]);
+        const double a = get(n - 1), b = get(n - 2), c = get(n - 3);
         return 0.5 * ((3.0 * a - 4.0 * b) + c);
     }
-    return 0.5 * (double(row[i + 1]) - double(row[i - 1]));
+    return 0.5 * (get(i + 1) - get(i - 1));
 }
 
-// Composes slices j_begin .. j_end-1.  A launch that starts at slice 0 takes
-// y0 from its arguments and resets the status; a later launch resumes from the
-// boundary state the previous one left in memory and adds to the status.
+template <class T>
+__device__ inline double node_slope(const T *row, long long i, int n) {
+    return node_slope_f([row](long long k) { return double(row[k]); }, i, n);
+}
+
+// Composes slices j_begin .. j_end-1, run by one whole wave: every lane takes
+// the same chain (uniform values, uniform loads, so the result is that of one
+// lane), and lane l keeps the boundary state of slice jb + l + 1 of the current
+// block of 64 slices; a block is written out with one coalesced store.  No
+// store then sits between one slice's loads and the next's (the memory counter
+// is in order, so a load issued after a store would also wait for the store):
+// the chain waits for a store once per 64 slices.  A launch that starts at
+// slice 0 takes y0 from its arguments and resets the status; a later launch
+// resumes from the boundary state the previous one left in memory and adds to
+// the status.  With final_out, the last state (that of the failing slice's
+// start when one fails) is also returned there ([dim]).
 template <class T, int Interp>
-__device__ inline void compose_range(const ComposeArgs &a) {
+__device__ inline void compose_range(const ComposeArgs &a, double *final_out = nullptr) {
 #pragma clang fp contract(off)
     constexpr int D = Interp == 2 ? 2 : 1;
+    const int lane = int(threadIdx.x) & 63;
     const T *tab0 = static_cast<const T *>(a.tab0);
     const T *tab1 = static_cast<const T *>(a.tab1);
     double lam0, lam1 = 0.0;
     if (a.j_begin == 0) {
         lam0 = a.y00;
         lam1 = a.y01;
-        a.boundary[0] = lam0;
-        if (D == 2) a.boundary[1] = lam1;
-        a.status->n_out_of_grid = 0;
-        a.status->bad_slice = -1;
-        a.status->done = 0;
+        if (lane == 0) {
+            a.boundary[0] = lam0;
+            if (D == 2) a.boundary[1] = lam1;
+            a.status->n_out_of_grid = 0;
+            a.status->bad_slice = -1;
+            a.status->done = 0;
+        }
     } else {
         if (a.status->bad_slice >= 0) return;     // an earlier range already failed
         lam0 = a.boundary[(long long)a.j_begin * D];
@@ -79,7 +96,10 @@ __device__ inline void compose_range(const ComposeArgs &a) {
     }
     long long oog = 0;
     int bad_slice = -1;
-    for (int j = a.j_begin; j < a.j_end; ++j) {
+    double keep0 = 0.0, keep1 = 0.0;
+    int jb = a.j_begin;                           // first slice of the current block
+    int j = a.j_begin;
+    for (; j < a.j_end; ++j) {
         if (!finite(lam0) || (D == 2 && !finite(lam1))) {
             bad_slice = j;
             break;
@@ -125,12 +145,30 @@ __device__ inline void compose_range(const ComposeArgs &a) {
         }
         lam0 = next0;
         lam1 = next1;
-        a.boundary[(long long)(j + 1) * D] = lam0;
-        if (D == 2) a.boundary[(long long)(j + 1) * D + 1] = lam1;
+        if (lane == j - jb) {
+            keep0 = lam0;
+            keep1 = lam1;
+        }
+        if (j - jb == 63) {
+            a.boundary[(long long)(jb + lane + 1) * D] = keep0;
+            if (D == 2) a.boundary[(long long)(jb + lane + 1) * D + 1] = keep1;
+            jb += 64;
+        }
     }
-    a.status->n_out_of_grid += oog;
-    if (bad_slice >= 0) a.status->bad_slice = bad_slice;
-    if (a.j_end == a.n_slices || bad_slice >= 0) a.status->done = 1;
+    // the states of the last, partial block (slices jb .. j-1)
+    if (lane < j - jb) {
+        a.boundary[(long long)(jb + lane + 1) * D] = keep0;
+        if (D == 2) a.boundary[(long long)(jb + lane + 1) * D + 1] = keep1;
+    }
+    if (lane == 0) {
+        a.status->n_out_of_grid += oog;
+        if (bad_slice >= 0) a.status->bad_slice = bad_slice;
+        if (a.j_end == a.n_slices || bad_slice >= 0) a.status->done = 1;
+    }
+    if (final_out) {
+        final_out[0] = lam0;
+        if (D == 2) final_out[1] = lam1;
+    }
 }
 
 // The chain with Lagrange interpolation on Chebyshev nodes (paper mode), run

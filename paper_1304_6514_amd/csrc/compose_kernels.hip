@@ -2,7 +2,7 @@
 // lambda_0 = y0, lambda_{j+1} = phi^j(lambda_j), one slice after the other.
 //
 // This is a chain of N dependent lookups (the N tau_N term of the cost model
-// of sec. 4), so one lane runs it, in FP64, directly on the tables the build
+// of sec. 4), so one wave runs it, in FP64, directly on the tables the build
 // left in HBM; nothing is copied to the host but the N+1 boundary states.
 //
 // Every floating-point operation here is a single IEEE binary64 operation
@@ -18,12 +18,10 @@ using namespace dev;
 template <class T, int Interp>
 __global__ void compose_kernel(ComposeArgs a) {
     if (blockIdx.x != 0) return;
-    if constexpr (Interp == 3) {
-        compose_range_lagrange<T>(a);       // the whole wave
-    } else {
-        if (threadIdx.x != 0) return;
+    if constexpr (Interp == 3)
+        compose_range_lagrange<T>(a);
+    else
         compose_range<T, Interp>(a);
-    }
 }
 
 __global__ void locate_kernel(double lo, double inv, int n, const double *x, long long count,

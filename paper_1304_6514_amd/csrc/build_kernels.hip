@@ -33,10 +33,13 @@ __global__ void __launch_bounds__(kBuildBlock) build_kernel(BuildArgs a) {
 // F[j][2s] = g(T_j + s h), F[j][2s+1] = g((T_j + s h) + h/2), F[j][2S] = g(T_j + S h).
 template <class R>
 __global__ void forcing_kernel(int rhs, R *F, int n_slices, int steps, double t0, double L,
-                               double h) {
+                               double h, uint32_t *nonfinite) {
 #pragma clang fp contract(off)
     const long long per = 2LL * steps + 1;
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // the build's per-slice non-finite counters start at zero (per >= 3, so
+    // the grid covers them): one launch fewer before the build
+    if (idx < n_slices) nonfinite[idx] = 0u;
     if (idx >= per * n_slices) return;
     const long long j = idx / per, m = idx - j * per;
     const double Tj = t0 + double(j) * L;
@@ -112,16 +115,16 @@ hipError_t launch_build(const BuildConfig &c, const BuildArgs &a, hipStream_t s)
 }
 
 hipError_t launch_forcing(int rhs, int precision, void *F, int n_slices, int steps,
-                          double t0, double L, double h, hipStream_t s) {
+                          double t0, double L, double h, uint32_t *nonfinite, hipStream_t s) {
     const long long n = (2LL * steps + 1) * n_slices;
     const int block = 256;
     const long long grid = (n + block - 1) / block;
     if (precision == 0)
         hipLaunchKernelGGL(forcing_kernel<double>, dim3(unsigned(grid)), dim3(block), 0, s, rhs,
-                           static_cast<double *>(F), n_slices, steps, t0, L, h);
+                           static_cast<double *>(F), n_slices, steps, t0, L, h, nonfinite);
     else
         hipLaunchKernelGGL(forcing_kernel<float>, dim3(unsigned(grid)), dim3(block), 0, s, rhs,
-                           static_cast<float *>(F), n_slices, steps, t0, L, h);
+                           static_cast<float *>(F), n_slices, steps, t0, L, h, nonfinite);
     return hipGetLastError();
 }
 

@@ -108,8 +108,8 @@ struct Plan {
     size_t table_bytes = 0;
     size_t forcing_off = 0, forcing_bytes = 0;
     size_t nonfinite_off = 0;
-    size_t boundary_off = 0, boundary_bytes = 0;
-    size_t status_off = 0;
+    size_t boundary_bytes = 0;     // in the mapped host stage, from offset 0
+    size_t stage_status_off = 0;   // the status, in the mapped host stage
     size_t nodes_off = 0;
     size_t work_bytes = 0;
     int tiles_per_slice = 0;
@@ -181,11 +181,10 @@ nv_status make_plan(int rhs, int n_slices, const nv_ic_grid *g, int steps,
     off = align_up(off + p->forcing_bytes);
     p->nonfinite_off = off;
     off = align_up(off + size_t(n_slices) * sizeof(uint32_t));
-    p->boundary_off = off;
+    // the boundary states and the status go to the context's mapped host
+    // memory: [boundary][status at stage_status_off]
     p->boundary_bytes = (size_t(n_slices) + 1) * size_t(g->dim) * sizeof(double);
-    off = align_up(off + p->boundary_bytes);
-    p->status_off = off;
-    off = align_up(off + sizeof(nv::ComposeStatus));
+    p->stage_status_off = align_up(p->boundary_bytes);
     p->nodes_off = off;
     off = align_up(off + kMaxChebyshev * sizeof(double));
     p->work_bytes = off;
@@ -218,8 +217,10 @@ struct nv_ctx {
     void *work = nullptr;
     size_t work_cap = 0;
     bool work_owned = true;
-    // pinned staging for the composition's outputs
+    // pinned, device-mapped memory that the composition writes its boundary
+    // states and status into (host and device addresses)
     void *host_stage = nullptr;
+    void *host_stage_dev = nullptr;
     double nodes_host[kMaxChebyshev] = {};
     // what the scratch's node array holds (uploaded once per grid and buffer)
     const void *nodes_dev = nullptr;
@@ -277,14 +278,20 @@ nv_status ensure_host_stage(nv_ctx *c, size_t need) {
     if (need <= c->host_stage_cap && c->host_stage) return NV_OK;
     if (c->host_stage) {
         NV_HIP(hipHostFree(c->host_stage));
-        c->host_stage = nullptr;
+        c->host_stage = c->host_stage_dev = nullptr;
         c->host_stage_cap = 0;
     }
-    hipError_t e = hipHostMalloc(&c->host_stage, need, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(&c->host_stage, need, hipHostMallocMapped);
     if (e != hipSuccess) {
         c->host_stage = nullptr;
         return fail(NV_ERR_OOM, "hipHostMalloc of %zu bytes failed: %s", need,
                     hipGetErrorString(e));
+    }
+    e = hipHostGetDevicePointer(&c->host_stage_dev, c->host_stage, 0);
+    if (e != hipSuccess) {
+        (void)hipHostFree(c->host_stage);
+        c->host_stage = c->host_stage_dev = nullptr;
+        return fail(NV_ERR_HIP, "hipHostGetDevicePointer failed: %s", hipGetErrorString(e));
     }
     c->host_stage_cap = need;
     return NV_OK;
@@ -343,7 +350,7 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
     s = ensure_device(&ctx->work, &ctx->work_cap, ctx->work_owned, p.work_bytes, "work");
     if (s != NV_OK) return s;
     if (ctx->work_cap != work_cap_before) ctx->nodes_dev = nullptr;   // a new allocation
-    s = ensure_host_stage(ctx, p.status_off - p.boundary_off + sizeof(nv::ComposeStatus));
+    s = ensure_host_stage(ctx, p.stage_status_off + sizeof(nv::ComposeStatus));
     if (s != NV_OK) return s;
     if (ctx->timing) {
         s = ensure_events(ctx);
@@ -404,10 +411,11 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
         }
         a.nodes = dn;
     }
-    NV_HIP(nv::launch_fill_u32(a.nonfinite, n_slices, 0u, st));
     if (a.forcing)
         NV_HIP(nv::launch_forcing(rhs_id, ctx->opt.precision, work_at(ctx, p.forcing_off),
-                                  n_slices, steps_per_slice, t0, L, h, st));
+                                  n_slices, steps_per_slice, t0, L, h, a.nonfinite, st));
+    else
+        NV_HIP(nv::launch_fill_u32(a.nonfinite, n_slices, 0u, st));
 
     ctx->plan = p;
     ctx->rhs = rhs_id;
@@ -424,8 +432,9 @@ nv::ComposeArgs compose_args(const nv_ctx *ctx, const double *y0, int j0, int j1
     nv::ComposeArgs a{};
     a.tab0 = ctx->tables;
     a.tab1 = p.dim == 2 ? static_cast<char *>(ctx->tables) + p.comp_bytes : nullptr;
-    a.boundary = reinterpret_cast<double *>(work_at(ctx, p.boundary_off));
-    a.status = reinterpret_cast<nv::ComposeStatus *>(work_at(ctx, p.status_off));
+    a.boundary = static_cast<double *>(ctx->host_stage_dev);
+    a.status = reinterpret_cast<nv::ComposeStatus *>(static_cast<char *>(ctx->host_stage_dev) +
+                                                     p.stage_status_off);
     a.M = p.M;
     a.n_slices = ctx->n_slices;
     a.j_begin = j0;
@@ -445,19 +454,15 @@ nv::ComposeArgs compose_args(const nv_ctx *ctx, const double *y0, int j0, int j1
     return a;
 }
 
-// Copy the boundary states and the status (adjacent in the scratch buffer) to
-// pinned memory on stream st, wait, and hand the results out.
+// Wait for stream st, whose composition wrote the boundary states and the
+// status straight into the context's mapped host memory, and hand them out.
 nv_status finish_compose(nv_ctx *ctx, hipStream_t st, double *yT, double *boundary,
                          nv_compose_info *info, int n_chunks) {
     const Plan &p = ctx->plan;
-    const size_t bytes = p.status_off - p.boundary_off + sizeof(nv::ComposeStatus);
-    NV_HIP(hipMemcpyAsync(ctx->host_stage, work_at(ctx, p.boundary_off), bytes,
-                          hipMemcpyDeviceToHost, st));
     NV_HIP(hipStreamSynchronize(st));
     const double *hb = static_cast<const double *>(ctx->host_stage);
     nv::ComposeStatus cs;
-    std::memcpy(&cs, static_cast<const char *>(ctx->host_stage) + (p.status_off - p.boundary_off),
-                sizeof cs);
+    std::memcpy(&cs, static_cast<const char *>(ctx->host_stage) + p.stage_status_off, sizeof cs);
     if (!cs.done) return fail(NV_ERR_HIP, "composition kernel did not complete");
     const int n_done = cs.bad_slice < 0 ? ctx->n_slices : cs.bad_slice;
     if (boundary) std::memcpy(boundary, hb, size_t(n_done + 1) * p.dim * sizeof(double));

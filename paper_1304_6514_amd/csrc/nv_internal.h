@@ -103,8 +103,9 @@ nv_status batch_slice_sources(nv_batch *b, std::vector<SliceMapSource> &out, int
 
 bool build_supported(const BuildConfig &c);
 hipError_t launch_build(const BuildConfig &c, const BuildArgs &a, hipStream_t s);
+// Also zeroes the n_slices non-finite counters.
 hipError_t launch_forcing(int rhs, int precision, void *F, int n_slices, int steps,
-                          double t0, double L, double h, hipStream_t s);
+                          double t0, double L, double h, uint32_t *nonfinite, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t s);
 hipError_t launch_compose(int interp, int precision, const ComposeArgs &a, hipStream_t s);
 hipError_t launch_locate(double lo, double inv, int n, const double *x, long long count,

@@ -216,12 +216,47 @@ __device__ inline double lagrange_value(double lam, double xk, double vk, int la
     return sum;
 }
 
+// The same value for a compile-time node count MC <= 8, with the M*M
+// quotients spread over the wave: lane k*MC + m forms f_km = (lam - x_m) /
+// den_km, den_km = x_k - x_m (the same operands as above, so the same
+// quotient), all in one division step, where the form above takes M divisions
+// one after another (each ends in v_div_fmas, which reads VCC, so two cannot
+// overlap).  Lane k < MC then gathers f_k0 .. f_k(MC-1) and multiplies them into
+// its term in ascending m, the factor with m = k replaced by 1 as above, and the
+// terms are summed in ascending k: the operation sequence of lagrange_value.
+template <int MC>
+__device__ inline double lagrange_value_pairs(double lam, double x_m, double den, double vk,
+                                              int lane) {
+#pragma clang fp contract(off)
+    static_assert(MC >= 1 && MC * MC <= 64, "one quotient per lane");
+    const double f = (lam - x_m) / den;
+    const int src0 = lane < MC ? lane * MC : 0;
+    double term = vk;
+#pragma unroll
+    for (int m = 0; m < MC; ++m) {
+        const double fm = __shfl(f, src0 + m);
+        term *= (m == lane) ? 1.0 : fm;
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < MC; ++k) sum += readlane_f64(term, k);
+    return sum;
+}
+
 template <class T, int MC>
 __device__ inline void lagrange_chain(const ComposeArgs &a, double *rows, double *bnd) {
 #pragma clang fp contract(off)
     const int lane = int(threadIdx.x);
     const int M = a.n0;
     const double xk = lane < M ? a.nodes[lane] : 0.0;
+    // lane k*MC + m (< MC*MC) of the spread quotients: x_m and x_k - x_m (zero
+    // for k = m, whose quotient is never used)
+    double pair_xm = 0.0, pair_den = 1.0;
+    if (MC > 0 && MC <= 8 && lane < MC * MC) {
+        const int pk = lane / (MC > 0 ? MC : 1), pm = lane - pk * MC;
+        pair_xm = a.nodes[pm];
+        pair_den = a.nodes[pk] - pair_xm;
+    }
     const T *tab0 = static_cast<const T *>(a.tab0);
     double lam;
     if (a.j_begin == 0) {
@@ -243,25 +278,39 @@ __device__ inline void lagrange_chain(const ComposeArgs &a, double *rows, double
         const int c1 = c0 + rows_per_chunk < a.j_end ? c0 + rows_per_chunk : a.j_end;
         __syncthreads();                          // the previous chunk is consumed
         const long long base = (long long)c0 * M, count = (long long)(c1 - c0) * M;
-        for (long long i = lane; i < count; i += int(blockDim.x))
-            rows[i] = double(tab0[base + i]);
+        // the chunk's first row holding a non-finite value, found while staging
+        // it, so that the chain itself needs no vote per slice
+        int first_bad = c1;
+        for (long long i = lane; i < count; i += int(blockDim.x)) {
+            const double v = double(tab0[base + i]);
+            rows[i] = v;
+            if (!finite(v) && c0 + int(i / M) < first_bad) first_bad = c0 + int(i / M);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int other = __shfl_xor(first_bad, o);
+            first_bad = other < first_bad ? other : first_bad;
+        }
         __syncthreads();
         int done = c0;                            // boundary states bnd[0 .. done-c0) ready
+        double vk = lane < M ? rows[lane] : 0.0;
         for (int j = c0; j < c1; ++j) {
-            if (!finite(lam)) {
+            if (!finite(lam) || j == first_bad) {
                 bad_slice = j;
                 break;
             }
-            const double vk = lane < M ? rows[(j - c0) * M + lane] : 0.0;
-            if (__any(lane < M && !finite(vk))) {
-                bad_slice = j;
-                break;
-            }
-            const double next = lagrange_value<MC>(lam, xk, vk, lane, M);
+            // the next slice's table values, read ahead of the chain
+            const double vnext = (lane < M && j + 1 < c1) ? rows[(j + 1 - c0) * M + lane] : 0.0;
+            double next;
+            if constexpr (MC > 0 && MC <= 8)
+                next = lagrange_value_pairs<MC>(lam, pair_xm, pair_den, vk, lane);
+            else
+                next = lagrange_value<MC>(lam, xk, vk, lane, M);
             oog += (lam < a.lo0 || lam > a.hi0) ? 1 : 0;
             lam = next;
             if (lane == 0) bnd[j - c0] = lam;
             done = j + 1;
+            vk = vnext;
         }
         __syncthreads();
         for (int i = lane; i < done - c0; i += int(blockDim.x)) a.boundary[c0 + 1 + i] = bnd[i];

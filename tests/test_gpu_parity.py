@@ -446,6 +446,32 @@ def test_solve_nonfinite_reports_same_slice(orc, torch):
     assert np.array_equal(r.boundary[:o.bad_slice + 1], o.boundary[:o.bad_slice + 1])
 
 
+@pytest.mark.parametrize("interp", ["linear", "hermite"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_chain_failure_after_several_blocks_of_states(orc, torch, interp, precision):
+    """The chain keeps boundary states in registers and writes them per block
+    of 64 slices; a failure at slice ~110 (y' = y^2 blows up at t = 1/y0, and
+    grid points above 1/L blow up within a slice, so their table entries are
+    not finite) must leave exactly the states before it, bit for bit, in the
+    single composition and in the chunked solve."""
+    from paper_1304_6514_amd.propagator import Propagator
+    w = W.Workload(f"square-blowup-{interp}-{precision}", "square", (), 0.0, 6.0, 200, (301,),
+                   (0.0,), (60.0,), 50, (0.3,), precision, interp)
+    say("late blowup", w.name)
+    with Propagator("cuda:0") as a:
+        a.build(w)
+        tab = gpu_tables(a, w)
+        ra = a.compose()
+    o = orc.compose_tables(ogrid(orc, w), w.interp, tab, w.y0)
+    assert o.status == orc.NONFINITE and o.bad_slice > 64, o.bad_slice
+    with Propagator("cuda:0", solve_chunks=5) as b:
+        rb = b.solve(w)
+    for r in (ra, rb):
+        assert r.status == nv.NV_ERR_NONFINITE and r.bad_slice == o.bad_slice
+        n = o.bad_slice + 1
+        assert np.array_equal(r.boundary[:n].view(np.int64), o.boundary[:n].view(np.int64))
+
+
 def test_fp32_accumulation_modes_full_size(orc, torch):
     # plain FP32 accumulation of the state misses the FP32 bar on this workload
     # (one rounding of y + dy per step over 2000 steps); Kahan-compensated and

@@ -419,10 +419,12 @@ __global__ __launch_bounds__(512) void lin_chain_kernel(ComposeArgs a) {
     if (tid == 0) *a.bad = bad_s == 0x7fffffff ? -1 : bad_s;
 }
 
-// prefetch depth for KM loads per slice: about 72 doubles of ring per lane,
+// prefetch depth for KM loads per slice: a ring of about 72 doubles per lane
+// (120 for the largest tables, KM >= 10, where a deeper ring measured faster),
 // at least 2 and at most 8 slices ahead
 constexpr int lin_depth(int KM) {
-    return 72 / (2 * KM + 1) < 2 ? 2 : (72 / (2 * KM + 1) > 8 ? 8 : 72 / (2 * KM + 1));
+    const int ring = KM >= 10 ? 120 : 72, d = ring / (2 * KM + 1);
+    return d < 2 ? 2 : (d > 8 ? 8 : d);
 }
 
 template <int KM>

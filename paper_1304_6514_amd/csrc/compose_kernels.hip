@@ -18,6 +18,10 @@ using namespace dev;
 template <class T, int Interp>
 __global__ void compose_kernel(ComposeArgs a) {
     if (blockIdx.x != 0) return;
+    // The chain usually shares its SIMD with waves of a build still running
+    // (nv_solve overlaps them); the highest wave priority lets its dependent
+    // instructions issue first instead of waiting behind those waves.
+    __builtin_amdgcn_s_setprio(3);
     if constexpr (Interp == 3)
         compose_range_lagrange<T>(a);
     else

@@ -230,13 +230,20 @@ def bench_batched(args):
     with Propagator("cuda:0") as p:
         for w in probs:                      # warm-up of every shape
             p.solve(w, want_boundary=False)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for w in probs:
-            r = p.solve(w, want_boundary=False)
-            plain_y.append(r.yT)
-        torch.cuda.synchronize()
-        plain_s = time.perf_counter() - t1
+        # best of three timed passes: a single pass has been seen to catch a
+        # one-off stall of ~30 ms on the host side
+        plain_s = float("inf")
+        for rep in range(3):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ys = []
+            for w in probs:
+                r = p.solve(w, want_boundary=False)
+                ys.append(r.yT)
+            torch.cuda.synchronize()
+            plain_s = min(plain_s, time.perf_counter() - t1)
+            if rep == 0:
+                plain_y = ys
     same = all(np.array_equal(yT[i, :w.dim], plain_y[i]) for i, w in enumerate(probs))
 
     ms = 1e3 * elapsed / args.steps
@@ -256,7 +263,8 @@ def bench_batched(args):
                      "order": ["longest-first", "natural"][sched.order],
                      "autotune_s": round(tune_s, 2)},
         "plain_form": {"value": total_steps / plain_s, "ms": round(1e3 * plain_s, 3),
-                       "what": "each problem alone through nv_solve, same options",
+                       "what": "each problem alone through nv_solve, same options; best of "
+                               "three timed passes",
                        "identical_results": bool(same)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",

@@ -149,9 +149,10 @@ NV_API nv_status nv_get_options(const nv_ctx *ctx, nv_options *opt);
  *                 working precision, 256-byte aligned per component;
  *   *work_bytes:  scratch (per-slice forcing values of non-autonomous
  *                 right-hand sides, per-slice non-finite counters, the
- *                 Chebyshev nodes).  The boundary states and the composition's
- *                 status go to pinned, device-mapped host memory that the
- *                 context allocates itself.
+ *                 composition's running status and carried state, the
+ *                 Chebyshev nodes).  The boundary states and the final status
+ *                 go to pinned, device-mapped host memory that the context
+ *                 allocates itself.
  * Pure host arithmetic: no device call. */
 NV_API nv_status nv_required_bytes(int rhs_id, int n_slices, const nv_ic_grid *grid,
                                    int steps_per_slice, const nv_options *opt,

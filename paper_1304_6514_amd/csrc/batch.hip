@@ -502,6 +502,8 @@ NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int co
         c.tab1 = t1;
         c.boundary = reinterpret_cast<double *>(b->work + b->off_boundary + b->bnd_off[i]);
         c.status = reinterpret_cast<nv::ComposeStatus *>(b->work + b->off_status) + i;
+        c.carry = nullptr;                  // one range per problem: nothing to carry
+        c.status_host = nullptr;
         c.M = a.M;
         c.n_slices = p.n_slices;
         c.j_begin = 0;

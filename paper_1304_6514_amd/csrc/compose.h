@@ -60,6 +60,52 @@ __device__ inline double node_slope(const T *row, long long i, int n) {
     return node_slope_f([row](long long k) { return double(row[k]); }, i, n);
 }
 
+// The start of a range of slices: y0 (a range from slice 0 also resets the
+// running status and writes lambda_0) or the state the previous range carried
+// over.  Returns false when an earlier range already failed.  Everything the
+// next range needs stays in device memory; the boundary states and the final
+// status may live in host-mapped memory, which the chain only writes.
+template <int D>
+__device__ inline bool range_begin(const ComposeArgs &a, int lane, double &l0, double &l1) {
+    if (a.j_begin == 0) {
+        l0 = a.y00;
+        l1 = a.y01;
+        if (lane == 0) {
+            a.boundary[0] = l0;
+            if (D == 2) a.boundary[1] = l1;
+            a.status->n_out_of_grid = 0;
+            a.status->bad_slice = -1;
+            a.status->done = 0;
+        }
+        return true;
+    }
+    if (a.status->bad_slice >= 0) return false;
+    l0 = a.carry[0];
+    l1 = a.carry[1];
+    return true;
+}
+
+// The end of a range: the running status, the carried state and, when the
+// chain ends here, a copy of the final status.
+__device__ inline void range_end(const ComposeArgs &a, int lane, double l0, double l1,
+                                 long long oog, int bad_slice) {
+    if (lane != 0) return;
+    const long long total = a.status->n_out_of_grid + oog;
+    a.status->n_out_of_grid = total;
+    if (bad_slice >= 0) a.status->bad_slice = bad_slice;
+    const bool last = a.j_end == a.n_slices || bad_slice >= 0;
+    if (last) a.status->done = 1;
+    if (a.carry) {
+        a.carry[0] = l0;
+        a.carry[1] = l1;
+    }
+    if (last && a.status_host) {
+        a.status_host->n_out_of_grid = total;
+        a.status_host->bad_slice = bad_slice;
+        a.status_host->done = 1;
+    }
+}
+
 // Composes slices j_begin .. j_end-1, run by one whole wave: every lane takes
 // the same chain (uniform values, uniform loads, so the result is that of one
 // lane), and lane l keeps the boundary state of slice jb + l + 1 of the current
@@ -78,22 +124,8 @@ __device__ inline void compose_range(const ComposeArgs &a, double *final_out = n
     const int lane = int(threadIdx.x) & 63;
     const T *tab0 = static_cast<const T *>(a.tab0);
     const T *tab1 = static_cast<const T *>(a.tab1);
-    double lam0, lam1 = 0.0;
-    if (a.j_begin == 0) {
-        lam0 = a.y00;
-        lam1 = a.y01;
-        if (lane == 0) {
-            a.boundary[0] = lam0;
-            if (D == 2) a.boundary[1] = lam1;
-            a.status->n_out_of_grid = 0;
-            a.status->bad_slice = -1;
-            a.status->done = 0;
-        }
-    } else {
-        if (a.status->bad_slice >= 0) return;     // an earlier range already failed
-        lam0 = a.boundary[(long long)a.j_begin * D];
-        if (D == 2) lam1 = a.boundary[(long long)a.j_begin * D + 1];
-    }
+    double lam0 = 0.0, lam1 = 0.0;
+    if (!range_begin<D>(a, lane, lam0, lam1)) return;     // an earlier range already failed
     long long oog = 0;
     int bad_slice = -1;
     double keep0 = 0.0, keep1 = 0.0;
@@ -160,11 +192,7 @@ __device__ inline void compose_range(const ComposeArgs &a, double *final_out = n
         a.boundary[(long long)(jb + lane + 1) * D] = keep0;
         if (D == 2) a.boundary[(long long)(jb + lane + 1) * D + 1] = keep1;
     }
-    if (lane == 0) {
-        a.status->n_out_of_grid += oog;
-        if (bad_slice >= 0) a.status->bad_slice = bad_slice;
-        if (a.j_end == a.n_slices || bad_slice >= 0) a.status->done = 1;
-    }
+    range_end(a, lane, lam0, lam1, oog, bad_slice);
     if (final_out) {
         final_out[0] = lam0;
         if (D == 2) final_out[1] = lam1;
@@ -258,19 +286,8 @@ __device__ inline void lagrange_chain(const ComposeArgs &a, double *rows, double
         pair_den = a.nodes[pk] - pair_xm;
     }
     const T *tab0 = static_cast<const T *>(a.tab0);
-    double lam;
-    if (a.j_begin == 0) {
-        lam = a.y00;
-        if (lane == 0) {
-            a.boundary[0] = lam;
-            a.status->n_out_of_grid = 0;
-            a.status->bad_slice = -1;
-            a.status->done = 0;
-        }
-    } else {
-        if (a.status->bad_slice >= 0) return;     // an earlier range already failed
-        lam = a.boundary[a.j_begin];
-    }
+    double lam = 0.0, unused = 0.0;
+    if (!range_begin<1>(a, lane, lam, unused)) return;    // an earlier range already failed
     long long oog = 0;
     int bad_slice = -1;
     const int rows_per_chunk = kLagrangeStage / M;
@@ -315,11 +332,7 @@ __device__ inline void lagrange_chain(const ComposeArgs &a, double *rows, double
         __syncthreads();
         for (int i = lane; i < done - c0; i += int(blockDim.x)) a.boundary[c0 + 1 + i] = bnd[i];
     }
-    if (lane == 0) {
-        a.status->n_out_of_grid += oog;
-        if (bad_slice >= 0) a.status->bad_slice = bad_slice;
-        if (a.j_end == a.n_slices || bad_slice >= 0) a.status->done = 1;
-    }
+    range_end(a, lane, lam, 0.0, oog, bad_slice);
 }
 
 template <class T>

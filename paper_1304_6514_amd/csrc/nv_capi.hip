@@ -108,8 +108,9 @@ struct Plan {
     size_t table_bytes = 0;
     size_t forcing_off = 0, forcing_bytes = 0;
     size_t nonfinite_off = 0;
+    size_t status_off = 0, carry_off = 0;   // device: running status, carried state
     size_t boundary_bytes = 0;     // in the mapped host stage, from offset 0
-    size_t stage_status_off = 0;   // the status, in the mapped host stage
+    size_t stage_status_off = 0;   // the final status, in the mapped host stage
     size_t nodes_off = 0;
     size_t work_bytes = 0;
     int tiles_per_slice = 0;
@@ -181,8 +182,14 @@ nv_status make_plan(int rhs, int n_slices, const nv_ic_grid *g, int steps,
     off = align_up(off + p->forcing_bytes);
     p->nonfinite_off = off;
     off = align_up(off + size_t(n_slices) * sizeof(uint32_t));
-    // the boundary states and the status go to the context's mapped host
-    // memory: [boundary][status at stage_status_off]
+    // the running status and the state carried from one range of slices to
+    // the next stay in device memory; the boundary states and a copy of the
+    // final status go to the context's mapped host memory:
+    // [boundary][status at stage_status_off]
+    p->status_off = off;
+    off = align_up(off + sizeof(nv::ComposeStatus));
+    p->carry_off = off;
+    off = align_up(off + 2 * sizeof(double));
     p->boundary_bytes = (size_t(n_slices) + 1) * size_t(g->dim) * sizeof(double);
     p->stage_status_off = align_up(p->boundary_bytes);
     p->nodes_off = off;
@@ -433,8 +440,10 @@ nv::ComposeArgs compose_args(const nv_ctx *ctx, const double *y0, int j0, int j1
     a.tab0 = ctx->tables;
     a.tab1 = p.dim == 2 ? static_cast<char *>(ctx->tables) + p.comp_bytes : nullptr;
     a.boundary = static_cast<double *>(ctx->host_stage_dev);
-    a.status = reinterpret_cast<nv::ComposeStatus *>(static_cast<char *>(ctx->host_stage_dev) +
-                                                     p.stage_status_off);
+    a.status = reinterpret_cast<nv::ComposeStatus *>(work_at(ctx, p.status_off));
+    a.carry = reinterpret_cast<double *>(work_at(ctx, p.carry_off));
+    a.status_host = reinterpret_cast<nv::ComposeStatus *>(
+        static_cast<char *>(ctx->host_stage_dev) + p.stage_status_off);
     a.M = p.M;
     a.n_slices = ctx->n_slices;
     a.j_begin = j0;

@@ -53,12 +53,14 @@ struct ComposeStatus {
 struct ComposeArgs {
     const void *tab0;
     const void *tab1;
-    double *boundary;         // [(n_slices+1) * dim]
-    ComposeStatus *status;
+    double *boundary;         // [(n_slices+1) * dim], written only (may be host-mapped)
+    ComposeStatus *status;    // device: the running status of the whole chain
+    double *carry;            // device [2]: the state a range ends with, or null
+    ComposeStatus *status_host;  // a copy of the final status, or null (may be host-mapped)
     long long M;
     int n_slices;
     int j_begin, j_end;       // slices this launch composes; lambda_{j_begin} is y0 when
-                              // j_begin == 0, else read from boundary
+                              // j_begin == 0, else the carry the previous range left
     int n0, n1;
     double lo0, inv0, lo1, inv1;   // inv = (n-1)/(hi-lo), computed on the host
     double hi0;                    // Chebyshev: the interval's upper end

@@ -340,7 +340,8 @@ NV_API nv_status nv_batch_run(nv_batch *batch, double *yT, nv_compose_info *info
 NV_API nv_status nv_batch_last_timing(nv_batch *batch, float *run_ms, long long *traj_steps);
 
 /* Copy problem p's component c table (layout of nv_get_table) or its boundary
- * states ((n_slices + 1) x dim doubles) of the last run to host memory. */
+ * states ((n_slices + 1) x dim doubles) of the last run to host memory;
+ * NV_ERR_NOT_BUILT before the first nv_batch_run. */
 NV_API nv_status nv_batch_get_table(nv_batch *batch, int problem, int component,
                                     void *host_dst, size_t bytes);
 NV_API nv_status nv_batch_get_boundary(nv_batch *batch, int problem, double *host_dst,

@@ -616,6 +616,7 @@ NV_API nv_status nv_batch_get_table(nv_batch *b, int problem, int component, voi
     if (problem < 0 || problem >= b->count) return fail(NV_ERR_INVALID_ARG, "bad problem index");
     if (component < 0 || component >= dim_of(b->problems[problem]))
         return fail(NV_ERR_INVALID_ARG, "bad component");
+    if (!b->ran) return fail(NV_ERR_NOT_BUILT, "the batch has not been run");
     const size_t need = b->elems[problem] * (b->precision == NV_FP64 ? 8 : 4);
     if (bytes < need) return fail(NV_ERR_BUFFER_TOO_SMALL, "need %zu bytes", need);
     NV_HIP(hipMemcpyAsync(host_dst,
@@ -632,6 +633,7 @@ NV_API nv_status nv_batch_get_boundary(nv_batch *b, int problem, double *host_ds
     const nv_problem &p = b->problems[problem];
     const size_t need = (size_t(p.n_slices) + 1) * size_t(dim_of(p));
     if (count < need) return fail(NV_ERR_BUFFER_TOO_SMALL, "need %zu values", need);
+    if (!b->ran) return fail(NV_ERR_NOT_BUILT, "the batch has not been run");
     NV_HIP(hipMemcpyAsync(host_dst, b->work + b->off_boundary + b->bnd_off[problem],
                           need * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     NV_HIP(hipStreamSynchronize(b->stream));

@@ -417,6 +417,10 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
             ctx->nodes_hi = grid->hi[0];
         }
         a.nodes = dn;
+    } else {
+        // this build's forcing values, counters and carried state may cover
+        // the place where an earlier build kept its nodes
+        ctx->nodes_dev = nullptr;
     }
     if (a.forcing)
         NV_HIP(nv::launch_forcing(rhs_id, ctx->opt.precision, work_at(ctx, p.forcing_off),
@@ -500,12 +504,13 @@ NV_API nv_status nv_ctx_create(nv_ctx **out) {
 
 NV_API nv_status nv_ctx_destroy(nv_ctx *ctx) {
     if (!ctx) return NV_OK;
-    if (ctx->built) (void)hipStreamSynchronize(stream_of(ctx));
+    // every stream that may still use the buffers is drained before they go
+    (void)hipStreamSynchronize(stream_of(ctx));
+    if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
+    if (ctx->aux2) (void)hipStreamSynchronize(ctx->aux2);
     if (ctx->tables_owned && ctx->tables) (void)hipFree(ctx->tables);
     if (ctx->work_owned && ctx->work) (void)hipFree(ctx->work);
     if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
-    if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
-    if (ctx->aux2) (void)hipStreamSynchronize(ctx->aux2);
     for (auto e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto e : ctx->chunk_ev)
@@ -553,7 +558,9 @@ NV_API nv_status nv_set_buffers(nv_ctx *ctx, void *tables_dev, size_t table_byte
     if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
     if ((tables_dev == nullptr) != (work_dev == nullptr))
         return fail(NV_ERR_INVALID_ARG, "give both buffers or neither");
-    if (ctx->built) NV_HIP(hipStreamSynchronize(stream_of(ctx)));
+    NV_HIP(hipStreamSynchronize(stream_of(ctx)));
+    if (ctx->aux) NV_HIP(hipStreamSynchronize(ctx->aux));
+    if (ctx->aux2) NV_HIP(hipStreamSynchronize(ctx->aux2));
     if (ctx->tables_owned && ctx->tables) NV_HIP(hipFree(ctx->tables));
     if (ctx->work_owned && ctx->work) NV_HIP(hipFree(ctx->work));
     ctx->built = false;

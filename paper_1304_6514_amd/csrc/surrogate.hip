@@ -1128,7 +1128,9 @@ NV_API nv_status nv_sur_compose(nv_sur *s, const nv_sur_chains *c, nv_sur_compos
     if (c->fb_tab0) {
         const nv_ic_grid &g = c->fb_grid;
         if (!c->fb_tab1 || g.dim != 2 || g.interp != NV_INTERP_BILINEAR || g.n[0] < 2 ||
-            g.n[1] < 2 || !(g.hi[0] > g.lo[0]) || !(g.hi[1] > g.lo[1]) ||
+            g.n[1] < 2 || !std::isfinite(g.lo[0]) || !std::isfinite(g.hi[0]) ||
+            !std::isfinite(g.lo[1]) || !std::isfinite(g.hi[1]) || !(g.hi[0] > g.lo[0]) ||
+            !(g.hi[1] > g.lo[1]) ||
             (c->fb_precision != NV_FP32 && c->fb_precision != NV_FP64))
             return fail(NV_ERR_INVALID_ARG, "the fallback needs two tables of a 2-D bilinear grid");
         a.tab0 = c->fb_tab0;

@@ -193,6 +193,10 @@ def test_batch_errors(torch):
         Batch(bad)
     assert e.value.status == nv.NV_ERR_INVALID_ARG and "problem 3" in str(e.value)
     with Batch(small_batch()[:2]) as b:
+        for get in (lambda: b.table(0), lambda: b.boundary(1)):
+            with pytest.raises(nv.NvError) as e:
+                get()                   # nothing to hand out before the first run
+            assert e.value.status == nv.NV_ERR_NOT_BUILT
         s = nv.nv_batch_schedule()
         for r in range(5):
             s.traj_per_lane[r] = 3

@@ -111,3 +111,19 @@ def test_paper_mode_argument_errors(prop):
     with pytest.raises(nv.NvError) as e:
         prop.build(W.small(W.FORCED_CUBIC_FP32, 2, (16,), 3).with_(dt=0.01))
     assert e.value.status == nv.NV_ERR_INVALID_ARG
+
+
+def test_chebyshev_nodes_survive_other_builds_in_between(prop):
+    # a forced build writes its forcing values over the start of the scratch,
+    # where a Chebyshev build of 32 slices keeps its nodes; the next Chebyshev
+    # build must not take the overwritten values for its nodes
+    forced = W.small(W.FORCED_CUBIC_FP32, 64, (256,), 50)
+    cheb = W.paper_model(32, 5, 2.0 ** -14, "fp64")
+    prop.build(forced)                 # scratch large enough for both from here on
+    first = prop.solve(cheb)
+    prop.build(forced)
+    again = prop.solve(cheb)
+    assert np.array_equal(first.boundary, again.boundary)
+    prop.build(W.small(W.LOGISTIC_FP64, 512, (64,), 10))   # counters and carry over the nodes
+    third = prop.solve(cheb)
+    assert np.array_equal(first.boundary, third.boundary)

@@ -14,50 +14,80 @@ namespace dev {
 
 // Cell and local coordinate of x on one axis.  Returns 1 when x lies outside
 // [lo, hi] (the lookup then extrapolates from the edge cell).  A NaN query
-// gives cell 0, w = NaN and counts as outside.
+// gives cell 0, w = NaN and counts as outside.  The cell is floor(u) clamped
+// to [0, n-2], formed without branches as u clamped to [0, n-2] and truncated
+// (the same integer: truncation is floor on [0, n-2], and fmax and fmin return
+// the other operand for a NaN); w = u - cell, the cell converted back exactly.
 __device__ inline int locate(double lo, double inv, int n, double x, long long &cell,
                              double &w) {
 #pragma clang fp contract(off)
     const double u = (x - lo) * inv;
-    if (u != u) {
-        cell = 0;
-        w = u;
-        return 1;
-    }
-    const double f = floor(u);
-    long long i;
-    if (f < 0.0)
-        i = 0;
-    else if (f > double(n - 2))
-        i = n - 2;
-    else
-        i = (long long)f;
+    const int i = int(fmin(fmax(u, 0.0), double(n - 2)));
     cell = i;
     w = u - double(i);
-    return (u < 0.0 || u > double(n - 1)) ? 1 : 0;
+    return (u < 0.0 || u > double(n - 1) || u != u) ? 1 : 0;
 }
 
 __device__ inline bool finite(double v) { return isfinite(v); }
 
-// Delta-xi times the slope at node i of a 1-D table row, by finite differences;
-// get(k) gives node k's table value.
-template <class F>
-__device__ inline double node_slope_f(const F &get, long long i, int n) {
+// The 1-D interpolants of one slice at cell i0, local coordinate w0: linear
+// (Interp 0) or cubic Hermite (Interp 1) with Delta-xi times the slope at node
+// i taken by finite differences, (t[i+1] - t[i-1])/2 inside the row and the
+// second-order one-sided forms (4 t[1] - 3 t[0] - t[2])/2 and
+// (3 t[n-1] - 4 t[n-2] + t[n-3])/2 at its ends; get(k) gives node k's table
+// value.  Returns false when an entry it reads (or a slope) is not finite.
+// The Hermite form reads the four nodes i0-1 .. i0+2 clamped to the row, all
+// at once, and picks an end's one-sided slope by selection, so no branch sits
+// between the reads.
+// The cubic Hermite basis at w (h00, h10, h01, h11); it does not depend on
+// the table, so the chain forms it while the table values are in flight.
+struct HermiteBasis {
+    double h00, h10, h01, h11;
+};
+
+__device__ inline HermiteBasis hermite_basis(double w) {
 #pragma clang fp contract(off)
-    if (i == 0) {
-        const double t0 = get(0), t1 = get(1), t2 = get(2);
-        return 0.5 * ((4.0 * t1 - 3.0 * t0) - t2);
-    }
-    if (i == n - 1) {
-        const double a = get(n - 1), b = get(n - 2), c = get(n - 3);
-        return 0.5 * ((3.0 * a - 4.0 * b) + c);
-    }
-    return 0.5 * (get(i + 1) - get(i - 1));
+    const double w2 = w * w, w3 = w2 * w;
+    HermiteBasis b;
+    b.h00 = (2.0 * w3 - 3.0 * w2) + 1.0;
+    b.h10 = (w3 - 2.0 * w2) + w;
+    b.h01 = 3.0 * w2 - 2.0 * w3;
+    b.h11 = w3 - w2;
+    return b;
 }
 
-template <class T>
-__device__ inline double node_slope(const T *row, long long i, int n) {
-    return node_slope_f([row](long long k) { return double(row[k]); }, i, n);
+template <int Interp>
+__device__ inline bool interp_1d_values(double tm, double ta, double tb, double tp, long long i0,
+                                        double w0, const HermiteBasis &hb, int n,
+                                        double &next) {
+#pragma clang fp contract(off)
+    if constexpr (Interp == 0) {
+        next = ta + w0 * (tb - ta);
+        return finite(ta) & finite(tb);
+    } else {
+        // node i0 (never the last): one-sided at the first node, else central;
+        // node i0+1 (never the first): one-sided at the last node, else central.
+        // Both forms are formed and one is selected (no branch).
+        const double da_end = 0.5 * ((4.0 * tb - 3.0 * ta) - tp), da_in = 0.5 * (tb - tm);
+        const double db_end = 0.5 * ((3.0 * tb - 4.0 * ta) + tm), db_in = 0.5 * (tp - ta);
+        const double da = i0 == 0 ? da_end : da_in;
+        const double db = i0 + 1 == n - 1 ? db_end : db_in;
+        next = ((hb.h00 * ta + hb.h10 * da) + hb.h01 * tb) + hb.h11 * db;
+        return finite(ta) & finite(tb) & finite(da) & finite(db);
+    }
+}
+
+// Nodes i0-1 (clamped to 0) and i0+2 (clamped to n-1) for the Hermite form.
+__device__ inline long long node_below(long long i0) { return i0 > 0 ? i0 - 1 : 0; }
+__device__ inline long long node_above(long long i0, int n) { return i0 + 2 < n ? i0 + 2 : n - 1; }
+
+template <int Interp, class F>
+__device__ inline bool interp_1d(const F &get, long long i0, double w0, int n, double &next) {
+    const double ta = get(i0), tb = get(i0 + 1);
+    const double tm = Interp == 1 ? get(node_below(i0)) : 0.0;
+    const double tp = Interp == 1 ? get(node_above(i0, n)) : 0.0;
+    const HermiteBasis hb = Interp == 1 ? hermite_basis(w0) : HermiteBasis{};
+    return interp_1d_values<Interp>(tm, ta, tb, tp, i0, w0, hb, n, next);
 }
 
 // The start of a range of slices: y0 (a range from slice 0 also resets the
@@ -142,20 +172,9 @@ __device__ inline void compose_range(const ComposeArgs &a, double *final_out = n
         oog += locate(a.lo0, a.inv0, a.n0, lam0, i0, w0);
         double next0, next1 = 0.0;
         bool bad = false;
-        if constexpr (Interp == 0) {
-            const double ta = double(row0[i0]), tb = double(row0[i0 + 1]);
-            bad = !finite(ta) || !finite(tb);
-            next0 = ta + w0 * (tb - ta);
-        } else if constexpr (Interp == 1) {
-            const double ta = double(row0[i0]), tb = double(row0[i0 + 1]);
-            const double da = node_slope(row0, i0, a.n0), db = node_slope(row0, i0 + 1, a.n0);
-            const double w2 = w0 * w0, w3 = w2 * w0;
-            const double h00 = (2.0 * w3 - 3.0 * w2) + 1.0;
-            const double h10 = (w3 - 2.0 * w2) + w0;
-            const double h01 = 3.0 * w2 - 2.0 * w3;
-            const double h11 = w3 - w2;
-            bad = !finite(ta) || !finite(tb) || !finite(da) || !finite(db);
-            next0 = ((h00 * ta + h10 * da) + h01 * tb) + h11 * db;
+        if constexpr (Interp == 0 || Interp == 1) {
+            bad = !interp_1d<Interp>([row0](long long k) { return double(row0[k]); }, i0, w0,
+                                     a.n0, next0);
         } else {
             oog += locate(a.lo1, a.inv1, a.n1, lam1, i1, w1);
             const long long c00 = i0 * a.n1 + i1, c10 = (i0 + 1) * a.n1 + i1;
@@ -196,6 +215,207 @@ __device__ inline void compose_range(const ComposeArgs &a, double *final_out = n
     if (final_out) {
         final_out[0] = lam0;
         if (D == 2) final_out[1] = lam1;
+    }
+}
+
+// The 1-D chain with its table windows staged ahead in LDS.  Each slice's
+// table read depends on the state the previous slice produced, so its latency
+// is on the chain's path.  Helper waves therefore fetch, for each coming
+// slice s, a window of kPfWin consecutive values of row s around the cell the
+// chain is predicted to need (the chain's latest cell, moved on at its latest
+// rate per slice), once the chain is within kPfAhead slices of s, into a ring
+// of kPfSlots LDS slots; the chain then pays an LDS read instead of a global
+// one.  The chain takes a slice's values from its slot when the slot holds
+// that slice and every value the interpolant reads, and from global memory
+// otherwise; it never waits for a helper, so the values it uses, and the
+// result, are the same either way.  A helper waits only for the chain's
+// progress, and gives up after a bounded number of polls.  What remains per
+// slice is the issue of the chain's own instructions by its one wave (the
+// cell, the weights, the interpolant, the checks), which is why the loop
+// keeps them few: one branch between the LDS and the global reads, central
+// slopes only on the LDS path, 32-bit offsets.
+constexpr int kPfHelpers = 8;      // helper waves
+constexpr int kPfSlots = 16;       // staged windows
+constexpr int kPfWin = 256;        // table values per window
+constexpr int kPfAhead = 8;        // a window is fetched this many slices ahead
+constexpr int kPfSpinMax = 1 << 20;
+
+struct PfShared {
+    double win[kPfSlots][kPfWin];
+    long long tag[kPfSlots];       // (slice << 32) | first cell of the window; -1 empty
+    long long hist[2];             // (slice << 32) | cell, of the last two slices the chain
+                                   // finished (slice j in hist[j & 1])
+    int done;                      // the chain has ended
+};
+
+__device__ inline double pf_read(const double *w, unsigned k) {
+    return __hip_atomic_load(w + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ inline long long pf_pack(int hi, long long lo) {
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <class T, int Interp>
+__device__ inline void pf_chain(const ComposeArgs &a, PfShared &sh) {
+#pragma clang fp contract(off)
+    const int lane = int(threadIdx.x) & 63;
+    const T *tab0 = static_cast<const T *>(a.tab0);
+    const int n = a.n0;
+    double lam = 0.0, unused = 0.0;
+    if (!range_begin<1>(a, lane, lam, unused)) return;    // an earlier range already failed
+    long long oog = 0;
+    int bad_slice = -1;
+    double keep = 0.0;
+    int jb = a.j_begin;
+    int j = a.j_begin;
+    // nodes the interpolant reads: i0-1 .. i0+2 (Hermite) or i0 .. i0+1 (linear)
+    constexpr int kBelow = Interp == 1 ? 1 : 0, kSpan = Interp == 1 ? 4 : 2;
+    for (; j < a.j_end; ++j) {
+        if (!finite(lam)) {
+            bad_slice = j;
+            break;
+        }
+        // the slot's tag, read while the cell is located; the window's values
+        // are read after it, at addresses that depend on it
+        const unsigned slot = unsigned(j) % kPfSlots;
+        const long long tg =
+            __hip_atomic_load(&sh.tag[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        // the slot's slice and first cell (-1 and -1 for an empty slot)
+        const int tag_slice = int(tg >> 32), base = int(tg & 0xffffffffLL);
+        const double *win = sh.win[slot];
+        long long i0;
+        double w0;
+        oog += locate(a.lo0, a.inv0, n, lam, i0, w0);
+        const int i = int(i0);
+        // a hit needs nodes i-kBelow .. i-kBelow+kSpan-1 inside the window and,
+        // for the Hermite form, a cell away from the row's ends (1 <= i <= n-3),
+        // where both slopes are central; every other case reads global memory
+        const unsigned o = unsigned(i - kBelow - base);
+        const bool hit = tag_slice == j && o <= unsigned(kPfWin - kSpan) &&
+                         (Interp == 0 || i <= n - 3);
+        double next;
+        bool ok;
+        if (hit) {
+            // offsets into the slot; atomic reads keep them LDS reads (a
+            // pointer chosen between LDS and global memory would make them
+            // flat loads)
+            if constexpr (Interp == 1) {
+                const double tm = pf_read(win, o), ta = pf_read(win, o + 1);
+                const double tb = pf_read(win, o + 2), tp = pf_read(win, o + 3);
+                // the weights do not depend on the table: formed while the
+                // reads are in flight (the empty asm keeps them there)
+                HermiteBasis hb = hermite_basis(w0);
+                asm volatile("" : "+v"(hb.h00), "+v"(hb.h10), "+v"(hb.h01), "+v"(hb.h11));
+                const double da = 0.5 * (tb - tm), db = 0.5 * (tp - ta);
+                next = ((hb.h00 * ta + hb.h10 * da) + hb.h01 * tb) + hb.h11 * db;
+                ok = finite(ta) & finite(tb) & finite(da) & finite(db);
+            } else {
+                const double ta = pf_read(win, o), tb = pf_read(win, o + 1);
+                next = ta + w0 * (tb - ta);
+                ok = finite(ta) & finite(tb);
+            }
+        } else {
+            const T *row = tab0 + (long long)j * a.M;
+            ok = interp_1d<Interp>([row](long long k) { return double(row[k]); }, i0, w0, n,
+                                   next);
+        }
+        asm volatile("" : "+v"(next));   // formed before the branch, not after it
+        if (!ok) {
+            bad_slice = j;
+            break;
+        }
+        lam = next;
+        // slice j is done.  Its slot is reused for slice j + kPfSlots, which no
+        // helper fetches before the chain is past slice j + kPfSlots - kPfAhead.
+        if (lane == 0)
+            __hip_atomic_store(&sh.hist[j & 1], pf_pack(j, i0), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (lane == j - jb) keep = lam;
+        if (j - jb == 63) {
+            a.boundary[jb + lane + 1] = keep;
+            jb += 64;
+        }
+    }
+    if (lane < j - jb) a.boundary[jb + lane + 1] = keep;
+    range_end(a, lane, lam, 0.0, oog, bad_slice);
+}
+
+// Helper wave r (1..kPfHelpers) stages slices j_begin + r, j_begin + r + kPfHelpers, ...
+template <class T>
+__device__ inline void pf_helper(const ComposeArgs &a, PfShared &sh, int r) {
+    const int lane = int(threadIdx.x) & 63;
+    const T *tab0 = static_cast<const T *>(a.tab0);
+    const int n = a.n0;
+    const long long top = n > kPfWin ? n - kPfWin : 0;
+    for (int s = a.j_begin + r; s < a.j_end; s += kPfHelpers) {
+        // wait until the chain is within kPfAhead slices of s
+        long long h0 = 0, h1 = 0;
+        int p = 0;                  // the chain has finished every slice before p
+        bool go = false;
+        for (int spin = 0; spin < kPfSpinMax; ++spin) {
+            if (__hip_atomic_load(&sh.done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP))
+                return;
+            h0 = __hip_atomic_load(&sh.hist[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            h1 = __hip_atomic_load(&sh.hist[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            p = int((h0 >> 32) > (h1 >> 32) ? h0 >> 32 : h1 >> 32) + 1;
+            if (p >= s - kPfAhead) {
+                go = true;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (!go) return;            // the chain does not depend on the helpers
+        if (p >= s) continue;       // the chain is already at or past slice s
+        // the latest cell, moved on at the latest rate per slice
+        const bool newer0 = (h0 >> 32) >= (h1 >> 32);
+        const long long hn = newer0 ? h0 : h1, ho = newer0 ? h1 : h0;
+        const long long jn = hn >> 32, in = hn & 0xffffffffLL;
+        const long long jo = ho >> 32, io = ho & 0xffffffffLL;
+        const long long rate = jn - jo == 1 ? in - io : 0;
+        long long base = in + rate * ((long long)s - jn) - kPfWin / 2;
+        base = base < 0 ? 0 : (base > top ? top : base);
+        const T *row = tab0 + (long long)s * a.M;
+        const int slot = s % kPfSlots;
+#pragma unroll
+        for (int q = 0; q < kPfWin / 64; ++q) {
+            // past the row's end (a row shorter than a window) the last value
+            // is read again; the chain never uses those entries
+            const long long k = base + q * 64 + lane;
+            sh.win[slot][q * 64 + lane] = double(row[k < n ? k : n - 1]);
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0)
+            __hip_atomic_store(&sh.tag[slot], pf_pack(s, base), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+// The whole 1-D composition of a range: wave 0 runs the chain, waves
+// 1..kPfHelpers stage windows for it.
+template <class T, int Interp>
+__device__ inline void compose_range_staged(const ComposeArgs &a, PfShared &sh) {
+    const int wave = int(threadIdx.x) >> 6;
+    if (threadIdx.x < kPfSlots) sh.tag[threadIdx.x] = -1;
+    if (threadIdx.x == 0) {
+        // the cell of the range's first state seeds the helpers' prediction
+        const double l = a.j_begin == 0 ? a.y00 : (a.carry ? a.carry[0] : a.y00);
+        long long c;
+        double w;
+        (void)locate(a.lo0, a.inv0, a.n0, l, c, w);
+        // as if the chain had just finished slice j_begin - 1 in that cell
+        sh.hist[0] = sh.hist[1] = pf_pack(a.j_begin - 1, c);
+        sh.done = 0;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        // the chain usually shares its CU with waves of a build still running
+        __builtin_amdgcn_s_setprio(3);
+        pf_chain<T, Interp>(a, sh);
+        if ((threadIdx.x & 63) == 0)
+            __hip_atomic_store(&sh.done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+        pf_helper<T>(a, sh, wave);
     }
 }
 

@@ -28,6 +28,15 @@ __global__ void compose_kernel(ComposeArgs a) {
         compose_range<T, Interp>(a);
 }
 
+// The 1-D chain with its table windows staged in LDS by helper waves: one
+// workgroup of 1 + kPfHelpers waves.
+template <class T, int Interp>
+__global__ __launch_bounds__(64 * (1 + kPfHelpers)) void compose_staged_kernel(ComposeArgs a) {
+    __shared__ PfShared sh;
+    if (blockIdx.x != 0) return;
+    compose_range_staged<T, Interp>(a, sh);
+}
+
 __global__ void locate_kernel(double lo, double inv, int n, const double *x, long long count,
                               long long *cell, double *w, int32_t *out) {
     const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -42,19 +51,19 @@ __global__ void locate_kernel(double lo, double inv, int n, const double *x, lon
 }  // namespace
 
 hipError_t launch_compose(int interp, int precision, const ComposeArgs &a, hipStream_t s) {
-    const dim3 grid(1), block(64);
+    const dim3 grid(1), block(64), staged(64 * (1 + kPfHelpers));
     if (precision == 0) {
         switch (interp) {
-        case 0: hipLaunchKernelGGL((compose_kernel<double, 0>), grid, block, 0, s, a); break;
-        case 1: hipLaunchKernelGGL((compose_kernel<double, 1>), grid, block, 0, s, a); break;
+        case 0: hipLaunchKernelGGL((compose_staged_kernel<double, 0>), grid, staged, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((compose_staged_kernel<double, 1>), grid, staged, 0, s, a); break;
         case 2: hipLaunchKernelGGL((compose_kernel<double, 2>), grid, block, 0, s, a); break;
         case 3: hipLaunchKernelGGL((compose_kernel<double, 3>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
         }
     } else {
         switch (interp) {
-        case 0: hipLaunchKernelGGL((compose_kernel<float, 0>), grid, block, 0, s, a); break;
-        case 1: hipLaunchKernelGGL((compose_kernel<float, 1>), grid, block, 0, s, a); break;
+        case 0: hipLaunchKernelGGL((compose_staged_kernel<float, 0>), grid, staged, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((compose_staged_kernel<float, 1>), grid, staged, 0, s, a); break;
         case 2: hipLaunchKernelGGL((compose_kernel<float, 2>), grid, block, 0, s, a); break;
         case 3: hipLaunchKernelGGL((compose_kernel<float, 3>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;

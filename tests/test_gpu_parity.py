@@ -487,3 +487,19 @@ def test_fp32_accumulation_modes_full_size(orc, torch):
     say("forced cubic fp32 sampled table error by accumulation mode", errs)
     assert errs[1] <= TOL["fp32"] and errs[2] <= TOL["fp32"]
     assert errs[0] > 3 * max(errs[1], errs[2])
+
+
+@pytest.mark.parametrize("interp", ["linear", "hermite"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("y0", [0.05, -0.05, 0.9])
+def test_long_chain_through_edge_cells(orc, prop, interp, precision, y0):
+    # y' = 0.8 y leaves [-1, 1] through its top (y0 > 0) or bottom (y0 < 0)
+    # edge cell after a few hundred of 300 slices, and keeps extrapolating from
+    # it: the chain meets the end-of-row slopes, long runs in one cell, and
+    # every slot of the composition's staged windows many times over
+    w = W.Workload("edge-chain", "linear", (0.8,), 0.0, 6.0, 300, (40,), (-1.0,), (1.0,), 3,
+                   (y0,), precision, interp)
+    prop.build(w)
+    tab = gpu_tables(prop, w)
+    g, o = check_compose_bit_exact(orc, prop, w, tab, w.y0)
+    assert o.n_out_of_grid > 0

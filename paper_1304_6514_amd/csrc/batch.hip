@@ -34,13 +34,15 @@ int step_cost(int rhs) {
 
 template <class R, int A, int P>
 __device__ inline void run_tile(const BuildArgs &a, int rhs, int j, int tile) {
+    unsigned bad = 0;
     switch (rhs) {
-    case NV_RHS_LINEAR: build_tile<RhsLinear<R>, R, 0, A, P>(a, j, tile); break;
-    case NV_RHS_LOGISTIC: build_tile<RhsLogistic<R>, R, 0, A, P>(a, j, tile); break;
-    case NV_RHS_VDP: build_tile<RhsVdp<R>, R, 0, A, P>(a, j, tile); break;
-    case NV_RHS_SQUARE: build_tile<RhsSquare<R>, R, 0, A, P>(a, j, tile); break;
+    case NV_RHS_LINEAR: bad = build_tile<RhsLinear<R>, R, 0, A, P>(a, j, tile); break;
+    case NV_RHS_LOGISTIC: bad = build_tile<RhsLogistic<R>, R, 0, A, P>(a, j, tile); break;
+    case NV_RHS_VDP: bad = build_tile<RhsVdp<R>, R, 0, A, P>(a, j, tile); break;
+    case NV_RHS_SQUARE: bad = build_tile<RhsSquare<R>, R, 0, A, P>(a, j, tile); break;
     default: break;
     }
+    if (bad) atomicAdd(&a.nonfinite[j], bad);      // counters cleared in the graph
 }
 
 template <class R, int A>

@@ -25,8 +25,20 @@ using namespace dev;
 template <class Rhs, class R, int Scheme, int A, int P>
 __global__ void __launch_bounds__(kBuildBlock) build_kernel(BuildArgs a) {
     const int lid = xcd_remap(int(blockIdx.x), a.total_blocks);
-    build_tile<Rhs, R, Scheme, A, P>(a, a.slice0 + lid / a.tiles_per_slice,
-                                     lid % a.tiles_per_slice);
+    const int j = a.slice0 + lid / a.tiles_per_slice;
+    const unsigned bad = build_tile<Rhs, R, Scheme, A, P>(a, j, lid % a.tiles_per_slice);
+    if (a.tiles_per_slice == 1) {
+        // the workgroup is the slice's only one: its sum is the slice's count,
+        // stored outright (the counter needs no clearing before the launch)
+        __shared__ unsigned count;
+        if (threadIdx.x == 0) count = 0;
+        __syncthreads();
+        if (bad) atomicAdd(&count, bad);
+        __syncthreads();
+        if (threadIdx.x == 0) a.nonfinite[j] = count;
+    } else if (bad) {
+        atomicAdd(&a.nonfinite[j], bad);
+    }
 }
 
 // Forcing values of slice j at the stage times of its steps:

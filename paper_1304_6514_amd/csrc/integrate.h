@@ -173,8 +173,10 @@ __device__ inline void end_block(R (&y)[P][D], R (&c)[P][D], R (&z)[P][D]) {
 }
 
 // Integrate and store one tile: 256*P consecutive grid points of slice j.
+// Returns how many non-finite end states (per trajectory: either component)
+// this lane stored.
 template <class Rhs, class R, int Scheme, int A, int P>
-__device__ inline void build_tile(const BuildArgs &a, int j, int tile) {
+__device__ inline unsigned build_tile(const BuildArgs &a, int j, int tile) {
     constexpr int D = Rhs::dim;
     const long long base = (long long)tile * (kBuildBlock * P) + threadIdx.x;
 
@@ -230,7 +232,7 @@ __device__ inline void build_tile(const BuildArgs &a, int j, int tile) {
             }
         }
     }
-    if (bad) atomicAdd(&a.nonfinite[j], bad);
+    return bad;
 }
 
 }  // namespace dev

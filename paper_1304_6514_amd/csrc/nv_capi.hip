@@ -422,10 +422,13 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
         // the place where an earlier build kept its nodes
         ctx->nodes_dev = nullptr;
     }
+    // the per-slice non-finite counters: with one workgroup per slice the build
+    // stores them outright; otherwise its workgroups add to them, and they are
+    // cleared first (by the forcing kernel when there is one)
     if (a.forcing)
         NV_HIP(nv::launch_forcing(rhs_id, ctx->opt.precision, work_at(ctx, p.forcing_off),
                                   n_slices, steps_per_slice, t0, L, h, a.nonfinite, st));
-    else
+    else if (p.tiles_per_slice > 1)
         NV_HIP(nv::launch_fill_u32(a.nonfinite, n_slices, 0u, st));
 
     ctx->plan = p;

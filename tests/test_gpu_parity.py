@@ -183,7 +183,8 @@ def _adversarial_queries(lo, hi, n, rng):
 
 
 @pytest.mark.parametrize("lo,hi,n", [(-3.0, 3.0, 4096), (-0.1, 1.2, 256), (-8.0, 8.0, 128),
-                                     (0.1, 0.7, 2), (-1.0 / 3.0, 2.0 / 7.0, 1001)])
+                                     (0.1, 0.7, 2), (-1.0 / 3.0, 2.0 / 7.0, 1001),
+                                     (0.0, 2.0, 64)])   # lo = +0: the query -0.0 gives u = -0.0
 def test_locate_bit_exact(orc, prop, torch, lo, hi, n):
     say("locate", lo, hi, n)
     x = _adversarial_queries(lo, hi, n, np.random.default_rng(n))

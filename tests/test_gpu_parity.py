@@ -504,3 +504,40 @@ def test_long_chain_through_edge_cells(orc, prop, interp, precision, y0):
     tab = gpu_tables(prop, w)
     g, o = check_compose_bit_exact(orc, prop, w, tab, w.y0)
     assert o.n_out_of_grid > 0
+
+
+@pytest.mark.parametrize("w", [
+    W.Workload("multi-tile-fcub", "forced_cubic", (), 0.0, 6.0, 300, (4000,), (-3.0,), (3.0,),
+               20, (1.0,), "fp32", "hermite"),
+    W.Workload("multi-tile-logistic", "logistic", (), 0.0, 3.0, 200, (2600,), (-0.1,), (1.2,),
+               15, (0.1,), "fp64", "linear"),
+    # y' = y^2 blows up inside a slice from xi > 1/L: non-finite counts under the counters
+    W.Workload("multi-tile-blowup", "square", (), 0.0, 1.0, 250, (3000,), (0.0,), (400.0,), 12,
+               (0.3,), "fp64", "linear"),
+], ids=lambda w: w.name)
+def test_single_launch_equals_chunked_launches(orc, torch, w):
+    # more tiles than one round of workgroups, several tiles per slice: one build launch
+    # over the workload against nv_solve's chunks on two streams, tables and non-finite
+    # counts bit for bit, and sampled entries against the oracle
+    from paper_1304_6514_amd.propagator import Propagator
+    say("one launch vs chunks", w.name, w.n_slices, w.grid_n, w.steps_per_slice)
+    with Propagator("cuda:0") as one, Propagator("cuda:0", solve_chunks=8) as chunked:
+        one.build(w)
+        t1, c1 = one.table(0), one.nonfinite_counts()
+        chunked.solve(w, want_boundary=False)
+        t8, c8 = chunked.table(0), chunked.nonfinite_counts()
+    assert np.array_equal(t1.view(np.uint8), t8.view(np.uint8))
+    assert np.array_equal(c1, c8)
+    ss, kk = W.sample_entries(w, 400, seed=7)
+    ref = orc.table_entries(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, ogrid(orc, w),
+                            w.steps_per_slice, ss, kk)[0]
+    got = t1[ss, kk].astype(np.float64)
+    # far from overflow both sides agree on finiteness
+    assert np.all(np.isfinite(got)[np.abs(np.nan_to_num(ref, nan=np.inf)) < 1e100])
+    # near the blow-up the slice map amplifies one rounding by (dy/dxi) ~ (y/xi)^2, so the
+    # entries compared at the FP64 tolerance are those well away from it
+    fin = np.isfinite(ref) & np.isfinite(got) & (np.abs(ref) <= 1e4)
+    assert fin.sum() > 100
+    assert mixed_err(got[fin], ref[fin]) <= TOL[w.precision]
+    if w.rhs == "square":
+        assert c1.sum() > 0 and c1.sum() == np.count_nonzero(~np.isfinite(t1))

@@ -30,6 +30,12 @@ __device__ inline int locate(double lo, double inv, int n, double x, long long &
 
 __device__ inline bool finite(double v) { return isfinite(v); }
 
+// The lanes of the wave on which v is not finite (one class test, its result
+// left in a scalar register pair).
+__device__ inline unsigned long long any_nonfinite(double v) {
+    return __builtin_amdgcn_ballot_w64(!isfinite(v));
+}
+
 // The 1-D interpolants of one slice at cell i0, local coordinate w0: linear
 // (Interp 0) or cubic Hermite (Interp 1) with Delta-xi times the slope at node
 // i taken by finite differences, (t[i+1] - t[i-1])/2 inside the row and the
@@ -183,8 +189,13 @@ __device__ inline void compose_range(const ComposeArgs &a, double *final_out = n
             const double p10 = double(row0[c10]), p11 = double(row0[c10 + 1]);
             const double q00 = double(row1[c00]), q01 = double(row1[c00 + 1]);
             const double q10 = double(row1[c10]), q11 = double(row1[c10 + 1]);
-            bad = !finite(p00) || !finite(p01) || !finite(p10) || !finite(p11) ||
-                  !finite(q00) || !finite(q01) || !finite(q10) || !finite(q11);
+            // the eight class tests as wave masks ORed in scalar registers (every
+            // lane holds the same values); written as plain boolean logic the
+            // compiler packs them into a vector bit mask, several instructions
+            // per entry
+            bad = (any_nonfinite(p00) | any_nonfinite(p01) | any_nonfinite(p10) |
+                   any_nonfinite(p11) | any_nonfinite(q00) | any_nonfinite(q01) |
+                   any_nonfinite(q10) | any_nonfinite(q11)) != 0;
             const double r0 = p00 + w1 * (p01 - p00), r1 = p10 + w1 * (p11 - p10);
             const double s0 = q00 + w1 * (q01 - q00), s1 = q10 + w1 * (q11 - q10);
             next0 = r0 + w0 * (r1 - r0);

@@ -21,8 +21,10 @@
  *     pointers are GPU memory on the context's device.
  *   - A context is not thread-safe: one thread drives it at a time.
  *   - All kernels of a context run on its stream (nv_options.stream).  The
- *     build is asynchronous with respect to the host; nv_compose and the
- *     copy-out calls synchronize the stream before returning.
+ *     build is asynchronous with respect to the host.  nv_compose and nv_solve
+ *     return once the composition has written its outputs into host memory
+ *     (the kernel's own exit may still be queued; it is ordered before later
+ *     work on the stream); the copy-out calls synchronize the stream.
  *   - Floating-point parameters and time values are IEEE binary64.
  */
 #ifndef NV_H

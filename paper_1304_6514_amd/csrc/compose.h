@@ -122,7 +122,7 @@ __device__ inline bool range_begin(const ComposeArgs &a, int lane, double &l0, d
 }
 
 // The end of a range: the running status, the carried state and, when the
-// chain ends here, a copy of the final status.
+// chain ends here, a copy of the final status whose done flag is written last.
 __device__ inline void range_end(const ComposeArgs &a, int lane, double l0, double l1,
                                  long long oog, int bad_slice) {
     if (lane != 0) return;
@@ -138,7 +138,10 @@ __device__ inline void range_end(const ComposeArgs &a, int lane, double l0, doub
     if (last && a.status_host) {
         a.status_host->n_out_of_grid = total;
         a.status_host->bad_slice = bad_slice;
-        a.status_host->done = 1;
+        // the wave's boundary states and the two fields above reach host memory
+        // before the flag that the host polls
+        __threadfence_system();
+        __hip_atomic_store(&a.status_host->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 

@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -470,15 +471,45 @@ nv::ComposeArgs compose_args(const nv_ctx *ctx, const double *y0, int j0, int j1
     return a;
 }
 
-// Wait for stream st, whose composition wrote the boundary states and the
-// status straight into the context's mapped host memory, and hand them out.
+volatile nv::ComposeStatus *host_status(const nv_ctx *ctx) {
+    return reinterpret_cast<volatile nv::ComposeStatus *>(static_cast<char *>(ctx->host_stage) +
+                                                          ctx->plan.stage_status_off);
+}
+
+// Cleared before a composition is launched; its last range sets it once the
+// outputs are in host memory.
+void clear_host_done(const nv_ctx *ctx) { host_status(ctx)->done = 0; }
+
+// Wait until the composition on stream st has written the boundary states and
+// the status into the context's mapped host memory, and hand them out.  The
+// chain's last range sets the status's done flag after a system-scope fence,
+// so the host polls that flag instead of waiting for the stream's completion
+// signal (the kernel's exit, still queued on the stream, is ordered before any
+// later work on it).  The stream is queried now and then, so a launch that
+// fails or ends without the flag ends the wait: the stream is then
+// synchronized, which reports its error.
 nv_status finish_compose(nv_ctx *ctx, hipStream_t st, double *yT, double *boundary,
                          nv_compose_info *info, int n_chunks) {
     const Plan &p = ctx->plan;
-    NV_HIP(hipStreamSynchronize(st));
+    volatile nv::ComposeStatus *hs = host_status(ctx);
+    bool seen = false;
+    for (unsigned n = 1;; ++n) {
+        if (hs->done) {
+            seen = true;
+            break;
+        }
+        if ((n & 1023u) == 0 && hipStreamQuery(st) != hipErrorNotReady) {
+            seen = hs->done != 0;
+            break;
+        }
+    }
+    if (!seen) NV_HIP(hipStreamSynchronize(st));
+    std::atomic_thread_fence(std::memory_order_acquire);
     const double *hb = static_cast<const double *>(ctx->host_stage);
     nv::ComposeStatus cs;
-    std::memcpy(&cs, static_cast<const char *>(ctx->host_stage) + p.stage_status_off, sizeof cs);
+    cs.n_out_of_grid = hs->n_out_of_grid;
+    cs.bad_slice = hs->bad_slice;
+    cs.done = hs->done;
     if (!cs.done) return fail(NV_ERR_HIP, "composition kernel did not complete");
     const int n_done = cs.bad_slice < 0 ? ctx->n_slices : cs.bad_slice;
     if (boundary) std::memcpy(boundary, hb, size_t(n_done + 1) * p.dim * sizeof(double));
@@ -616,6 +647,7 @@ NV_API nv_status nv_compose(nv_ctx *ctx, const double *y0, double *yT, double *b
         if (s != NV_OK) return s;
         NV_HIP(hipEventRecord(ctx->ev[2], st));
     }
+    clear_host_done(ctx);
     NV_HIP(nv::launch_compose(ctx->grid.interp, ctx->precision,
                               compose_args(ctx, y0, 0, ctx->n_slices), st));
     if (ctx->timing) {
@@ -652,6 +684,7 @@ NV_API nv_status nv_solve(nv_ctx *ctx, int rhs_id, const double *params, double 
         if (ctx->timing) NV_HIP(hipEventRecord(ctx->ev[0], st));
         NV_HIP(nv::launch_build(pb.cfg, pb.args, st));
         if (ctx->timing) NV_HIP(hipEventRecord(ctx->ev[1], st));
+        clear_host_done(ctx);
         NV_HIP(nv::launch_compose(ctx->grid.interp, ctx->precision,
                                   compose_args(ctx, y0, 0, n_slices), st));
         if (ctx->timing) {
@@ -690,6 +723,7 @@ NV_API nv_status nv_solve(nv_ctx *ctx, int rhs_id, const double *params, double 
     if (chunks > 1) NV_HIP(hipStreamWaitEvent(st, ctx->chunk_ev[chunks % 2 == 0 ? chunks - 1
                                                                             : chunks - 2], 0));
     if (ctx->timing) NV_HIP(hipEventRecord(ctx->ev[1], st));
+    clear_host_done(ctx);
     for (int c = 0; c < chunks; ++c) {
         const int j0 = c * per, j1 = (j0 + per <= n_slices ? j0 + per : n_slices);
         NV_HIP(hipStreamWaitEvent(aux, ctx->chunk_ev[c], 0));

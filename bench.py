@@ -482,7 +482,7 @@ def bench_surrogate(args):
             plain.append({"grid": n, "max_error": max(errs), "errors": errs,
                           "ms_per_mu": round(float(np.mean(ms)), 3),
                           "table_bytes": base.n_slices * n * n * 2 * 4})
-        # the network with the 128 x 128 table of the first mu as fallback and judge
+        # the network with the 128 x 128 table of the first mu as fallback and check
         wf = base.with_(params=(float(mus[0]),))
         pr.build(wf)
         torch.cuda.synchronize()

@@ -6,7 +6,7 @@
  * is the only sequential part.  This interface trains a small network on the
  * endpoints that the computation phase itself tabulates, and runs the
  * composition with the network in place of the table lookup; a built table
- * stays available as the fallback and as the judge of the network's error.
+ * stays available as the fallback and as the check on the network's error.
  *
  * The network (one per nv_sur), for x = (y1, y2, t, mu), t the slice start
  * time T_j and mu the Van der Pol parameter:
@@ -139,7 +139,7 @@ NV_API nv_status nv_sur_dataset_from_batch(nv_sur *sur, nv_batch *batch,
  * T_j = t0 + j (T - t0) / N, the state kept in FP64; (T - t0) / N must equal
  * the configured slice_length (relative 1e-9).
  *
- * Fallback and judge: when fb_tab0 is not NULL, (fb_tab0, fb_tab1) are the
+ * Fallback and check: when fb_tab0 is not NULL, (fb_tab0, fb_tab1) are the
  * two component tables of a built Van der Pol context for the same mu, t0, T
  * and N (nv_table_device_ptr; layout tab[j][k], fb_precision NV_FP32 or
  * NV_FP64, bilinear grid fb_grid).  Each step then also evaluates the table's

@@ -511,6 +511,11 @@ nv_status finish_compose(nv_ctx *ctx, hipStream_t st, double *yT, double *bounda
     cs.bad_slice = hs->bad_slice;
     cs.done = hs->done;
     if (!cs.done) return fail(NV_ERR_HIP, "composition kernel did not complete");
+    // a range that fails sets the flag while the later ranges of an nv_solve
+    // may still be queued (each returns at once on seeing the failure); they
+    // are drained here, before a later call can reset the running status they
+    // read
+    if (cs.bad_slice >= 0) NV_HIP(hipStreamSynchronize(st));
     const int n_done = cs.bad_slice < 0 ? ctx->n_slices : cs.bad_slice;
     if (boundary) std::memcpy(boundary, hb, size_t(n_done + 1) * p.dim * sizeof(double));
     for (int c = 0; c < p.dim; ++c) yT[c] = hb[size_t(n_done) * p.dim + c];

@@ -541,3 +541,26 @@ def test_single_launch_equals_chunked_launches(orc, torch, w):
     assert mixed_err(got[fin], ref[fin]) <= TOL[w.precision]
     if w.rhs == "square":
         assert c1.sum() > 0 and c1.sum() == np.count_nonzero(~np.isfinite(t1))
+
+
+def test_failed_chunked_solve_then_compose_and_solve(orc, torch):
+    # y' = y^2 from 0.3 blows up at t = 10/3: the chain fails in the third of eight
+    # chunks while the later chunks' compositions are still queued; a composition on
+    # the context's stream right after, and a second solve, must see none of them
+    from paper_1304_6514_amd.propagator import Propagator
+    w = W.Workload("square-fail-mid", "square", (), 0.0, 12.0, 48, (64,), (0.0,), (8.0,), 50,
+                   (0.3,), "fp64", "linear")
+    say("failed chunked solve, then compose and solve")
+    with Propagator("cuda:0", solve_chunks=8) as b:
+        r = b.solve(w)
+        g = b.compose((0.01,))
+        tab = gpu_tables(b, w)
+        r2 = b.solve(w, y0=(-0.5,))
+    o = orc.compose_tables(ogrid(orc, w), w.interp, tab, w.y0)
+    assert o.status == orc.NONFINITE and 6 <= o.bad_slice < 42
+    assert r.status == nv.NV_ERR_NONFINITE and r.bad_slice == o.bad_slice
+    for res, y0 in ((g, (0.01,)), (r2, (-0.5,))):
+        o = orc.compose_tables(ogrid(orc, w), w.interp, tab, y0)
+        assert o.status == 0 and res.status == nv.NV_OK
+        assert np.array_equal(res.boundary.view(np.int64), o.boundary.view(np.int64))
+        assert res.n_out_of_grid == o.n_out_of_grid

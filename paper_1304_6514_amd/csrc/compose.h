@@ -83,6 +83,26 @@ __device__ inline bool interp_1d_values(double tm, double ta, double tb, double 
     }
 }
 
+// The bilinear interpolant of the two components from the corner values
+// p (component 0) and q (component 1) of cell (i0, i1), local coordinates
+// (w0, w1).  Returns true when a corner value is not finite.  The eight class
+// tests are wave masks ORed in scalar registers (every lane holds the same
+// values); written as plain boolean logic the compiler packs them into a
+// vector bit mask, several instructions per entry.
+__device__ inline bool bilinear_values(double p00, double p01, double p10, double p11,
+                                       double q00, double q01, double q10, double q11,
+                                       double w0, double w1, double &next0, double &next1) {
+#pragma clang fp contract(off)
+    const bool bad = (any_nonfinite(p00) | any_nonfinite(p01) | any_nonfinite(p10) |
+                      any_nonfinite(p11) | any_nonfinite(q00) | any_nonfinite(q01) |
+                      any_nonfinite(q10) | any_nonfinite(q11)) != 0;
+    const double r0 = p00 + w1 * (p01 - p00), r1 = p10 + w1 * (p11 - p10);
+    const double s0 = q00 + w1 * (q01 - q00), s1 = q10 + w1 * (q11 - q10);
+    next0 = r0 + w0 * (r1 - r0);
+    next1 = s0 + w0 * (s1 - s0);
+    return bad;
+}
+
 // Nodes i0-1 (clamped to 0) and i0+2 (clamped to n-1) for the Hermite form.
 __device__ inline long long node_below(long long i0) { return i0 > 0 ? i0 - 1 : 0; }
 __device__ inline long long node_above(long long i0, int n) { return i0 + 2 < n ? i0 + 2 : n - 1; }
@@ -192,17 +212,7 @@ __device__ inline void compose_range(const ComposeArgs &a, double *final_out = n
             const double p10 = double(row0[c10]), p11 = double(row0[c10 + 1]);
             const double q00 = double(row1[c00]), q01 = double(row1[c00 + 1]);
             const double q10 = double(row1[c10]), q11 = double(row1[c10 + 1]);
-            // the eight class tests as wave masks ORed in scalar registers (every
-            // lane holds the same values); written as plain boolean logic the
-            // compiler packs them into a vector bit mask, several instructions
-            // per entry
-            bad = (any_nonfinite(p00) | any_nonfinite(p01) | any_nonfinite(p10) |
-                   any_nonfinite(p11) | any_nonfinite(q00) | any_nonfinite(q01) |
-                   any_nonfinite(q10) | any_nonfinite(q11)) != 0;
-            const double r0 = p00 + w1 * (p01 - p00), r1 = p10 + w1 * (p11 - p10);
-            const double s0 = q00 + w1 * (q01 - q00), s1 = q10 + w1 * (q11 - q10);
-            next0 = r0 + w0 * (r1 - r0);
-            next1 = s0 + w0 * (s1 - s0);
+            bad = bilinear_values(p00, p01, p10, p11, q00, q01, q10, q11, w0, w1, next0, next1);
         }
         if (bad) {
             bad_slice = j;
@@ -430,6 +440,200 @@ __device__ inline void compose_range_staged(const ComposeArgs &a, PfShared &sh) 
             __hip_atomic_store(&sh.done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
         pf_helper<T>(a, sh, wave);
+    }
+}
+
+// The bilinear (2-D) chain with staged windows, as the 1-D one above: a window
+// is 16 x 16 grid cells' corner values of both table components of a coming
+// slice, around the chain's predicted cell on each axis, fetched kPf2Ahead
+// slices ahead (the state moves farther per slice, so the prediction reaches
+// less far: on the Van der Pol workload 2 slices ahead measured best, 0.45 us
+// per slice against 0.47, 0.48 and 0.51 us at 3, 4 and 6).  Cells and window origins are packed 16 bits per axis, so the path
+// serves grids of at most 65,536 points per axis; larger ones take the plain
+// chain.
+constexpr int kPf2Side = 16;                 // window cells per axis
+constexpr int kPf2Win = kPf2Side * kPf2Side;
+constexpr int kPf2Ahead = 2;
+constexpr int kPf2Slots = 15;                // the ring within 64 KB of LDS
+constexpr int kPf2MaxAxis = 65536;
+
+struct PfShared2 {
+    double win[kPf2Slots][2][kPf2Win];       // [slot][component][row * 16 + column]
+    long long tag[kPf2Slots];                // (slice << 32) | (base0 << 16) | base1; -1 empty
+    long long hist[2];                       // (slice << 32) | (cell0 << 16) | cell1 of the
+                                             // last two slices the chain finished
+    int done;
+};
+
+template <class T>
+__device__ inline void pf2_chain(const ComposeArgs &a, PfShared2 &sh) {
+#pragma clang fp contract(off)
+    const int lane = int(threadIdx.x) & 63;
+    const T *tab0 = static_cast<const T *>(a.tab0);
+    const T *tab1 = static_cast<const T *>(a.tab1);
+    double lam0 = 0.0, lam1 = 0.0;
+    if (!range_begin<2>(a, lane, lam0, lam1)) return;     // an earlier range already failed
+    long long oog = 0;
+    int bad_slice = -1;
+    double keep0 = 0.0, keep1 = 0.0;
+    int jb = a.j_begin;
+    int j = a.j_begin;
+    for (; j < a.j_end; ++j) {
+        if (!finite(lam0) || !finite(lam1)) {
+            bad_slice = j;
+            break;
+        }
+        const unsigned slot = unsigned(j) % kPf2Slots;
+        const long long tg =
+            __hip_atomic_load(&sh.tag[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int tag_slice = int(tg >> 32);
+        const int b0 = int((tg >> 16) & 0xffff), b1 = int(tg & 0xffff);
+        long long i0, i1;
+        double w0, w1;
+        oog += locate(a.lo0, a.inv0, a.n0, lam0, i0, w0);
+        oog += locate(a.lo1, a.inv1, a.n1, lam1, i1, w1);
+        // a hit needs cells i0, i0+1 and i1, i1+1 inside the window
+        const unsigned o0 = unsigned(int(i0) - b0), o1 = unsigned(int(i1) - b1);
+        const bool hit = tag_slice == j && o0 <= unsigned(kPf2Side - 2) &&
+                         o1 <= unsigned(kPf2Side - 2);
+        double p00, p01, p10, p11, q00, q01, q10, q11;
+        if (hit) {
+            const double *u = sh.win[slot][0], *v = sh.win[slot][1];
+            const unsigned e = o0 * kPf2Side + o1;
+            p00 = pf_read(u, e);
+            p01 = pf_read(u, e + 1);
+            p10 = pf_read(u, e + kPf2Side);
+            p11 = pf_read(u, e + kPf2Side + 1);
+            q00 = pf_read(v, e);
+            q01 = pf_read(v, e + 1);
+            q10 = pf_read(v, e + kPf2Side);
+            q11 = pf_read(v, e + kPf2Side + 1);
+        } else {
+            const long long c00 = i0 * a.n1 + i1, c10 = (i0 + 1) * a.n1 + i1;
+            const T *row0 = tab0 + (long long)j * a.M, *row1 = tab1 + (long long)j * a.M;
+            p00 = double(row0[c00]);
+            p01 = double(row0[c00 + 1]);
+            p10 = double(row0[c10]);
+            p11 = double(row0[c10 + 1]);
+            q00 = double(row1[c00]);
+            q01 = double(row1[c00 + 1]);
+            q10 = double(row1[c10]);
+            q11 = double(row1[c10 + 1]);
+        }
+        double next0, next1;
+        const bool bad =
+            bilinear_values(p00, p01, p10, p11, q00, q01, q10, q11, w0, w1, next0, next1);
+        asm volatile("" : "+v"(next0), "+v"(next1));   // formed before the branch
+        if (bad) {
+            bad_slice = j;
+            break;
+        }
+        lam0 = next0;
+        lam1 = next1;
+        // slice j is done (its slot is reused for slice j + kPf2Slots, which no
+        // helper fetches before the chain is past slice j + kPf2Slots - kPf2Ahead)
+        if (lane == 0)
+            __hip_atomic_store(&sh.hist[j & 1], pf_pack(j, (i0 << 16) | i1), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (lane == j - jb) {
+            keep0 = lam0;
+            keep1 = lam1;
+        }
+        if (j - jb == 63) {
+            a.boundary[(long long)(jb + lane + 1) * 2] = keep0;
+            a.boundary[(long long)(jb + lane + 1) * 2 + 1] = keep1;
+            jb += 64;
+        }
+    }
+    if (lane < j - jb) {
+        a.boundary[(long long)(jb + lane + 1) * 2] = keep0;
+        a.boundary[(long long)(jb + lane + 1) * 2 + 1] = keep1;
+    }
+    range_end(a, lane, lam0, lam1, oog, bad_slice);
+}
+
+// Helper wave r (1..kPfHelpers) stages slices j_begin + r, j_begin + r + kPfHelpers, ...
+template <class T>
+__device__ inline void pf2_helper(const ComposeArgs &a, PfShared2 &sh, int r) {
+    const int lane = int(threadIdx.x) & 63;
+    const T *tab0 = static_cast<const T *>(a.tab0);
+    const T *tab1 = static_cast<const T *>(a.tab1);
+    const int n0 = a.n0, n1 = a.n1;
+    const long long top0 = n0 > kPf2Side ? n0 - kPf2Side : 0;
+    const long long top1 = n1 > kPf2Side ? n1 - kPf2Side : 0;
+    for (int s = a.j_begin + r; s < a.j_end; s += kPfHelpers) {
+        long long h0 = 0, h1 = 0;
+        int p = 0;                  // the chain has finished every slice before p
+        bool go = false;
+        for (int spin = 0; spin < kPfSpinMax; ++spin) {
+            if (__hip_atomic_load(&sh.done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP))
+                return;
+            h0 = __hip_atomic_load(&sh.hist[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            h1 = __hip_atomic_load(&sh.hist[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            p = int((h0 >> 32) > (h1 >> 32) ? h0 >> 32 : h1 >> 32) + 1;
+            if (p >= s - kPf2Ahead) {
+                go = true;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (!go) return;            // the chain does not depend on the helpers
+        if (p >= s) continue;       // the chain is already at or past slice s
+        // each axis's latest cell, moved on at its latest rate per slice
+        const bool newer0 = (h0 >> 32) >= (h1 >> 32);
+        const long long hn = newer0 ? h0 : h1, ho = newer0 ? h1 : h0;
+        const long long jn = hn >> 32, jo = ho >> 32;
+        const long long cn0 = (hn >> 16) & 0xffff, cn1 = hn & 0xffff;
+        const long long co0 = (ho >> 16) & 0xffff, co1 = ho & 0xffff;
+        const bool consecutive = jn - jo == 1;
+        const long long ds = (long long)s - jn;
+        long long base0 = cn0 + (consecutive ? cn0 - co0 : 0) * ds - (kPf2Side / 2 - 1);
+        long long base1 = cn1 + (consecutive ? cn1 - co1 : 0) * ds - (kPf2Side / 2 - 1);
+        base0 = base0 < 0 ? 0 : (base0 > top0 ? top0 : base0);
+        base1 = base1 < 0 ? 0 : (base1 > top1 ? top1 : base1);
+        const T *row0 = tab0 + (long long)s * a.M, *row1 = tab1 + (long long)s * a.M;
+        const int slot = s % kPf2Slots;
+#pragma unroll
+        for (int q = 0; q < kPf2Win / 64; ++q) {
+            // past the grid's end (an axis shorter than a window) the last cell
+            // is read again; the chain never uses those entries
+            const int e = q * 64 + lane;
+            const long long k0 = base0 + e / kPf2Side, k1 = base1 + e % kPf2Side;
+            const long long k = (k0 < n0 ? k0 : n0 - 1) * n1 + (k1 < n1 ? k1 : n1 - 1);
+            sh.win[slot][0][e] = double(row0[k]);
+            sh.win[slot][1][e] = double(row1[k]);
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0)
+            __hip_atomic_store(&sh.tag[slot], pf_pack(s, (base0 << 16) | base1),
+                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+template <class T>
+__device__ inline void compose_range_staged2(const ComposeArgs &a, PfShared2 &sh) {
+    const int wave = int(threadIdx.x) >> 6;
+    if (threadIdx.x < kPf2Slots) sh.tag[threadIdx.x] = -1;
+    if (threadIdx.x == 0) {
+        // the cells of the range's first state seed the helpers' prediction
+        const bool first = a.j_begin == 0 || !a.carry;
+        const double l0 = first ? a.y00 : a.carry[0], l1 = first ? a.y01 : a.carry[1];
+        long long c0, c1;
+        double w;
+        (void)locate(a.lo0, a.inv0, a.n0, l0, c0, w);
+        (void)locate(a.lo1, a.inv1, a.n1, l1, c1, w);
+        // as if the chain had just finished slice j_begin - 1 in that cell
+        sh.hist[0] = sh.hist[1] = pf_pack(a.j_begin - 1, (c0 << 16) | c1);
+        sh.done = 0;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        __builtin_amdgcn_s_setprio(3);
+        pf2_chain<T>(a, sh);
+        if ((threadIdx.x & 63) == 0)
+            __hip_atomic_store(&sh.done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+        pf2_helper<T>(a, sh, wave);
     }
 }
 

@@ -37,6 +37,15 @@ __global__ __launch_bounds__(64 * (1 + kPfHelpers)) void compose_staged_kernel(C
     compose_range_staged<T, Interp>(a, sh);
 }
 
+// The bilinear chain with its windows staged in LDS: one workgroup of
+// 1 + kPfHelpers waves.
+template <class T>
+__global__ __launch_bounds__(64 * (1 + kPfHelpers)) void compose_staged2_kernel(ComposeArgs a) {
+    __shared__ PfShared2 sh;
+    if (blockIdx.x != 0) return;
+    compose_range_staged2<T>(a, sh);
+}
+
 __global__ void locate_kernel(double lo, double inv, int n, const double *x, long long count,
                               long long *cell, double *w, int32_t *out) {
     const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -52,11 +61,18 @@ __global__ void locate_kernel(double lo, double inv, int n, const double *x, lon
 
 hipError_t launch_compose(int interp, int precision, const ComposeArgs &a, hipStream_t s) {
     const dim3 grid(1), block(64), staged(64 * (1 + kPfHelpers));
+    // cells and window origins of the staged bilinear chain are packed 16 bits per axis
+    const bool staged2 = a.n0 <= kPf2MaxAxis && a.n1 <= kPf2MaxAxis;
     if (precision == 0) {
         switch (interp) {
         case 0: hipLaunchKernelGGL((compose_staged_kernel<double, 0>), grid, staged, 0, s, a); break;
         case 1: hipLaunchKernelGGL((compose_staged_kernel<double, 1>), grid, staged, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((compose_kernel<double, 2>), grid, block, 0, s, a); break;
+        case 2:
+            if (staged2)
+                hipLaunchKernelGGL((compose_staged2_kernel<double>), grid, staged, 0, s, a);
+            else
+                hipLaunchKernelGGL((compose_kernel<double, 2>), grid, block, 0, s, a);
+            break;
         case 3: hipLaunchKernelGGL((compose_kernel<double, 3>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
         }
@@ -64,7 +80,12 @@ hipError_t launch_compose(int interp, int precision, const ComposeArgs &a, hipSt
         switch (interp) {
         case 0: hipLaunchKernelGGL((compose_staged_kernel<float, 0>), grid, staged, 0, s, a); break;
         case 1: hipLaunchKernelGGL((compose_staged_kernel<float, 1>), grid, staged, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((compose_kernel<float, 2>), grid, block, 0, s, a); break;
+        case 2:
+            if (staged2)
+                hipLaunchKernelGGL((compose_staged2_kernel<float>), grid, staged, 0, s, a);
+            else
+                hipLaunchKernelGGL((compose_kernel<float, 2>), grid, block, 0, s, a);
+            break;
         case 3: hipLaunchKernelGGL((compose_kernel<float, 3>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
         }

@@ -22,42 +22,67 @@ namespace nv {
 namespace {
 using namespace dev;
 
+// The workgroup's count of non-finite end states, stored in its tile's own
+// word (the host sums a slice's tiles), so no counter is cleared before a
+// build.
+__device__ inline void store_tile_count(const BuildArgs &a, int j, int tile, unsigned bad) {
+    __shared__ unsigned count;
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+    if (bad) atomicAdd(&count, bad);
+    __syncthreads();
+    if (threadIdx.x == 0) a.nonfinite[(long long)j * a.tiles_per_slice + tile] = count;
+}
+
+// Entry m of slice j's forcing row: the right-hand side's forcing at
+// T_j + (m/2) h, plus h/2 for odd m (the step's start, midpoint and end times),
+// in FP64, rounded once.
+template <class R>
+__device__ inline R forcing_entry(int rhs, double Tj, long long m, double h) {
+#pragma clang fp contract(off)
+    double t = Tj + double(m >> 1) * h;
+    if (m & 1) t = t + h / 2.0;
+    return R(forcing_value(rhs, t));
+}
+
 template <class Rhs, class R, int Scheme, int A, int P>
 __global__ void __launch_bounds__(kBuildBlock) build_kernel(BuildArgs a) {
     const int lid = xcd_remap(int(blockIdx.x), a.total_blocks);
-    const int j = a.slice0 + lid / a.tiles_per_slice;
-    const unsigned bad = build_tile<Rhs, R, Scheme, A, P>(a, j, lid % a.tiles_per_slice);
-    if (a.tiles_per_slice == 1) {
-        // the workgroup is the slice's only one: its sum is the slice's count,
-        // stored outright (the counter needs no clearing before the launch)
-        __shared__ unsigned count;
-        if (threadIdx.x == 0) count = 0;
-        __syncthreads();
-        if (bad) atomicAdd(&count, bad);
-        __syncthreads();
-        if (threadIdx.x == 0) a.nonfinite[j] = count;
-    } else if (bad) {
-        atomicAdd(&a.nonfinite[j], bad);
-    }
+    const int j = a.slice0 + lid / a.tiles_per_slice, tile = lid % a.tiles_per_slice;
+    const unsigned bad = build_tile<Rhs, R, Scheme, A, P>(a, j, tile);
+    store_tile_count(a, j, tile, bad);
+}
+
+// The same for small builds of a right-hand side with forcing: each workgroup
+// forms its slice's forcing row in LDS (dynamic, 2 steps + 1 values) before
+// integrating, so no forcing launch precedes the build.  The values are those
+// of forcing_kernel, entry for entry.
+template <class Rhs, class R, int Scheme, int A, int P>
+__global__ void __launch_bounds__(kBuildBlock) build_local_forcing_kernel(BuildArgs a) {
+    extern __shared__ unsigned char forcing_lds[];
+    R *F = reinterpret_cast<R *>(forcing_lds);
+    const int lid = xcd_remap(int(blockIdx.x), a.total_blocks);
+    const int j = a.slice0 + lid / a.tiles_per_slice, tile = lid % a.tiles_per_slice;
+    const long long per = 2LL * a.steps + 1;
+    const double Tj = a.t0 + double(j) * a.L;
+    for (long long m = threadIdx.x; m < per; m += kBuildBlock)
+        F[m] = forcing_entry<R>(Rhs::rhs_id, Tj, m, a.h);
+    __syncthreads();
+    const unsigned bad = build_tile_rows<Rhs, R, Scheme, A, P>(a, j, tile, F);
+    store_tile_count(a, j, tile, bad);
 }
 
 // Forcing values of slice j at the stage times of its steps:
 // F[j][2s] = g(T_j + s h), F[j][2s+1] = g((T_j + s h) + h/2), F[j][2S] = g(T_j + S h).
 template <class R>
 __global__ void forcing_kernel(int rhs, R *F, int n_slices, int steps, double t0, double L,
-                               double h, uint32_t *nonfinite) {
+                               double h) {
 #pragma clang fp contract(off)
     const long long per = 2LL * steps + 1;
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    // the build's per-slice non-finite counters start at zero (per >= 3, so
-    // the grid covers them): one launch fewer before the build
-    if (idx < n_slices) nonfinite[idx] = 0u;
     if (idx >= per * n_slices) return;
     const long long j = idx / per, m = idx - j * per;
-    const double Tj = t0 + double(j) * L;
-    double t = Tj + double(m >> 1) * h;
-    if (m & 1) t = t + h / 2.0;
-    F[idx] = R(forcing_value(rhs, t));
+    F[idx] = forcing_entry<R>(rhs, t0 + double(j) * L, m, h);
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, long long n, uint32_t v) {
@@ -67,6 +92,14 @@ __global__ void fill_u32_kernel(uint32_t *p, long long n, uint32_t v) {
 
 template <class Rhs, class R, int Scheme, int A, int P>
 hipError_t launch_one(const BuildArgs &a, hipStream_t s) {
+    if constexpr (Rhs::forced) {
+        if (a.local_forcing) {
+            const size_t lds = size_t(2LL * a.steps + 1) * sizeof(R);
+            hipLaunchKernelGGL((build_local_forcing_kernel<Rhs, R, Scheme, A, P>),
+                               dim3(a.total_blocks), dim3(kBuildBlock), lds, s, a);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((build_kernel<Rhs, R, Scheme, A, P>), dim3(a.total_blocks),
                        dim3(kBuildBlock), 0, s, a);
     return hipGetLastError();
@@ -127,16 +160,16 @@ hipError_t launch_build(const BuildConfig &c, const BuildArgs &a, hipStream_t s)
 }
 
 hipError_t launch_forcing(int rhs, int precision, void *F, int n_slices, int steps,
-                          double t0, double L, double h, uint32_t *nonfinite, hipStream_t s) {
+                          double t0, double L, double h, hipStream_t s) {
     const long long n = (2LL * steps + 1) * n_slices;
     const int block = 256;
     const long long grid = (n + block - 1) / block;
     if (precision == 0)
         hipLaunchKernelGGL(forcing_kernel<double>, dim3(unsigned(grid)), dim3(block), 0, s, rhs,
-                           static_cast<double *>(F), n_slices, steps, t0, L, h, nonfinite);
+                           static_cast<double *>(F), n_slices, steps, t0, L, h);
     else
         hipLaunchKernelGGL(forcing_kernel<float>, dim3(unsigned(grid)), dim3(block), 0, s, rhs,
-                           static_cast<float *>(F), n_slices, steps, t0, L, h, nonfinite);
+                           static_cast<float *>(F), n_slices, steps, t0, L, h);
     return hipGetLastError();
 }
 

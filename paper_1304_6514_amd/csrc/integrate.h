@@ -35,6 +35,7 @@ template <class R>
 struct RhsForcedCubic {         // y' = sin(3t) - y^3, F = sin(3t)
     static constexpr int dim = 1;
     static constexpr bool forced = true;
+    static constexpr int rhs_id = 2;  // nv_rhs_id, for forcing_value
     __device__ static void f(R F, R, const R *y, R *k) {
         R y2 = y[0] * y[0];
         k[0] = F - y2 * y[0];
@@ -172,11 +173,12 @@ __device__ inline void end_block(R (&y)[P][D], R (&c)[P][D], R (&z)[P][D]) {
     }
 }
 
-// Integrate and store one tile: 256*P consecutive grid points of slice j.
-// Returns how many non-finite end states (per trajectory: either component)
-// this lane stored.
+// Integrate and store one tile: 256*P consecutive grid points of slice j, F
+// the slice's forcing row (right-hand sides with forcing).  Returns how many
+// non-finite end states (per trajectory: either component) this lane stored.
 template <class Rhs, class R, int Scheme, int A, int P>
-__device__ inline unsigned build_tile(const BuildArgs &a, int j, int tile) {
+__device__ inline unsigned build_tile_rows(const BuildArgs &a, int j, int tile,
+                                           const R *__restrict__ F) {
     constexpr int D = Rhs::dim;
     const long long base = (long long)tile * (kBuildBlock * P) + threadIdx.x;
 
@@ -195,8 +197,6 @@ __device__ inline unsigned build_tile(const BuildArgs &a, int j, int tile) {
 
     const R h = R(a.h), h2 = R(a.h * 0.5), h6 = R(a.h / 6.0), p = R(a.p0);
     const int S = a.steps;
-    const R *__restrict__ F =
-        Rhs::forced ? static_cast<const R *>(a.forcing) + (long long)j * (2 * S + 1) : nullptr;
     for (int s0 = 0; s0 < S; s0 += kSumBlock) {
         const int s1 = min(s0 + kSumBlock, S);
 #pragma unroll 2
@@ -233,6 +233,15 @@ __device__ inline unsigned build_tile(const BuildArgs &a, int j, int tile) {
         }
     }
     return bad;
+}
+
+// The same, the forcing row taken from the build's forcing array.
+template <class Rhs, class R, int Scheme, int A, int P>
+__device__ inline unsigned build_tile(const BuildArgs &a, int j, int tile) {
+    const R *F = Rhs::forced
+                     ? static_cast<const R *>(a.forcing) + (long long)j * (2 * a.steps + 1)
+                     : nullptr;
+    return build_tile_rows<Rhs, R, Scheme, A, P>(a, j, tile, F);
 }
 
 }  // namespace dev

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 namespace {
 thread_local std::string g_last_error;
@@ -42,6 +43,11 @@ using nv::fail;
 constexpr size_t kAlign = 256;
 constexpr int kMaxChunks = 64;
 constexpr int kMaxChebyshev = 64;
+// a build of a right-hand side with forcing forms each slice's forcing row in
+// its workgroups' LDS (no forcing launch) when it has at most this many
+// workgroups and a row fits in this many bytes
+constexpr long long kLocalForcingBlocks = 2048;
+constexpr size_t kLocalForcingBytes = 16384;
 // automatic chunking of nv_solve: about this many workgroups per build launch
 // (half a round of 256 CUs x 8 resident workgroups; consecutive chunks overlap)
 constexpr long long kBlocksPerChunk = 1024;
@@ -181,8 +187,10 @@ nv_status make_plan(int rhs, int n_slices, const nv_ic_grid *g, int steps,
     p->forcing_off = off;
     p->forcing_bytes = rhs_forced(rhs) ? (2 * size_t(steps) + 1) * size_t(n_slices) * p->elem : 0;
     off = align_up(off + p->forcing_bytes);
+    // one non-finite count per tile, stored by its workgroup (the host sums a
+    // slice's tiles)
     p->nonfinite_off = off;
-    off = align_up(off + size_t(n_slices) * sizeof(uint32_t));
+    off = align_up(off + size_t(n_slices) * size_t(tiles) * sizeof(uint32_t));
     // the running status and the state carried from one range of slices to
     // the next stay in device memory; the boundary states and a copy of the
     // final status go to the context's mapped host memory:
@@ -403,6 +411,10 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
     a.steps = S;
     a.tiles_per_slice = p.tiles_per_slice;
     a.total_blocks = int(p.total_blocks);
+    a.t0 = t0;
+    a.L = L;
+    a.local_forcing = rhs_forced(rhs_id) && p.total_blocks <= kLocalForcingBlocks &&
+                      (2 * size_t(steps_per_slice) + 1) * p.elem <= kLocalForcingBytes;
     pb->cfg = cfg;
 
     if (grid->interp == NV_INTERP_CHEBYSHEV) {
@@ -423,14 +435,10 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
         // the place where an earlier build kept its nodes
         ctx->nodes_dev = nullptr;
     }
-    // the per-slice non-finite counters: with one workgroup per slice the build
-    // stores them outright; otherwise its workgroups add to them, and they are
-    // cleared first (by the forcing kernel when there is one)
-    if (a.forcing)
+    // the forcing rows, unless the build forms them itself
+    if (a.forcing && !a.local_forcing)
         NV_HIP(nv::launch_forcing(rhs_id, ctx->opt.precision, work_at(ctx, p.forcing_off),
-                                  n_slices, steps_per_slice, t0, L, h, a.nonfinite, st));
-    else if (p.tiles_per_slice > 1)
-        NV_HIP(nv::launch_fill_u32(a.nonfinite, n_slices, 0u, st));
+                                  n_slices, steps_per_slice, t0, L, h, st));
 
     ctx->plan = p;
     ctx->rhs = rhs_id;
@@ -776,9 +784,17 @@ NV_API nv_status nv_get_nonfinite_counts(nv_ctx *ctx, uint32_t *host_counts, int
     if (!ctx->built) return fail(NV_ERR_NOT_BUILT, "no counts before a successful build");
     if (n < ctx->n_slices) return fail(NV_ERR_BUFFER_TOO_SMALL, "need %d counts", ctx->n_slices);
     hipStream_t st = stream_of(ctx);
-    NV_HIP(hipMemcpyAsync(host_counts, work_at(ctx, ctx->plan.nonfinite_off),
-                          size_t(ctx->n_slices) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    // one count per tile: the slice's count is their sum
+    const size_t tiles = size_t(ctx->plan.tiles_per_slice), ns = size_t(ctx->n_slices);
+    std::vector<uint32_t> per_tile(ns * tiles);
+    NV_HIP(hipMemcpyAsync(per_tile.data(), work_at(ctx, ctx->plan.nonfinite_off),
+                          per_tile.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     NV_HIP(hipStreamSynchronize(st));
+    for (size_t j = 0; j < ns; ++j) {
+        uint32_t sum = 0;
+        for (size_t t = 0; t < tiles; ++t) sum += per_tile[j * tiles + t];
+        host_counts[j] = sum;
+    }
     return NV_OK;
 }
 

@@ -19,7 +19,8 @@ struct BuildArgs {
     void *tab0;               // component 0 table, [n_slices][M] of the working type
     void *tab1;               // component 1 table (2-D problems) or null
     const void *forcing;      // [n_slices][2*steps+1] forcing values, or null
-    uint32_t *nonfinite;      // [n_slices] counters
+    uint32_t *nonfinite;      // single-problem build: [n_slices][tiles_per_slice] counts, one
+                              // per tile, stored; batch: [n_slices] counters, added to
     double lo0, dxi0;         // axis 0: xi = lo0 + k0 * dxi0
     double lo1, dxi1;         // axis 1 (2-D)
     double h;                 // step
@@ -33,6 +34,8 @@ struct BuildArgs {
     int steps;
     int tiles_per_slice;      // workgroups per slice
     int total_blocks;         // (slices of this launch) * tiles_per_slice
+    int local_forcing;        // 1: each workgroup forms its slice's forcing row in LDS
+    double t0, L;             // T_j = t0 + j L (for local_forcing)
 };
 
 struct BuildConfig {
@@ -105,9 +108,9 @@ nv_status batch_slice_sources(nv_batch *b, std::vector<SliceMapSource> &out, int
 
 bool build_supported(const BuildConfig &c);
 hipError_t launch_build(const BuildConfig &c, const BuildArgs &a, hipStream_t s);
-// Also zeroes the n_slices non-finite counters.
+// The forcing rows of every slice (right-hand sides with forcing).
 hipError_t launch_forcing(int rhs, int precision, void *F, int n_slices, int steps,
-                          double t0, double L, double h, uint32_t *nonfinite, hipStream_t s);
+                          double t0, double L, double h, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t s);
 hipError_t launch_compose(int interp, int precision, const ComposeArgs &a, hipStream_t s);
 hipError_t launch_locate(double lo, double inv, int n, const double *x, long long count,

@@ -64,8 +64,9 @@ def test_required_bytes_layout(nvmod):
     o = nvmod.make_options("rk4", "fp32")
     tb, wb = nvmod.nv_required_bytes(nvmod.NV_RHS_FORCED_CUBIC, 4096, g, 2000, o)
     assert tb == 4096 * 4096 * 4                         # 64 MiB, one FP32 component
-    # forcing values + non-finite counters (the boundary states go to mapped host memory)
-    assert 4096 * 4001 * 4 + 4096 * 4 <= wb < 4096 * 4001 * 4 + 4096 * 4 + 4097 * 8 + 4096
+    # forcing values + one non-finite count per tile (8 tiles of 512 points per slice; the
+    # boundary states go to mapped host memory)
+    assert 4096 * 4001 * 4 + 4096 * 8 * 4 <= wb < 4096 * 4001 * 4 + 4096 * 8 * 4 + 4097 * 8 + 4096
     g2 = _grid(nvmod, (128, 128), (-3.0, -8.0), (3.0, 8.0), "bilinear")
     tb2, _ = nvmod.nv_required_bytes(nvmod.NV_RHS_VDP, 1024, g2, 500, o)
     assert tb2 == 2 * 1024 * 128 * 128 * 4               # two 64 MiB tables

@@ -150,7 +150,7 @@ NV_API nv_status nv_get_options(const nv_ctx *ctx, nv_options *opt);
  *   *table_bytes: the map tables, dim x N x (points per slice) values of the
  *                 working precision, 256-byte aligned per component;
  *   *work_bytes:  scratch (per-slice forcing values of non-autonomous
- *                 right-hand sides, per-slice non-finite counters, the
+ *                 right-hand sides, one non-finite count per build tile, the
  *                 composition's running status and carried state, the
  *                 Chebyshev nodes).  The boundary states and the final status
  *                 go to pinned, device-mapped host memory that the context

@@ -543,6 +543,32 @@ def test_single_launch_equals_chunked_launches(orc, torch, w):
         assert c1.sum() > 0 and c1.sum() == np.count_nonzero(~np.isfinite(t1))
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_forcing_rows_in_lds_equal_precomputed_rows(orc, prop, precision):
+    # 8 slices x 4 tiles of 256 points (ragged: 1000 points) is small enough for each
+    # workgroup to form its slice's forcing row in LDS; 600 slices x 4 tiles is too many
+    # workgroups for that, so its rows come from their own launch. Both have slices of
+    # length 1/16 from t0 = 0, so slices 0..7 are the same problems: bit for bit equal
+    kw = dict(rhs="forced_cubic", params=(), t0=0.0, grid_n=(1000,), grid_lo=(-3.0,),
+              grid_hi=(3.0,), steps_per_slice=40, y0=(1.0,), precision=precision,
+              interp="hermite")
+    small = W.Workload(name="fcub-rows-in-lds", T=0.5, n_slices=8, **kw)
+    large = W.Workload(name="fcub-rows-precomputed", T=37.5, n_slices=600, **kw)
+    say("forcing rows in LDS vs precomputed", precision)
+    prop.build(small)
+    ts, cs = prop.table(0), prop.nonfinite_counts()
+    prop.build(large)
+    tl, cl = prop.table(0), prop.nonfinite_counts()
+    assert ts.shape == (8, 1000) and tl.shape == (600, 1000)
+    assert np.array_equal(ts.view(np.uint8), tl[:8].view(np.uint8))
+    assert np.array_equal(cs, cl[:8]) and cs.sum() == 0
+    ss, kk = W.sample_entries(small, 300, seed=11)
+    ref = orc.table_entries(small.rhs, small.params, small.scheme, small.t0, small.T,
+                            small.n_slices, ogrid(orc, small), small.steps_per_slice,
+                            ss, kk)[0]
+    assert mixed_err(ts[ss, kk], ref) <= TOL[precision]
+
+
 def test_failed_chunked_solve_then_compose_and_solve(orc, torch):
     # y' = y^2 from 0.3 blows up at t = 10/3: the chain fails in the third of eight
     # chunks while the later chunks' compositions are still queued; a composition on

@@ -34,6 +34,14 @@ __device__ inline void store_tile_count(const BuildArgs &a, int j, int tile, uns
     if (threadIdx.x == 0) a.nonfinite[(long long)j * a.tiles_per_slice + tile] = count;
 }
 
+// Start time of slice j, T_j = t0 + j L: the product rounded, then the sum,
+// never one fused operation, so that every kernel that forms a forcing row
+// sees the same T_j.
+__device__ inline double slice_start(double t0, long long j, double L) {
+#pragma clang fp contract(off)
+    return t0 + double(j) * L;
+}
+
 // Entry m of slice j's forcing row: the right-hand side's forcing at
 // T_j + (m/2) h, plus h/2 for odd m (the step's start, midpoint and end times),
 // in FP64, rounded once.
@@ -64,7 +72,7 @@ __global__ void __launch_bounds__(kBuildBlock) build_local_forcing_kernel(BuildA
     const int lid = xcd_remap(int(blockIdx.x), a.total_blocks);
     const int j = a.slice0 + lid / a.tiles_per_slice, tile = lid % a.tiles_per_slice;
     const long long per = 2LL * a.steps + 1;
-    const double Tj = a.t0 + double(j) * a.L;
+    const double Tj = slice_start(a.t0, j, a.L);
     for (long long m = threadIdx.x; m < per; m += kBuildBlock)
         F[m] = forcing_entry<R>(Rhs::rhs_id, Tj, m, a.h);
     __syncthreads();
@@ -82,7 +90,7 @@ __global__ void forcing_kernel(int rhs, R *F, int n_slices, int steps, double t0
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= per * n_slices) return;
     const long long j = idx / per, m = idx - j * per;
-    F[idx] = forcing_entry<R>(rhs, t0 + double(j) * L, m, h);
+    F[idx] = forcing_entry<R>(rhs, slice_start(t0, j, L), m, h);
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, long long n, uint32_t v) {

@@ -548,12 +548,14 @@ def test_forcing_rows_in_lds_equal_precomputed_rows(orc, prop, precision):
     # 8 slices x 4 tiles of 256 points (ragged: 1000 points) is small enough for each
     # workgroup to form its slice's forcing row in LDS; 600 slices x 4 tiles is too many
     # workgroups for that, so its rows come from their own launch. Both have slices of
-    # length 1/16 from t0 = 0, so slices 0..7 are the same problems: bit for bit equal
-    kw = dict(rhs="forced_cubic", params=(), t0=0.0, grid_n=(1000,), grid_lo=(-3.0,),
+    # length 0.1 (the same double) from t0 = 0.3, so slices 0..7 are the same problems:
+    # bit for bit equal. Slices 3 and 6 start where t0 + round(j L) and the fused
+    # t0 + j L round differently, so both kernels must form T_j unfused
+    kw = dict(rhs="forced_cubic", params=(), t0=0.3, grid_n=(1000,), grid_lo=(-3.0,),
               grid_hi=(3.0,), steps_per_slice=40, y0=(1.0,), precision=precision,
               interp="hermite")
-    small = W.Workload(name="fcub-rows-in-lds", T=0.5, n_slices=8, **kw)
-    large = W.Workload(name="fcub-rows-precomputed", T=37.5, n_slices=600, **kw)
+    small = W.Workload(name="fcub-rows-in-lds", T=1.1, n_slices=8, **kw)
+    large = W.Workload(name="fcub-rows-precomputed", T=60.3, n_slices=600, **kw)
     say("forcing rows in LDS vs precomputed", precision)
     prop.build(small)
     ts, cs = prop.table(0), prop.nonfinite_counts()

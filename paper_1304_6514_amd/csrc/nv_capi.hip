@@ -431,7 +431,7 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
         }
         a.nodes = dn;
     } else {
-        // this build's forcing values, counters and carried state may cover
+        // the new table build's forcing values, counters and carried state may cover
         // the place where an earlier build kept its nodes
         ctx->nodes_dev = nullptr;
     }

@@ -571,6 +571,37 @@ def test_forcing_rows_in_lds_equal_precomputed_rows(orc, prop, precision):
     assert mixed_err(ts[ss, kk], ref) <= TOL[precision]
 
 
+@pytest.mark.parametrize("precision,steps", [("fp64", 1023), ("fp64", 1024),
+                                             ("fp32", 2047), ("fp32", 2048)])
+def test_forced_builds_at_the_lds_row_limit(orc, prop, precision, steps):
+    # a slice's forcing row holds 2 steps + 1 values: 16,376 / 16,392 bytes in FP64 and
+    # 16,380 / 16,388 in FP32, on either side of the 16 KiB a workgroup may form in LDS
+    w = W.Workload(f"fcub-row-limit-{steps}", "forced_cubic", (), 0.3, 1.9, 16, (200,),
+                   (-2.0,), (2.0,), steps, (1.0,), precision, "hermite")
+    say("forced build at the LDS row limit", precision, steps)
+    prop.build(w)
+    t = prop.table(0)
+    assert np.all(prop.nonfinite_counts() == 0)
+    ss, kk = W.sample_entries(w, 120, seed=steps)
+    ref = orc.table_entries(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, ogrid(orc, w),
+                            w.steps_per_slice, ss, kk)[0]
+    assert mixed_err(t[ss, kk], ref) <= TOL[precision]
+
+
+def test_forced_builds_at_the_workgroup_limit(prop):
+    # 512 slices x 4 tiles = 2048 workgroups form their rows in LDS, 513 x 4 take them
+    # from the forcing launch; equal slice lengths (1/16), so the first 512 slices agree
+    kw = dict(rhs="forced_cubic", params=(), t0=0.0, grid_n=(1000,), grid_lo=(-3.0,),
+              grid_hi=(3.0,), steps_per_slice=10, y0=(1.0,), precision="fp64",
+              interp="linear")
+    say("forced builds at the workgroup limit")
+    prop.build(W.Workload(name="fcub-2048-wg", T=32.0, n_slices=512, **kw))
+    a = prop.table(0)
+    prop.build(W.Workload(name="fcub-2052-wg", T=32.0625, n_slices=513, **kw))
+    b = prop.table(0)
+    assert np.array_equal(a.view(np.uint8), b[:512].view(np.uint8))
+
+
 def test_failed_chunked_solve_then_compose_and_solve(orc, torch):
     # y' = y^2 from 0.3 blows up at t = 10/3: the chain fails in the third of eight
     # chunks while the later chunks' compositions are still queued; a composition on

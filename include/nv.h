@@ -44,7 +44,7 @@ typedef enum {
     NV_ERR_INVALID_ARG = -1,      /* an argument is out of its documented range */
     NV_ERR_NOT_BUILT = -2,        /* compose/inspect before any successful build */
     NV_ERR_NONFINITE = -3,        /* the composition met a non-finite value */
-    NV_ERR_OOM = -4,              /* device allocation failed */
+    NV_ERR_OOM = -4,              /* a device (or host) allocation failed */
     NV_ERR_HIP = -5,              /* a HIP runtime call failed */
     NV_ERR_UNSUPPORTED = -6,      /* a combination this library does not build */
     NV_ERR_BUFFER_TOO_SMALL = -7  /* caller-provided memory is too small */
@@ -250,7 +250,10 @@ NV_API nv_status nv_get_table(nv_ctx *ctx, int component, void *host_dst, size_t
 NV_API nv_status nv_table_device_ptr(nv_ctx *ctx, int component, void **dev_ptr);
 
 /* Copy the per-slice counts of trajectories that ended non-finite (n_slices
- * uint32 values) to host memory. */
+ * uint32 values) to host memory; n is the capacity of host_counts.  Waits on
+ * the context's stream.  Errors: NV_ERR_INVALID_ARG (NULL argument),
+ * NV_ERR_NOT_BUILT, NV_ERR_BUFFER_TOO_SMALL (n < n_slices), NV_ERR_OOM (no
+ * host memory to gather the per-tile counts), NV_ERR_HIP. */
 NV_API nv_status nv_get_nonfinite_counts(nv_ctx *ctx, uint32_t *host_counts, int n);
 
 /* The lookup of nv_compose applied to count device-resident queries x_dev:

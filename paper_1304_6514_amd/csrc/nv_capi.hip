@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <new>
 #include <vector>
 
 namespace {
@@ -786,7 +787,12 @@ NV_API nv_status nv_get_nonfinite_counts(nv_ctx *ctx, uint32_t *host_counts, int
     hipStream_t st = stream_of(ctx);
     // one count per tile: the slice's count is their sum
     const size_t tiles = size_t(ctx->plan.tiles_per_slice), ns = size_t(ctx->n_slices);
-    std::vector<uint32_t> per_tile(ns * tiles);
+    std::vector<uint32_t> per_tile;
+    try {
+        per_tile.resize(ns * tiles);
+    } catch (const std::bad_alloc &) {
+        return fail(NV_ERR_OOM, "no host memory for %zu per-tile counts", ns * tiles);
+    }
     NV_HIP(hipMemcpyAsync(per_tile.data(), work_at(ctx, ctx->plan.nonfinite_off),
                           per_tile.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     NV_HIP(hipStreamSynchronize(st));

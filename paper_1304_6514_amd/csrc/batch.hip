@@ -376,7 +376,7 @@ nv_status autotune(nv_batch *b, int reps, nv_batch_schedule *chosen) {
 extern "C" {
 
 NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int count,
-                                 nv_batch **out) {
+                                 nv_batch **out) try {
     if (!ctx || !problems || !out) return fail(NV_ERR_INVALID_ARG, "NULL argument");
     if (count < 1) return fail(NV_ERR_INVALID_ARG, "count must be >= 1");
     *out = nullptr;
@@ -537,6 +537,8 @@ NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int co
     }
     *out = b;
     return NV_OK;
+} catch (const std::bad_alloc &) {
+    return fail(NV_ERR_OOM, "nv_batch_create: host allocation failed");
 }
 
 NV_API nv_status nv_batch_destroy(nv_batch *batch) {
@@ -544,11 +546,13 @@ NV_API nv_status nv_batch_destroy(nv_batch *batch) {
     return NV_OK;
 }
 
-NV_API nv_status nv_batch_set_schedule(nv_batch *batch, const nv_batch_schedule *sched) {
+NV_API nv_status nv_batch_set_schedule(nv_batch *batch, const nv_batch_schedule *sched) try {
     if (!batch) return fail(NV_ERR_INVALID_ARG, "batch is NULL");
     nv_status s = check_schedule(sched);
     if (s != NV_OK) return s;
     return apply_schedule(batch, *sched);
+} catch (const std::bad_alloc &) {
+    return fail(NV_ERR_OOM, "nv_batch_set_schedule: host allocation failed");
 }
 
 NV_API nv_status nv_batch_get_schedule(const nv_batch *batch, nv_batch_schedule *sched) {
@@ -557,7 +561,7 @@ NV_API nv_status nv_batch_get_schedule(const nv_batch *batch, nv_batch_schedule 
     return NV_OK;
 }
 
-NV_API nv_status nv_batch_autotune(nv_batch *b, int reps, nv_batch_schedule *chosen) {
+NV_API nv_status nv_batch_autotune(nv_batch *b, int reps, nv_batch_schedule *chosen) try {
     if (!b) return fail(NV_ERR_INVALID_ARG, "batch is NULL");
     if (reps < 1) return fail(NV_ERR_INVALID_ARG, "reps must be >= 1");
     const nv_batch_schedule before = b->sched;
@@ -568,9 +572,11 @@ NV_API nv_status nv_batch_autotune(nv_batch *b, int reps, nv_batch_schedule *cho
         return fail(s, "%s", msg.c_str());
     }
     return NV_OK;
+} catch (const std::bad_alloc &) {
+    return fail(NV_ERR_OOM, "nv_batch_autotune: host allocation failed");
 }
 
-NV_API nv_status nv_batch_run(nv_batch *b, double *yT, nv_compose_info *info) {
+NV_API nv_status nv_batch_run(nv_batch *b, double *yT, nv_compose_info *info) try {
     if (!b || !yT) return fail(NV_ERR_INVALID_ARG, "NULL argument");
     nv_status s = ensure_graph(b);
     if (s != NV_OK) return s;
@@ -600,6 +606,8 @@ NV_API nv_status nv_batch_run(nv_batch *b, double *yT, nv_compose_info *info) {
         return fail(NV_ERR_NONFINITE, "problem %d met a non-finite value in slice %d", first_bad,
                     st[first_bad].bad_slice);
     return NV_OK;
+} catch (const std::bad_alloc &) {
+    return fail(NV_ERR_OOM, "nv_batch_run: host allocation failed");
 }
 
 NV_API nv_status nv_batch_last_timing(nv_batch *b, float *run_ms, long long *traj_steps) {
@@ -613,7 +621,7 @@ NV_API nv_status nv_batch_last_timing(nv_batch *b, float *run_ms, long long *tra
 }
 
 NV_API nv_status nv_batch_get_table(nv_batch *b, int problem, int component, void *host_dst,
-                                    size_t bytes) {
+                                    size_t bytes) try {
     if (!b || !host_dst) return fail(NV_ERR_INVALID_ARG, "NULL argument");
     if (problem < 0 || problem >= b->count) return fail(NV_ERR_INVALID_ARG, "bad problem index");
     if (component < 0 || component >= dim_of(b->problems[problem]))
@@ -626,10 +634,12 @@ NV_API nv_status nv_batch_get_table(nv_batch *b, int problem, int component, voi
                           need, hipMemcpyDeviceToHost, b->stream));
     NV_HIP(hipStreamSynchronize(b->stream));
     return NV_OK;
+} catch (const std::bad_alloc &) {
+    return fail(NV_ERR_OOM, "nv_batch_get_table: host allocation failed");
 }
 
 NV_API nv_status nv_batch_get_boundary(nv_batch *b, int problem, double *host_dst,
-                                       size_t count) {
+                                       size_t count) try {
     if (!b || !host_dst) return fail(NV_ERR_INVALID_ARG, "NULL argument");
     if (problem < 0 || problem >= b->count) return fail(NV_ERR_INVALID_ARG, "bad problem index");
     const nv_problem &p = b->problems[problem];
@@ -640,6 +650,8 @@ NV_API nv_status nv_batch_get_boundary(nv_batch *b, int problem, double *host_ds
                           need * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     NV_HIP(hipStreamSynchronize(b->stream));
     return NV_OK;
+} catch (const std::bad_alloc &) {
+    return fail(NV_ERR_OOM, "nv_batch_get_boundary: host allocation failed");
 }
 
 }  // extern "C"

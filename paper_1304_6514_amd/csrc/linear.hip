@@ -508,7 +508,7 @@ long long step_scalars(const nv_heat &p, double t0, double L, double dt, int S, 
 
 extern "C" {
 
-NV_API nv_status nv_lin_create(void *stream, nv_lin **out) {
+NV_API nv_status nv_lin_create(void *stream, nv_lin **out) try {
     if (!out) return fail(NV_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
     nv_lin *l = new (std::nothrow) nv_lin();
@@ -524,6 +524,8 @@ NV_API nv_status nv_lin_create(void *stream, nv_lin **out) {
     }
     *out = l;
     return NV_OK;
+} catch (const std::bad_alloc &) {
+    return fail(NV_ERR_OOM, "nv_lin_create: host allocation failed");
 }
 
 NV_API nv_status nv_lin_destroy(nv_lin *l) {
@@ -539,7 +541,7 @@ NV_API nv_status nv_lin_destroy(nv_lin *l) {
 }
 
 NV_API nv_status nv_lin_build(nv_lin *l, const nv_heat *p, double t0, double T, int n_slices,
-                              double dt) {
+                              double dt) try {
 #pragma clang fp contract(off)
     if (!l || !p) return fail(NV_ERR_INVALID_ARG, "NULL argument");
     l->built = false;                        // a failed build leaves nothing to compose
@@ -655,6 +657,8 @@ NV_API nv_status nv_lin_build(nv_lin *l, const nv_heat *p, double t0, double T, 
     NV_HIP(hipEventElapsedTime(&l->build_ms, l->e0, l->e1));
     l->built = true;
     return NV_OK;
+} catch (const std::bad_alloc &) {
+    return fail(NV_ERR_OOM, "nv_lin_build: host allocation failed");
 }
 
 NV_API nv_status nv_lin_compose(nv_lin *l, const double *y0, double *yT, double *boundary) {

@@ -863,7 +863,7 @@ nv_status minibatch(nv_sur *s, const float *x, const float *t, long long ld, lon
 
 extern "C" {
 
-NV_API nv_status nv_sur_create(const nv_sur_config *cfg, nv_sur **out) {
+NV_API nv_status nv_sur_create(const nv_sur_config *cfg, nv_sur **out) try {
     if (!cfg || !out) return fail(NV_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
     for (int k = 0; k < 4; ++k)
@@ -933,6 +933,8 @@ NV_API nv_status nv_sur_create(const nv_sur_config *cfg, nv_sur **out) {
     }
     *out = s;
     return NV_OK;
+} catch (const std::bad_alloc &) {
+    return fail(NV_ERR_OOM, "nv_sur_create: host allocation failed");
 }
 
 NV_API nv_status nv_sur_destroy(nv_sur *s) {
@@ -1007,7 +1009,7 @@ NV_API nv_status nv_sur_loss_grad(nv_sur *s, const float *x, const float *t, lon
 }
 
 NV_API nv_status nv_sur_train(nv_sur *s, const float *x, const float *t, long long n_samples,
-                              const nv_sur_train_opts *o, float *loss_dev) {
+                              const nv_sur_train_opts *o, float *loss_dev) try {
     if (!s || !x || !t || !o) return fail(NV_ERR_INVALID_ARG, "NULL argument");
     const long long B = o->batch;
     if (B < 16 || B % 16 != 0 || B > s->max_batch)
@@ -1039,10 +1041,12 @@ NV_API nv_status nv_sur_train(nv_sur *s, const float *x, const float *t, long lo
     NV_HIP(hipStreamSynchronize(s->stream));
     NV_HIP(hipEventElapsedTime(&s->last_ms, s->ev0, s->ev1));
     return NV_OK;
+} catch (const std::bad_alloc &) {
+    return fail(NV_ERR_OOM, "nv_sur_train: host allocation failed");
 }
 
 NV_API nv_status nv_sur_dataset_from_batch(nv_sur *s, nv_batch *batch, const long long *perm,
-                                           float *x, float *t, long long cap, long long *total) {
+                                           float *x, float *t, long long cap, long long *total) try {
     if (!s || !batch || !total) return fail(NV_ERR_INVALID_ARG, "NULL argument");
     std::vector<nv::SliceMapSource> src;
     int precision = 0;
@@ -1094,9 +1098,11 @@ NV_API nv_status nv_sur_dataset_from_batch(nv_sur *s, nv_batch *batch, const lon
     if (err & 1) return fail(NV_ERR_INVALID_ARG, "perm holds a position outside [0, cap)");
     if (err & 2) return fail(NV_ERR_NONFINITE, "the batch's tables hold non-finite endpoints");
     return NV_OK;
+} catch (const std::bad_alloc &) {
+    return fail(NV_ERR_OOM, "nv_sur_dataset_from_batch: host allocation failed");
 }
 
-NV_API nv_status nv_sur_compose(nv_sur *s, const nv_sur_chains *c, nv_sur_compose_info *info) {
+NV_API nv_status nv_sur_compose(nv_sur *s, const nv_sur_chains *c, nv_sur_compose_info *info) try {
     if (!s || !c || !info) return fail(NV_ERR_INVALID_ARG, "NULL argument");
     if (c->count < 1 || c->n_slices < 1 || !c->y0 || !c->mu || !c->final_state)
         return fail(NV_ERR_INVALID_ARG, "need count >= 1, n_slices >= 1, y0, mu, final_state");
@@ -1168,6 +1174,8 @@ NV_API nv_status nv_sur_compose(nv_sur *s, const nv_sur_chains *c, nv_sur_compos
     if (info->bad_chain >= 0)
         return fail(NV_ERR_NONFINITE, "chain %lld became non-finite", info->bad_chain);
     return NV_OK;
+} catch (const std::bad_alloc &) {
+    return fail(NV_ERR_OOM, "nv_sur_compose: host allocation failed");
 }
 
 NV_API nv_status nv_sur_last_ms(nv_sur *s, float *ms) {

@@ -44,12 +44,13 @@ WORKLOADS = {"forced_cubic": W.FORCED_CUBIC_FP32, "logistic": W.LOGISTIC_FP64,
 # HBM bytes per launch of the build kernel over the whole workload, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the same counters' reading of
 # a cold 256 MiB elementwise copy (profiles/build_kernel_forced_cubic_*.md,
-# profiles/build_and_compose_vdp_*.md).
+# profiles/build_and_compose_*.md).
 # Valid only for the kernel source they were taken with (SHA-1 below); any
 # other source gives traffic = null.
 MEASURED_TRAFFIC = {
     ("forced-cubic-fp32-4096sl-4096pt-2000st", "blocked", "e03ec79969c5e4534c83aee7e785134af2500475"): 198.4e6,
     ("vdp-fp32-1024sl-128x128pt-500st", "blocked", "e03ec79969c5e4534c83aee7e785134af2500475"): 134.4e6,
+    ("logistic-fp64-64sl-256pt-1000st", "blocked", "e03ec79969c5e4534c83aee7e785134af2500475"): 174.0e3,
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1304_6514_amd", "csrc", f)
                   for f in ("integrate.h", "build_kernels.hip")]

@@ -35,11 +35,9 @@ The affine propagator of slice j (`linearreconstruct`): c_j = the slice's
 solve from y = 0 with the forcing, column k of G_j = the homogeneous solve
 from the unit vector e_k; then phi_j(y) = c_j + G_j y exactly (no
 interpolation error), and the composition is lambda_{j+1} = c_j + G_j
-lambda_j.  The paper fixes no summation order; component i is formed here as
-eight interleaved partial sums p_r = G_i,r l_r + G_i,r+8 l_r+8 + ... (each
-left to right from 0), combined as ((p0 + p1) + (p2 + p3)) + ((p4 + p5) +
-(p6 + p7)), then c_i + that, so that the dependent chain of one component is
-about M/8 additions long.
+lambda_j, each component summed in index order starting from c_i.  The paper
+fixes the affine map, not a summation order; any other order differs from
+this one by rounding only (tests bound that difference).
 """
 from __future__ import annotations
 
@@ -153,24 +151,19 @@ def build_tables(M, a0, a1, forcing, t0, T, n_slices, dt, slices=None):
     return G, cvec
 
 
-def affine_component(g_row, lam, c):
-    """c + sum_k g_row[k] lam[k] in the order stated in the module docstring."""
-    p = [0.0] * 8
-    for k in range(len(lam)):
-        p[k % 8] = p[k % 8] + g_row[k] * lam[k]
-    s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]))
-    return c + s
-
-
 def compose(G, cvec, y0):
-    """The communication phase: lambda_{j+1} = c_j + G_j lambda_j.
-    Returns lambda_0 .. lambda_N."""
+    """The communication phase: lambda_{j+1} = c_j + G_j lambda_j, every
+    component summed left to right from c.  Returns lambda_0 .. lambda_N."""
     N, M, _ = G.shape
     lam = np.array(y0, dtype=np.float64)
     out = [lam.copy()]
     for j in range(N):
-        nxt = np.array([affine_component(G[j, i], lam, cvec[j, i]) for i in range(M)])
-        lam = nxt
+        # all components at once, each still c_i + G_i0 l_0 + G_i1 l_1 + ...
+        # in that order: one elementwise product and one elementwise sum per k
+        acc = np.array(cvec[j], dtype=np.float64)
+        for k in range(M):
+            acc = acc + G[j, :, k] * lam[k]
+        lam = acc
         out.append(lam.copy())
     return np.array(out)
 

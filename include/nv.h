@@ -352,6 +352,55 @@ NV_API nv_status nv_batch_get_table(nv_batch *batch, int problem, int component,
 NV_API nv_status nv_batch_get_boundary(nv_batch *batch, int problem, double *host_dst,
                                        size_t count);
 
+/* ------------------------------------------------------------------------
+ * nv_solve for callers that cannot allocate: code under HIP graph capture,
+ * serving loops that must not call hipMalloc, harnesses that forbid it.
+ *
+ * The build and the composition of nv_solve (same kernels, same options, one
+ * slice chunk: no overlap) with no context and no allocation of any kind:
+ * the caller passes every input and output, and the scratch (forcing rows,
+ * per-tile non-finite counts, the composition's running status and carried
+ * state) is a library-owned static array of NV_STATIC_SCRATCH_BYTES on each
+ * device, held from the library's first use on that device until the process
+ * ends.  The scratch a build needs is nv_required_bytes' *work_bytes; builds
+ * that need more are rejected with NV_ERR_BUFFER_TOO_SMALL (the forced cubic
+ * in FP32 fits up to (2 steps + 1) x slices x 4 bytes of forcing rows, about
+ * 63 MiB with its per-tile counts at 4096 slices x 2000 steps x 4096 points).
+ *
+ *   opt           host; scheme, precision, accumulation, trajectories per lane,
+ *                 dt and the stream to launch on (solve_chunks is ignored)
+ *   tables_dev    device, 256-byte aligned, table_bytes >= nv_required_bytes'
+ *                 *table_bytes; receives the tables (layout of nv_get_table,
+ *                 component c at c x the 256-byte-aligned component size)
+ *   y0            host, dim values (read before the call returns)
+ *   boundary_dev  device, (n_slices + 1) x dim doubles, 8-byte aligned:
+ *                 lambda_j at [j * dim + c]; lambda_N is the method's y(T)
+ *   status_dev    device, 8-byte aligned: n_out_of_grid, bad_slice (-1 when
+ *                 none; then boundary_dev holds lambda_0..lambda_bad_slice) and
+ *                 done = 1, written by the composition when it ends
+ *
+ * Asynchronous: returns once the launches are queued on opt->stream (no
+ * synchronization, no memset, no copy); read the outputs after the stream.
+ * Every call on one device uses that device's one scratch, which keeps the
+ * last call's contents (nothing in it needs to start at zero): calls that
+ * may overlap on one device race and must be ordered by the caller (e.g. one
+ * stream).  Chebyshev (paper-mode) grids give NV_ERR_UNSUPPORTED (their nodes
+ * come from host memory).  Errors: those of nv_solve, found before anything is
+ * launched, and NV_ERR_HIP. */
+#define NV_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+typedef struct {
+    long long n_out_of_grid;
+    int bad_slice;
+    int done;
+} nv_solve_status;
+
+NV_API nv_status nv_solve_static(int rhs_id, const double *params, double t0, double T,
+                                 int n_slices, const nv_ic_grid *grid, int steps_per_slice,
+                                 const nv_options *opt, void *tables_dev, size_t table_bytes,
+                                 const double *y0, double *boundary_dev,
+                                 nv_solve_status *status_dev);
+
 /* Message of the last failure on the calling thread ("" if none). */
 NV_API const char *nv_last_error(void);
 

@@ -12,22 +12,25 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
-#include <string>
+#include <mutex>
 #include <new>
 #include <vector>
 
 namespace {
-thread_local std::string g_last_error;
+// a fixed buffer, so that reporting an error allocates nothing
+thread_local char g_last_error[512];
 }  // namespace
 
 nv_status nv::fail(nv_status s, const char *fmt, ...) {
-    char buf[512];
+    // formatted apart first: an argument may be the current message itself
+    char buf[sizeof g_last_error];
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    g_last_error = buf;
+    std::memcpy(g_last_error, buf, sizeof buf);
     return s;
 }
 
@@ -332,22 +335,19 @@ void chebyshev_nodes(int n, double a, double b, double *xs) {
 }
 
 
-// Checks, buffers, the pre-launch kernels (counter reset, forcing values) on
-// the context's stream and the integration kernel's arguments; records the
-// build's description in the context (marked built by the caller once the
-// integration is launched).
+// One build: its configuration and the integration kernel's arguments.
 struct PreparedBuild {
     nv::BuildConfig cfg;
     nv::BuildArgs args;
 };
 
-nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0, double T,
-                        int n_slices, const nv_ic_grid *grid, int steps_per_slice,
-                        PreparedBuild *pb) {
-    if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
-    ctx->built = false;
-    Plan p;
-    nv_status s = make_plan(rhs_id, n_slices, grid, steps_per_slice, ctx->opt, &p);
+// Checks of one build and every argument of its integration kernel but the
+// device addresses (place_build): the plan, the slice partition and the grid.
+nv_status describe_build(const nv_options &o, int rhs_id, const double *params, double t0,
+                         double T, int n_slices, const nv_ic_grid *grid, int steps_per_slice,
+                         Plan *pp, PreparedBuild *pb) {
+    Plan &p = *pp;
+    nv_status s = make_plan(rhs_id, n_slices, grid, steps_per_slice, o, &p);
     if (s != NV_OK) return s;
     if (!std::isfinite(t0) || !std::isfinite(T) || !(T > t0))
         return fail(NV_ERR_INVALID_ARG, "need finite t0 < T (got %g, %g)", t0, T);
@@ -357,35 +357,20 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
         if (!std::isfinite(params[0])) return fail(NV_ERR_INVALID_ARG, "parameter not finite");
         p0 = params[0];
     }
-    nv::BuildConfig cfg{rhs_id, ctx->opt.scheme, ctx->opt.precision, ctx->opt.compensated,
-                        p.traj_per_lane};
+    nv::BuildConfig cfg{rhs_id, o.scheme, o.precision, o.compensated, p.traj_per_lane};
     if (!nv::build_supported(cfg)) return fail(NV_ERR_UNSUPPORTED, "unsupported configuration");
 
-    s = ensure_device(&ctx->tables, &ctx->tables_cap, ctx->tables_owned, p.table_bytes, "table");
-    if (s != NV_OK) return s;
-    const size_t work_cap_before = ctx->work_cap;
-    s = ensure_device(&ctx->work, &ctx->work_cap, ctx->work_owned, p.work_bytes, "work");
-    if (s != NV_OK) return s;
-    if (ctx->work_cap != work_cap_before) ctx->nodes_dev = nullptr;   // a new allocation
-    s = ensure_host_stage(ctx, p.stage_status_off + sizeof(nv::ComposeStatus));
-    if (s != NV_OK) return s;
-    if (ctx->timing) {
-        s = ensure_events(ctx);
-        if (s != NV_OK) return s;
-    }
-
-    hipStream_t st = stream_of(ctx);
     // slice partition (sec. 3): L = (T - t0)/N, T_j = t0 + j L; either S equal
     // steps h = L / S, or steps of the fixed dt plus one shorter final step
     const double L = (T - t0) / double(n_slices);
     double h, h_last = 0.0;
     int S = steps_per_slice;
-    if (ctx->opt.dt > 0.0) {
-        const double n = std::floor(L / ctx->opt.dt + 1e-9);
+    if (o.dt > 0.0) {
+        const double n = std::floor(L / o.dt + 1e-9);
         if (n > 2147483647.0) return fail(NV_ERR_INVALID_ARG, "dt gives too many steps");
         S = int(n);
-        h = ctx->opt.dt;
-        const double rem = L - double(S) * ctx->opt.dt;
+        h = o.dt;
+        const double rem = L - double(S) * o.dt;
         if (rem > 1e-12 * L) h_last = rem;
     } else {
         h = L / double(steps_per_slice);
@@ -393,10 +378,6 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
 
     nv::BuildArgs &a = pb->args;
     a = nv::BuildArgs{};
-    a.tab0 = ctx->tables;
-    a.tab1 = p.dim == 2 ? static_cast<char *>(ctx->tables) + p.comp_bytes : nullptr;
-    a.forcing = rhs_forced(rhs_id) ? work_at(ctx, p.forcing_off) : nullptr;
-    a.nonfinite = reinterpret_cast<uint32_t *>(work_at(ctx, p.nonfinite_off));
     a.lo0 = grid->lo[0];
     a.dxi0 = (grid->hi[0] - grid->lo[0]) / double(grid->n[0] - 1);
     a.lo1 = p.dim == 2 ? grid->lo[1] : 0.0;
@@ -417,7 +398,57 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
     a.local_forcing = rhs_forced(rhs_id) && p.total_blocks <= kLocalForcingBlocks &&
                       (2 * size_t(steps_per_slice) + 1) * p.elem <= kLocalForcingBytes;
     pb->cfg = cfg;
+    return NV_OK;
+}
 
+// The device addresses of a described build: its tables at `tables`, its
+// scratch (laid out by the plan) at `work`.
+void place_build(PreparedBuild *pb, const Plan &p, void *tables, char *work) {
+    nv::BuildArgs &a = pb->args;
+    a.tab0 = tables;
+    a.tab1 = p.dim == 2 ? static_cast<char *>(tables) + p.comp_bytes : nullptr;
+    a.forcing = rhs_forced(pb->cfg.rhs) ? work + p.forcing_off : nullptr;
+    a.nonfinite = reinterpret_cast<uint32_t *>(work + p.nonfinite_off);
+}
+
+// The forcing rows of a placed build, unless its workgroups form them themselves.
+hipError_t launch_forcing_rows(const PreparedBuild &pb, const Plan &p, char *work,
+                               hipStream_t st) {
+    const nv::BuildArgs &a = pb.args;
+    if (!a.forcing || a.local_forcing) return hipSuccess;
+    return nv::launch_forcing(pb.cfg.rhs, pb.cfg.precision, work + p.forcing_off, a.n_slices,
+                              a.steps, a.t0, a.L, a.h, st);
+}
+
+// Checks, buffers, the pre-launch kernels (forcing values, Chebyshev nodes) on
+// the context's stream and the integration kernel's arguments; records the
+// build's description in the context (marked built by the caller once the
+// integration is launched).
+nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0, double T,
+                        int n_slices, const nv_ic_grid *grid, int steps_per_slice,
+                        PreparedBuild *pb) {
+    if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->built = false;
+    Plan p;
+    nv_status s = describe_build(ctx->opt, rhs_id, params, t0, T, n_slices, grid,
+                                 steps_per_slice, &p, pb);
+    if (s != NV_OK) return s;
+
+    s = ensure_device(&ctx->tables, &ctx->tables_cap, ctx->tables_owned, p.table_bytes, "table");
+    if (s != NV_OK) return s;
+    const size_t work_cap_before = ctx->work_cap;
+    s = ensure_device(&ctx->work, &ctx->work_cap, ctx->work_owned, p.work_bytes, "work");
+    if (s != NV_OK) return s;
+    if (ctx->work_cap != work_cap_before) ctx->nodes_dev = nullptr;   // a new allocation
+    s = ensure_host_stage(ctx, p.stage_status_off + sizeof(nv::ComposeStatus));
+    if (s != NV_OK) return s;
+    if (ctx->timing) {
+        s = ensure_events(ctx);
+        if (s != NV_OK) return s;
+    }
+    place_build(pb, p, ctx->tables, work_at(ctx, 0));
+
+    hipStream_t st = stream_of(ctx);
     if (grid->interp == NV_INTERP_CHEBYSHEV) {
         double *dn = reinterpret_cast<double *>(work_at(ctx, p.nodes_off));
         if (ctx->nodes_dev != dn || ctx->nodes_n != grid->n[0] ||
@@ -430,16 +461,13 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
             ctx->nodes_lo = grid->lo[0];
             ctx->nodes_hi = grid->hi[0];
         }
-        a.nodes = dn;
+        pb->args.nodes = dn;
     } else {
         // the new table build's forcing values, counters and carried state may cover
         // the place where an earlier build kept its nodes
         ctx->nodes_dev = nullptr;
     }
-    // the forcing rows, unless the build forms them itself
-    if (a.forcing && !a.local_forcing)
-        NV_HIP(nv::launch_forcing(rhs_id, ctx->opt.precision, work_at(ctx, p.forcing_off),
-                                  n_slices, steps_per_slice, t0, L, h, st));
+    NV_HIP(launch_forcing_rows(*pb, p, work_at(ctx, 0), st));
 
     ctx->plan = p;
     ctx->rhs = rhs_id;
@@ -449,20 +477,22 @@ nv_status prepare_build(nv_ctx *ctx, int rhs_id, const double *params, double t0
     return NV_OK;
 }
 
-// Arguments of the composition kernel over slices [j0, j1) of the last build.
-nv::ComposeArgs compose_args(const nv_ctx *ctx, const double *y0, int j0, int j1) {
-    const Plan &p = ctx->plan;
-    const nv_ic_grid &g = ctx->grid;
+// Arguments of the composition kernel over slices [j0, j1) of a build with
+// tables at `tables` and scratch at `work`; it writes the boundary states to
+// `boundary` and, when the chain ends, the final status to `status_out`.
+nv::ComposeArgs compose_args_at(const Plan &p, const nv_ic_grid &g, int n_slices,
+                                const void *tables, char *work, double *boundary,
+                                nv::ComposeStatus *status_out, const double *y0, int j0,
+                                int j1) {
     nv::ComposeArgs a{};
-    a.tab0 = ctx->tables;
-    a.tab1 = p.dim == 2 ? static_cast<char *>(ctx->tables) + p.comp_bytes : nullptr;
-    a.boundary = static_cast<double *>(ctx->host_stage_dev);
-    a.status = reinterpret_cast<nv::ComposeStatus *>(work_at(ctx, p.status_off));
-    a.carry = reinterpret_cast<double *>(work_at(ctx, p.carry_off));
-    a.status_host = reinterpret_cast<nv::ComposeStatus *>(
-        static_cast<char *>(ctx->host_stage_dev) + p.stage_status_off);
+    a.tab0 = tables;
+    a.tab1 = p.dim == 2 ? static_cast<const char *>(tables) + p.comp_bytes : nullptr;
+    a.boundary = boundary;
+    a.status = reinterpret_cast<nv::ComposeStatus *>(work + p.status_off);
+    a.carry = reinterpret_cast<double *>(work + p.carry_off);
+    a.status_host = status_out;
     a.M = p.M;
-    a.n_slices = ctx->n_slices;
+    a.n_slices = n_slices;
     a.j_begin = j0;
     a.j_end = j1;
     a.n0 = g.n[0];
@@ -473,11 +503,22 @@ nv::ComposeArgs compose_args(const nv_ctx *ctx, const double *y0, int j0, int j1
     a.inv1 = p.dim == 2 ? double(g.n[1] - 1) / (g.hi[1] - g.lo[1]) : 0.0;
     a.hi0 = g.hi[0];
     a.nodes = g.interp == NV_INTERP_CHEBYSHEV
-                  ? reinterpret_cast<const double *>(work_at(ctx, p.nodes_off))
+                  ? reinterpret_cast<const double *>(work + p.nodes_off)
                   : nullptr;
     a.y00 = y0[0];
     a.y01 = p.dim == 2 ? y0[1] : 0.0;
     return a;
+}
+
+// ... over slices [j0, j1) of the context's last build, writing into the
+// context's mapped host memory.
+nv::ComposeArgs compose_args(const nv_ctx *ctx, const double *y0, int j0, int j1) {
+    return compose_args_at(
+        ctx->plan, ctx->grid, ctx->n_slices, ctx->tables, work_at(ctx, 0),
+        static_cast<double *>(ctx->host_stage_dev),
+        reinterpret_cast<nv::ComposeStatus *>(static_cast<char *>(ctx->host_stage_dev) +
+                                              ctx->plan.stage_status_off),
+        y0, j0, j1);
 }
 
 volatile nv::ComposeStatus *host_status(const nv_ctx *ctx) {
@@ -538,6 +579,48 @@ nv_status finish_compose(nv_ctx *ctx, hipStream_t st, double *yT, double *bounda
                     cs.bad_slice);
     return NV_OK;
 }
+
+}  // namespace
+
+// The scratch of nv_solve_static: one build's scratch, laid out as a
+// context's (the plan's offsets).  Each device that runs the library holds
+// its own copy until the process ends.  In host code this name stands for no
+// device address: the kernels get the address hipGetSymbolAddress gives for
+// the current device (static_scratch below).
+constexpr size_t kStaticScratchBytes = NV_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// The current device's address of the scratch, looked up once per device.
+nv_status static_scratch(char **out) {
+    int dev = -1;
+    NV_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(NV_ERR_UNSUPPORTED, "device %d: the static scratch serves devices 0..%d",
+                    dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(NV_ERR_HIP, "hipGetSymbolAddress of the static scratch failed on "
+                        "device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = static_cast<char *>(g_scratch_dev[dev]);
+    return NV_OK;
+}
+
+static_assert(sizeof(nv_solve_status) == sizeof(nv::ComposeStatus) &&
+                  offsetof(nv_solve_status, n_out_of_grid) ==
+                      offsetof(nv::ComposeStatus, n_out_of_grid) &&
+                  offsetof(nv_solve_status, bad_slice) == offsetof(nv::ComposeStatus, bad_slice) &&
+                  offsetof(nv_solve_status, done) == offsetof(nv::ComposeStatus, done),
+              "nv_solve_status is the composition's final status");
 
 }  // namespace
 
@@ -757,6 +840,50 @@ NV_API nv_status nv_solve(nv_ctx *ctx, int rhs_id, const double *params, double 
     return s;
 }
 
+NV_API nv_status nv_solve_static(int rhs_id, const double *params, double t0, double T,
+                                 int n_slices, const nv_ic_grid *grid, int steps_per_slice,
+                                 const nv_options *opt, void *tables_dev, size_t table_bytes,
+                                 const double *y0, double *boundary_dev,
+                                 nv_solve_status *status_dev) {
+    nv_status s = check_options(opt);
+    if (s != NV_OK) return s;
+    if (!y0 || !tables_dev || !boundary_dev || !status_dev)
+        return fail(NV_ERR_INVALID_ARG, "y0, tables_dev, boundary_dev and status_dev must not "
+                    "be NULL");
+    if (reinterpret_cast<uintptr_t>(tables_dev) % kAlign != 0 ||
+        reinterpret_cast<uintptr_t>(boundary_dev) % alignof(double) != 0 ||
+        reinterpret_cast<uintptr_t>(status_dev) % alignof(nv_solve_status) != 0)
+        return fail(NV_ERR_INVALID_ARG, "tables_dev must be 256-byte aligned, boundary_dev and "
+                    "status_dev 8-byte aligned");
+    if (grid && grid->interp == NV_INTERP_CHEBYSHEV)
+        return fail(NV_ERR_UNSUPPORTED, "nv_solve_static takes no Chebyshev grid (its nodes "
+                    "are uploaded from host memory)");
+    Plan p;
+    PreparedBuild pb;
+    s = describe_build(*opt, rhs_id, params, t0, T, n_slices, grid, steps_per_slice, &p, &pb);
+    if (s != NV_OK) return s;
+    if (p.table_bytes > table_bytes)
+        return fail(NV_ERR_BUFFER_TOO_SMALL, "tables need %zu bytes, %zu given", p.table_bytes,
+                    table_bytes);
+    if (p.work_bytes > kStaticScratchBytes)
+        return fail(NV_ERR_BUFFER_TOO_SMALL, "this build needs %zu bytes of scratch; the static "
+                    "scratch holds %zu (NV_STATIC_SCRATCH_BYTES)", p.work_bytes,
+                    kStaticScratchBytes);
+    char *work = nullptr;
+    s = static_scratch(&work);
+    if (s != NV_OK) return s;
+    place_build(&pb, p, tables_dev, work);
+    hipStream_t st = static_cast<hipStream_t>(opt->stream);
+    NV_HIP(launch_forcing_rows(pb, p, work, st));
+    NV_HIP(nv::launch_build(pb.cfg, pb.args, st));
+    NV_HIP(nv::launch_compose(grid->interp, opt->precision,
+                              compose_args_at(p, *grid, n_slices, tables_dev, work, boundary_dev,
+                                              reinterpret_cast<nv::ComposeStatus *>(status_dev),
+                                              y0, 0, n_slices),
+                              st));
+    return NV_OK;
+}
+
 NV_API nv_status nv_get_table(nv_ctx *ctx, int component, void *host_dst, size_t bytes) {
     if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
     if (!ctx->built) return fail(NV_ERR_NOT_BUILT, "no table before a successful build");
@@ -848,7 +975,7 @@ NV_API nv_status nv_last_timing(nv_ctx *ctx, float *build_ms, float *compose_ms)
     return NV_OK;
 }
 
-NV_API const char *nv_last_error(void) { return g_last_error.c_str(); }
+NV_API const char *nv_last_error(void) { return g_last_error; }
 
 NV_API const char *nv_status_string(int status) {
     switch (status) {

@@ -54,6 +54,14 @@ class nv_compose_info(ctypes.Structure):
                 ("n_chunks", ctypes.c_int)]
 
 
+class nv_solve_status(ctypes.Structure):
+    _fields_ = [("n_out_of_grid", ctypes.c_longlong), ("bad_slice", ctypes.c_int),
+                ("done", ctypes.c_int)]
+
+
+NV_STATIC_SCRATCH_BYTES = 64 << 20
+
+
 class nv_problem(ctypes.Structure):
     _fields_ = [("rhs_id", ctypes.c_int), ("params", ctypes.c_double * 2),
                 ("t0", ctypes.c_double), ("T", ctypes.c_double), ("n_slices", ctypes.c_int),
@@ -90,6 +98,9 @@ _SIGNATURES = {
     "nv_solve": [_P, ctypes.c_int, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                  ctypes.POINTER(nv_ic_grid), ctypes.c_int, _P, _P, _P,
                  ctypes.POINTER(nv_compose_info)],
+    "nv_solve_static": [ctypes.c_int, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                        ctypes.POINTER(nv_ic_grid), ctypes.c_int, ctypes.POINTER(nv_options),
+                        _P, ctypes.c_size_t, _P, _P, _P],
     "nv_get_table": [_P, ctypes.c_int, _P, ctypes.c_size_t],
     "nv_table_device_ptr": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)],
     "nv_get_nonfinite_counts": [_P, _P, ctypes.c_int],
@@ -253,6 +264,22 @@ def nv_solve(ctx, rhs_id, params, t0, T, n_slices, grid: nv_ic_grid, steps_per_s
     if st not in (NV_OK, NV_ERR_NONFINITE):
         _check(st)
     return st, yT, boundary, info
+
+
+def nv_solve_static(rhs_id, params, t0, T, n_slices, grid: nv_ic_grid, steps_per_slice,
+                    opt: nv_options, tables_dev, table_bytes, y0, boundary_dev, status_dev):
+    """Queues the build and the composition on opt.stream with the library's
+    static scratch; the outputs are device addresses (read them after the
+    stream).  Raises on every status other than NV_OK."""
+    p = np.ascontiguousarray(np.asarray(params if params is not None else [0.0],
+                                        dtype=np.float64).reshape(-1))
+    if p.size == 0:
+        p = np.zeros(1)
+    y0 = np.ascontiguousarray(np.asarray(y0, dtype=np.float64).reshape(-1))
+    return _check(load().nv_solve_static(int(rhs_id), _ptr(p), float(t0), float(T),
+                                         int(n_slices), ctypes.byref(grid),
+                                         int(steps_per_slice), ctypes.byref(opt), tables_dev,
+                                         int(table_bytes), _ptr(y0), boundary_dev, status_dev))
 
 
 def nv_get_table(ctx, component, n_slices, points, precision):

@@ -145,6 +145,43 @@ def test_null_context_and_destroy_null(nvmod):
         nvmod.NV_ERR_INVALID_ARG
 
 
+def test_solve_static_argument_errors_need_no_gpu(nvmod):
+    # every rejection happens before the library looks up its static scratch
+    # (its first HIP call): the device addresses below are never touched
+    lib = nvmod.load()
+    fake_tab, fake_b, fake_s = 0x10000, 0x20000, 0x30000
+    y0 = np.array([0.1])
+    p0 = np.zeros(1)
+
+    def call(grid, n_slices=64, steps=1000, opt=None, tab=fake_tab, tab_bytes=1 << 40,
+             y=y0, rhs=nvmod.NV_RHS_LOGISTIC, t0=0.0, T=10.0):
+        o = opt if opt is not None else nvmod.make_options(precision="fp32")
+        return lib.nv_solve_static(rhs, nvmod._ptr(p0), t0, T, n_slices, ctypes.byref(grid),
+                                   steps, ctypes.byref(o), tab, tab_bytes,
+                                   nvmod._ptr(y) if y is not None else None, fake_b, fake_s)
+
+    g = _grid(nvmod)
+    assert lib.nv_solve_static(1, None, 0.0, 1.0, 1, ctypes.byref(g), 1, None, fake_tab, 1,
+                               nvmod._ptr(y0), fake_b, fake_s) == nvmod.NV_ERR_INVALID_ARG
+    assert call(g, y=None) == nvmod.NV_ERR_INVALID_ARG
+    assert call(g, tab=fake_tab + 8) == nvmod.NV_ERR_INVALID_ARG       # not 256-byte aligned
+    assert call(g, n_slices=0) == nvmod.NV_ERR_INVALID_ARG
+    assert call(g, t0=1.0, T=1.0) == nvmod.NV_ERR_INVALID_ARG
+    assert call(_grid(nvmod, n=(5,), lo=(0.0,), hi=(2.0,), interp="chebyshev"),
+                rhs=nvmod.NV_RHS_SQUARE) == nvmod.NV_ERR_UNSUPPORTED
+    assert call(g, tab_bytes=1024) == nvmod.NV_ERR_BUFFER_TOO_SMALL     # tables too small
+    assert "tables need" in nvmod.nv_last_error()
+    # FP64 forcing rows of 4096 slices x 2000 steps: 131 MB > the static scratch
+    big = _grid(nvmod, n=(4096,), lo=(-3.0,), hi=(3.0,), interp="hermite")
+    assert call(big, n_slices=4096, steps=2000, rhs=nvmod.NV_RHS_FORCED_CUBIC, T=100.0,
+                opt=nvmod.make_options(precision="fp64")) == nvmod.NV_ERR_BUFFER_TOO_SMALL
+    assert "static scratch" in nvmod.nv_last_error()
+    # the FP32 build of the same shape fits
+    _, wb = nvmod.nv_required_bytes(nvmod.NV_RHS_FORCED_CUBIC, 4096, big, 2000,
+                                    nvmod.make_options(precision="fp32"))
+    assert wb <= nvmod.NV_STATIC_SCRATCH_BYTES
+
+
 def test_product_path_does_not_import_the_oracle():
     pkg = os.path.join(ROOT, "paper_1304_6514_amd")
     for dirpath, _, files in os.walk(pkg):

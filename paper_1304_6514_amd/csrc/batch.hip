@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -398,7 +399,11 @@ NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int co
             return fail(s, "%s", msg);
         }
     }
-    nv_batch *b = new (std::nothrow) nv_batch();
+    // owned by the guard until the batch is complete: every failure below,
+    // a host allocation that throws included, frees what was set up so far
+    std::unique_ptr<nv_batch, void (*)(nv_batch *)> guard(new (std::nothrow) nv_batch(),
+                                                          free_batch);
+    nv_batch *b = guard.get();
     if (!b) return fail(NV_ERR_OOM, "out of host memory");
     b->count = count;
     b->problems.assign(problems, problems + count);
@@ -406,7 +411,6 @@ NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int co
     b->accumulation = opt.compensated;
     b->scheme = opt.scheme;
     if (b->scheme != NV_SCHEME_RK4 || opt.dt != 0.0) {
-        delete b;
         return fail(NV_ERR_UNSUPPORTED, "batches integrate with RK4 and equal steps per slice");
     }
     const size_t elem = b->precision == NV_FP64 ? sizeof(double) : sizeof(float);
@@ -434,7 +438,6 @@ NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int co
     b->total_slices = nf;
     b->tables_bytes = toff;
     if (b->max_items > 0x7fffffffLL) {
-        delete b;
         return fail(NV_ERR_INVALID_ARG, "batch has more than 2^31-1 work items");
     }
     size_t off = 0;
@@ -456,7 +459,6 @@ NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int co
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&b->tables), b->tables_bytes);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&b->work), b->work_bytes);
     if (e != hipSuccess) {
-        free_batch(b);
         return fail(NV_ERR_OOM, "device allocation of %zu + %zu bytes failed", b->tables_bytes,
                     b->work_bytes);
     }
@@ -465,7 +467,6 @@ NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int co
     if (e == hipSuccess) e = hipEventCreate(&b->ev0);
     if (e == hipSuccess) e = hipEventCreate(&b->ev1);
     if (e != hipSuccess) {
-        free_batch(b);
         return fail(NV_ERR_HIP, "batch set-up failed: %s", hipGetErrorString(e));
     }
 
@@ -531,11 +532,8 @@ NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int co
     def.workgroups_per_cu = 8;
     def.order = 0;
     s = apply_schedule(b, def);
-    if (s != NV_OK) {
-        free_batch(b);
-        return s;
-    }
-    *out = b;
+    if (s != NV_OK) return s;
+    *out = guard.release();
     return NV_OK;
 } catch (const std::bad_alloc &) {
     return fail(NV_ERR_OOM, "nv_batch_create: host allocation failed");

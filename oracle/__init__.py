@@ -25,6 +25,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nv_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_CB_SRC = os.path.join(_HERE, "cpu_build.c")
+_CB_LIB = os.path.join(_HERE, "libcpubuild.so")
 
 _RHS = {"linear": 10, "logistic": 11, "forced_cubic": 12, "vdp": 13, "square": 14}
 _SCHEME = {"rk4": 1, "euler": 2}
@@ -35,11 +37,16 @@ _lib = None
 
 
 def build() -> str:
-    """Compile the oracle with gcc (FP64, one rounding per operation)."""
+    """Compile the oracle with gcc (FP64, one rounding per operation), and the
+    CPU throughput baseline beside it (cpu_build.c, OpenMP)."""
     cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
            "-fno-fast-math", "-Wall", "-Wextra", "-o", _LIB + ".tmp", _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
+    cmd = ["gcc", "-std=c99", "-O3", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-o", _CB_LIB + ".tmp", _CB_SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_CB_LIB + ".tmp", _CB_LIB)
     return _LIB
 
 
@@ -83,6 +90,55 @@ def _load():
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+_cb = None
+
+
+def _load_cpu_build():
+    global _cb
+    if _cb is not None:
+        return _cb
+    if not os.path.exists(_CB_LIB):
+        build()
+    lib = ctypes.CDLL(_CB_LIB)
+    D, I, P = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
+    for name in ("cb_build_f64", "cb_build_f32"):
+        fn = getattr(lib, name)
+        fn.restype = I
+        fn.argtypes = [I, D, D, D, I, I, I, I, P, P, P, I, I, P]
+    lib.cb_max_threads.restype = I
+    lib.cb_max_threads.argtypes = []
+    _cb = lib
+    return lib
+
+
+_CB_RHS = {"logistic": 1, "forced_cubic": 2, "vdp": 3}
+
+
+def cpu_build(rhs, params, t0, T, n_slices, grid_n, grid_lo, grid_hi, steps_per_slice,
+              precision="fp64", slices=None, threads=None):
+    """NOT the oracle: the CPU throughput baseline of cpu_build.c (OpenMP over
+    all host cores, forcing hoisted per slice, FP64 = the oracle's operations
+    in its order, FP32 with blocked summation).  Tables of slices
+    [slices[0], slices[1]) as an array (dim, slices, points)."""
+    lib = _load_cpu_build()
+    n = np.ascontiguousarray(np.atleast_1d(grid_n), dtype=np.int32)
+    lo = _f64(grid_lo)
+    hi = _f64(grid_hi)
+    dim = n.size
+    s0, s1 = slices if slices is not None else (0, n_slices)
+    M = int(np.prod(n))
+    dt = np.float64 if precision == "fp64" else np.float32
+    tab = np.empty((dim, s1 - s0, M), dtype=dt)
+    fn = lib.cb_build_f64 if precision == "fp64" else lib.cb_build_f32
+    mu = float(params[0]) if params else 0.0
+    th = int(threads) if threads else lib.cb_max_threads()
+    rc = fn(_CB_RHS[rhs], mu, float(t0), float(T), int(n_slices), int(s0), int(s1), dim,
+            _ptr(n), _ptr(lo), _ptr(hi), int(steps_per_slice), th, _ptr(tab))
+    if rc != 0:
+        raise OracleError(f"cpu_build: status {rc}")
+    return tab
 
 
 class OracleError(RuntimeError):

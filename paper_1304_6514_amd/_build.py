@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnv.so")
 OBJDIR = os.path.join(PKG, "_build")
 SOURCES = ["nv_capi.hip", "build_kernels.hip", "compose_kernels.hip", "batch.hip",
-           "surrogate.hip", "linear.hip"]
+           "surrogate.hip", "linear.hip", "probe.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

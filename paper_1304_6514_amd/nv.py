@@ -119,6 +119,8 @@ _SIGNATURES = {
                              ctypes.POINTER(ctypes.c_longlong)],
     "nv_batch_get_table": [_P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t],
     "nv_batch_get_boundary": [_P, ctypes.c_int, _P, ctypes.c_size_t],
+    "nv_probe_fma_latency": [ctypes.c_int, ctypes.c_longlong, _P,
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "nv_last_error": [],
     "nv_status_string": [ctypes.c_int],
 }
@@ -314,6 +316,14 @@ def nv_last_timing(ctx):
     b, c = ctypes.c_float(), ctypes.c_float()
     _check(load().nv_last_timing(ctx, ctypes.byref(b), ctypes.byref(c)))
     return b.value, c.value
+
+
+def nv_probe_fma_latency(precision="fp64", ops=1 << 22, stream=None):
+    """(ns, shader-clock cycles) per dependent FMA of one wave's chain."""
+    ns, cyc = ctypes.c_double(), ctypes.c_double()
+    _check(load().nv_probe_fma_latency(PRECISIONS.get(precision, precision), int(ops), stream,
+                                       ctypes.byref(ns), ctypes.byref(cyc)))
+    return ns.value, cyc.value
 
 
 # ---- batches ----------------------------------------------------------------

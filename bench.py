@@ -41,17 +41,22 @@ RHS_FLOPS = {"linear": 1, "logistic": 2, "forced_cubic": 3, "vdp": 5, "square": 
 WORKLOADS = {"forced_cubic": W.FORCED_CUBIC_FP32, "logistic": W.LOGISTIC_FP64,
              "vdp": W.VDP_FP32}
 
-# HBM bytes per launch of the build kernel over the whole workload, from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the same counters' reading of
-# a cold 256 MiB elementwise copy (profiles/build_kernel_forced_cubic_*.md,
-# profiles/build_and_compose_*.md).
-# Valid only for the kernel source they were taken with (SHA-1 below); any
-# other source gives traffic = null.
+# HBM bytes per timed step of the build launches, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (raw counters, summed over the step's build dispatches; the
+# profile files under profiles/ give the commands).  Keyed by workload,
+# accumulation, mode, build launches per step and the SHA-1 of the kernel
+# sources they were taken with; any other source gives traffic = null.
 MEASURED_TRAFFIC = {
-    ("forced-cubic-fp32-4096sl-4096pt-2000st", "blocked", "e03ec79969c5e4534c83aee7e785134af2500475"): 198.4e6,
-    ("vdp-fp32-1024sl-128x128pt-500st", "blocked", "e03ec79969c5e4534c83aee7e785134af2500475"): 134.4e6,
-    ("logistic-fp64-64sl-256pt-1000st", "blocked", "e03ec79969c5e4534c83aee7e785134af2500475"): 174.0e3,
+    ("forced-cubic-fp32-4096sl-4096pt-2000st", "blocked", "solve", 32,
+     "e03ec79969c5e4534c83aee7e785134af2500475"): (64800.0 + 65664.0) * 1024,
 }
+
+# dependent floating-point operations on the critical path of one RK4 step of
+# the builds bound by that chain (read off the compiled loop): FP64 logistic:
+# k1, the stage value, k2, the stage value, k3, the stage value, k4, k1 + k4,
+# + 2 (k2 + k3), y + (h/6) (...)
+CHAIN_OPS = {"logistic-fp64-64sl-256pt-1000st": 10}
+
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1304_6514_amd", "csrc", f)
                   for f in ("integrate.h", "build_kernels.hip")]
 
@@ -83,24 +88,90 @@ def flops_per_step(w: W.Workload, compensated: bool) -> int:
     return f
 
 
-def cpu_baseline(w: W.Workload, n_slices_sample: int):
-    """The oracle (as it is, single-threaded C) on the first slices of w."""
+def host_description():
+    """nproc, the CPUs this process may run on, and the CPU model name."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "model": model}
+
+
+def cpu_threads(host) -> int:
+    """Host threads for the CPU baselines: every usable CPU, at most 16 (the
+    host share of one GPU)."""
+    return max(1, min(16, int(host["usable_cpus"] or 1)))
+
+
+def cpu_baseline(w: W.Workload, threads: int, steps_per_thread: float = 1.5e8):
+    """The oracle as it is (plain serial C, FP64) on `threads` host threads at
+    once, each integrating its own whole slices of w (ctypes releases the
+    interpreter lock during each call): a bounded sample of the workload."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
 
     oracle._load()
     g = oracle.make_grid(w.grid_n, w.grid_lo, w.grid_hi)
-    sl = np.repeat(np.arange(n_slices_sample, dtype=np.int64), w.points_per_slice)
-    pt = np.tile(np.arange(w.points_per_slice, dtype=np.int64), n_slices_sample)
-    t = time.perf_counter()
-    oracle.table_entries(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, g,
-                         w.steps_per_slice, sl, pt)
-    dt = time.perf_counter() - t
-    steps = sl.size * w.steps_per_slice
-    return {"value": steps / dt, "unit": "trajectory-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"slices 0..{n_slices_sample - 1} of {w.name}: "
-                      f"{sl.size} trajectories x {w.steps_per_slice} steps "
-                      f"({steps:.3g} trajectory-steps, {dt:.1f} s, FP64, one thread)"}
+    per_slice = w.points_per_slice * w.steps_per_slice
+    per_thread = int(max(1, min(w.n_slices // threads, round(steps_per_thread / per_slice))))
+    per_thread = max(per_thread, 1)
+    threads = min(threads, w.n_slices)
+
+    def run(i):
+        sl = np.repeat(np.arange(i * per_thread, (i + 1) * per_thread, dtype=np.int64),
+                       w.points_per_slice)
+        pt = np.tile(np.arange(w.points_per_slice, dtype=np.int64), per_thread)
+        oracle.table_entries(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, g,
+                             w.steps_per_slice, sl, pt)
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        t = time.perf_counter()
+        list(ex.map(run, range(threads)))
+        dt = time.perf_counter() - t
+    steps = threads * per_thread * per_slice
+    return {"value": steps / dt, "unit": "trajectory-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"slices 0..{threads * per_thread - 1} of {w.name} "
+                      f"({threads} threads x {per_thread} slices, {steps:.3g} "
+                      f"trajectory-steps, {dt:.1f} s, FP64 serial oracle per thread)"}
+
+
+def cpu_parallel_build(w: W.Workload, threads: int, slices_per_thread: int = 64):
+    """The CPU throughput baseline of the table build (OpenMP over `threads`
+    host threads, forcing hoisted per slice, vectorised over trajectories) in
+    FP64 and FP32 on a bounded number of the workload's slices."""
+    import oracle
+
+    ns = min(w.n_slices, threads * slices_per_thread)
+    out = {"threads": threads, "slices": ns,
+           "what": "table build of the first slices, OpenMP over host threads, 64 "
+                   "trajectories per vectorised block; FP64 = the oracle's operations, FP32 "
+                   "with blocked summation"}
+    for prec in ("fp64", "fp32"):
+        oracle.cpu_build(w.rhs, w.params, w.t0, w.T, w.n_slices, w.grid_n, w.grid_lo,
+                         w.grid_hi, w.steps_per_slice, prec, slices=(0, min(ns, threads)),
+                         threads=threads)                       # warm-up
+        # repeated until 0.3 s have passed (small workloads take milliseconds)
+        reps, t = 0, time.perf_counter()
+        while reps == 0 or time.perf_counter() - t < 0.3:
+            oracle.cpu_build(w.rhs, w.params, w.t0, w.T, w.n_slices, w.grid_n, w.grid_lo,
+                             w.grid_hi, w.steps_per_slice, prec, slices=(0, ns), threads=threads)
+            reps += 1
+        dt = (time.perf_counter() - t) / reps
+        out[prec] = {"trajectory_steps_per_s": ns * w.points_per_slice * w.steps_per_slice / dt,
+                     "s_per_build": round(dt, 4), "repetitions": reps}
+    return out
 
 
 def method_equal_error(prop, w: W.Workload, ref, target):
@@ -116,13 +187,17 @@ def method_equal_error(prop, w: W.Workload, ref, target):
     from paper_1304_6514_amd import nv
 
     tried, meeting, best = 0, 0, None
+    # grids: 1-D point counts, or square 2-D grids on the same box
+    grids = ([(M,) for M in (256, 512, 1024, 2048, 4096)] if w.dim == 1 else
+             [(n, n) for n in (16, 32, 64, 128)])
     for N in (8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096):
-        for M in (256, 512, 1024, 2048, 4096):
+        for gn in grids:
             for S in (10, 20, 50, 100, 200, 500):
+                M = int(np.prod(gn))
                 if N > w.n_slices or M > w.points_per_slice or S > w.steps_per_slice:
                     continue
-                c = w.with_(name=f"{w.name}-eq-{N}x{M}x{S}", n_slices=N, grid_n=(M,),
-                            steps_per_slice=S)
+                c = w.with_(name=f"{w.name}-eq-{N}x{'x'.join(map(str, gn))}x{S}", n_slices=N,
+                            grid_n=gn, steps_per_slice=S)
                 tried += 1
                 r = prop.solve(c)
                 if r.status != nv.NV_OK:
@@ -140,7 +215,8 @@ def method_equal_error(prop, w: W.Workload, ref, target):
                     ts.append(time.perf_counter() - t)
                 ms = 1e3 * min(ts)
                 if best is None or ms < best["gpu_ms"]:
-                    best = {"n_slices": N, "points_per_slice": M, "steps_per_slice": S,
+                    best = {"n_slices": N, "grid": list(gn), "points_per_slice": M,
+                            "steps_per_slice": S,
                             "error": e, "gpu_ms": round(ms, 4),
                             "trajectory_steps": N * M * S}
     return {"configs_tried": tried, "configs_meeting_error": meeting, "fastest": best}
@@ -193,7 +269,7 @@ def fixed_error(w: W.Workload, yT_method, gpu_ms, prop=None):
            "serial_same_step": {"steps": n_same, "ms": round(1e3 * t_same, 3)},
            "serial_equal_error": {"steps": hi, "error": err(hi), "ms": round(1e3 * t_eq, 4)},
            "cores": 1}
-    if prop is not None and w.dim == 1:
+    if prop is not None:
         out["method_equal_error"] = method_equal_error(prop, w, ref, method_err)
     return out
 
@@ -209,8 +285,7 @@ def bench_batched(args):
 
     probs = W.batched_problems()
     total_steps = sum(w.trajectory_steps for w in probs)
-    flops = sum(w.trajectory_steps * (flops_per_step(w, compensated=False) + w.dim)
-                for w in probs)
+    flops = sum(w.trajectory_steps * flops_per_step(w, compensated=False) for w in probs)
     b = Batch(probs)
     t = time.perf_counter()
     sched = b.autotune(reps=2)
@@ -630,8 +705,6 @@ def main():
     ap.add_argument("--two-phase", action="store_true",
                     help="time nv_build_propagators + nv_compose instead of nv_solve")
     ap.add_argument("--solve-chunks", type=int, default=0)
-    ap.add_argument("--cpu-slices", type=int, default=32,
-                    help="slices of the workload the CPU oracle baseline integrates")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one elementwise copy kernel (reads and writes this many "
@@ -703,32 +776,31 @@ def main():
         torch.cuda.synchronize()
         del x, y, flush
 
+    # HIP events bracket the build launches of every step (in solve mode the
+    # span from before the first chunk launch to after the last one, on the
+    # stream they are launched on) and the composition
+    prop.set_timing(True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
-    # timed region: K whole steps
+    # timed region: K whole steps; each step's build span is read once the
+    # step has returned (its events are complete by then)
+    span_ms, exposed_ms = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         r = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-
-    # build span of the timed path (HIP events; in solve mode all chunk launches)
-    prop.set_timing(True)
-    span_ms, exposed_ms = [], []
-    for _ in range(args.steps):
-        rr = step()
         b, c = prop.last_timing()
         span_ms.append(b)
         exposed_ms.append(c)
-    launches = rr.n_chunks if not args.two_phase else 1
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    launches = r.n_chunks if not args.two_phase else 1
 
-    # the dominant kernel alone: one launch of the integration kernel over the
-    # whole workload, and one composition launch over all slices (tau_N); HIP
-    # events on the stream the kernels run on
+    # for comparison: one launch of the integration kernel over the whole
+    # workload, and one composition launch over all slices (tau_N)
     kern_ms, comp_ms = [], []
     for _ in range(args.steps):
         prop.build(w)
@@ -737,27 +809,46 @@ def main():
         kern_ms.append(b)
         comp_ms.append(c)
     prop.set_timing(False)
-    avg_kernel_ms = sum(kern_ms) / len(kern_ms)
+    avg_single_ms = sum(kern_ms) / len(kern_ms)
     avg_compose_ms = sum(comp_ms) / len(comp_ms)
+    avg_span_ms = sum(span_ms) / len(span_ms)
 
-    fps = flops_per_step(w, compensated=args.compensated != 0)
-    if w.precision == "fp32" and args.compensated == 2:
-        fps = flops_per_step(w, compensated=False) + w.dim   # one extra add per component
-    achieved_tflops = w.trajectory_steps * fps / (avg_kernel_ms * 1e-3) / 1e12
+    # algorithmic FLOPs of the method's RK4 step (the accumulation mode's extra
+    # operations are not counted)
+    fps = flops_per_step(w, compensated=False)
+    achieved_tflops = w.trajectory_steps * fps / (avg_span_ms * 1e-3) / 1e12
     peak = PEAK_FP64_VECTOR_TFLOPS if w.precision == "fp64" else PEAK_FP32_VECTOR_TFLOPS
+    chunking = "solve" if not args.two_phase else "two-phase"
+    traffic = MEASURED_TRAFFIC.get((w.name, ["plain", "kahan", "blocked"][args.compensated],
+                                    chunking, launches, kernel_source_sha1()))
     roofline = {
         "bound": "alu", "achieved": round(achieved_tflops, 3), "peak": peak,
         "unit": "TFLOP/s", "frac": round(achieved_tflops / peak, 4),
-        "traffic": MEASURED_TRAFFIC.get(
-            (w.name, ["plain", "kahan", "blocked"][args.compensated], kernel_source_sha1())),
-        "traffic_unit": "HBM bytes per launch",
+        "traffic": traffic,
+        "traffic_unit": "HBM bytes per step (raw FETCH_SIZE + WRITE_SIZE over the step's "
+                        "build launches)",
         "algorithmic_bytes": algorithmic_bytes(w),
-        "kernel": "build_kernel (ensemble RK4 integration + table write), one launch over "
-                  "the whole workload",
-        "kernel_ms": round(avg_kernel_ms, 4),
+        "kernel": f"build_kernel (ensemble RK4 integration + table write): the {launches} "
+                  f"build launches of the timed step, HIP-event span",
+        "kernel_ms": round(avg_span_ms, 4),
         "flops_per_trajectory_step": fps,
-        "trajectory_steps_per_launch": w.trajectory_steps,
+        "trajectory_steps_per_span": w.trajectory_steps,
+        "single_launch_ms": round(avg_single_ms, 4),
     }
+    if w.name in CHAIN_OPS:
+        # too few trajectories to fill the chip: bound by each trajectory's
+        # chain of dependent operations (S x critical path x dependent latency)
+        ns_op, cyc_op = nv.nv_probe_fma_latency(w.precision, 1 << 22,
+                                                prop.stream.cuda_stream)
+        ops = CHAIN_OPS[w.name]
+        bound_ms = w.steps_per_slice * ops * ns_op * 1e-6
+        roofline["chain_bound"] = {
+            "dependent_ops_per_step": ops, "ns_per_dependent_fma": round(ns_op, 4),
+            "clock_ticks_per_dependent_fma": round(cyc_op, 3),
+            "bound_ms": round(bound_ms, 5), "frac": round(bound_ms / avg_span_ms, 4),
+            "what": "steps x dependent FP operations on one RK4 step's critical path x the "
+                    "measured dependent-FMA latency (every trajectory is one such chain; "
+                    "the build has one wave per SIMD on a quarter of the CUs)"}
 
     value = w.trajectory_steps * args.steps / elapsed
     out = {
@@ -781,17 +872,21 @@ def main():
         "accumulation": ["plain", "kahan", "blocked"][args.compensated]
         if w.precision == "fp32" else "fp64",
         "build_launches_per_step": launches,
-        "build_span_ms": round(sum(span_ms) / len(span_ms), 4),
+        "build_span_ms": round(avg_span_ms, 4),
         "compose_exposed_ms": round(sum(exposed_ms) / len(exposed_ms), 4)
         if not args.two_phase else None,
-        "build_kernel_trajectory_steps_per_s": w.trajectory_steps / (avg_kernel_ms * 1e-3),
+        "build_trajectory_steps_per_s": w.trajectory_steps / (avg_span_ms * 1e-3),
         "compose_alone_ms": round(avg_compose_ms, 4),
         "tau_N_us": round(1e3 * avg_compose_ms / w.n_slices, 4),
         "yT": [float(v) for v in r.yT],
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_slices, w.n_slices))
+        host = host_description()
+        threads = cpu_threads(host)
+        out["cpu_baseline"] = cpu_baseline(w, threads)
+        out["cpu_baseline"]["host"] = host
+        out["cpu_parallel_build"] = cpu_parallel_build(w, threads)
         out["time_to_yT_vs_serial"] = fixed_error(w, r.yT, round(ms_per_step, 4), prop)
     prop.close()
     print(json.dumps(out), flush=True)

@@ -469,8 +469,18 @@ def bench_surrogate(args):
         raise RuntimeError(f"training build failed: {nv.status_name(st)}")
     build_ms, build_steps = b.last_timing()
     coarse = args.sur_coarse
-    sur = Surrogate("cuda:0", max_batch=B, coarse_steps=coarse,
-                    out_scale=W.SUR_OUT_SCALE if coarse == 0 else W.SUR_OUT_SCALE_COARSE)
+    base = W.VDP_FP32
+    # the step-doubling form: phi ~ G1 + d (16/15 + out_scale g out)
+    sur = Surrogate("cuda:0", max_batch=B, coarse_steps=coarse, correction="step-doubling",
+                    out_scale=W.SUR_SD_OUT_SCALE, gate=W.SUR_SD_GATE,
+                    loss_scale=W.SUR_SD_LOSS_SCALE)
+    # visit weights: the states Richardson chains (the untrained form) visit
+    mug = np.linspace(1.0, 5.0, W.SUR_VISIT_MUS)
+    t = time.perf_counter()
+    st, _, vis, _ = sur.compose(np.tile(base.y0, (len(mug), 1)), mug, base.t0, base.T,
+                                base.n_slices, want_boundary=True)
+    visit_ms = 1e3 * (time.perf_counter() - t)
+    sur.set_visits(vis, 1.0, 5.0, W.SUR_VISIT_SIGMA, W.SUR_VISIT_FLOOR)
     total = nv.nv_sur_dataset_from_batch(sur.h, b.batch)
     perm = W.surrogate_perm(total)
     t = time.perf_counter()
@@ -495,6 +505,7 @@ def bench_surrogate(args):
 
     # the kernels of one training step, timed alone (HIP events inside the call)
     xs, ts = W.surrogate_samples(B, seed=31)
+    ts = np.concatenate([ts, np.ones_like(ts)])      # rho, and unit weights
     sur.loss_grad(xs, ts)
     step_ms = []
     xd = torch.from_numpy(xs).cuda()
@@ -514,7 +525,6 @@ def bench_surrogate(args):
     # evaluation on held-out mu: truth = the library's FP64 integration of the
     # whole interval from y0 (a one-slice build whose first grid point is y0)
     mus = W.surrogate_eval_mus(8)
-    base = W.VDP_FP32
     truth = []
     with Propagator("cuda:0") as pr:
         for mu in mus:
@@ -535,11 +545,14 @@ def bench_surrogate(args):
     err_sur = np.max(np.abs(fin.cpu().numpy() - truth), axis=1)
     trained = sur.params()
     off = trained.copy()
-    off[-258:] = 0.0                          # W4 = 0, b4 = 0: the coarse propagator alone
+    off[-258:] = 0.0                          # W4 = 0, b4 = 0: Richardson alone
     sur.set_params(off)
     _, fin0, _, _ = sur.compose(y0, mus, base.t0, base.T, base.n_slices)
-    err_coarse = np.max(np.abs(fin0.cpu().numpy() - truth), axis=1)
+    err_rich = np.max(np.abs(fin0.cpu().numpy() - truth), axis=1)
     sur.set_params(trained)
+    with Surrogate("cuda:0", max_batch=16, coarse_steps=coarse) as g1:   # zero network: G1
+        _, fin1, _, _ = g1.compose(y0, mus, base.t0, base.T, base.n_slices)
+        err_coarse = np.max(np.abs(fin1.cpu().numpy() - truth), axis=1)
     st1, _, _, info1 = sur.compose(y0[:1], mus[:1], base.t0, base.T, base.n_slices)
     many = 16384
     stq, _, _, infoq = sur.compose(np.tile(base.y0, (many, 1)), np.resize(mus, many), base.t0,
@@ -581,19 +594,23 @@ def bench_surrogate(args):
         "data": "synthetic",
         "config": {"workload": "vdp-surrogate-1024x128x128x500-perslice-mu",
                    "network": "4-128-128-128-2 exact GELU", "batch": B, "epochs": args.sur_epochs,
+                   "form": "step-doubling (G1 + d (16/15 + s g out)), visit-weighted loss",
                    "coarse_rk4_steps": coarse,
                    "samples": total, "lr": [args.sur_lr, args.sur_lr_final],
                    "parallelism": "single-gpu"},
         "training_build": {"ms": round(build_ms, 3), "trajectory_steps": build_steps,
                            "trajectory_steps_per_s": build_steps / (build_ms * 1e-3)},
-        "gather_ms": round(gather_ms, 3),
+        "gather_ms": round(gather_ms, 3), "visit_chains_ms": round(visit_ms, 3),
         "train_s": round(train_s, 3), "train_events_ms": round(train_ms_events, 2),
         "loss": {"first": float(losses[0]), "last": float(losses[-1]),
                  "last_epoch_mean": float(losses[-steps_per_epoch:].mean())},
         "step_ms_loss_grad": round(min(step_ms), 4),
         "eval": {"mus": [float(m) for m in mus], "truth": "library FP64 serial RK4, 512000 steps",
                  "surrogate_errors": [float(e) for e in err_sur], "surrogate_max_error": e_sur,
+                 "richardson_alone_errors": [float(e) for e in err_rich],
+                 "richardson_alone_max_error": float(np.max(err_rich)),
                  "coarse_alone_errors": [float(e) for e in err_coarse],
+                 "coarse_alone_max_error": float(np.max(err_coarse)),
                  "surrogate_compose_ms_8_chains": round(sur_ms, 3),
                  "surrogate_compose_ms_1_chain": round(info1.ms, 3),
                  "surrogate_compose_ms_16384_chains": round(infoq.ms, 3),

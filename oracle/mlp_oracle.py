@@ -16,11 +16,15 @@ multilayer perceptron
     out = W4 a3 + b4                         W4: 2 x 128
 
 with the exact GELU, gelu(z) = z Phi(z), Phi the standard normal distribution
-function.  Its output is the slice map's correction to a coarse propagator G
-in units of ``out_scale``: phi^j(y) ~ G(y) + out_scale * out, G the identity
-or a few RK4 steps over the slice (``coarse_step``).  The training loss is the mean over samples of
-the squared error summed over the two outputs; the optimiser is Adam (Kingma
-and Ba, "Adam: a method for stochastic optimization", Algorithm 1).
+function.  Its output corrects a coarse propagator: additively,
+phi^j(y) ~ G(y) + out_scale * out, G the identity or a few RK4 steps over the
+slice (``coarse_step``); or in the step-doubling form, phi^j(y) ~ G1 +
+d (16/15 + out_scale g out) with d the difference of one coarse step to two of
+half the length and g a gate in d (``step_doubling_map``; with out = 0 this is
+Richardson extrapolation of the coarse step).  The training loss is the mean
+over samples of the squared error summed over the two outputs (weighted per
+sample in the step-doubling form); the optimiser is Adam (Kingma and Ba,
+"Adam: a method for stochastic optimization", Algorithm 1).
 
 Flat parameter order: W1 (row-major, out x in), b1, W2, b2, W3, b3, W4, b4;
 33,922 numbers.
@@ -105,16 +109,19 @@ def forward(params, x, shift, scale, emulate_bf16=False):
     return out, cache
 
 
-def loss_and_grad(params, x, target, shift, scale, emulate_bf16=False):
-    """Loss = mean over the n samples of sum_c (out_c - target_c)^2, and its
-    gradient by the chain rule, layer by layer from the output back."""
+def loss_and_grad(params, x, target, shift, scale, emulate_bf16=False, weights=None):
+    """Loss = mean over the n samples of sum_c e_c^2, e_c = out_c - target_c, or
+    with per-sample weights w (n, 2) the weighted least-squares error
+    e_c = w_c out_c - target_c; and its gradient by the chain rule, layer by
+    layer from the output back."""
     p = params if isinstance(params, dict) else unflatten(params)
     r = bf16 if emulate_bf16 else (lambda v: v)
     out, c = forward(p, x, shift, scale, emulate_bf16)
     n = out.shape[0]
-    err = out - np.asarray(target, np.float64)
+    w = np.ones_like(out) if weights is None else np.asarray(weights, np.float64)
+    err = w * out - np.asarray(target, np.float64)
     loss = float(np.sum(err * err) / n)
-    dout = 2.0 * err / n                                   # dL/d out
+    dout = 2.0 * err * w / n                               # dL/d out
     g = {}
     dq = r(dout)
     g["W4"] = dq.T @ r(c["a3"])
@@ -175,11 +182,70 @@ def coarse_step(y, mu, L, k):
     return y
 
 
+# Richardson's constant of a fourth-order step: G1's error is about 16/15 of
+# the step-doubling difference G2 - G1.
+RICHARDSON = 16.0 / 15.0
+
+
+def step_doubling(y, mu, L, k, gate):
+    """The step-doubling form's pieces at y (..., 2): G1 = k RK4 steps of L / k,
+    d = G2 - G1 with G2 = 2k RK4 steps of L / (2k), and the gate
+    g_c = d_c^2 / (d_c^2 + gate_c^2).  Returns (G1, d, g)."""
+    g1 = coarse_step(y, mu, L, k)
+    g2 = coarse_step(y, mu, L, 2 * k)
+    d = g2 - g1
+    tau2 = np.asarray(gate, np.float64) ** 2
+    dd = d * d
+    return g1, d, dd / (dd + tau2)
+
+
+def step_doubling_map(y, out, mu, L, k, gate, out_scale):
+    """phi(y)_c ~ G1_c + d_c (16/15 + (out_scale_c g_c) out_c)."""
+    g1, d, g = step_doubling(y, mu, L, k, gate)
+    return g1 + d * (RICHARDSON + (np.asarray(out_scale, np.float64) * g) * out)
+
+
+def visit_d2(xi, states, in_scale):
+    """Squared distance, in the network's input units, from points xi (n, 2) to
+    the nearest of a chain's states (m, 2); fp32, one rounding per operation."""
+    xi = np.asarray(xi, np.float32)
+    st = np.asarray(states, np.float64).astype(np.float32)
+    sc = np.asarray(in_scale, np.float32)[:2]
+    best = np.full(xi.shape[0], np.inf, np.float32)
+    for s in st:
+        e0 = (xi[:, 0] - s[0]) * sc[0]
+        e1 = (xi[:, 1] - s[1]) * sc[1]
+        best = np.minimum(best, e0 * e0 + e1 * e1)
+    return best
+
+
+def visit_weight(d2, sigma, floor_weight):
+    """v = exp(-D^2 / (2 sigma^2)) + floor, in fp32."""
+    inv = np.float32(1.0 / (2.0 * sigma * sigma))
+    return np.exp(-(np.asarray(d2, np.float32) * inv)) + np.float32(floor_weight)
+
+
+def step_doubling_targets(tab, xi, mu, L, k, gate, out_scale, loss_scale, v=None):
+    """Training targets of the step-doubling form for endpoints tab (n, 2) of
+    the slice map from xi (n, 2): rho_c = sqrt(v) r_c / q_c with
+    r = (tab - G1) - 16/15 d, and w_c = sqrt(v) (d_c out_scale_c) g_c / q_c,
+    q = loss_scale, so that w out - rho is sqrt(v) times the surrogate map's
+    error in units of q.  Returns (rho, w), (n, 2) each, FP64."""
+    g1, d, g = step_doubling(np.asarray(xi, np.float64), mu, L, k, gate)
+    sv = np.ones((d.shape[0], 1)) if v is None else \
+        np.sqrt(np.asarray(v, np.float64))[:, None]
+    q = np.asarray(loss_scale, np.float64)
+    r = (np.asarray(tab, np.float64) - g1) - RICHARDSON * d
+    return (sv * r) / q, (sv * ((d * np.asarray(out_scale, np.float64)) * g)) / q
+
+
 def surrogate_chain(params, shift, scale, out_scale, y0, mu, t0, T, n_slices,
-                    emulate_bf16=False, coarse_steps=0):
+                    emulate_bf16=False, coarse_steps=0, correction="additive",
+                    gate=(1.0, 1.0)):
     """The sequential pass with the network in place of the lookup:
-    lambda_0 = y0, lambda_{j+1} = G(lambda_j) + out_scale * net(lambda_j, T_j, mu),
-    T_j = t0 + j (T - t0) / n_slices, G the coarse propagator (coarse_step).
+    lambda_0 = y0, lambda_{j+1} = the surrogate map at (lambda_j, T_j, mu),
+    T_j = t0 + j (T - t0) / n_slices: G(lambda_j) + out_scale * net (additive,
+    G the coarse propagator of coarse_step) or step_doubling_map.
     Returns lambda_0 .. lambda_N, (N+1, 2)."""
     L = (T - t0) / n_slices
     lam = np.array(y0, np.float64)
@@ -187,6 +253,10 @@ def surrogate_chain(params, shift, scale, out_scale, y0, mu, t0, T, n_slices,
     for j in range(n_slices):
         x = np.array([[lam[0], lam[1], t0 + j * L, mu]])
         out, _ = forward(params, x, shift, scale, emulate_bf16)
-        lam = coarse_step(lam, mu, L, coarse_steps) + np.asarray(out_scale, np.float64) * out[0]
+        if correction == "step-doubling":
+            lam = step_doubling_map(lam, out[0], mu, L, coarse_steps, gate, out_scale)
+        else:
+            lam = coarse_step(lam, mu, L, coarse_steps) + \
+                np.asarray(out_scale, np.float64) * out[0]
         bnd.append(lam.copy())
     return np.array(bnd)

@@ -51,6 +51,33 @@ __host__ __device__ inline void coarse_rk4(double mu, double h, int k, double &y
     }
 }
 
+// The step-doubling form's pieces at y: G1 (k RK4 steps of L / k), the
+// difference d = G2 - G1 to 2k steps of half that length, and the gate
+// g = d^2 / (d^2 + tau2), tau2 = gate^2, per component; FP64.
+struct StepDoubling {
+    double g0, g1, d0, d1, gt0, gt1;
+};
+__host__ __device__ inline StepDoubling step_doubling(double mu, double L, int k, double y0,
+                                                      double y1, double tau2_0, double tau2_1) {
+#pragma clang fp contract(off)
+    StepDoubling r;
+    double a0 = y0, a1 = y1, b0 = y0, b1 = y1;
+    coarse_rk4(mu, L / double(k), k, a0, a1);
+    coarse_rk4(mu, L / double(2 * k), 2 * k, b0, b1);
+    r.g0 = a0;
+    r.g1 = a1;
+    r.d0 = b0 - a0;
+    r.d1 = b1 - a1;
+    const double dd0 = r.d0 * r.d0, dd1 = r.d1 * r.d1;
+    r.gt0 = dd0 / (dd0 + tau2_0);
+    r.gt1 = dd1 / (dd1 + tau2_1);
+    return r;
+}
+
+// Richardson's constant of a fourth-order step: the error of G1 is about
+// 16/15 (G2 - G1).
+constexpr double kRichardson = 16.0 / 15.0;
+
 // ---------------------------------------------------------------- kernels
 
 struct TrainArgs {
@@ -63,6 +90,7 @@ struct TrainArgs {
     float *loss_part;            // one sum per 16 samples
     float shift[4], scale[4];
     float inv_n;
+    int weighted;                // targets are rho_0, rho_1, w_0, w_1: e = w out - rho
 };
 
 // Inputs and targets of up to kStageTiles tiles are staged in LDS before the
@@ -74,8 +102,9 @@ struct TrainLds {
     __bf16 w[4 * kWidth * kLdsRow];
     SmallParams sp;
     float xs[4 * kStageTiles * 16];
-    float ts[2 * kStageTiles * 16];
+    float ts[4 * kStageTiles * 16];   // targets (2 rows) or rho and weights (4 rows)
 };
+static_assert(sizeof(TrainLds) <= 160 * 1024, "the training kernel's LDS exceeds 160 KiB");
 
 // Forward pass, loss and back-propagation of one tile of 16 samples (lane
 // l: sample l % 16), writing the workspace rows of every sample.
@@ -88,6 +117,8 @@ __device__ inline void train_tile(const TrainArgs &a, const TrainLds &L, long lo
 #pragma unroll
     for (int k = 0; k < 4; ++k) u[k] = (L.xs[k * kStageTiles * 16 + li] - a.shift[k]) * a.scale[k];
     const float t0 = L.ts[li], t1 = L.ts[kStageTiles * 16 + li];
+    const float w0 = a.weighted ? L.ts[2 * kStageTiles * 16 + li] : 1.0f;
+    const float w1 = a.weighted ? L.ts[3 * kStageTiles * 16 + li] : 1.0f;
     Layer d1, d2, d3, x;
     bf16x8 b[4];
     float o0, o1;
@@ -96,8 +127,20 @@ __device__ inline void train_tile(const TrainArgs &a, const TrainLds &L, long lo
     pack(x, b);
     store_rows(sink, kRowH + 256, b, lane);
 
-    const float e0 = o0 - t0, e1 = o1 - t1;
-    const float dout0 = 2.0f * e0 * a.inv_n, dout1 = 2.0f * e1 * a.inv_n;
+    // the error of the sample (weighted: e = w out - rho, whose gradient in out is
+    // 2 e w / n)
+    float e0, e1, dout0, dout1;
+    if (a.weighted) {
+        e0 = w0 * o0 - t0;
+        e1 = w1 * o1 - t1;
+        dout0 = 2.0f * e0 * w0 * a.inv_n;
+        dout1 = 2.0f * e1 * w1 * a.inv_n;
+    } else {
+        e0 = o0 - t0;
+        e1 = o1 - t1;
+        dout0 = 2.0f * e0 * a.inv_n;
+        dout1 = 2.0f * e1 * a.inv_n;
+    }
     // layer 3: dL/dz3 = (W4^T dout) * gelu'(z3)
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) {
@@ -167,6 +210,10 @@ __global__ __launch_bounds__(kTrainThreads) void sur_train_kernel(TrainArgs a) {
             for (int k = 0; k < 4; ++k) L.xs[k * kStageTiles * 16 + i] = a.x[k * a.ld + src];
             L.ts[i] = a.t[src];
             L.ts[kStageTiles * 16 + i] = a.t[a.ld + src];
+            if (a.weighted) {
+                L.ts[2 * kStageTiles * 16 + i] = a.t[2 * a.ld + src];
+                L.ts[3 * kStageTiles * 16 + i] = a.t[3 * a.ld + src];
+            }
         }
         __syncthreads();
         for (long long tile = c0 + wave; tile < c1; tile += kTrainThreads / 64) {
@@ -476,6 +523,8 @@ struct ChainArgs {
     long long count;
     double t0, L;
     int coarse;                  // coarse RK4 steps (0: identity)
+    int step_doubling;           // 1: the step-doubling form
+    double tau2_0, tau2_1;       // squared gate scales
     int n_slices;
     double *final_state, *boundary;
     const void *tab0, *tab1;
@@ -650,9 +699,18 @@ __global__ __launch_bounds__(kInferThreads) void sur_chain_kernel(ChainArgs a) {
                       (tj - a.shift[2]) * a.scale[2], (muf - a.shift[3]) * a.scale[3]};
         float o0, o1;
         forward_split(L, u, w, lane, o0, o1);
-        double g0 = l0, g1 = l1;
-        coarse_rk4(double(a.mu[qc]), a.L / double(a.coarse), a.coarse, g0, g1);
-        double n0 = g0 + a.os0 * double(o0), n1 = g1 + a.os1 * double(o1);
+        double n0, n1;
+        if (a.step_doubling) {
+            const StepDoubling sd = step_doubling(a.mu[qc], a.L, a.coarse, l0, l1, a.tau2_0,
+                                                  a.tau2_1);
+            n0 = sd.g0 + sd.d0 * (kRichardson + (a.os0 * sd.gt0) * double(o0));
+            n1 = sd.g1 + sd.d1 * (kRichardson + (a.os1 * sd.gt1) * double(o1));
+        } else {
+            double g0 = l0, g1 = l1;
+            coarse_rk4(double(a.mu[qc]), a.L / double(a.coarse), a.coarse, g0, g1);
+            n0 = g0 + a.os0 * double(o0);
+            n1 = g1 + a.os1 * double(o1);
+        }
         const bool outside = !(l0 >= a.blo0 && l0 <= a.bhi0 && l1 >= a.blo1 && l1 <= a.bhi1);
         if (a.tab0) {
             double p, pq;
@@ -700,21 +758,75 @@ struct DatasetArgs {
     double os0, os1;
     int coarse;
     int *error;
+    int step_doubling;           // targets rho_0, rho_1, w_0, w_1 (4 rows)
+    double tau2_0, tau2_1, q0, q1;
+    // visit weights (step-doubling only; visits null: v = 1)
+    const double *visits;        // [n_mu][n_states][2]
+    int n_mu, n_states;
+    double mu_lo, mu_step;       // chain i for mu_lo + i mu_step
+    float sc0, sc1, inv2s2, floor_w;
 };
 
+constexpr int kMaxVisitStates = 4096;     // states of one chain staged in LDS (32 KiB)
+
+// The source (problem) of sample n: the last whose first sample is <= n.
+__device__ inline int source_of(const DatasetArgs &a, long long n) {
+    int lo = 0, hi = a.n_src - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.src[mid].first <= n)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline int visit_chain(const DatasetArgs &a, double mu) {
+    double c = rint((mu - a.mu_lo) / a.mu_step);
+    c = c < 0.0 ? 0.0 : (c > double(a.n_mu - 1) ? double(a.n_mu - 1) : c);
+    return int(c);
+}
+
+// Squared distance, in the network's input units, from (y0, y1) to the
+// nearest state of a chain (fp32, one rounding per operation).
+template <class Get>
+__device__ inline float nearest_d2(const Get &state, int n, float y0, float y1, float sc0,
+                                   float sc1) {
+#pragma clang fp contract(off)
+    float best = INFINITY;
+    for (int i = 0; i < n; ++i) {
+        const float2 v = state(i);
+        const float e0 = (y0 - v.x) * sc0, e1 = (y1 - v.y) * sc1;
+        const float d2 = e0 * e0 + e1 * e1;
+        best = d2 < best ? d2 : best;
+    }
+    return best;
+}
+
+// Grid-stride over chunks of 256 consecutive samples (natural numbering, so
+// that a chunk usually lies in one problem and shares its mu's visit chain,
+// which the workgroup stages in LDS).
 __global__ __launch_bounds__(256) void sur_dataset_kernel(DatasetArgs a) {
 #pragma clang fp contract(off)
+    __shared__ float2 vis[kMaxVisitStates];
+    int staged = -1;                                      // workgroup-uniform
     const long long step = (long long)gridDim.x * 256;
-    for (long long n = (long long)blockIdx.x * 256 + threadIdx.x; n < a.total; n += step) {
-        int lo = 0, hi = a.n_src - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.src[mid].first <= n)
-                lo = mid;
-            else
-                hi = mid - 1;
+    for (long long base = (long long)blockIdx.x * 256; base < a.total; base += step) {
+        if (a.visits) {
+            const int cf = visit_chain(a, a.src[source_of(a, base)].mu);
+            if (cf != staged) {
+                __syncthreads();                          // the previous chain is consumed
+                const double *cs = a.visits + (long long)cf * a.n_states * 2;
+                for (int i = int(threadIdx.x); i < a.n_states; i += 256)
+                    vis[i] = make_float2(float(cs[2 * i]), float(cs[2 * i + 1]));
+                __syncthreads();
+                staged = cf;
+            }
         }
-        const nv::SliceMapSource &s = a.src[lo];
+        const long long n = base + threadIdx.x;
+        if (n >= a.total) continue;
+        const nv::SliceMapSource &s = a.src[source_of(a, n)];
         const long long r = n - s.first, j = r / s.M, k = r - j * s.M;
         const unsigned kk = unsigned(k), n1 = unsigned(s.n1);
         const unsigned k0 = kk / n1, k1 = kk - k0 * n1;
@@ -738,10 +850,36 @@ __global__ __launch_bounds__(256) void sur_dataset_kernel(DatasetArgs a) {
         a.x[a.cap + pos] = y1;
         a.x[2 * a.cap + pos] = float(s.t0 + double(j) * s.L);
         a.x[3 * a.cap + pos] = float(s.mu);
-        double g0 = double(y0), g1 = double(y1);
-        coarse_rk4(s.mu, s.L / double(a.coarse), a.coarse, g0, g1);
-        a.t[pos] = float((e0 - g0) / a.os0);
-        a.t[a.cap + pos] = float((e1 - g1) / a.os1);
+        if (!a.step_doubling) {
+            double g0 = double(y0), g1 = double(y1);
+            coarse_rk4(s.mu, s.L / double(a.coarse), a.coarse, g0, g1);
+            a.t[pos] = float((e0 - g0) / a.os0);
+            a.t[a.cap + pos] = float((e1 - g1) / a.os1);
+            continue;
+        }
+        const StepDoubling sd =
+            step_doubling(s.mu, s.L, a.coarse, double(y0), double(y1), a.tau2_0, a.tau2_1);
+        double sv = 1.0;
+        if (a.visits) {
+            const int ci = visit_chain(a, s.mu);
+            float d2;
+            if (ci == staged) {
+                d2 = nearest_d2([&](int i) { return vis[i]; }, a.n_states, y0, y1, a.sc0, a.sc1);
+            } else {
+                const double *cs = a.visits + (long long)ci * a.n_states * 2;
+                d2 = nearest_d2(
+                    [&](int i) { return make_float2(float(cs[2 * i]), float(cs[2 * i + 1])); },
+                    a.n_states, y0, y1, a.sc0, a.sc1);
+            }
+            const float v = expf(-(d2 * a.inv2s2)) + a.floor_w;
+            sv = sqrt(double(v));
+        }
+        const double r0 = (e0 - sd.g0) - kRichardson * sd.d0;
+        const double r1 = (e1 - sd.g1) - kRichardson * sd.d1;
+        a.t[pos] = float((sv * r0) / a.q0);
+        a.t[a.cap + pos] = float((sv * r1) / a.q1);
+        a.t[2 * a.cap + pos] = float((sv * ((sd.d0 * a.os0) * sd.gt0)) / a.q0);
+        a.t[3 * a.cap + pos] = float((sv * ((sd.d1 * a.os1) * sd.gt1)) / a.q1);
     }
 }
 
@@ -763,6 +901,10 @@ struct nv_sur {
     long long adam_t = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float last_ms = 0.f;
+    // visit weights of the step-doubling training set (nv_sur_set_visits)
+    const double *visits = nullptr;
+    int n_mu = 0, n_states = 0;
+    double mu_lo = 0.0, mu_hi = 0.0, sigma = 0.0, floor_w = 0.0;
 };
 
 namespace {
@@ -810,6 +952,7 @@ nv_status minibatch(nv_sur *s, const float *x, const float *t, long long ld, lon
     ta.loss_part = s->loss_part;
     fill_norm(s, ta.shift, ta.scale);
     ta.inv_n = float(1.0 / double(n));
+    ta.weighted = s->cfg.correction == NV_SUR_STEP_DOUBLING;
     const long long tiles = n / 16;
     const int wpb = kTrainThreads / 64;                        // waves per workgroup
     const int blocks = int(std::min<long long>((tiles + wpb - 1) / wpb, s->n_cu));
@@ -877,6 +1020,17 @@ NV_API nv_status nv_sur_create(const nv_sur_config *cfg, nv_sur **out) try {
     if (cfg->coarse_steps < 0 || cfg->coarse_steps > kMaxCoarse)
         return fail(NV_ERR_INVALID_ARG, "coarse_steps %d: need 0..%d", cfg->coarse_steps,
                     kMaxCoarse);
+    if (cfg->correction != NV_SUR_ADDITIVE && cfg->correction != NV_SUR_STEP_DOUBLING)
+        return fail(NV_ERR_INVALID_ARG, "unknown correction %d", cfg->correction);
+    if (cfg->correction == NV_SUR_STEP_DOUBLING) {
+        if (cfg->coarse_steps < 1)
+            return fail(NV_ERR_INVALID_ARG, "the step-doubling form needs coarse_steps >= 1");
+        for (int c = 0; c < 2; ++c)
+            if (!(cfg->gate[c] > 0.0) || !std::isfinite(cfg->gate[c]) ||
+                !(cfg->loss_scale[c] > 0.0) || !std::isfinite(cfg->loss_scale[c]))
+                return fail(NV_ERR_INVALID_ARG, "gate[%d] and loss_scale[%d] must be positive "
+                            "and finite", c, c);
+    }
     const long long mb = cfg->max_batch == 0 ? 65536 : cfg->max_batch;
     if (mb < 16 || mb > kMaxBatch || mb % 16 != 0)
         return fail(NV_ERR_INVALID_ARG, "max_batch %lld: need a multiple of 16 in [16, 2^20]",
@@ -1064,6 +1218,8 @@ NV_API nv_status nv_sur_dataset_from_batch(nv_sur *s, nv_batch *batch, const lon
     if (!x && !t) return NV_OK;
     if (!x || !t) return fail(NV_ERR_INVALID_ARG, "x and target must both be given");
     if (cap < n) return fail(NV_ERR_INVALID_ARG, "capacity %lld < %lld samples", cap, n);
+    if (s->cfg.correction == NV_SUR_STEP_DOUBLING && s->cfg.coarse_steps < 1)
+        return fail(NV_ERR_INVALID_ARG, "the step-doubling form needs coarse_steps >= 1");
     void *dsrc = nullptr;
     NV_HIP(hipMalloc(&dsrc, src.size() * sizeof(nv::SliceMapSource)));
     hipError_t e = hipMemcpyAsync(dsrc, src.data(), src.size() * sizeof(nv::SliceMapSource),
@@ -1083,6 +1239,24 @@ NV_API nv_status nv_sur_dataset_from_batch(nv_sur *s, nv_batch *batch, const lon
         da.os1 = s->cfg.out_scale[1];
         da.coarse = s->cfg.coarse_steps;
         da.error = s->error;
+        if (s->cfg.correction == NV_SUR_STEP_DOUBLING) {
+            da.step_doubling = 1;
+            da.tau2_0 = s->cfg.gate[0] * s->cfg.gate[0];
+            da.tau2_1 = s->cfg.gate[1] * s->cfg.gate[1];
+            da.q0 = s->cfg.loss_scale[0];
+            da.q1 = s->cfg.loss_scale[1];
+            if (s->visits) {
+                da.visits = s->visits;
+                da.n_mu = s->n_mu;
+                da.n_states = s->n_states;
+                da.mu_lo = s->mu_lo;
+                da.mu_step = (s->mu_hi - s->mu_lo) / double(s->n_mu - 1);
+                da.sc0 = s->cfg.in_scale[0];
+                da.sc1 = s->cfg.in_scale[1];
+                da.inv2s2 = float(1.0 / (2.0 * s->sigma * s->sigma));
+                da.floor_w = float(s->floor_w);
+            }
+        }
         const long long blocks = std::min<long long>((n + 255) / 256, 65536);
         hipLaunchKernelGGL(sur_dataset_kernel, dim3(unsigned(blocks)), dim3(256), 0, s->stream,
                            da);
@@ -1100,6 +1274,29 @@ NV_API nv_status nv_sur_dataset_from_batch(nv_sur *s, nv_batch *batch, const lon
     return NV_OK;
 } catch (const std::bad_alloc &) {
     return fail(NV_ERR_OOM, "nv_sur_dataset_from_batch: host allocation failed");
+}
+
+NV_API nv_status nv_sur_set_visits(nv_sur *s, const double *states, int n_mu, int n_states,
+                                   double mu_lo, double mu_hi, double sigma, double floor_w) {
+    if (!s) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    if (!states) {
+        s->visits = nullptr;
+        return NV_OK;
+    }
+    if (n_mu < 2 || n_states < 1 || n_states > kMaxVisitStates)
+        return fail(NV_ERR_INVALID_ARG, "need n_mu >= 2 and 1 <= n_states <= %d",
+                    kMaxVisitStates);
+    if (!std::isfinite(mu_lo) || !std::isfinite(mu_hi) || !(mu_hi > mu_lo) ||
+        !std::isfinite(sigma) || !(sigma > 0.0) || !std::isfinite(floor_w) || floor_w < 0.0)
+        return fail(NV_ERR_INVALID_ARG, "need finite mu_lo < mu_hi, sigma > 0, floor >= 0");
+    s->visits = states;
+    s->n_mu = n_mu;
+    s->n_states = n_states;
+    s->mu_lo = mu_lo;
+    s->mu_hi = mu_hi;
+    s->sigma = sigma;
+    s->floor_w = floor_w;
+    return NV_OK;
 }
 
 NV_API nv_status nv_sur_compose(nv_sur *s, const nv_sur_chains *c, nv_sur_compose_info *info) try {
@@ -1123,6 +1320,9 @@ NV_API nv_status nv_sur_compose(nv_sur *s, const nv_sur_chains *c, nv_sur_compos
         return fail(NV_ERR_INVALID_ARG, "slices of length %.17g; the network is configured "
                     "for %.17g", a.L, s->cfg.slice_length);
     a.coarse = s->cfg.coarse_steps;
+    a.step_doubling = s->cfg.correction == NV_SUR_STEP_DOUBLING;
+    a.tau2_0 = s->cfg.gate[0] * s->cfg.gate[0];
+    a.tau2_1 = s->cfg.gate[1] * s->cfg.gate[1];
     a.n_slices = c->n_slices;
     a.final_state = c->final_state;
     a.boundary = c->boundary;

@@ -408,7 +408,11 @@ class nv_sur_config(ctypes.Structure):
     _fields_ = [("in_shift", ctypes.c_float * 4), ("in_scale", ctypes.c_float * 4),
                 ("out_scale", ctypes.c_double * 2), ("slice_length", ctypes.c_double),
                 ("coarse_steps", ctypes.c_int), ("max_batch", ctypes.c_longlong),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("correction", ctypes.c_int),
+                ("gate", ctypes.c_double * 2), ("loss_scale", ctypes.c_double * 2)]
+
+
+NV_SUR_ADDITIVE, NV_SUR_STEP_DOUBLING = 0, 1
 
 
 class nv_sur_train_opts(ctypes.Structure):
@@ -445,11 +449,14 @@ _SIGNATURES.update({
                                   ctypes.POINTER(ctypes.c_longlong)],
     "nv_sur_compose": [_P, ctypes.POINTER(nv_sur_chains), ctypes.POINTER(nv_sur_compose_info)],
     "nv_sur_last_ms": [_P, ctypes.POINTER(ctypes.c_float)],
+    "nv_sur_set_visits": [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                          ctypes.c_double, ctypes.c_double],
 })
 
 
 def make_sur_config(in_shift, in_scale, out_scale, slice_length, coarse_steps=0, max_batch=0,
-                    stream=None) -> nv_sur_config:
+                    stream=None, correction=NV_SUR_ADDITIVE, gate=(1.0, 1.0),
+                    loss_scale=(1.0, 1.0)) -> nv_sur_config:
     c = nv_sur_config()
     for k in range(4):
         c.in_shift[k], c.in_scale[k] = float(in_shift[k]), float(in_scale[k])
@@ -457,7 +464,16 @@ def make_sur_config(in_shift, in_scale, out_scale, slice_length, coarse_steps=0,
     c.slice_length, c.coarse_steps = float(slice_length), int(coarse_steps)
     c.max_batch = int(max_batch)
     c.stream = stream
+    c.correction = int(correction)
+    for k in range(2):
+        c.gate[k], c.loss_scale[k] = float(gate[k]), float(loss_scale[k])
     return c
+
+
+def nv_sur_set_visits(sur, states_dev, n_mu, n_states, mu_lo, mu_hi, sigma, floor_weight):
+    return _check(load().nv_sur_set_visits(sur, states_dev, int(n_mu), int(n_states),
+                                           float(mu_lo), float(mu_hi), float(sigma),
+                                           float(floor_weight)))
 
 
 def nv_sur_create(cfg: nv_sur_config):

@@ -15,9 +15,14 @@ from .workloads import SUR_IN_SCALE, SUR_IN_SHIFT, SUR_OUT_SCALE, SUR_SLICE_LENG
 
 
 class Surrogate:
+    """correction "additive" (phi ~ G + out_scale * out) or "step-doubling"
+    (phi ~ G1 + d (16/15 + out_scale g out), gate and loss_scale per component);
+    see include/nv_surrogate.h."""
+
     def __init__(self, device="cuda:0", max_batch=65536, in_shift=SUR_IN_SHIFT,
                  in_scale=SUR_IN_SCALE, out_scale=SUR_OUT_SCALE, slice_length=SUR_SLICE_LENGTH,
-                 coarse_steps=0, stream=None):
+                 coarse_steps=0, stream=None, correction="additive", gate=(1.0, 1.0),
+                 loss_scale=(1.0, 1.0)):
         import torch
 
         self.torch = torch
@@ -29,9 +34,14 @@ class Surrogate:
         self.out_scale = tuple(out_scale)
         self.slice_length, self.coarse_steps = float(slice_length), int(coarse_steps)
         self.max_batch = int(max_batch)
+        self.correction = correction
+        self.target_rows = 4 if correction == "step-doubling" else 2
+        self._visits = None
+        kind = {"additive": nv.NV_SUR_ADDITIVE, "step-doubling": nv.NV_SUR_STEP_DOUBLING}
         with torch.cuda.device(self.device):
             cfg = nv.make_sur_config(in_shift, in_scale, out_scale, slice_length, coarse_steps,
-                                     max_batch, self.stream.cuda_stream)
+                                     max_batch, self.stream.cuda_stream, kind[correction], gate,
+                                     loss_scale)
             self.h = nv.nv_sur_create(cfg)
 
     def close(self):
@@ -98,7 +108,7 @@ class Surrogate:
         t = self.torch
         total = nv.nv_sur_dataset_from_batch(self.h, batch.batch)
         x = t.empty((4, total), dtype=t.float32, device=self.device)
-        tg = t.empty((2, total), dtype=t.float32, device=self.device)
+        tg = t.empty((self.target_rows, total), dtype=t.float32, device=self.device)
         p = None
         if perm is not None:
             p = self._dev(perm, t.int64)
@@ -108,6 +118,23 @@ class Surrogate:
         nv.nv_sur_dataset_from_batch(self.h, batch.batch, p.data_ptr() if p is not None else None,
                                      x.data_ptr(), tg.data_ptr(), total)
         return x, tg
+
+    def set_visits(self, states, mu_lo, mu_hi, sigma, floor_weight):
+        """Visit weights of the step-doubling training set from chains of states,
+        (n_mu, n_states, 2) FP64 (a device tensor is kept alive here); None
+        switches them off."""
+        t = self.torch
+        if states is None:
+            nv.nv_sur_set_visits(self.h, None, 0, 0, 0.0, 0.0, 0.0, 0.0)
+            self._visits = None
+            return
+        st = self._dev(states, t.float64).contiguous()
+        if st.dim() != 3 or st.shape[2] != 2:
+            raise ValueError("states must be (n_mu, n_states, 2)")
+        self.stream.synchronize()
+        nv.nv_sur_set_visits(self.h, st.data_ptr(), st.shape[0], st.shape[1], mu_lo, mu_hi,
+                             sigma, floor_weight)
+        self._visits = st
 
     # -- the composition ------------------------------------------------------------
     def compose(self, y0, mu, t0, T, n_slices, fallback: Propagator | None = None, guard=0.0,

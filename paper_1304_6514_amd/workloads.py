@@ -191,6 +191,21 @@ SUR_SLICE_LENGTH = 50.0 / 1024
 SUR_OUT_SCALE_COARSE = (0.01, 0.2)
 
 
+# The step-doubling form (phi ~ G1 + d (16/15 + out_scale g out), G1 one RK4
+# step over the slice, d the difference to two half steps): the gate scale per
+# component (0.1 of d's spread over the visited training states), the unit of
+# the training residual (its spread there) and the output scale; the training
+# samples are weighted by their distance to the states that Richardson chains
+# from y0 = (2, 0) visit for SUR_VISIT_MUS values of mu on [1, 5] (Gaussian of
+# width SUR_VISIT_SIGMA in the network's input units, plus a floor).
+SUR_SD_GATE = (5.7e-5, 2.0e-3)
+SUR_SD_LOSS_SCALE = (1.8e-5, 7.4e-4)
+SUR_SD_OUT_SCALE = (0.05, 0.05)
+SUR_VISIT_MUS = 81
+SUR_VISIT_SIGMA = 0.05
+SUR_VISIT_FLOOR = 0.02
+
+
 def surrogate_training_problems(n_slices: int = 1024, grid_n=(128, 128), steps: int = 500,
                                 seed: int = 17, T: float = 50.0):
     """The training build: Van der Pol on [0, T] cut into n_slices slices, slice j

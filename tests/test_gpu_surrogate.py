@@ -25,6 +25,9 @@ pytestmark = pytest.mark.gpu
 SHIFT = np.array(W.SUR_IN_SHIFT)
 SCALE = np.array(W.SUR_IN_SCALE, dtype=np.float32).astype(np.float64)
 OUT_SCALE = np.array(W.SUR_OUT_SCALE)
+# the step-doubling form of the workload
+SD_KW = dict(correction="step-doubling", coarse_steps=1, out_scale=W.SUR_SD_OUT_SCALE,
+             gate=W.SUR_SD_GATE, loss_scale=W.SUR_SD_LOSS_SCALE)
 
 
 def say(*a):
@@ -139,6 +142,56 @@ def test_training_run_tracks_oracle(sur, torch):
     assert losses[-1] < losses[0]
 
 
+def test_weighted_loss_gradient_and_training_match_oracle(torch):
+    """The step-doubling form's training loss, e = w out - rho with per-sample
+    weights: loss and gradient of one minibatch, then a 12-step training run,
+    against the oracle's weighted least squares (bf16-emulating)."""
+    from paper_1304_6514_amd.surrogate import Surrogate
+    with Surrogate("cuda:0", max_batch=4112, **SD_KW) as s2:
+        p = W.surrogate_init_params(3)
+        s2.set_params(p)
+        n = 4112
+        x, t = W.surrogate_samples(n, seed=4)
+        wts = np.random.default_rng(41).uniform(-2.0, 2.0, (2, n)).astype(np.float32)
+        tg = np.concatenate([t, wts]).astype(np.float32)      # rows rho_0, rho_1, w_0, w_1
+        say("weighted loss_grad n=4112")
+        loss, g = s2.loss_grad(x, tg)
+        p64 = p.astype(np.float64)
+        args = (x.T.astype(np.float64), t.T.astype(np.float64), SHIFT, SCALE)
+        l_emu, g_emu = mo.loss_and_grad(p64, *args, emulate_bf16=True,
+                                        weights=wts.T.astype(np.float64))
+        l_ref, g_ref = mo.loss_and_grad(p64, *args, weights=wts.T.astype(np.float64))
+        assert abs(loss - l_emu) <= 1e-5 * l_emu, (loss, l_emu)
+        assert abs(loss - l_ref) <= 1e-3 * l_ref, (loss, l_ref)
+        gu = mo.unflatten(g)
+        for name, _ in mo.SHAPES:
+            assert _rel(gu[name], g_emu[name]) < 2e-3, name
+            assert _rel(gu[name], g_ref[name]) < 3e-2, name
+
+        B, steps = 1024, 12
+        p = W.surrogate_init_params(7)
+        s2.set_params(p)
+        x, t = W.surrogate_samples(4 * B, seed=8)
+        wts = np.random.default_rng(42).uniform(0.0, 2.0, (2, 4 * B)).astype(np.float32)
+        losses = s2.train(x, np.concatenate([t, wts]), batch=B, steps=steps,
+                          lr=3e-3).cpu().numpy()
+        opt = mo.Adam(mo.N_PARAMS, lr=3e-3)
+        theta = p.astype(np.float64)
+        ref = []
+        for k in range(steps):
+            sl = slice((k * B) % (4 * B), (k * B) % (4 * B) + B)
+            l, gk = mo.loss_and_grad(theta, x[:, sl].T.astype(np.float64),
+                                     t[:, sl].T.astype(np.float64), SHIFT, SCALE,
+                                     emulate_bf16=True, weights=wts[:, sl].T.astype(np.float64))
+            ref.append(l)
+            theta = opt.step(theta, mo.flatten(gk))
+        ref = np.array(ref)
+        say("weighted losses gpu   ", np.array2string(losses, precision=5))
+        say("weighted losses oracle", np.array2string(ref, precision=5))
+        assert np.max(np.abs(losses - ref) / ref) < 2e-3
+        assert losses[-1] < losses[0]
+
+
 def _train_batch(torch):
     from paper_1304_6514_amd.propagator import Batch
     # eight slices of the training build's length 50/1024
@@ -187,6 +240,88 @@ def test_training_set_gather_is_exact(sur, torch, coarse):
     finally:
         s2.close()
         b.close()
+
+
+@pytest.mark.parametrize("visits", [False, True])
+def test_step_doubling_gather_matches_oracle(torch, visits):
+    """The step-doubling training set: inputs bit for bit, the targets rho and
+    weights w against the oracle's (FP64 on both sides, one fp32 rounding at
+    the end; the visit weight's fp32 exponential may differ in its last bit)."""
+    from paper_1304_6514_amd.surrogate import Surrogate
+    probs, b = _train_batch(torch)
+    s2 = Surrogate("cuda:0", max_batch=1024, **SD_KW)
+    try:
+        M = 12 * 10
+        total = len(probs) * M
+        states = None
+        if visits:
+            rng = np.random.default_rng(61)
+            n_mu, n_states = 5, 37
+            states = np.stack([np.column_stack([rng.uniform(-2.5, 2.5, n_states),
+                                                rng.uniform(-7.0, 7.0, n_states)])
+                               for _ in range(n_mu)])
+            s2.set_visits(states, 1.0, 5.0, 0.3, 0.02)
+        perm = W.surrogate_perm(total, seed=10)
+        x, t = s2.dataset_from_batch(b, perm)
+        x, t = x.cpu().numpy(), t.cpu().numpy()
+        assert t.shape == (4, total)
+        worst = 0.0
+        for i, w in enumerate(probs):
+            tabs = [nv.nv_batch_get_table(b.batch, i, c, 1, M, "fp32")[0] for c in range(2)]
+            k = np.arange(M)
+            k0, k1 = k // 10, k % 10
+            d0 = (w.grid_hi[0] - w.grid_lo[0]) / 11
+            d1 = (w.grid_hi[1] - w.grid_lo[1]) / 9
+            y0 = (w.grid_lo[0] + k0 * d0).astype(np.float32)
+            y1 = (w.grid_lo[1] + k1 * d1).astype(np.float32)
+            pos = perm[i * M + k]
+            assert np.array_equal(x[0, pos], y0) and np.array_equal(x[1, pos], y1)
+            assert np.all(x[2, pos] == np.float32(w.t0))
+            assert np.all(x[3, pos] == np.float32(w.params[0]))
+            xi = np.stack([y0, y1], -1)
+            v = None
+            if visits:
+                ci = int(np.clip(np.rint((w.params[0] - 1.0) / 1.0), 0, 4))
+                v = mo.visit_weight(mo.visit_d2(xi, states[ci], SCALE), 0.3, 0.02)
+            rho, wt = mo.step_doubling_targets(
+                np.stack([tb.astype(np.float64) for tb in tabs], -1), xi.astype(np.float64),
+                w.params[0], w.T - w.t0, 1, W.SUR_SD_GATE, W.SUR_SD_OUT_SCALE,
+                W.SUR_SD_LOSS_SCALE, v)
+            for row, ref in ((0, rho[:, 0]), (1, rho[:, 1]), (2, wt[:, 0]), (3, wt[:, 1])):
+                scale = max(float(np.max(np.abs(ref))), 1e-30)
+                err = float(np.max(np.abs(t[row, pos] - ref)) / scale)
+                worst = max(worst, err)
+                assert err < 1e-6, (i, row, err)
+        say(f"step-doubling gather (visits {visits}): {total} samples, worst relative "
+            f"difference {worst:.3g}")
+    finally:
+        s2.close()
+        b.close()
+
+
+def test_step_doubling_chain_matches_oracle(torch):
+    from paper_1304_6514_amd.surrogate import Surrogate
+    p = W.surrogate_init_params(11)
+    with Surrogate("cuda:0", max_batch=1024, **SD_KW) as s2:
+        s2.set_params(p)
+        rng = np.random.default_rng(12)
+        Q, N = 37, 16
+        y0 = np.column_stack([rng.uniform(-2, 2, Q), rng.uniform(-4, 4, Q)])
+        mu = rng.uniform(1, 5, Q)
+        say(f"step-doubling compose Q={Q} N={N}")
+        st, final, bnd, info = s2.compose(y0, mu, 0.0, 50.0 * N / 1024, N, want_boundary=True)
+        assert st == nv.NV_OK and info.bad_chain == -1
+        bnd = bnd.cpu().numpy()
+        worst = 0.0
+        for q in range(Q):
+            ref = mo.surrogate_chain(p.astype(np.float64), SHIFT, SCALE, W.SUR_SD_OUT_SCALE,
+                                     y0[q], mu[q], 0.0, 50.0 * N / 1024, N, emulate_bf16=True,
+                                     coarse_steps=1, correction="step-doubling",
+                                     gate=W.SUR_SD_GATE)
+            worst = max(worst, float(np.max(np.abs(bnd[q] - ref))))
+        say(f"step-doubling chains: max |gpu - oracle(bf16)| = {worst:.3g}")
+        # the network's output enters scaled by d (about 1e-3 at most here) x 0.05
+        assert worst < 1e-7
 
 
 @pytest.mark.parametrize("coarse", [0, 1])
@@ -249,75 +384,81 @@ def test_compose_fallback_reproduces_bilinear_composition(sur, torch):
             f"{info2.n_fallback} fallbacks, max deviation {info2.max_deviation:.3g}")
 
 
-def test_trained_network_gains_over_the_method_without_it(torch):
-    """The whole learned path at full size: the training build (1024 one-slice
-    Van der Pol problems with their own mu, 128 x 128 grid, 500 RK4 steps),
-    the training set (16.7M endpoints), 20 epochs of Adam, then the
-    composition over [0, 50] (1024 slices) for held-out mu that no table was
-    built for.  The method without the network needs a table build for every
-    new mu; against the plain method with a fresh 64 x 64 table build per mu
-    the trained network's max final-state error is smaller.  The coarse RK4
-    step alone is reported too: at this slice length one RK4 step is already
-    accurate to about 1e-6 per slice, below the network's bfloat16 resolution,
-    so the learned correction does not improve on it."""
+def test_trained_network_gains_over_the_method_without_it(torch, orc):
+    """The whole learned path at full size, in the step-doubling form: the
+    training build (1024 one-slice Van der Pol problems with their own mu,
+    128 x 128 grid, 500 RK4 steps: 16.7M endpoints), the visit weights from
+    Richardson chains of the untrained form for 81 mu, 20 epochs of Adam, then
+    the composition over [0, 50] (1024 slices) for eight held-out mu that no
+    table was built for.  Truth: the oracle's serial RK4 run (512,000 steps).
+    The trained network's max final-state error must be below each method
+    without it: the same form with the network's output zeroed (Richardson
+    extrapolation of one RK4 step per slice), the coarse step alone (one RK4
+    step per slice), and the plain method with a fresh 128 x 128 table build
+    per mu."""
     from paper_1304_6514_amd.propagator import Batch, Propagator
     from paper_1304_6514_amd.surrogate import Surrogate
     B = 65536
+    base = W.VDP_FP32
     probs = W.surrogate_training_problems()
     b = Batch(probs)
     st, _, _ = b.run()
     assert st == nv.NV_OK
-    sur = Surrogate("cuda:0", max_batch=B, out_scale=W.SUR_OUT_SCALE_COARSE, coarse_steps=1)
+    sur = Surrogate("cuda:0", max_batch=B, **SD_KW)
+    g1 = Surrogate("cuda:0", max_batch=16, coarse_steps=1, out_scale=(1.0, 1.0))
     try:
+        # the states the composition visits: the untrained form (zero network:
+        # Richardson) from the workload's y0 for a grid of mu
+        mug = np.linspace(1.0, 5.0, W.SUR_VISIT_MUS)
+        st, _, vis, _ = sur.compose(np.tile(base.y0, (len(mug), 1)), mug, base.t0, base.T,
+                                    base.n_slices, want_boundary=True)
+        assert st == nv.NV_OK
+        sur.set_visits(vis, 1.0, 5.0, W.SUR_VISIT_SIGMA, W.SUR_VISIT_FLOOR)
         total = nv.nv_sur_dataset_from_batch(sur.h, b.batch)
         x, t = sur.dataset_from_batch(b, W.surrogate_perm(total))
         b.close()
-        p0 = W.surrogate_init_params(0)
-        sur.set_params(p0)
+        sur.set_params(W.surrogate_init_params(0))
         losses = sur.train(x, t, batch=B, steps=20 * (total // B), lr=2e-3,
                            lr_final=2e-5).cpu().numpy()
         del x, t
         say(f"training: {len(losses)} steps, loss {losses[0]:.3g} -> {losses[-1]:.3g}, "
             f"{sur.last_ms():.0f} ms")
-        assert losses[-1] < 1e-3 * losses[0]
 
-        base = W.VDP_FP32
         mus = W.surrogate_eval_mus(8)
         y0 = np.tile(base.y0, (len(mus), 1))
-        truth, plain = [], []
-        with Propagator("cuda:0") as pr:
-            for mu in mus:
-                wt = base.with_(name="vdp-serial-fp64", params=(float(mu),), n_slices=1,
-                                grid_n=(2, 2), grid_lo=base.y0,
-                                grid_hi=(base.y0[0] + 1.0, base.y0[1] + 1.0),
-                                steps_per_slice=base.n_slices * base.steps_per_slice,
-                                precision="fp64")
-                pr.build(wt)
-                truth.append([float(pr.table(0)[0, 0]), float(pr.table(1)[0, 0])])
-            truth = np.array(truth)
-            for i, mu in enumerate(mus):
-                r = pr.solve(base.with_(params=(float(mu),), grid_n=(64, 64)),
-                             want_boundary=False)
-                plain.append(float(np.max(np.abs(np.asarray(r.yT) - truth[i]))))
-        st, fin, _, info = sur.compose(y0, mus, base.t0, base.T, base.n_slices)
-        assert st == nv.NV_OK
-        e_net = np.max(np.abs(fin.cpu().numpy() - truth), axis=1)
+        truth = np.array([orc.serial("vdp", [float(mu)], "rk4", base.t0, base.T, base.n_slices,
+                                     base.steps_per_slice, base.y0) for mu in mus])
+
+        def errors(s):
+            st, fin, _, _ = s.compose(y0, mus, base.t0, base.T, base.n_slices)
+            assert st == nv.NV_OK
+            return np.max(np.abs(fin.cpu().numpy() - truth), axis=1)
+
+        e_net = errors(sur)
         trained = sur.params()
         off = trained.copy()
-        off[mo.N_PARAMS - 258:] = 0.0                # W4 = 0, b4 = 0: the coarse step alone
+        off[mo.N_PARAMS - 258:] = 0.0                # W4 = 0, b4 = 0: Richardson alone
         sur.set_params(off)
-        st, fin0, _, _ = sur.compose(y0, mus, base.t0, base.T, base.n_slices)
-        e_coarse = np.max(np.abs(fin0.cpu().numpy() - truth), axis=1)
-        e_coarse = np.where(np.isfinite(e_coarse), e_coarse, np.inf)
-        say("held-out mu        ", np.array2string(mus, precision=3))
-        say("network error      ", np.array2string(e_net, precision=4))
-        say("coarse step alone  ", np.array2string(e_coarse, precision=4))
-        say("plain 64x64 build  ", np.array2string(np.array(plain), precision=4))
-        say(f"network compose of {len(mus)} chains: {info.ms:.2f} ms")
+        e_rich = errors(sur)
+        e_g1 = errors(g1)                            # untrained additive form: G alone
+        plain = []
+        with Propagator("cuda:0") as pr:
+            for i, mu in enumerate(mus):
+                r = pr.solve(base.with_(params=(float(mu),)), want_boundary=False)
+                plain.append(float(np.max(np.abs(np.asarray(r.yT) - truth[i]))))
+        plain = np.array(plain)
+        say("held-out mu          ", np.array2string(mus, precision=3))
+        say("network error        ", np.array2string(e_net, precision=3))
+        say("Richardson alone     ", np.array2string(e_rich, precision=3))
+        say("one RK4 step alone   ", np.array2string(e_g1, precision=3))
+        say("plain 128x128 build  ", np.array2string(plain, precision=3))
+        assert losses[-1] < 0.1 * losses[0]
+        assert np.max(e_net) < np.max(e_rich)
+        assert np.max(e_net) < np.max(e_g1)
         assert np.max(e_net) < np.max(plain)
-        assert np.all(np.isfinite(e_coarse))
     finally:
         sur.close()
+        g1.close()
 
 
 def test_surrogate_error_paths(sur, torch):

@@ -202,3 +202,124 @@ def test_coarse_step_is_the_rk4_of_the_library_oracle(orc):
         ref = orc.integrate("vdp", [mu], "rk4", 0.0, L / k, k, y)
         assert np.max(np.abs(mo.coarse_step(y, mu, L, k) - ref)) < 1e-15
     assert np.array_equal(mo.coarse_step([0.3, -1.0], 2.0, 0.1, 0), [0.3, -1.0])
+
+
+# ---- the step-doubling form ------------------------------------------------
+
+def test_weighted_gradient_matches_torch_autograd_and_differences():
+    """e_c = w_c out_c - target_c: the weighted least-squares loss's gradient
+    against torch autograd and, for a few parameters, central differences."""
+    flat = _params(31)
+    x, t = _inputs(32, 40)
+    w = np.random.default_rng(33).uniform(-2.0, 2.0, (40, 2))
+    loss, g = mo.loss_and_grad(flat, x, t, SHIFT, SCALE, weights=w)
+    p = {k: torch.tensor(v, requires_grad=True) for k, v in mo.unflatten(flat).items()}
+    F = torch.nn.functional
+    u = (torch.from_numpy(x) - torch.from_numpy(SHIFT)) * torch.from_numpy(SCALE)
+    a = F.gelu(u @ p["W1"].T + p["b1"])
+    a = F.gelu(a @ p["W2"].T + p["b2"])
+    a = F.gelu(a @ p["W3"].T + p["b3"])
+    out = a @ p["W4"].T + p["b4"]
+    L = ((torch.from_numpy(w) * out - torch.from_numpy(t)) ** 2).sum(dim=1).mean()
+    L.backward()
+    assert abs(L.item() - loss) < 1e-12
+    for k in p:
+        assert np.max(np.abs(p[k].grad.numpy() - g[k])) < 1e-12 * max(1.0, np.abs(g[k]).max())
+    gf = mo.flatten(g)
+    h = 1e-6
+    for i in (3, 600, 17000, 33921):
+        e = np.zeros(mo.N_PARAMS)
+        e[i] = h
+        lp, _ = mo.loss_and_grad(flat + e, x, t, SHIFT, SCALE, weights=w)
+        lm, _ = mo.loss_and_grad(flat - e, x, t, SHIFT, SCALE, weights=w)
+        assert abs((lp - lm) / (2 * h) - gf[i]) <= 1e-7 * max(1.0, abs(gf[i]))
+    # unit weights are the plain loss
+    l1, g1 = mo.loss_and_grad(flat, x, t, SHIFT, SCALE, weights=np.ones((40, 2)))
+    l0, g0 = mo.loss_and_grad(flat, x, t, SHIFT, SCALE)
+    assert l1 == l0 and all(np.array_equal(g1[k], g0[k]) for k in g0)
+
+
+def _vdp_flow(y, mu, L):
+    """The Van der Pol slice map from a library integrator (DOP853, tight tolerances)."""
+    from scipy.integrate import solve_ivp
+    r = solve_ivp(lambda t, v: [v[1], mu * (1 - v[0] ** 2) * v[1] - v[0]], (0.0, L), y,
+                  method="DOP853", rtol=1e-13, atol=1e-14)
+    return r.y[:, -1]
+
+
+def test_richardson_map_is_fifth_order_and_step_doubling_difference_estimates_the_error():
+    """With out = 0 the step-doubling map is Richardson extrapolation of RK4:
+    its one-slice error falls by about 2^6 when L halves (RK4's by 2^5), and
+    16/15 (G2 - G1) estimates G1's error to leading order."""
+    y, mu = np.array([1.2, -0.7]), 2.5
+    errs_r, errs_1 = [], []
+    for L in (0.2, 0.1, 0.05):
+        phi = _vdp_flow(y, mu, L)
+        g1, d, _ = mo.step_doubling(y, mu, L, 1, (1.0, 1.0))
+        rich = mo.step_doubling_map(y, np.zeros(2), mu, L, 1, (1.0, 1.0), (1.0, 1.0))
+        errs_r.append(np.max(np.abs(rich - phi)))
+        errs_1.append(np.max(np.abs(g1 - phi)))
+        # the leading term of G1's error is 16/15 d
+        assert np.max(np.abs((phi - g1) - mo.RICHARDSON * d)) < 0.2 * np.max(np.abs(phi - g1))
+    r_rich = [errs_r[i] / errs_r[i + 1] for i in range(2)]
+    r_one = [errs_1[i] / errs_1[i + 1] for i in range(2)]
+    assert all(40.0 < r < 90.0 for r in r_rich), r_rich
+    assert all(24.0 < r < 40.0 for r in r_one), r_one
+    # the same extrapolation written the other way round: G2 + (G2 - G1)/15
+    g1 = mo.coarse_step(y, mu, 0.1, 1)
+    g2 = mo.coarse_step(y, mu, 0.1, 2)
+    rich = mo.step_doubling_map(y, np.zeros(2), mu, 0.1, 1, (1.0, 1.0), (1.0, 1.0))
+    assert np.max(np.abs(rich - (g2 + (g2 - g1) / 15.0))) < 1e-15
+
+
+def test_gate_values_and_network_scaling():
+    """g = d^2 / (d^2 + gate^2): 0 at d = 0, 1/2 at |d| = gate, 4/5 at 2 gate;
+    the network's output enters as d * out_scale * g * out."""
+    y, mu, L = np.array([0.4, 1.5]), 3.0, 50.0 / 1024
+    g1, d, _ = mo.step_doubling(y, mu, L, 1, (1.0, 1.0))
+    for k in (1.0, 2.0, 0.5):
+        gate = np.abs(d) / k
+        _, _, g = mo.step_doubling(y, mu, L, 1, gate)
+        assert np.allclose(g, k * k / (k * k + 1.0), rtol=1e-14)
+    out = np.array([0.3, -0.7])
+    os_ = np.array([0.05, 0.1])
+    gate = np.abs(d)
+    m = mo.step_doubling_map(y, out, mu, L, 1, gate, os_)
+    m0 = mo.step_doubling_map(y, np.zeros(2), mu, L, 1, gate, os_)
+    # (the difference of two states near 1 resolves to about 1e-16)
+    assert np.allclose(m - m0, d * os_ * 0.5 * out, rtol=1e-6, atol=4e-16)
+    assert np.all(np.abs(d * os_ * 0.5 * out) > 1e-12)
+
+
+def test_step_doubling_targets_make_the_weighted_error_the_map_error():
+    """w out - rho = sqrt(v) (surrogate map - endpoint) / loss_scale for any out."""
+    rng = np.random.default_rng(41)
+    n = 200
+    xi = np.column_stack([rng.uniform(-3, 3, n), rng.uniform(-8, 8, n)])
+    mu, L = 2.2, 50.0 / 1024
+    tab = np.array([_vdp_flow(p, mu, L) for p in xi[:20]])
+    xi = xi[:20]
+    gate, os_, q = (1e-4, 3e-3), (0.05, 0.05), (2e-5, 7e-4)
+    v = rng.uniform(0.02, 1.02, 20)
+    rho, w = mo.step_doubling_targets(tab, xi, mu, L, 1, gate, os_, q, v)
+    out = rng.normal(0, 1, (20, 2))
+    surrogate = np.array([mo.step_doubling_map(xi[i], out[i], mu, L, 1, gate, os_)
+                          for i in range(20)])
+    want = np.sqrt(v)[:, None] * (surrogate - tab) / np.array(q)
+    assert np.allclose(w * out - rho, want, rtol=1e-7, atol=1e-9)
+
+
+def test_visit_distance_is_the_nearest_neighbour_distance():
+    """D^2 against scipy's k-d tree on the scaled coordinates, and the weight's
+    value at D = 0, D = sigma."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(51)
+    states = np.column_stack([rng.uniform(-2.5, 2.5, 300), rng.uniform(-7, 7, 300)])
+    xi = np.column_stack([rng.uniform(-3, 3, 500), rng.uniform(-8, 8, 500)]).astype(np.float32)
+    sc = np.array([1 / 3, 1 / 8, 1 / 25, 1 / 2], dtype=np.float32)
+    d2 = mo.visit_d2(xi, states, sc)
+    tree = cKDTree(states * sc[:2].astype(np.float64))
+    ref = tree.query(xi.astype(np.float64) * sc[:2].astype(np.float64))[0] ** 2
+    assert np.allclose(d2, ref, rtol=2e-6, atol=1e-7)
+    v = mo.visit_weight(np.array([0.0, 0.05 ** 2], np.float32), 0.05, 0.02)
+    assert np.allclose(v, [1.02, math.exp(-0.5) + 0.02], rtol=1e-6)

@@ -681,6 +681,28 @@ def bench_heat(args):
                          "solve_steps": solve_steps,
                          "error_vs_closed_form": err,
                          "paper_T_total_s": paper_t, "paper_serial_s": paper_serial})
+        # many initial values at once on the matrix cores (the last shape's tables)
+        import torch
+        M, N = rows[-1]["M"], rows[-1]["N"]
+        single_ms = rows[-1]["compose_kernel_ms"]
+        many = []
+        rng = np.random.default_rng(3)
+        for Q in (1, 16, 256, 1024, 4096, 16384):
+            y0q = torch.from_numpy(rng.normal(0.0, 1.0, (Q, M))).cuda()
+            lp.compose_many(y0q)                                   # warm-up
+            ms = []
+            for _ in range(3):
+                st, _, _ = lp.compose_many(y0q)
+                ms.append(lp.last_timing()[1])
+            best = min(ms)
+            flops = 2.0 * M * M * Q * N
+            tf = flops / (best * 1e-3) / 1e12
+            many.append({"Q": Q, "kernel_ms": round(best, 4), "chains_per_s": Q / (best * 1e-3),
+                         "fp64_tflops": round(tf, 3),
+                         "frac_fp64_peak": round(tf / PEAK_FP64_VECTOR_TFLOPS, 4),
+                         "single_chains_ms": round(Q * single_ms, 3),
+                         "gain_over_single_chains": round(Q * single_ms / best, 2)})
+            del y0q
     big = rows[-1]
     out = {
         "metric": "affine basis propagator (heat equation): backward-Euler solve-steps/s, "
@@ -691,6 +713,11 @@ def bench_heat(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "heat-sec6-tables-5-7-8", "parallelism": "single-gpu"},
         "rows": rows,
+        "many_initial_values": {
+            "what": f"nv_lin_compose_many on the M = {M}, N = {N} tables: Q chains as FP64 "
+                    "matrix products (v_mfma_f64_16x16x4f64), 16 chains per workgroup; "
+                    "FLOPs 2 M^2 Q N; single_chains_ms = Q x one nv_lin_compose",
+            "runs": many},
         "vs_baseline_note": "the paper's heat timings are cluster runs (context only)",
     }
     if not args.no_cpu_baseline:

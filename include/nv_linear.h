@@ -74,6 +74,24 @@ NV_API nv_status nv_lin_build(nv_lin *lin, const nv_heat *problem, double t0, do
  * NONFINITE (a state became non-finite), HIP. */
 NV_API nv_status nv_lin_compose(nv_lin *lin, const double *y0, double *yT, double *boundary);
 
+/* Communication phase for many initial values (sec. 5, equation
+ * `linearreconstruct`, applied to count independent initial values): the
+ * chains lambda^q_{j+1} = c_j + G_j lambda^q_j, q = 0..count-1, evaluated as
+ * FP64 matrix products G_j [lambda^q ... lambda^{q+15}] on the matrix cores,
+ * 16 chains per workgroup.  Each component's sum c_i + sum_k G_ik l_k is
+ * formed by the matrix cores in an order this interface does not fix (so
+ * results are within the FP64 inner-product rounding bound of any order, not
+ * bit-equal to nv_lin_compose).
+ *   y0_dev        device, count x M doubles (chain q's initial value at q M)
+ *   yT_dev        device, count x M doubles: lambda^q_N
+ *   boundary_dev  device, count x (N + 1) x M doubles, chain-major
+ *                 (lambda^q_j at (q (N + 1) + j) M), or NULL
+ * Synchronous.  Errors: INVALID_ARG (NULL pointers, count < 1), NOT_BUILT,
+ * NONFINITE (some chain's state became non-finite; the message names the
+ * first such slice), HIP. */
+NV_API nv_status nv_lin_compose_many(nv_lin *lin, const double *y0_dev, long long count,
+                                     double *yT_dev, double *boundary_dev);
+
 /* Copy the tables of the last build to host memory (G: n_slices*M*M values,
  * c: n_slices*M values; either may be NULL).  Errors: NOT_BUILT, HIP. */
 NV_API nv_status nv_lin_get_tables(nv_lin *lin, double *G, double *c);

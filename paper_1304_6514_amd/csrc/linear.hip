@@ -445,6 +445,144 @@ struct LinChainTable {
 };
 const LinChainTable lin_chain;
 
+// ---- many initial values: the chain as FP64 matrix products -------------
+//
+// Q chains lambda^q_{j+1} = c_j + G_j lambda^q_j are independent, so workgroup
+// b carries the 16 chains q = 16 b .. 16 b + 15 through every slice alone (no
+// synchronisation between workgroups): per slice the product G_j Lambda_j of
+// the M x M table with the M x 16 block of states, on the matrix cores
+// (v_mfma_f64_16x16x4f64: wave w forms rows 16 w .. 16 w + 15 of the product,
+// k = 0 .. 4 KP - 1 in steps of four), then c_j added.  Lambda_j lives in LDS,
+// double buffered (rows k >= M are zero), one barrier per slice; every wave
+// holds the A fragments of its rows of G_{j+1} in registers while it computes
+// slice j.
+struct ManyArgs {
+    const double *T;            // [N][Ms (M + 1)]
+    const double *y0;           // [Q][M]
+    double *yT;                 // [Q][M]
+    double *boundary;           // [Q][N+1][M] or null
+    int *bad;                   // first slice whose state is not finite (atomic min), or -1
+    long long Q;
+    int M, N;
+};
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int KP>
+__global__ __launch_bounds__(512) void lin_many_kernel(ManyArgs a) {
+#pragma clang fp contract(off)
+    constexpr int K = 4 * KP;                    // rows of Lambda in LDS (M <= K)
+    __shared__ double lam[2][K][16];
+    const int tid = int(threadIdx.x), lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int M = a.M, N = a.N, Ms = lin_stride(M), per = Ms * (M + 1);
+    const int col = lane & 15, kq = lane >> 4;
+    const long long q0 = (long long)blockIdx.x * 16;
+    for (int e = tid; e < 2 * K * 16; e += 512) {
+        const int buf = e / (K * 16), k = (e / 16) % K, c = e % 16;
+        const long long qq = q0 + c < a.Q ? q0 + c : a.Q - 1;
+        lam[buf][k][c] = (buf == 0 && k < M) ? a.y0[qq * M + k] : 0.0;
+        if (a.boundary && buf == 0 && k < M && q0 + c < a.Q)
+            a.boundary[(q0 + c) * (long long)(N + 1) * M + k] = a.y0[qq * M + k];
+    }
+    // the lane's A operand: row 16 w + col of G, columns 4 kk + kq (A[i][k] in
+    // lane i + 16 k), B[k][j] in lane j + 16 k; the FP64 16 x 16 accumulator
+    // interleaves its rows: lane l holds D[4 i + l/16][l % 16] (i = 0..3,
+    // measured on the device), so the lane's outputs are rows 16 w + 4 i + kq
+    // of chain column col
+    const int arow = 16 * w + col;
+    const bool active = 16 * w < M;
+    const long long q = q0 + col;
+    const bool live = q < a.Q;
+    // the A fragments and the c values of a slice, loaded unconditionally from
+    // clamped (in-block) addresses, with no select after the load (which would
+    // wait for it): a column k >= M meets the zero row k of Lambda, a row
+    // >= M of the product is never stored.  Two register sets in turn, so that
+    // a slice's operands were loaded during the previous slice and nothing
+    // waits for the prefetch.  (A non-finite table value in column M - 1 thus
+    // also reaches the padded terms; it makes its row non-finite in the exact
+    // sum as well.)
+    double ga[KP], gb[KP], ca[4], cb[4];
+#define NV_LIN_LOAD(g, cv, j)                                                            \
+    do {                                                                                 \
+        const double *Tj_ = a.T + (long long)(j) * per;                                  \
+        const int ar_ = arow < M ? arow : M - 1;                                         \
+        _Pragma("unroll") for (int kk = 0; kk < KP; ++kk) {                              \
+            const int k_ = 4 * kk + kq;                                                  \
+            g[kk] = Tj_[(k_ < M ? k_ : M - 1) * Ms + ar_];                               \
+        }                                                                                \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                  \
+            const int r_ = 16 * w + 4 * i + kq;                                          \
+            cv[i] = Tj_[Ms * M + (r_ < M ? r_ : M - 1)];                                 \
+        }                                                                                \
+    } while (0)
+    // one slice: the product on the matrix cores (even and odd k-steps in two
+    // accumulators), c added, the new states to LDS (and the boundary), barrier
+#define NV_LIN_SLICE(g, cv, j)                                                           \
+    do {                                                                                 \
+        if (active) {                                                                    \
+            v4d acc = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};                 \
+            _Pragma("unroll") for (int kk = 0; kk < KP; ++kk) {                          \
+                if (kk % 2 == 0)                                                         \
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(                          \
+                        g[kk], lam[cur][4 * kk + kq][col], acc, 0, 0, 0);                \
+                else                                                                     \
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(                         \
+                        g[kk], lam[cur][4 * kk + kq][col], acc1, 0, 0, 0);               \
+            }                                                                            \
+            acc = acc + acc1;                                                            \
+            _Pragma("unroll") for (int i = 0; i < 4; ++i) {                              \
+                const int r = 16 * w + 4 * i + kq;                                       \
+                const double v = cv[i] + acc[i];                                         \
+                if (r < M) {                                                             \
+                    lam[cur ^ 1][r][col] = v;                                            \
+                    if (live && a.boundary)                                              \
+                        a.boundary[(q * (N + 1) + (j) + 1) * (long long)M + r] = v;      \
+                    if (live && !isfinite(v) && (j) < bad) bad = (j);                    \
+                }                                                                        \
+            }                                                                            \
+        }                                                                                \
+        __syncthreads();                                                                 \
+        cur ^= 1;                                                                        \
+    } while (0)
+    int cur = 0, bad = 0x7fffffff;
+    if (active) NV_LIN_LOAD(ga, ca, 0);
+    __syncthreads();
+    for (int j = 0; j < N; j += 2) {
+        if (active) NV_LIN_LOAD(gb, cb, j + 1 < N ? j + 1 : N - 1);
+        NV_LIN_SLICE(ga, ca, j);
+        if (j + 1 >= N) break;
+        if (active) NV_LIN_LOAD(ga, ca, j + 2 < N ? j + 2 : N - 1);
+        NV_LIN_SLICE(gb, cb, j + 1);
+    }
+#undef NV_LIN_LOAD
+#undef NV_LIN_SLICE
+    for (int e = tid; e < M * 16; e += 512) {
+        const int k = e / 16, c = e % 16;
+        if (q0 + c < a.Q) a.yT[(q0 + c) * M + k] = lam[cur][k][c];
+    }
+    if (bad != 0x7fffffff) atomicMin(a.bad, bad);
+}
+
+template <int KP>
+void lin_launch_many(const ManyArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL((lin_many_kernel<KP>), dim3(unsigned((a.Q + 15) / 16)), dim3(512), 0, st,
+                       a);
+}
+
+using ManyLaunch = void (*)(const ManyArgs &, hipStream_t);
+template <int... K>
+constexpr void many_fill(ManyLaunch *t, std::integer_sequence<int, K...>) {
+    ((t[K] = &lin_launch_many<K + 1>), ...);
+}
+
+// lin_many[KP - 1] launches the product chain for ceil(M/4) = KP
+struct LinManyTable {
+    ManyLaunch f[32];
+    LinManyTable() { many_fill(f, std::make_integer_sequence<int, 32>{}); }
+};
+const LinManyTable lin_many;
+
 }  // namespace
 
 struct nv_lin {
@@ -681,6 +819,29 @@ NV_API nv_status nv_lin_compose(nv_lin *l, const double *y0, double *yT, double 
     NV_HIP(hipStreamSynchronize(l->stream));
     NV_HIP(hipEventElapsedTime(&l->compose_ms, l->e2, l->e3));
     if (bad >= 0) return fail(NV_ERR_NONFINITE, "the state became non-finite in slice %d", bad);
+    return NV_OK;
+}
+
+NV_API nv_status nv_lin_compose_many(nv_lin *l, const double *y0_dev, long long count,
+                                     double *yT_dev, double *boundary_dev) {
+    if (!l || !y0_dev || !yT_dev) return fail(NV_ERR_INVALID_ARG, "NULL argument");
+    if (count < 1) return fail(NV_ERR_INVALID_ARG, "count = %lld", count);
+    if ((count + 15) / 16 > 0x7fffffffLL) return fail(NV_ERR_INVALID_ARG, "too many chains");
+    if (!l->built) return fail(NV_ERR_NOT_BUILT, "no successful nv_lin_build");
+    const int M = l->M, N = l->N;
+    const int init = 0x7fffffff;
+    NV_HIP(hipMemcpyAsync(l->bad, &init, sizeof(int), hipMemcpyHostToDevice, l->stream));
+    NV_HIP(hipEventRecord(l->e2, l->stream));
+    ManyArgs a{l->T, y0_dev, yT_dev, boundary_dev, l->bad, count, M, N};
+    lin_many.f[(M + 3) / 4 - 1](a, l->stream);
+    NV_HIP(hipGetLastError());
+    NV_HIP(hipEventRecord(l->e3, l->stream));
+    int bad = init;
+    NV_HIP(hipMemcpyAsync(&bad, l->bad, sizeof(int), hipMemcpyDeviceToHost, l->stream));
+    NV_HIP(hipStreamSynchronize(l->stream));
+    NV_HIP(hipEventElapsedTime(&l->compose_ms, l->e2, l->e3));
+    if (bad != init)
+        return fail(NV_ERR_NONFINITE, "a state became non-finite in slice %d", bad);
     return NV_OK;
 }
 

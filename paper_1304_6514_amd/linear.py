@@ -60,6 +60,27 @@ class LinearPropagator:
         w = self.workload
         return nv.nv_lin_compose(self.h, y0, w.M, w.n_slices, want_boundary)
 
+    def compose_many(self, y0, want_boundary=False, device="cuda:0"):
+        """Many chains at once on the matrix cores: y0 (Q, M) (numpy or a torch
+        tensor) -> (status, yT (Q, M), boundary (Q, N+1, M) or None), torch FP64
+        device tensors."""
+        import numpy as np
+        import torch
+
+        w = self.workload
+        y = y0 if isinstance(y0, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(y0))
+        y = y.to(device=device, dtype=torch.float64).contiguous()
+        if y.dim() != 2 or y.shape[1] != w.M:
+            raise ValueError(f"y0 must be (Q, {w.M})")
+        Q = y.shape[0]
+        yT = torch.empty_like(y)
+        b = (torch.empty((Q, w.n_slices + 1, w.M), dtype=torch.float64, device=device)
+             if want_boundary else None)
+        torch.cuda.synchronize(device)
+        st = nv.nv_lin_compose_many(self.h, y.data_ptr(), Q, yT.data_ptr(),
+                                    b.data_ptr() if b is not None else None)
+        return st, yT, b
+
     def tables(self):
         w = self.workload
         return nv.nv_lin_get_tables(self.h, w.M, w.n_slices)

@@ -563,6 +563,7 @@ _SIGNATURES.update({
     "nv_lin_build": [_P, ctypes.POINTER(nv_heat), ctypes.c_double, ctypes.c_double,
                      ctypes.c_int, ctypes.c_double],
     "nv_lin_compose": [_P, _P, _P, _P],
+    "nv_lin_compose_many": [_P, _P, ctypes.c_longlong, _P, _P],
     "nv_lin_get_tables": [_P, _P, _P],
     "nv_lin_last_timing": [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
 })
@@ -601,6 +602,14 @@ def nv_lin_compose(lin, y0, M, n_slices, want_boundary=True):
     if st not in (NV_OK, NV_ERR_NONFINITE):
         _check(st)
     return st, yT, b
+
+
+def nv_lin_compose_many(lin, y0_dev, count, yT_dev, boundary_dev=None):
+    """Status (NV_OK or NV_ERR_NONFINITE); raises on every other status."""
+    st = load().nv_lin_compose_many(lin, y0_dev, int(count), yT_dev, boundary_dev)
+    if st not in (NV_OK, NV_ERR_NONFINITE):
+        _check(st)
+    return st
 
 
 def nv_lin_get_tables(lin, M, n_slices):

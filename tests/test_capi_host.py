@@ -282,5 +282,6 @@ def test_linear_argument_errors_need_no_gpu(nvmod):
     h = nvmod.make_heat(9)
     assert lib.nv_lin_build(None, ctypes.byref(h), 0.0, 1.0, 4, 0.01) == nvmod.NV_ERR_INVALID_ARG
     assert lib.nv_lin_compose(None, None, None, None) == nvmod.NV_ERR_INVALID_ARG
+    assert lib.nv_lin_compose_many(None, None, 4, None, None) == nvmod.NV_ERR_INVALID_ARG
     assert lib.nv_lin_get_tables(None, None, None) == nvmod.NV_ERR_INVALID_ARG
     assert lib.nv_lin_last_timing(None, None, None) == nvmod.NV_ERR_INVALID_ARG

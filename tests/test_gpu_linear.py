@@ -182,3 +182,46 @@ def test_linear_single_slice_equals_serial(lin):
     assert st == nv.NV_OK
     ref = lo.compose(G, c, y0)
     check_chain(G, c, np.stack([y0, yT]), ref, "one slice")
+
+
+# ---- many initial values on the matrix cores --------------------------------
+
+@pytest.mark.parametrize("w", CASES + [HeatWorkload("heat-M99-N40", 99, 0.0005, 40, T=0.5)],
+                         ids=lambda w: w.name)
+def test_compose_many_within_rounding_bound_of_oracle(lin, w):
+    """nv_lin_compose_many: 37 chains (two full groups of 16 and a ragged
+    third) through the same tables; every chain's boundary states stay within
+    the FP64 inner-product rounding bound of the oracle's index-order chain."""
+    import torch
+    say("linear many", w.name)
+    lin.build(w)
+    G, c = lin.tables()
+    Q = 37
+    rng = np.random.default_rng(71)
+    y0 = rng.normal(0.0, 1.0, (Q, w.M))
+    st, yT, bnd = lin.compose_many(y0, want_boundary=True)
+    torch.cuda.synchronize()
+    assert st == nv.NV_OK
+    yT, bnd = yT.cpu().numpy(), bnd.cpu().numpy()
+    assert np.array_equal(yT, bnd[:, -1]) and np.array_equal(bnd[:, 0], y0)
+    for q in (0, 15, 16, 31, 32, 36):
+        check_chain(G, c, bnd[q], lo.compose(G, c, y0[q]), f"{w.name} chain {q}")
+    # without boundary states: the same final states
+    st, yT2, _ = lin.compose_many(y0)
+    assert st == nv.NV_OK and np.array_equal(yT2.cpu().numpy(), yT)
+
+
+def test_compose_many_reports_a_nonfinite_chain(lin):
+    import torch
+    w = HeatWorkload("heat-M9-nan-many", 9, 0.01, 5, T=0.5)
+    lin.build(w)
+    y0 = np.tile(lo.exact(0.0, 9), (20, 1))
+    y0[17, 3] = np.nan
+    st, yT, _ = lin.compose_many(y0)
+    torch.cuda.synchronize()
+    assert st == nv.NV_ERR_NONFINITE and "slice 0" in nv.nv_last_error()
+    yT = yT.cpu().numpy()
+    assert not np.all(np.isfinite(yT[17])) and np.all(np.isfinite(np.delete(yT, 17, 0)))
+    with pytest.raises(nv.NvError) as e:
+        nv.nv_lin_compose_many(lin.h, None, 4, None)
+    assert e.value.status == nv.NV_ERR_INVALID_ARG

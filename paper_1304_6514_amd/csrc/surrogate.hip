@@ -116,9 +116,7 @@ __device__ inline void train_tile(const TrainArgs &a, const TrainLds &L, long lo
     float u[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) u[k] = (L.xs[k * kStageTiles * 16 + li] - a.shift[k]) * a.scale[k];
-    const float t0 = L.ts[li], t1 = L.ts[kStageTiles * 16 + li];
-    const float w0 = a.weighted ? L.ts[2 * kStageTiles * 16 + li] : 1.0f;
-    const float w1 = a.weighted ? L.ts[3 * kStageTiles * 16 + li] : 1.0f;
+
     Layer d1, d2, d3, x;
     bf16x8 b[4];
     float o0, o1;
@@ -127,20 +125,16 @@ __device__ inline void train_tile(const TrainArgs &a, const TrainLds &L, long lo
     pack(x, b);
     store_rows(sink, kRowH + 256, b, lane);
 
-    // the error of the sample (weighted: e = w out - rho, whose gradient in out is
-    // 2 e w / n)
-    float e0, e1, dout0, dout1;
-    if (a.weighted) {
-        e0 = w0 * o0 - t0;
-        e1 = w1 * o1 - t1;
-        dout0 = 2.0f * e0 * w0 * a.inv_n;
-        dout1 = 2.0f * e1 * w1 * a.inv_n;
-    } else {
-        e0 = o0 - t0;
-        e1 = o1 - t1;
-        dout0 = 2.0f * e0 * a.inv_n;
-        dout1 = 2.0f * e1 * a.inv_n;
-    }
+    // the error of the sample, e = w out - target (w = 1 unweighted, where this
+    // is out - target to the bit), and dL/dout = 2 e w / n; the targets are read
+    // only now, after the forward pass has released its registers
+    const float t0 = L.ts[li], t1 = L.ts[kStageTiles * 16 + li];
+    // (rows 2 and 3 of the staged targets hold the weights, 1 when unweighted:
+    // an unconditional read keeps the kernel within its register budget, where
+    // a read under the condition made it spill)
+    const float w0 = L.ts[2 * kStageTiles * 16 + li], w1 = L.ts[3 * kStageTiles * 16 + li];
+    const float e0 = w0 * o0 - t0, e1 = w1 * o1 - t1;
+    const float dout0 = 2.0f * e0 * w0 * a.inv_n, dout1 = 2.0f * e1 * w1 * a.inv_n;
     // layer 3: dL/dz3 = (W4^T dout) * gelu'(z3)
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) {
@@ -210,10 +204,8 @@ __global__ __launch_bounds__(kTrainThreads) void sur_train_kernel(TrainArgs a) {
             for (int k = 0; k < 4; ++k) L.xs[k * kStageTiles * 16 + i] = a.x[k * a.ld + src];
             L.ts[i] = a.t[src];
             L.ts[kStageTiles * 16 + i] = a.t[a.ld + src];
-            if (a.weighted) {
-                L.ts[2 * kStageTiles * 16 + i] = a.t[2 * a.ld + src];
-                L.ts[3 * kStageTiles * 16 + i] = a.t[3 * a.ld + src];
-            }
+            L.ts[2 * kStageTiles * 16 + i] = a.weighted ? a.t[2 * a.ld + src] : 1.0f;
+            L.ts[3 * kStageTiles * 16 + i] = a.weighted ? a.t[3 * a.ld + src] : 1.0f;
         }
         __syncthreads();
         for (long long tile = c0 + wave; tile < c1; tile += kTrainThreads / 64) {

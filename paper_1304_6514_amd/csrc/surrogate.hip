@@ -25,7 +25,6 @@ using namespace nv::mlp;
 
 namespace {
 
-constexpr int kTrainThreads = 256;       // 4 waves, 1 workgroup per CU (LDS): 512 registers per wave
 constexpr int kInferThreads = 256;       // 4 waves
 constexpr int kMaxSplits = 128;          // weight-gradient sums: splits of the minibatch
 constexpr long long kMinSplit = 512;      // samples per split, at least
@@ -92,128 +91,6 @@ struct TrainArgs {
     float inv_n;
     int weighted;                // targets are rho_0, rho_1, w_0, w_1: e = w out - rho
 };
-
-// Inputs and targets of up to kStageTiles tiles are staged in LDS before the
-// tiles are processed: a global load inside the tile loop would have to wait
-// for every store of the previous tile (the memory counter is in order).
-constexpr int kStageTiles = 32;
-
-struct TrainLds {
-    __bf16 w[4 * kWidth * kLdsRow];
-    SmallParams sp;
-    float xs[4 * kStageTiles * 16];
-    float ts[4 * kStageTiles * 16];   // targets (2 rows) or rho and weights (4 rows)
-};
-static_assert(sizeof(TrainLds) <= 160 * 1024, "the training kernel's LDS exceeds 160 KiB");
-
-// Forward pass, loss and back-propagation of one tile of 16 samples (lane
-// l: sample l % 16), writing the workspace rows of every sample.
-__device__ inline void train_tile(const TrainArgs &a, const TrainLds &L, long long tile, int li,
-                                  int lane) {
-    const int g = lane >> 4;
-    const __bf16 *Wf2 = L.w, *Wf3 = L.w + kWidth * kLdsRow;
-    const __bf16 *Wb2 = L.w + 2 * kWidth * kLdsRow, *Wb3 = L.w + 3 * kWidth * kLdsRow;
-    float u[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) u[k] = (L.xs[k * kStageTiles * 16 + li] - a.shift[k]) * a.scale[k];
-
-    Layer d1, d2, d3, x;
-    bf16x8 b[4];
-    float o0, o1;
-    const RowSink sink{a.S + tile * 16, a.ldS};
-    forward<true>(L.sp, Wf2, Wf3, u, lane, d1, d2, d3, x, o0, o1, &sink);
-    pack(x, b);
-    store_rows(sink, kRowH + 256, b, lane);
-
-    // the error of the sample, e = w out - target (w = 1 unweighted, where this
-    // is out - target to the bit), and dL/dout = 2 e w / n; the targets are read
-    // only now, after the forward pass has released its registers
-    const float t0 = L.ts[li], t1 = L.ts[kStageTiles * 16 + li];
-    // (rows 2 and 3 of the staged targets hold the weights, 1 when unweighted:
-    // an unconditional read keeps the kernel within its register budget, where
-    // a read under the condition made it spill)
-    const float w0 = L.ts[2 * kStageTiles * 16 + li], w1 = L.ts[3 * kStageTiles * 16 + li];
-    const float e0 = w0 * o0 - t0, e1 = w1 * o1 - t1;
-    const float dout0 = 2.0f * e0 * w0 * a.inv_n, dout1 = 2.0f * e1 * w1 * a.inv_n;
-    // layer 3: dL/dz3 = (W4^T dout) * gelu'(z3)
-#pragma unroll
-    for (int mt = 0; mt < 8; ++mt) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int f = 16 * mt + 4 * g + i;
-            x.v[mt][i] = (L.sp.w4[f] * dout0 + L.sp.w4[kWidth + f] * dout1) * d3.v[mt][i];
-        }
-    }
-    pack(x, b);
-    store_rows(sink, kRowD + 256, b, lane);
-    matmul(Wb3, b, x, lane);                              // W3^T dL/dz3
-#pragma unroll
-    for (int mt = 0; mt < 8; ++mt) x.v[mt] *= d2.v[mt];
-    pack(x, b);
-    store_rows(sink, kRowD + 128, b, lane);
-    matmul(Wb2, b, x, lane);                              // W2^T dL/dz2
-#pragma unroll
-    for (int mt = 0; mt < 8; ++mt) x.v[mt] *= d1.v[mt];
-    pack(x, b);
-    store_rows(sink, kRowD, b, lane);
-
-    // rows of XO: group 0 writes u0..u3, group 1 writes 1, dout0, dout1, 0,
-    // groups 2 and 3 the zero rows
-    __bf16 xo[4];
-    if (g == 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) xo[r] = __bf16(u[r]);
-    } else if (g == 1) {
-        xo[0] = __bf16(1.0f);
-        xo[1] = __bf16(dout0);
-        xo[2] = __bf16(dout1);
-        xo[3] = __bf16(0.0f);
-    } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) xo[r] = __bf16(0.0f);
-    }
-    store_rows16(sink, kRowXO, xo, lane);
-
-    float sq = g == 0 ? e0 * e0 + e1 * e1 : 0.0f;
-    sq += __shfl_xor(sq, 1);
-    sq += __shfl_xor(sq, 2);
-    sq += __shfl_xor(sq, 4);
-    sq += __shfl_xor(sq, 8);
-    if (lane == 0) a.loss_part[tile] = sq;
-}
-
-__global__ __launch_bounds__(kTrainThreads) void sur_train_kernel(TrainArgs a) {
-    __shared__ TrainLds L;
-    const int tid = int(threadIdx.x);
-    load_mats(L.w, a.shadow, 4, tid, kTrainThreads);
-    load_small(L.sp, a.params, tid, kTrainThreads);
-    const int lane = tid & 63, wave = tid >> 6;
-    const long long tiles = a.n / 16;
-    // workgroup b owns the contiguous tiles [b * per, (b+1) * per), staged in
-    // chunks of kStageTiles
-    const long long per = (tiles + gridDim.x - 1) / gridDim.x;
-    const long long tb = (long long)blockIdx.x * per;
-    const long long te = tb + per < tiles ? tb + per : tiles;
-    for (long long c0 = tb; c0 < te; c0 += kStageTiles) {
-        const long long c1 = c0 + kStageTiles < te ? c0 + kStageTiles : te;
-        const int cn = int(c1 - c0) * 16;
-        __syncthreads();                              // the previous chunk is consumed
-        for (int i = tid; i < cn; i += kTrainThreads) {
-            const long long src = a.start + c0 * 16 + i;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) L.xs[k * kStageTiles * 16 + i] = a.x[k * a.ld + src];
-            L.ts[i] = a.t[src];
-            L.ts[kStageTiles * 16 + i] = a.t[a.ld + src];
-            L.ts[2 * kStageTiles * 16 + i] = a.weighted ? a.t[2 * a.ld + src] : 1.0f;
-            L.ts[3 * kStageTiles * 16 + i] = a.weighted ? a.t[3 * a.ld + src] : 1.0f;
-        }
-        __syncthreads();
-        for (long long tile = c0 + wave; tile < c1; tile += kTrainThreads / 64) {
-            asm volatile("" ::: "memory");            // keep the weight reads inside the loop
-            train_tile(a, L, tile, int(tile - c0) * 16 + (lane & 15), lane);
-        }
-    }
-}
 
 // Weight-gradient sums G = A B^T over samples k0..k1-1 of the minibatch, A and
 // B row blocks of S; each wave computes a 32 x 32 block of one of the products
@@ -738,6 +615,246 @@ __global__ __launch_bounds__(kInferThreads) void sur_chain_kernel(ChainArgs a) {
         if (nout) atomicAdd(&a.stats[1], nout);
         if (maxdev > 0.0) atomicMax(&a.stats[2], (unsigned long long)__double_as_longlong(maxdev));
         if (bad) atomicMin(&a.stats[3], (unsigned long long)q);
+    }
+}
+
+// ---- training: forward pass, loss and back-propagation ------------------
+//
+// Four waves share a tile of 16 samples, as in the composition above: wave w
+// of a group computes features 32 w .. 32 w + 31 (output tiles 2w, 2w+1) of
+// every 128-wide layer, which is exactly k-block w of the next product's
+// operand, and the four blocks are exchanged through LDS.  A wave so holds a
+// quarter of each layer's values and GELU derivatives, which lets two groups
+// (two waves per SIMD) share the workgroup's one copy of the four bf16
+// weight matrices in LDS: the second group's instructions fill the first's
+// latency.  Each product's output element is summed over the same k-blocks in
+// the same order as a whole-layer product; the network's two outputs are the
+// four waves' partial sums added in wave order.
+constexpr int kTrainGroups = 3;                        // tiles in flight per workgroup
+constexpr int kTrainThreads = 256 * kTrainGroups;
+// Inputs and targets of kStageTiles tiles are staged in LDS before the tiles
+// are processed: a global load inside the tile loop would have to wait for
+// every store of the previous tile (the memory counter is in order).
+constexpr int kStageTiles = 8;
+
+struct TrainLds {
+    __bf16 w[4 * kWidth * kLdsRow];         // Wf2, Wf3, Wb2, Wb3
+    SmallParams sp;
+    float xs[4 * kStageTiles * 16];
+    float ts[4 * kStageTiles * 16];         // targets and weights (1 when unweighted)
+    bf16x8 xb[kTrainGroups][4][64];         // per group: each wave's operand k-block
+    float part[kTrainGroups][4][2][16];     // per group: the outputs' partial sums
+};
+static_assert(sizeof(TrainLds) <= 160 * 1024, "the training kernel's LDS exceeds 160 KiB");
+
+// Publish this wave's block to its group and gather all four (two barriers:
+// the group's previous reads are complete before the block is overwritten).
+__device__ inline void train_exchange(TrainLds &L, int gi, const bf16x8 &mine, int w, int lane,
+                                      bf16x8 (&b)[4]) {
+    __syncthreads();
+    L.xb[gi][w][lane] = mine;
+    __syncthreads();
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) b[kb] = L.xb[gi][kb][lane];
+}
+
+__device__ inline bf16x8 pack_block(const f32x4 (&x)[2]) {
+    bf16x8 blk;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        blk[e] = __bf16(x[0][e]);
+        blk[e + 4] = __bf16(x[1][e]);
+    }
+    return blk;
+}
+
+// Rows row0 + 32 w + (features of the block) of the tile: element e of the
+// block is feature 4 g + e (e < 4) or 16 + 4 g + (e - 4) of the wave's 32.
+__device__ inline void store_block(const RowSink &o, int row0, int w, const bf16x8 &blk,
+                                   int lane) {
+    const int s = lane & 15, g = lane >> 4;
+    __bf16 *col = o.tile + (long long)(row0 + 32 * w + 4 * g) * o.ld + s;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) col[(long long)(e < 4 ? e : 12 + e) * o.ld] = blk[e];
+}
+
+// One tile (16 samples, staged at li0 .. li0 + 15 of the chunk) by wave w of
+// group gi.  When !live the group only keeps step with the other group's
+// barriers (its tile is a copy of a live one) and stores nothing.
+__device__ inline void train_tile(const TrainArgs &a, TrainLds &L, long long tile, int li0,
+                                  bool live, int gi, int w, int lane) {
+    const int s = lane & 15, g = lane >> 4, li = li0 + s;
+    const __bf16 *Wf2 = L.w, *Wf3 = L.w + kWidth * kLdsRow;
+    const __bf16 *Wb2 = L.w + 2 * kWidth * kLdsRow, *Wb3 = L.w + 3 * kWidth * kLdsRow;
+    const RowSink sink{a.S + tile * 16, a.ldS};
+    float u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k] = (L.xs[k * kStageTiles * 16 + li] - a.shift[k]) * a.scale[k];
+    f32x4 x[2], d1[2], d2[2], d3[2];
+    bf16x8 b[4], blk;
+    // layer 1 (FP32): the wave's 32 features
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = 16 * (2 * w + t) + 4 * g + i;
+            float z = L.sp.b1[f];
+            z = fmaf(L.sp.w1[4 * f + 0], u[0], z);
+            z = fmaf(L.sp.w1[4 * f + 1], u[1], z);
+            z = fmaf(L.sp.w1[4 * f + 2], u[2], z);
+            z = fmaf(L.sp.w1[4 * f + 3], u[3], z);
+            float d;
+            x[t][i] = gelu_d(z, d);
+            d1[t][i] = d;
+        }
+    }
+    blk = pack_block(x);
+    if (live) store_block(sink, kRowH, w, blk, lane);
+    train_exchange(L, gi, blk, w, lane, b);
+    // layers 2 and 3 on the matrix cores
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+        layer_split(layer == 0 ? Wf2 : Wf3, b, w, lane, x);
+        const float *bias = layer == 0 ? L.sp.b2 : L.sp.b3;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float d;
+                x[t][i] = gelu_d(x[t][i] + bias[16 * (2 * w + t) + 4 * g + i], d);
+                if (layer == 0)
+                    d2[t][i] = d;
+                else
+                    d3[t][i] = d;
+            }
+        }
+        blk = pack_block(x);
+        if (live) store_block(sink, kRowH + 128 * (layer + 1), w, blk, lane);
+        if (layer == 0) train_exchange(L, gi, blk, w, lane, b);
+    }
+    // the two outputs: the wave's partial sums over its 32 features of a3
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = 16 * (2 * w + t) + 4 * g + i;
+            s0 = fmaf(L.sp.w4[f], x[t][i], s0);
+            s1 = fmaf(L.sp.w4[kWidth + f], x[t][i], s1);
+        }
+    }
+    s0 += __shfl_xor(s0, 16);
+    s1 += __shfl_xor(s1, 16);
+    s0 += __shfl_xor(s0, 32);
+    s1 += __shfl_xor(s1, 32);
+    if (g == 0) {
+        L.part[gi][w][0][s] = s0;
+        L.part[gi][w][1][s] = s1;
+    }
+    __syncthreads();
+    const float o0 = ((L.part[gi][0][0][s] + L.part[gi][1][0][s]) +
+                      (L.part[gi][2][0][s] + L.part[gi][3][0][s])) + L.sp.b4[0];
+    const float o1 = ((L.part[gi][0][1][s] + L.part[gi][1][1][s]) +
+                      (L.part[gi][2][1][s] + L.part[gi][3][1][s])) + L.sp.b4[1];
+
+    // the error of the sample, e = w out - target (w = 1 unweighted, where this
+    // is out - target to the bit), and dL/dout = 2 e w / n.  Rows 2 and 3 of the
+    // staged targets hold the weights, 1 when unweighted: an unconditional read
+    // keeps the kernel within its register budget.
+    const float t0 = L.ts[li], t1 = L.ts[kStageTiles * 16 + li];
+    const float w0 = L.ts[2 * kStageTiles * 16 + li], w1 = L.ts[3 * kStageTiles * 16 + li];
+    const float e0 = w0 * o0 - t0, e1 = w1 * o1 - t1;
+    const float dout0 = 2.0f * e0 * w0 * a.inv_n, dout1 = 2.0f * e1 * w1 * a.inv_n;
+
+    // back-propagation: dL/dz3 = (W4^T dout) * gelu'(z3) for the wave's features
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = 16 * (2 * w + t) + 4 * g + i;
+            x[t][i] = (L.sp.w4[f] * dout0 + L.sp.w4[kWidth + f] * dout1) * d3[t][i];
+        }
+    }
+    blk = pack_block(x);
+    if (live) store_block(sink, kRowD + 256, w, blk, lane);
+    train_exchange(L, gi, blk, w, lane, b);
+    layer_split(Wb3, b, w, lane, x);                      // W3^T dL/dz3
+#pragma unroll
+    for (int t = 0; t < 2; ++t) x[t] *= d2[t];
+    blk = pack_block(x);
+    if (live) store_block(sink, kRowD + 128, w, blk, lane);
+    train_exchange(L, gi, blk, w, lane, b);
+    layer_split(Wb2, b, w, lane, x);                      // W2^T dL/dz2
+#pragma unroll
+    for (int t = 0; t < 2; ++t) x[t] *= d1[t];
+    blk = pack_block(x);
+    if (live) store_block(sink, kRowD, w, blk, lane);
+
+    if (live && w == 0) {
+        // rows of XO: group 0 writes u0..u3, group 1 writes 1, dout0, dout1, 0,
+        // groups 2 and 3 the zero rows
+        __bf16 xo[4];
+        if (g == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xo[r] = __bf16(u[r]);
+        } else if (g == 1) {
+            xo[0] = __bf16(1.0f);
+            xo[1] = __bf16(dout0);
+            xo[2] = __bf16(dout1);
+            xo[3] = __bf16(0.0f);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xo[r] = __bf16(0.0f);
+        }
+        store_rows16(sink, kRowXO, xo, lane);
+        float sq = g == 0 ? e0 * e0 + e1 * e1 : 0.0f;
+        sq += __shfl_xor(sq, 1);
+        sq += __shfl_xor(sq, 2);
+        sq += __shfl_xor(sq, 4);
+        sq += __shfl_xor(sq, 8);
+        if (lane == 0) a.loss_part[tile] = sq;
+    }
+}
+
+__global__ __launch_bounds__(kTrainThreads) void sur_train_kernel(TrainArgs a) {
+    __shared__ TrainLds L;
+    const int tid = int(threadIdx.x);
+    load_mats(L.w, a.shadow, 4, tid, kTrainThreads);
+    load_small(L.sp, a.params, tid, kTrainThreads);
+    const int lane = tid & 63;
+    const int gi = __builtin_amdgcn_readfirstlane(tid >> 8);        // group
+    const int w = __builtin_amdgcn_readfirstlane((tid >> 6) & 3);   // wave in the group
+    const long long tiles = a.n / 16;
+    // workgroup b owns the contiguous tiles [b * per, (b+1) * per), staged in
+    // chunks of kStageTiles; group gi takes tiles c0 + gi, c0 + gi + G, ...
+    const long long per = (tiles + gridDim.x - 1) / gridDim.x;
+    const long long tb = (long long)blockIdx.x * per;
+    const long long te = tb + per < tiles ? tb + per : tiles;
+    for (long long c0 = tb; c0 < te; c0 += kStageTiles) {
+        const long long c1 = c0 + kStageTiles < te ? c0 + kStageTiles : te;
+        const int cn = int(c1 - c0) * 16;
+        __syncthreads();                              // the previous chunk is consumed
+        for (int i = tid; i < cn; i += kTrainThreads) {
+            const long long src = a.start + c0 * 16 + i;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) L.xs[k * kStageTiles * 16 + i] = a.x[k * a.ld + src];
+            L.ts[i] = a.t[src];
+            L.ts[kStageTiles * 16 + i] = a.t[a.ld + src];
+            L.ts[2 * kStageTiles * 16 + i] = a.weighted ? a.t[2 * a.ld + src] : 1.0f;
+            L.ts[3 * kStageTiles * 16 + i] = a.weighted ? a.t[3 * a.ld + src] : 1.0f;
+        }
+        __syncthreads();
+        // every group runs the same number of rounds (the barriers inside a
+        // tile are the workgroup's); a group past the chunk's end repeats the
+        // chunk's first tile without storing
+        const int rounds = (int(c1 - c0) + kTrainGroups - 1) / kTrainGroups;
+        for (int r = 0; r < rounds; ++r) {
+            asm volatile("" ::: "memory");            // keep the weight reads inside the loop
+            const long long tile = c0 + r * kTrainGroups + gi;
+            const bool live = tile < c1;
+            const long long tt = live ? tile : c0;
+            train_tile(a, L, tt, int(tt - c0) * 16, live, gi, w, lane);
+        }
     }
 }
 

@@ -679,8 +679,9 @@ __device__ inline void store_block(const RowSink &o, int row0, int w, const bf16
 }
 
 // One tile (16 samples, staged at li0 .. li0 + 15 of the chunk) by wave w of
-// group gi.  When !live the group only keeps step with the other group's
-// barriers (its tile is a copy of a live one) and stores nothing.
+// group gi.  When !live the group computes and stores nothing but passes the
+// same barriers (every barrier below is outside the `live` conditions, so all
+// waves of the workgroup meet the same sequence of them).
 __device__ inline void train_tile(const TrainArgs &a, TrainLds &L, long long tile, int li0,
                                   bool live, int gi, int w, int lane) {
     const int s = lane & 15, g = lane >> 4, li = li0 + s;
@@ -690,105 +691,119 @@ __device__ inline void train_tile(const TrainArgs &a, TrainLds &L, long long til
     float u[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) u[k] = (L.xs[k * kStageTiles * 16 + li] - a.shift[k]) * a.scale[k];
-    f32x4 x[2], d1[2], d2[2], d3[2];
-    bf16x8 b[4], blk;
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    f32x4 x[2] = {zero, zero}, d1[2] = {zero, zero}, d2[2] = {zero, zero}, d3[2] = {zero, zero};
+    bf16x8 b[4], blk = {};
     // layer 1 (FP32): the wave's 32 features
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int f = 16 * (2 * w + t) + 4 * g + i;
-            float z = L.sp.b1[f];
-            z = fmaf(L.sp.w1[4 * f + 0], u[0], z);
-            z = fmaf(L.sp.w1[4 * f + 1], u[1], z);
-            z = fmaf(L.sp.w1[4 * f + 2], u[2], z);
-            z = fmaf(L.sp.w1[4 * f + 3], u[3], z);
-            float d;
-            x[t][i] = gelu_d(z, d);
-            d1[t][i] = d;
-        }
-    }
-    blk = pack_block(x);
-    if (live) store_block(sink, kRowH, w, blk, lane);
-    train_exchange(L, gi, blk, w, lane, b);
-    // layers 2 and 3 on the matrix cores
-#pragma unroll
-    for (int layer = 0; layer < 2; ++layer) {
-        layer_split(layer == 0 ? Wf2 : Wf3, b, w, lane, x);
-        const float *bias = layer == 0 ? L.sp.b2 : L.sp.b3;
+    if (live) {
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
+                const int f = 16 * (2 * w + t) + 4 * g + i;
+                float z = L.sp.b1[f];
+                z = fmaf(L.sp.w1[4 * f + 0], u[0], z);
+                z = fmaf(L.sp.w1[4 * f + 1], u[1], z);
+                z = fmaf(L.sp.w1[4 * f + 2], u[2], z);
+                z = fmaf(L.sp.w1[4 * f + 3], u[3], z);
                 float d;
-                x[t][i] = gelu_d(x[t][i] + bias[16 * (2 * w + t) + 4 * g + i], d);
-                if (layer == 0)
-                    d2[t][i] = d;
-                else
-                    d3[t][i] = d;
+                x[t][i] = gelu_d(z, d);
+                d1[t][i] = d;
             }
         }
         blk = pack_block(x);
-        if (live) store_block(sink, kRowH + 128 * (layer + 1), w, blk, lane);
+        store_block(sink, kRowH, w, blk, lane);
+    }
+    train_exchange(L, gi, blk, w, lane, b);
+    // layers 2 and 3 on the matrix cores
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+        if (live) {
+            layer_split(layer == 0 ? Wf2 : Wf3, b, w, lane, x);
+            const float *bias = layer == 0 ? L.sp.b2 : L.sp.b3;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float d;
+                    x[t][i] = gelu_d(x[t][i] + bias[16 * (2 * w + t) + 4 * g + i], d);
+                    if (layer == 0)
+                        d2[t][i] = d;
+                    else
+                        d3[t][i] = d;
+                }
+            }
+            blk = pack_block(x);
+            store_block(sink, kRowH + 128 * (layer + 1), w, blk, lane);
+        }
         if (layer == 0) train_exchange(L, gi, blk, w, lane, b);
     }
     // the two outputs: the wave's partial sums over its 32 features of a3
-    float s0 = 0.f, s1 = 0.f;
+    if (live) {
+        float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < 2; ++t) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int f = 16 * (2 * w + t) + 4 * g + i;
-            s0 = fmaf(L.sp.w4[f], x[t][i], s0);
-            s1 = fmaf(L.sp.w4[kWidth + f], x[t][i], s1);
+            for (int i = 0; i < 4; ++i) {
+                const int f = 16 * (2 * w + t) + 4 * g + i;
+                s0 = fmaf(L.sp.w4[f], x[t][i], s0);
+                s1 = fmaf(L.sp.w4[kWidth + f], x[t][i], s1);
+            }
         }
-    }
-    s0 += __shfl_xor(s0, 16);
-    s1 += __shfl_xor(s1, 16);
-    s0 += __shfl_xor(s0, 32);
-    s1 += __shfl_xor(s1, 32);
-    if (g == 0) {
-        L.part[gi][w][0][s] = s0;
-        L.part[gi][w][1][s] = s1;
+        s0 += __shfl_xor(s0, 16);
+        s1 += __shfl_xor(s1, 16);
+        s0 += __shfl_xor(s0, 32);
+        s1 += __shfl_xor(s1, 32);
+        if (g == 0) {
+            L.part[gi][w][0][s] = s0;
+            L.part[gi][w][1][s] = s1;
+        }
     }
     __syncthreads();
-    const float o0 = ((L.part[gi][0][0][s] + L.part[gi][1][0][s]) +
-                      (L.part[gi][2][0][s] + L.part[gi][3][0][s])) + L.sp.b4[0];
-    const float o1 = ((L.part[gi][0][1][s] + L.part[gi][1][1][s]) +
-                      (L.part[gi][2][1][s] + L.part[gi][3][1][s])) + L.sp.b4[1];
-
-    // the error of the sample, e = w out - target (w = 1 unweighted, where this
-    // is out - target to the bit), and dL/dout = 2 e w / n.  Rows 2 and 3 of the
-    // staged targets hold the weights, 1 when unweighted: an unconditional read
-    // keeps the kernel within its register budget.
-    const float t0 = L.ts[li], t1 = L.ts[kStageTiles * 16 + li];
-    const float w0 = L.ts[2 * kStageTiles * 16 + li], w1 = L.ts[3 * kStageTiles * 16 + li];
-    const float e0 = w0 * o0 - t0, e1 = w1 * o1 - t1;
-    const float dout0 = 2.0f * e0 * w0 * a.inv_n, dout1 = 2.0f * e1 * w1 * a.inv_n;
-
-    // back-propagation: dL/dz3 = (W4^T dout) * gelu'(z3) for the wave's features
+    float e0 = 0.f, e1 = 0.f, dout0 = 0.f, dout1 = 0.f;
+    if (live) {
+        const float o0 = ((L.part[gi][0][0][s] + L.part[gi][1][0][s]) +
+                          (L.part[gi][2][0][s] + L.part[gi][3][0][s])) + L.sp.b4[0];
+        const float o1 = ((L.part[gi][0][1][s] + L.part[gi][1][1][s]) +
+                          (L.part[gi][2][1][s] + L.part[gi][3][1][s])) + L.sp.b4[1];
+        // the error of the sample, e = w out - target (w = 1 unweighted, where
+        // this is out - target to the bit), and dL/dout = 2 e w / n.  Rows 2 and 3
+        // of the staged targets hold the weights, 1 when unweighted: an
+        // unconditional read keeps the kernel within its register budget.
+        const float t0 = L.ts[li], t1 = L.ts[kStageTiles * 16 + li];
+        const float w0 = L.ts[2 * kStageTiles * 16 + li], w1 = L.ts[3 * kStageTiles * 16 + li];
+        e0 = w0 * o0 - t0;
+        e1 = w1 * o1 - t1;
+        dout0 = 2.0f * e0 * w0 * a.inv_n;
+        dout1 = 2.0f * e1 * w1 * a.inv_n;
+        // back-propagation: dL/dz3 = (W4^T dout) * gelu'(z3) for the wave's features
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < 2; ++t) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int f = 16 * (2 * w + t) + 4 * g + i;
-            x[t][i] = (L.sp.w4[f] * dout0 + L.sp.w4[kWidth + f] * dout1) * d3[t][i];
+            for (int i = 0; i < 4; ++i) {
+                const int f = 16 * (2 * w + t) + 4 * g + i;
+                x[t][i] = (L.sp.w4[f] * dout0 + L.sp.w4[kWidth + f] * dout1) * d3[t][i];
+            }
         }
+        blk = pack_block(x);
+        store_block(sink, kRowD + 256, w, blk, lane);
     }
-    blk = pack_block(x);
-    if (live) store_block(sink, kRowD + 256, w, blk, lane);
     train_exchange(L, gi, blk, w, lane, b);
-    layer_split(Wb3, b, w, lane, x);                      // W3^T dL/dz3
+    if (live) {
+        layer_split(Wb3, b, w, lane, x);                  // W3^T dL/dz3
 #pragma unroll
-    for (int t = 0; t < 2; ++t) x[t] *= d2[t];
-    blk = pack_block(x);
-    if (live) store_block(sink, kRowD + 128, w, blk, lane);
+        for (int t = 0; t < 2; ++t) x[t] *= d2[t];
+        blk = pack_block(x);
+        store_block(sink, kRowD + 128, w, blk, lane);
+    }
     train_exchange(L, gi, blk, w, lane, b);
-    layer_split(Wb2, b, w, lane, x);                      // W2^T dL/dz2
+    if (live) {
+        layer_split(Wb2, b, w, lane, x);                  // W2^T dL/dz2
 #pragma unroll
-    for (int t = 0; t < 2; ++t) x[t] *= d1[t];
-    blk = pack_block(x);
-    if (live) store_block(sink, kRowD, w, blk, lane);
+        for (int t = 0; t < 2; ++t) x[t] *= d1[t];
+        blk = pack_block(x);
+        store_block(sink, kRowD, w, blk, lane);
+    }
 
     if (live && w == 0) {
         // rows of XO: group 0 writes u0..u3, group 1 writes 1, dout0, dout1, 0,
@@ -845,8 +860,8 @@ __global__ __launch_bounds__(kTrainThreads) void sur_train_kernel(TrainArgs a) {
         }
         __syncthreads();
         // every group runs the same number of rounds (the barriers inside a
-        // tile are the workgroup's); a group past the chunk's end repeats the
-        // chunk's first tile without storing
+        // tile are the workgroup's); a group past the chunk's end only passes
+        // the barriers
         const int rounds = (int(c1 - c0) + kTrainGroups - 1) / kTrainGroups;
         for (int r = 0; r < rounds; ++r) {
             asm volatile("" ::: "memory");            // keep the weight reads inside the loop

@@ -206,8 +206,24 @@ def test_locate_bit_exact(orc, prop, torch, lo, hi, n):
 
 
 # ---------------------------------------------------------------------------
-# full-size workloads, in the configuration the benchmark times
+# full-size workloads: one build launch and nv_compose against the oracle, then
+# the configuration the benchmark times (nv_solve: the build cut into chunks on
+# two streams, each chunk composed as soon as its tables are complete) against
+# that, bit for bit
 # ---------------------------------------------------------------------------
+
+def check_timed_configuration(prop, w, tab, gres):
+    """nv_solve on the same workload: tables and boundary states equal the
+    single launch's and nv_compose's to the bit."""
+    r = prop.solve(w)
+    assert r.status == gres.status and r.n_out_of_grid == gres.n_out_of_grid
+    assert np.array_equal(r.boundary.view(np.int64), gres.boundary.view(np.int64))
+    for c in range(w.dim):
+        t = prop.table(c).astype(np.float64)
+        assert np.array_equal(t.view(np.int64), tab[c].view(np.int64)), c
+    say(f"{w.name}: nv_solve in {r.n_chunks} chunks equals the single launch bit for bit")
+    return r
+
 
 def test_full_logistic_fp64(orc, prop):
     w = W.LOGISTIC_FP64
@@ -219,6 +235,7 @@ def test_full_logistic_fp64(orc, prop):
                            w.steps_per_slice)
     assert mixed_err(tab, ref) <= TOL["fp64"]
     gres, _ = check_compose_bit_exact(orc, prop, w, tab, w.y0)
+    check_timed_configuration(prop, w, tab, gres)
     oracle_method = orc.compose_tables(g, w.interp, ref, w.y0)
     assert abs(gres.yT[0] - oracle_method.yT[0]) <= TOL["fp64"]
     ser = orc.serial(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, w.steps_per_slice,
@@ -277,6 +294,7 @@ def test_full_forced_cubic_fp32(orc, prop):
     assert np.all(prop.nonfinite_counts() == 0)
     tab = gpu_tables(prop, w)
     gres, _ = check_compose_bit_exact(orc, prop, w, tab, w.y0)
+    assert check_timed_configuration(prop, w, tab, gres).n_chunks == 32
     _fp32_vs_fp64_method(orc, w, tab, gres, "forced cubic")
     ser = orc.serial(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, w.steps_per_slice,
                      w.y0)[0]
@@ -295,6 +313,7 @@ def test_full_vdp_fp32(orc, prop):
     tab = gpu_tables(prop, w)
     gres, _ = check_compose_bit_exact(orc, prop, w, tab, w.y0)
     assert gres.n_out_of_grid == 0
+    assert check_timed_configuration(prop, w, tab, gres).n_chunks > 1
     _fp32_vs_fp64_method(orc, w, tab, gres, "vdp")
 
 
@@ -449,19 +468,6 @@ def test_solve_equals_build_then_compose(orc, torch, w, chunks):
         tab = gpu_tables(b, w)
         o = orc.compose_tables(ogrid(orc, w), w.interp, tab, tuple(v * 0.9 for v in w.y0))
         assert np.array_equal(rc.boundary, o.boundary)
-
-
-def test_solve_full_size_matches_two_phase(prop, torch):
-    from paper_1304_6514_amd.propagator import Propagator
-    for w in (W.FORCED_CUBIC_FP32, W.VDP_FP32):
-        say("solve full", w.name)
-        prop.build(w)
-        ra = prop.compose()
-        with Propagator("cuda:0") as b:
-            rb = b.solve(w)
-        say("chunks", rb.n_chunks)
-        assert rb.n_chunks > 1
-        assert rb.status == nv.NV_OK and np.array_equal(ra.boundary, rb.boundary)
 
 
 def test_solve_nonfinite_reports_same_slice(orc, torch):

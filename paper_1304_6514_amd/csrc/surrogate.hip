@@ -93,20 +93,20 @@ struct TrainArgs {
 };
 
 // Weight-gradient sums G = A B^T over samples k0..k1-1 of the minibatch, A and
-// B row blocks of S; each wave computes a 32 x 32 block of one of the products
-// (wave tiles kGemmSmallFirst.. of kGemmWaveTiles: the two small products
-// D1 . XO^T, giving dW1 and db1, and XO . [H3; XO]^T, giving dW4 and db4),
-// blockIdx.y is the split of the sum.  (db2 and db3 are row sums that
-// sur_grad_mat_kernel forms from the rows it stages anyway.)
+// B row blocks of S; blockIdx.y of the launch is the split of the sum.  In the
+// small products each wave computes a 32 x 32 block (wave tiles
+// kGemmSmallFirst.. of kGemmWaveTiles: D1 . XO^T, giving dW1 and db1, and
+// XO . [H3; XO]^T, giving dW4 and db4; db2 and db3 are row sums that the
+// 128 x 128 products form from the rows they stage anyway).
 struct GemmArgs {
     const __bf16 *S;
     long long ldS, n, k_per_split;
     float *part;                 // [splits][kGradEntries]
 };
 
-__global__ __launch_bounds__(256) void sur_grad_kernel(GemmArgs a) {
+__device__ inline void grad_small(const GemmArgs &a, int bx) {
     const int lane = int(threadIdx.x) & 63, r = lane & 15, g = lane >> 4;
-    const int wt = kGemmSmallFirst + int(blockIdx.x) * 4 + (int(threadIdx.x) >> 6);
+    const int wt = kGemmSmallFirst + bx * 4 + (int(threadIdx.x) >> 6);
     if (wt >= kGemmWaveTiles) return;
     int a_row, b_row, M, N, out, t, tiles_n;
     if (wt < 16) {
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void sur_grad_kernel(GemmArgs a) {
 }
 
 // The two 128 x 128 weight gradients, dW2 = D2 . H1^T and dW3 = D3 . H2^T
-// (blockIdx.x = 0, 1), over samples k0..k1-1 (blockIdx.y = split), and the
+// (job 0, 1), over samples k0..k1-1 (blockIdx.y = split), and the
 // bias gradients db2, db3, the row sums of D2 and D3.  The workgroup stages
 // each 32-sample step of its 128 A rows and 128 B rows in LDS once (rows
 // padded to 80 bytes: 16 lanes reading 16 bytes from 16 rows hit disjoint
@@ -181,9 +181,12 @@ __global__ __launch_bounds__(256) void sur_grad_kernel(GemmArgs a) {
 // into registers while the current one is multiplied.
 constexpr int kGmPad = 40;                 // bf16 per LDS row
 
-__global__ __launch_bounds__(256) void sur_grad_mat_kernel(GemmArgs a) {
-    __shared__ __bf16 As[128 * kGmPad], Bs[128 * kGmPad];
-    const int job = int(blockIdx.x);
+struct GradMatLds {
+    __bf16 As[128 * kGmPad], Bs[128 * kGmPad];
+};
+
+__device__ inline void grad_mat(const GemmArgs &a, GradMatLds &L, int job) {
+    __bf16 *As = L.As, *Bs = L.Bs;
     const int a_row = job == 0 ? kRowD + 128 : kRowD + 256;
     const int b_row = job == 0 ? kRowH : kRowH + 128;
     const int out = job == 0 ? kG_W2 : kG_W3;
@@ -253,6 +256,19 @@ __global__ __launch_bounds__(256) void sur_grad_mat_kernel(GemmArgs a) {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 P[(64 * mh + 16 * i + 4 * g + e) * 128 + 64 * nh + 16 * j + r] = acc[i][j][e];
+}
+
+// All weight-gradient sums of one step in one launch: blockIdx.x 0 and 1 are
+// the two 128 x 128 products (the long-running workgroups, dispatched first),
+// the others the small products; blockIdx.y is the split of the sum.
+constexpr int kGradSmallBlocks = (kGemmWaveTiles - kGemmSmallFirst + 3) / 4;
+
+__global__ __launch_bounds__(256) void sur_grad_kernel(GemmArgs a) {
+    __shared__ GradMatLds L;
+    if (blockIdx.x < 2)
+        grad_mat(a, L, int(blockIdx.x));
+    else
+        grad_small(a, int(blockIdx.x) - 2);
 }
 
 // Offset of parameter p's gradient in the partial vector.
@@ -1090,10 +1106,8 @@ nv_status minibatch(nv_sur *s, const float *x, const float *t, long long ld, lon
     ga.k_per_split = k_per_split(n);
     ga.part = s->part;
     const int splits = int((n + ga.k_per_split - 1) / ga.k_per_split);
-    hipLaunchKernelGGL(sur_grad_mat_kernel, dim3(2, splits), dim3(256), 0, s->stream, ga);
-    NV_HIP(hipGetLastError());
-    hipLaunchKernelGGL(sur_grad_kernel, dim3((kGemmWaveTiles - kGemmSmallFirst + 3) / 4, splits),
-                       dim3(256), 0, s->stream, ga);
+    hipLaunchKernelGGL(sur_grad_kernel, dim3(2 + kGradSmallBlocks, splits), dim3(256), 0,
+                       s->stream, ga);
     NV_HIP(hipGetLastError());
 
     UpdateArgs ua{};

@@ -30,7 +30,7 @@ _CB_LIB = os.path.join(_HERE, "libcpubuild.so")
 
 _RHS = {"linear": 10, "logistic": 11, "forced_cubic": 12, "vdp": 13, "square": 14}
 _SCHEME = {"rk4": 1, "euler": 2}
-_INTERP = {"linear": 1, "hermite": 2, "bilinear": 3}
+_INTERP = {"linear": 1, "hermite": 2, "bilinear": 3, "hermite_slopes": 4}
 OK, BAD_ARG, NONFINITE = 0, 1, 2
 
 _lib = None
@@ -73,6 +73,10 @@ def _load():
         "orc_grid_point": (I, [G, LL, P]),
         "orc_build_tables": (I, [I, P, I, D, D, I, G, I, P]),
         "orc_table_entries": (I, [I, P, I, D, D, I, G, I, LL, P, P, P]),
+        "orc_integrate_tangent": (I, [I, P, I, D, D, LL, ctypes.POINTER(D),
+                                      ctypes.POINTER(D)]),
+        "orc_build_tables_slopes": (I, [I, P, I, D, D, I, G, I, P]),
+        "orc_table_entries_slopes": (I, [I, P, I, D, D, I, G, I, LL, P, P, P]),
         "orc_locate": (I, [D, D, I, D, ctypes.POINTER(LL), ctypes.POINTER(D)]),
         "orc_compose_tables": (I, [G, I, I, P, P, P, P, P, ctypes.POINTER(LL),
                                    ctypes.POINTER(I)]),
@@ -237,6 +241,45 @@ def build_tables(rhs, params, scheme, t0, T, n_slices, grid: _Grid, steps_per_sl
                                 ctypes.byref(grid), steps_per_slice, _ptr(tab)),
            "build_tables")
     return tab
+
+
+def build_tables_slopes(rhs, params, scheme, t0, T, n_slices, grid: _Grid, steps_per_slice):
+    """Computation phase with slopes (1-D problems): shape (2, n_slices, M), [0] the
+    values, [1] their derivatives with respect to the grid point."""
+    lib = _load()
+    p = _params(params)
+    M = grid.n[0]
+    tab = np.zeros((2, n_slices, M))
+    _check(lib.orc_build_tables_slopes(_RHS[rhs], _ptr(p), _SCHEME[scheme], t0, T, n_slices,
+                                       ctypes.byref(grid), steps_per_slice, _ptr(tab)),
+           "build_tables_slopes")
+    return tab
+
+
+def table_entries_slopes(rhs, params, scheme, t0, T, n_slices, grid: _Grid, steps_per_slice,
+                         slices, points):
+    """Selected values and slopes (1-D problems): shape (2, count)."""
+    lib = _load()
+    p = _params(params)
+    sl = np.ascontiguousarray(np.asarray(slices, dtype=np.int64))
+    pt = np.ascontiguousarray(np.asarray(points, dtype=np.int64))
+    out = np.zeros((2, sl.size))
+    _check(lib.orc_table_entries_slopes(_RHS[rhs], _ptr(p), _SCHEME[scheme], t0, T, n_slices,
+                                        ctypes.byref(grid), steps_per_slice, sl.size, _ptr(sl),
+                                        _ptr(pt), _ptr(out)), "table_entries_slopes")
+    return out
+
+
+def integrate_tangent(rhs, params, scheme, t_base, h, nsteps, y, v=1.0):
+    """(y, dy/dy0) after nsteps steps of a 1-D problem from (y, v)."""
+    lib = _load()
+    p = _params(params)
+    yy = ctypes.c_double(float(y))
+    vv = ctypes.c_double(float(v))
+    _check(lib.orc_integrate_tangent(_RHS[rhs], _ptr(p), _SCHEME[scheme], float(t_base),
+                                     float(h), int(nsteps), ctypes.byref(yy), ctypes.byref(vv)),
+           "integrate_tangent")
+    return yy.value, vv.value
 
 
 def table_entries(rhs, params, scheme, t0, T, n_slices, grid: _Grid, steps_per_slice,

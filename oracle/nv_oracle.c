@@ -9,7 +9,11 @@
  *     lambda_j = phi^j(lambda_{j-1}), starting from y0 (slice 1 is
  *     interpolated too);
  *   - the interpolation rules (linear, cubic Hermite with finite-difference
- *     slopes, bilinear) and the lookup are the plain definitions written out;
+ *     slopes or with stored slopes, bilinear) and the lookup are the plain
+ *     definitions written out;
+ *   - the optional slope table holds the derivative of each entry's discrete
+ *     map with respect to its grid point, carried through every stage by the
+ *     chain rule (one-dimensional problems);
  *   - paper mode is backward Euler plus Lagrange interpolation on Chebyshev
  *     nodes, as in sec. 3 and Table 1.
  * No blocking, no reordering, no vectorisation.
@@ -78,6 +82,55 @@ static void one_step(int rhs, const double *p, int scheme, double ta, double tb,
         y[c] = y[c] + (h / 6.0) * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
 }
 
+/* df/dy of a one-dimensional right-hand side at (t, y). */
+static double rhs_jacobian(int rhs, const double *p, double y) {
+    switch (rhs) {
+    case ORC_LIN:
+        return p[0];
+    case ORC_LOG:
+        return 1.0 - 2.0 * y;
+    case ORC_FCUB:
+        return -3.0 * y * y;
+    case ORC_SQR:
+        return 2.0 * y;
+    default:
+        return 0.0;
+    }
+}
+
+/* One step of a one-dimensional problem together with the derivative of the
+ * step's result with respect to the initial value of the trajectory: v holds
+ * dy/dxi before the step and afterwards the derivative of the new y, by the
+ * chain rule through every stage of the step (the derivative of the discrete
+ * map, not of the exact flow).  y follows exactly the operations of one_step. */
+static void one_step_tangent(int rhs, const double *p, int scheme, double ta, double tb,
+                             double tc, double h, double *y, double *v) {
+    double k1, k2, k3, k4, z, d1, d2, d3, d4, dz, yy = *y, vv = *v;
+    if (scheme == ORC_EULER) {
+        rhs_eval(rhs, p, ta, &yy, &k1);
+        d1 = rhs_jacobian(rhs, p, yy) * vv;
+        *y = yy + h * k1;
+        *v = vv + h * d1;
+        return;
+    }
+    rhs_eval(rhs, p, ta, &yy, &k1);
+    d1 = rhs_jacobian(rhs, p, yy) * vv;
+    z = yy + (h / 2.0) * k1;
+    dz = vv + (h / 2.0) * d1;
+    rhs_eval(rhs, p, tb, &z, &k2);
+    d2 = rhs_jacobian(rhs, p, z) * dz;
+    z = yy + (h / 2.0) * k2;
+    dz = vv + (h / 2.0) * d2;
+    rhs_eval(rhs, p, tb, &z, &k3);
+    d3 = rhs_jacobian(rhs, p, z) * dz;
+    z = yy + h * k3;
+    dz = vv + h * d3;
+    rhs_eval(rhs, p, tc, &z, &k4);
+    d4 = rhs_jacobian(rhs, p, z) * dz;
+    *y = yy + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4);
+    *v = vv + (h / 6.0) * (d1 + 2.0 * d2 + 2.0 * d3 + d4);
+}
+
 static int valid_problem(int rhs, int scheme) {
     return orc_rhs_dim(rhs) > 0 && (scheme == ORC_RK4 || scheme == ORC_EULER);
 }
@@ -91,6 +144,19 @@ int orc_integrate(int rhs, const double *p, int scheme, double t_base, double h,
         double tb = ta + h / 2.0;
         double tc = t_base + (double)(s + 1) * h;
         one_step(rhs, p, scheme, ta, tb, tc, h, y);
+    }
+    return ORC_OK;
+}
+
+int orc_integrate_tangent(int rhs, const double *p, int scheme, double t_base, double h,
+                          long long nsteps, double *y, double *v) {
+    long long s;
+    if (!valid_problem(rhs, scheme) || orc_rhs_dim(rhs) != 1 || nsteps < 0) return ORC_BAD_ARG;
+    for (s = 0; s < nsteps; ++s) {
+        double ta = t_base + (double)s * h;
+        double tb = ta + h / 2.0;
+        double tc = t_base + (double)(s + 1) * h;
+        one_step_tangent(rhs, p, scheme, ta, tb, tc, h, y, v);
     }
     return ORC_OK;
 }
@@ -188,6 +254,35 @@ int orc_build_tables(int rhs, const double *p, int scheme, double t0, double T,
     return ORC_OK;
 }
 
+/* The value and the slope (its derivative with respect to the grid point) of
+ * entry (slice j, grid point k) of a one-dimensional problem. */
+static void table_entry_tangent(int rhs, const double *p, int scheme, double t0, double L,
+                                double h, int steps, const orc_grid *g, long long j,
+                                long long k, double *value, double *slope) {
+    orc_grid_point(g, k, value);
+    *slope = 1.0;
+    orc_integrate_tangent(rhs, p, scheme, slice_start(t0, L, j), h, steps, value, slope);
+}
+
+int orc_build_tables_slopes(int rhs, const double *p, int scheme, double t0, double T,
+                            int n_slices, const orc_grid *g, int steps_per_slice,
+                            double *tab) {
+    long long j, k, M;
+    double L, h, v, m;
+    if (!check_method_args(rhs, scheme, n_slices, g, steps_per_slice) || g->dim != 1)
+        return ORC_BAD_ARG;
+    M = grid_size(g);
+    L = slice_length(t0, T, n_slices);
+    h = L / (double)steps_per_slice;
+    for (j = 0; j < n_slices; ++j)
+        for (k = 0; k < M; ++k) {
+            table_entry_tangent(rhs, p, scheme, t0, L, h, steps_per_slice, g, j, k, &v, &m);
+            tab[j * M + k] = v;
+            tab[((long long)n_slices + j) * M + k] = m;
+        }
+    return ORC_OK;
+}
+
 int orc_table_entries(int rhs, const double *p, int scheme, double t0, double T,
                       int n_slices, const orc_grid *g, int steps_per_slice,
                       long long count, const long long *slice,
@@ -205,6 +300,26 @@ int orc_table_entries(int rhs, const double *p, int scheme, double t0, double T,
             return ORC_BAD_ARG;
         table_entry(rhs, p, scheme, t0, L, h, steps_per_slice, g, slice[q], point[q], y);
         for (c = 0; c < d; ++c) out[(long long)c * count + q] = y[c];
+    }
+    return ORC_OK;
+}
+
+int orc_table_entries_slopes(int rhs, const double *p, int scheme, double t0, double T,
+                             int n_slices, const orc_grid *g, int steps_per_slice,
+                             long long count, const long long *slice,
+                             const long long *point, double *out) {
+    long long q, M;
+    double L, h;
+    if (!check_method_args(rhs, scheme, n_slices, g, steps_per_slice) || g->dim != 1)
+        return ORC_BAD_ARG;
+    M = grid_size(g);
+    L = slice_length(t0, T, n_slices);
+    h = L / (double)steps_per_slice;
+    for (q = 0; q < count; ++q) {
+        if (slice[q] < 0 || slice[q] >= n_slices || point[q] < 0 || point[q] >= M)
+            return ORC_BAD_ARG;
+        table_entry_tangent(rhs, p, scheme, t0, L, h, steps_per_slice, g, slice[q], point[q],
+                            &out[q], &out[count + q]);
     }
     return ORC_OK;
 }
@@ -245,6 +360,8 @@ typedef struct {
     const double *p;
     double t0, L, h;
     const orc_grid *g;
+    /* component 1 is the slope table of a one-dimensional problem */
+    int slopes;
     /* one-entry memo so that a 2-D entry is integrated once for both components */
     long long memo_j, memo_k;
     double memo[2];
@@ -253,8 +370,12 @@ typedef struct {
 static double entry_value(entry_source *src, int c, long long j, long long k) {
     if (src->tab) return src->tab[((long long)c * src->n_slices + j) * src->M + k];
     if (src->memo_j != j || src->memo_k != k) {
-        table_entry(src->rhs, src->p, src->scheme, src->t0, src->L, src->h, src->steps,
-                    src->g, j, k, src->memo);
+        if (src->slopes)
+            table_entry_tangent(src->rhs, src->p, src->scheme, src->t0, src->L, src->h,
+                                src->steps, src->g, j, k, &src->memo[0], &src->memo[1]);
+        else
+            table_entry(src->rhs, src->p, src->scheme, src->t0, src->L, src->h, src->steps,
+                        src->g, j, k, src->memo);
         src->memo_j = j;
         src->memo_k = k;
     }
@@ -297,6 +418,22 @@ static double interp_hermite(entry_source *src, long long j, long long i, double
     return ((h00 * a + h10 * da) + h01 * b) + h11 * db;
 }
 
+/* Cubic Hermite with the stored slopes (component 1): the same basis and
+ * sum as interp_hermite, Delta-xi times the slope at each node taken from the
+ * slope table, Delta-xi = (hi - lo)/(n - 1). */
+static double interp_hermite_slopes(entry_source *src, long long j, long long i, double w,
+                                    double dxi, int *bad) {
+    double a = entry_value(src, 0, j, i), b = entry_value(src, 0, j, i + 1);
+    double da = dxi * entry_value(src, 1, j, i), db = dxi * entry_value(src, 1, j, i + 1);
+    double w2 = w * w, w3 = w2 * w;
+    double h00 = (2.0 * w3 - 3.0 * w2) + 1.0;
+    double h10 = (w3 - 2.0 * w2) + w;
+    double h01 = 3.0 * w2 - 2.0 * w3;
+    double h11 = w3 - w2;
+    if (!isfinite(a) || !isfinite(b) || !isfinite(da) || !isfinite(db)) *bad = 1;
+    return ((h00 * a + h10 * da) + h01 * b) + h11 * db;
+}
+
 static void interp_bilinear(entry_source *src, long long j, long long i0, double w0,
                             long long i1, double w1, int n1, double *out, int *bad) {
     int c;
@@ -316,6 +453,7 @@ static int interp_fits(const orc_grid *g, int interp) {
     if (interp == ORC_I_LINEAR) return g->dim == 1;
     if (interp == ORC_I_HERMITE) return g->dim == 1 && g->n[0] >= 3;
     if (interp == ORC_I_BILINEAR) return g->dim == 2;
+    if (interp == ORC_I_HERMITE_SLOPES) return g->dim == 1;
     return 0;
 }
 
@@ -350,6 +488,9 @@ static int compose(entry_source *src, const orc_grid *g, int interp, int n_slice
             next[0] = interp_linear(src, j, cell[0], w[0], &bad);
         else if (interp == ORC_I_HERMITE)
             next[0] = interp_hermite(src, j, cell[0], w[0], g->n[0], &bad);
+        else if (interp == ORC_I_HERMITE_SLOPES)
+            next[0] = interp_hermite_slopes(src, j, cell[0], w[0],
+                                            (g->hi[0] - g->lo[0]) / (double)(g->n[0] - 1), &bad);
         else
             interp_bilinear(src, j, cell[0], w[0], cell[1], w[1], g->n[1], next, &bad);
         if (bad) {
@@ -396,6 +537,7 @@ int orc_method_lazy(int rhs, const double *p, int scheme, double t0, double T,
     src.L = slice_length(t0, T, n_slices);
     src.h = src.L / (double)steps_per_slice;
     src.g = g;
+    src.slopes = interp == ORC_I_HERMITE_SLOPES;
     src.memo_j = -1;
     src.memo_k = -1;
     return compose(&src, g, interp, n_slices, y0, boundary, NULL, NULL, n_out_of_grid,

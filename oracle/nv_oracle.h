@@ -20,7 +20,9 @@
  * Schemes: ORC_RK4 (classical fourth-order Runge-Kutta), ORC_EULER (forward
  * Euler, the scheme of Nievergelt's own analysis, sec. 5).
  * Interpolation: ORC_I_LINEAR, ORC_I_HERMITE (cubic Hermite, slopes by finite
- * differences of the table), ORC_I_BILINEAR (2-D tensor grid).
+ * differences of the table), ORC_I_BILINEAR (2-D tensor grid),
+ * ORC_I_HERMITE_SLOPES (cubic Hermite with the slopes of a slope table: the
+ * derivative of each entry with respect to its grid point).
  */
 #ifndef NV_ORACLE_H
 #define NV_ORACLE_H
@@ -31,7 +33,7 @@ extern "C" {
 
 enum { ORC_LIN = 10, ORC_LOG = 11, ORC_FCUB = 12, ORC_VDP = 13, ORC_SQR = 14 };
 enum { ORC_RK4 = 1, ORC_EULER = 2 };
-enum { ORC_I_LINEAR = 1, ORC_I_HERMITE = 2, ORC_I_BILINEAR = 3 };
+enum { ORC_I_LINEAR = 1, ORC_I_HERMITE = 2, ORC_I_BILINEAR = 3, ORC_I_HERMITE_SLOPES = 4 };
 enum { ORC_OK = 0, ORC_BAD_ARG = 1, ORC_NONFINITE = 2 };
 
 /* A uniform grid of the initial value space, endpoints included:
@@ -51,6 +53,12 @@ int orc_rhs_dim(int rhs);
 int orc_integrate(int rhs, const double *p, int scheme, double t_base, double h,
                   long long nsteps, double *y);
 
+/* The same for a one-dimensional problem, with v (in place) the derivative of
+ * y with respect to its initial value, carried through every stage of every
+ * step by the chain rule (the derivative of the discrete map). */
+int orc_integrate_tangent(int rhs, const double *p, int scheme, double t_base, double h,
+                          long long nsteps, double *y, double *v);
+
 /* O1, serial truth: the whole interval [t0, T] from y0 in n_slices *
  * steps_per_slice steps of h = ((T - t0) / n_slices) / steps_per_slice. */
 int orc_serial(int rhs, const double *p, int scheme, double t0, double T,
@@ -69,6 +77,14 @@ int orc_build_tables(int rhs, const double *p, int scheme, double t0, double T,
                      int n_slices, const orc_grid *g, int steps_per_slice,
                      double *tab);
 
+/* The computation phase with slopes (one-dimensional problems): tab[j * Mtot
+ * + k] as orc_build_tables, tab[(N + j) * Mtot + k] the derivative of that
+ * entry with respect to grid point k (orc_integrate_tangent from slope 1).
+ * This two-component layout is what ORC_I_HERMITE_SLOPES composes. */
+int orc_build_tables_slopes(int rhs, const double *p, int scheme, double t0, double T,
+                            int n_slices, const orc_grid *g, int steps_per_slice,
+                            double *tab);
+
 /* The same entries for a list of (slice, grid point) pairs:
  * out[c * count + q] for pair q. */
 int orc_table_entries(int rhs, const double *p, int scheme, double t0, double T,
@@ -76,11 +92,19 @@ int orc_table_entries(int rhs, const double *p, int scheme, double t0, double T,
                       long long count, const long long *slice,
                       const long long *point, double *out);
 
+/* Values and slopes for a list of pairs (one-dimensional problems):
+ * out[q] the value, out[count + q] the slope of pair q. */
+int orc_table_entries_slopes(int rhs, const double *p, int scheme, double t0, double T,
+                             int n_slices, const orc_grid *g, int steps_per_slice,
+                             long long count, const long long *slice,
+                             const long long *point, double *out);
+
 /* Lookup on one axis: cell index and local coordinate of x.
  * Returns 1 when x lies outside [lo, hi], else 0. */
 int orc_locate(double lo, double hi, int n, double x, long long *cell, double *w);
 
-/* O2 communication phase over given tables (same layout as orc_build_tables).
+/* O2 communication phase over given tables (same layout as orc_build_tables;
+ * for ORC_I_HERMITE_SLOPES that of orc_build_tables_slopes).
  *   boundary[(j) * dim + c], j = 0..N : the states lambda_j
  *   cells[j * dim + a], weights[j * dim + a], j = 0..N-1 : lookup of lambda_j
  *   (either may be NULL).  *n_out_of_grid counts lookups outside the grid.

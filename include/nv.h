@@ -80,12 +80,24 @@ typedef enum { NV_FP64 = 0, NV_FP32 = 1 } nv_precision;
  *              [lo, hi], xi_k = (lo+hi)/2 + (hi-lo)/2 cos(k pi/(n-1)),
  *              k = 0..n-1 (sec. 3, Table 1), 2 <= n <= 64; the nodes REPLACE
  *              the uniform grid.  phi(x) = sum_k t[k] prod_{m != k}
- *              ((x - xi_m) / (xi_k - xi_m)), k and m ascending, in FP64.      */
+ *              ((x - xi_m) / (xi_k - xi_m)), k and m ascending, in FP64.
+ *   HERMITE_SLOPES  1-D cubic Hermite with stored slopes: the build also
+ *              integrates, for every trajectory, the derivative of its state
+ *              with respect to its grid point (the scheme applied to the
+ *              variational equation v' = df/dy v, v = 1 at the grid point:
+ *              exactly the derivative of the scheme's own map) and stores it
+ *              as a second table, component 1.  Order 4 in the grid spacing
+ *              instead of 3; twice the table memory and about twice the
+ *              build's arithmetic.  RK4 or forward Euler, 1-D right-hand
+ *              sides, n >= 2.  With d = (hi - lo)/(n - 1), values a, b and
+ *              slopes ma, mb of cell i, the same basis and sum as HERMITE with
+ *              da = d * ma, db = d * mb.                                      */
 typedef enum {
     NV_INTERP_LINEAR = 0,
     NV_INTERP_HERMITE = 1,
     NV_INTERP_BILINEAR = 2,
-    NV_INTERP_CHEBYSHEV = 3
+    NV_INTERP_CHEBYSHEV = 3,
+    NV_INTERP_HERMITE_SLOPES = 4
 } nv_interp;
 
 /* Sample Xi_h of the initial value space (sec. 3): a uniform tensor grid with
@@ -243,7 +255,8 @@ NV_API nv_status nv_solve(nv_ctx *ctx, int rhs_id, const double *params, double 
 
 /* Copy component c's table of the last build to host memory: n_slices rows of
  * (points per slice) values in the build's precision (double or float),
- * row j at offset j * points.  bytes must be at least that size. */
+ * row j at offset j * points.  bytes must be at least that size.  Components:
+ * one per state component; with HERMITE_SLOPES, 0 the values and 1 the slopes. */
 NV_API nv_status nv_get_table(nv_ctx *ctx, int component, void *host_dst, size_t bytes);
 
 /* Device address of component c's table (same layout as nv_get_table). */

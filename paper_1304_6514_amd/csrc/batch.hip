@@ -391,6 +391,8 @@ NV_API nv_status nv_batch_create(nv_ctx *ctx, const nv_problem *problems, int co
                         i);
         if (p.grid.interp == NV_INTERP_CHEBYSHEV)
             return fail(NV_ERR_UNSUPPORTED, "problem %d: batches take uniform grids", i);
+        if (p.grid.interp == NV_INTERP_HERMITE_SLOPES)
+            return fail(NV_ERR_UNSUPPORTED, "problem %d: batches build no slope tables", i);
         s = nv::check_problem(p.rhs_id, p.params, p.t0, p.T, p.n_slices, &p.grid,
                               p.steps_per_slice);
         if (s != NV_OK) {

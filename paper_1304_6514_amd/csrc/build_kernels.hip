@@ -146,6 +146,13 @@ hipError_t by_config(const BuildConfig &c, const BuildArgs &a, hipStream_t s) {
     }
 }
 
+// The one-dimensional right-hand sides with their variational equations
+// (builds that also store slopes).
+template <class R> using LinearSlopes = RhsTangent<RhsLinear, R>;
+template <class R> using LogisticSlopes = RhsTangent<RhsLogistic, R>;
+template <class R> using ForcedCubicSlopes = RhsTangent<RhsForcedCubic, R>;
+template <class R> using SquareSlopes = RhsTangent<RhsSquare, R>;
+
 }  // namespace
 
 bool build_supported(const BuildConfig &c) {
@@ -153,10 +160,20 @@ bool build_supported(const BuildConfig &c) {
            !(c.scheme == 2 && c.rhs == 3) &&
            (c.precision == 0 || c.precision == 1) &&
            (c.compensated >= 0 && c.compensated <= 2) &&
-           (c.traj_per_lane == 1 || c.traj_per_lane == 2 || c.traj_per_lane == 4);
+           (c.traj_per_lane == 1 || c.traj_per_lane == 2 || c.traj_per_lane == 4) &&
+           !(c.slopes && (c.rhs == 3 || c.scheme == 2));
 }
 
 hipError_t launch_build(const BuildConfig &c, const BuildArgs &a, hipStream_t s) {
+    if (c.slopes) {
+        switch (c.rhs) {
+        case 0: return by_config<LinearSlopes>(c, a, s);
+        case 1: return by_config<LogisticSlopes>(c, a, s);
+        case 2: return by_config<ForcedCubicSlopes>(c, a, s);
+        case 4: return by_config<SquareSlopes>(c, a, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (c.rhs) {
     case 0: return by_config<RhsLinear>(c, a, s);
     case 1: return by_config<RhsLogistic>(c, a, s);

@@ -176,6 +176,17 @@ __device__ inline void range_end(const ComposeArgs &a, int lane, double l0, doub
 // resumes from the boundary state the previous one left in memory and adds to
 // the status.  With final_out, the last state (that of the failing slice's
 // start when one fails) is also returned there ([dim]).
+// Cubic Hermite with stored slopes (Interp 4): node values ta, tb of cell i0
+// and the slopes ma, mb the build stored for them (component 1), each times
+// the grid spacing, in the basis and order of the finite-difference form.
+__device__ inline bool hermite_slopes_values(double ta, double tb, double ma, double mb,
+                                             double dxi, const HermiteBasis &hb, double &next) {
+#pragma clang fp contract(off)
+    const double da = dxi * ma, db = dxi * mb;
+    next = ((hb.h00 * ta + hb.h10 * da) + hb.h01 * tb) + hb.h11 * db;
+    return finite(ta) & finite(tb) & finite(da) & finite(db);
+}
+
 template <class T, int Interp>
 __device__ inline void compose_range(const ComposeArgs &a, double *final_out = nullptr) {
 #pragma clang fp contract(off)
@@ -204,6 +215,11 @@ __device__ inline void compose_range(const ComposeArgs &a, double *final_out = n
         if constexpr (Interp == 0 || Interp == 1) {
             bad = !interp_1d<Interp>([row0](long long k) { return double(row0[k]); }, i0, w0,
                                      a.n0, next0);
+        } else if constexpr (Interp == 4) {
+            const T *row1 = tab1 + (long long)j * a.M;
+            const double ta = double(row0[i0]), tb = double(row0[i0 + 1]);
+            const double ma = double(row1[i0]), mb = double(row1[i0 + 1]);
+            bad = !hermite_slopes_values(ta, tb, ma, mb, a.dxi0, hermite_basis(w0), next0);
         } else {
             oog += locate(a.lo1, a.inv1, a.n1, lam1, i1, w1);
             const long long c00 = i0 * a.n1 + i1, c10 = (i0 + 1) * a.n1 + i1;

@@ -74,6 +74,7 @@ hipError_t launch_compose(int interp, int precision, const ComposeArgs &a, hipSt
                 hipLaunchKernelGGL((compose_kernel<double, 2>), grid, block, 0, s, a);
             break;
         case 3: hipLaunchKernelGGL((compose_kernel<double, 3>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((compose_kernel<double, 4>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -87,6 +88,7 @@ hipError_t launch_compose(int interp, int precision, const ComposeArgs &a, hipSt
                 hipLaunchKernelGGL((compose_kernel<float, 2>), grid, block, 0, s, a);
             break;
         case 3: hipLaunchKernelGGL((compose_kernel<float, 3>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((compose_kernel<float, 4>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
         }
     }

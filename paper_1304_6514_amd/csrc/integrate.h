@@ -19,6 +19,8 @@ template <class R>
 struct RhsLinear {              // y' = p y
     static constexpr int dim = 1;
     static constexpr bool forced = false;
+    static constexpr bool tangent = false;
+    static constexpr int rhs_id = 0;
     __device__ static void f(R, R p, const R *y, R *k) { k[0] = p * y[0]; }
     __device__ static R df(R, R p, R) { return p; }
 };
@@ -27,6 +29,8 @@ template <class R>
 struct RhsLogistic {            // y' = y (1 - y)
     static constexpr int dim = 1;
     static constexpr bool forced = false;
+    static constexpr bool tangent = false;
+    static constexpr int rhs_id = 1;
     __device__ static void f(R, R, const R *y, R *k) { k[0] = y[0] - y[0] * y[0]; }
     __device__ static R df(R, R, R y) { return R(1) - R(2) * y; }
 };
@@ -35,6 +39,7 @@ template <class R>
 struct RhsForcedCubic {         // y' = sin(3t) - y^3, F = sin(3t)
     static constexpr int dim = 1;
     static constexpr bool forced = true;
+    static constexpr bool tangent = false;
     static constexpr int rhs_id = 2;  // nv_rhs_id, for forcing_value
     __device__ static void f(R F, R, const R *y, R *k) {
         R y2 = y[0] * y[0];
@@ -47,6 +52,8 @@ template <class R>
 struct RhsVdp {                 // y1' = y2, y2' = mu (1 - y1^2) y2 - y1
     static constexpr int dim = 2;
     static constexpr bool forced = false;
+    static constexpr bool tangent = false;
+    static constexpr int rhs_id = 3;
     __device__ static void f(R, R mu, const R *y, R *k) {
         R a = R(1) - y[0] * y[0];
         k[0] = y[1];
@@ -58,8 +65,29 @@ template <class R>
 struct RhsSquare {              // y' = y^2
     static constexpr int dim = 1;
     static constexpr bool forced = false;
+    static constexpr bool tangent = false;
+    static constexpr int rhs_id = 4;
     __device__ static void f(R, R, const R *y, R *k) { k[0] = y[0] * y[0]; }
     __device__ static R df(R, R, R y) { return R(2) * y; }
+};
+
+// A one-dimensional right-hand side together with its variational equation:
+// state (y, v), y' = f(t, y), v' = df/dy(t, y) v.  A scheme applied to this
+// pair gives, in v, the derivative of the scheme's own map for y with respect
+// to y's initial value when v starts at 1 (a Runge-Kutta method commutes with
+// differentiation with respect to the initial value), and the y component is
+// formed by exactly the operations of the plain build.
+template <template <class> class Base, class R>
+struct RhsTangent {
+    static_assert(Base<R>::dim == 1, "slopes are built for one-dimensional right-hand sides");
+    static constexpr int dim = 2;
+    static constexpr bool forced = Base<R>::forced;
+    static constexpr bool tangent = true;
+    static constexpr int rhs_id = Base<R>::rhs_id;
+    __device__ static void f(R F, R p, const R *y, R *k) {
+        Base<R>::f(F, p, y, k);
+        k[1] = Base<R>::df(F, p, y[0]) * y[1];
+    }
 };
 
 // The forcing function of non-autonomous right-hand sides.
@@ -187,7 +215,12 @@ __device__ inline unsigned build_tile_rows(const BuildArgs &a, int j, int tile,
     for (int q = 0; q < P; ++q) {
         long long k = base + (long long)q * kBuildBlock;
         if (k >= a.M) k = a.M - 1;           // ragged tail: compute, do not store
-        grid_point<R, D>(a, k, y[q]);
+        if constexpr (Rhs::tangent) {
+            grid_point<R, 1>(a, k, y[q]);    // the grid is one-dimensional
+            y[q][1] = R(1);                  // d y0 / d xi
+        } else {
+            grid_point<R, D>(a, k, y[q]);
+        }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             c[q][d] = R(0);

@@ -112,7 +112,8 @@ nv_status check_options(const nv_options *o) {
 
 // Where everything lives for one build shape.
 struct Plan {
-    int dim = 0;
+    int dim = 0;                  // state dimension
+    int components = 0;           // tables: one per state component, plus the slopes
     long long M = 0;              // points per slice
     size_t elem = 0;              // bytes per table value
     size_t comp_bytes = 0;        // one component's table, aligned
@@ -166,6 +167,12 @@ nv_status make_plan(int rhs, int n_slices, const nv_ic_grid *g, int steps,
     case NV_INTERP_BILINEAR:
         if (g->dim != 2) return fail(NV_ERR_INVALID_ARG, "BILINEAR interpolation needs dim 2");
         break;
+    case NV_INTERP_HERMITE_SLOPES:
+        if (g->dim != 1)
+            return fail(NV_ERR_INVALID_ARG, "HERMITE_SLOPES interpolation needs dim 1");
+        if (o.scheme == NV_SCHEME_BACKWARD_EULER)
+            return fail(NV_ERR_UNSUPPORTED, "slopes are integrated with RK4 or forward Euler");
+        break;
     case NV_INTERP_CHEBYSHEV:
         if (g->dim != 1) return fail(NV_ERR_INVALID_ARG, "CHEBYSHEV interpolation needs dim 1");
         if (g->n[0] > kMaxChebyshev)
@@ -183,10 +190,11 @@ nv_status make_plan(int rhs, int n_slices, const nv_ic_grid *g, int steps,
         return fail(NV_ERR_INVALID_ARG, "build needs %lld workgroups; at most 2^31-1", blocks);
 
     p->dim = g->dim;
+    p->components = g->interp == NV_INTERP_HERMITE_SLOPES ? 2 : g->dim;
     p->M = M;
     p->elem = o.precision == NV_FP64 ? sizeof(double) : sizeof(float);
     p->comp_bytes = align_up(size_t(M) * size_t(n_slices) * p->elem);
-    p->table_bytes = p->comp_bytes * size_t(g->dim);
+    p->table_bytes = p->comp_bytes * size_t(p->components);
     size_t off = 0;
     p->forcing_off = off;
     p->forcing_bytes = rhs_forced(rhs) ? (2 * size_t(steps) + 1) * size_t(n_slices) * p->elem : 0;
@@ -357,7 +365,8 @@ nv_status describe_build(const nv_options &o, int rhs_id, const double *params, 
         if (!std::isfinite(params[0])) return fail(NV_ERR_INVALID_ARG, "parameter not finite");
         p0 = params[0];
     }
-    nv::BuildConfig cfg{rhs_id, o.scheme, o.precision, o.compensated, p.traj_per_lane};
+    nv::BuildConfig cfg{rhs_id, o.scheme, o.precision, o.compensated, p.traj_per_lane,
+                        grid->interp == NV_INTERP_HERMITE_SLOPES ? 1 : 0};
     if (!nv::build_supported(cfg)) return fail(NV_ERR_UNSUPPORTED, "unsupported configuration");
 
     // slice partition (sec. 3): L = (T - t0)/N, T_j = t0 + j L; either S equal
@@ -406,7 +415,7 @@ nv_status describe_build(const nv_options &o, int rhs_id, const double *params, 
 void place_build(PreparedBuild *pb, const Plan &p, void *tables, char *work) {
     nv::BuildArgs &a = pb->args;
     a.tab0 = tables;
-    a.tab1 = p.dim == 2 ? static_cast<char *>(tables) + p.comp_bytes : nullptr;
+    a.tab1 = p.components == 2 ? static_cast<char *>(tables) + p.comp_bytes : nullptr;
     a.forcing = rhs_forced(pb->cfg.rhs) ? work + p.forcing_off : nullptr;
     a.nonfinite = reinterpret_cast<uint32_t *>(work + p.nonfinite_off);
 }
@@ -486,7 +495,7 @@ nv::ComposeArgs compose_args_at(const Plan &p, const nv_ic_grid &g, int n_slices
                                 int j1) {
     nv::ComposeArgs a{};
     a.tab0 = tables;
-    a.tab1 = p.dim == 2 ? static_cast<const char *>(tables) + p.comp_bytes : nullptr;
+    a.tab1 = p.components == 2 ? static_cast<const char *>(tables) + p.comp_bytes : nullptr;
     a.boundary = boundary;
     a.status = reinterpret_cast<nv::ComposeStatus *>(work + p.status_off);
     a.carry = reinterpret_cast<double *>(work + p.carry_off);
@@ -502,6 +511,7 @@ nv::ComposeArgs compose_args_at(const Plan &p, const nv_ic_grid &g, int n_slices
     a.lo1 = p.dim == 2 ? g.lo[1] : 0.0;
     a.inv1 = p.dim == 2 ? double(g.n[1] - 1) / (g.hi[1] - g.lo[1]) : 0.0;
     a.hi0 = g.hi[0];
+    a.dxi0 = (g.hi[0] - g.lo[0]) / double(g.n[0] - 1);
     a.nodes = g.interp == NV_INTERP_CHEBYSHEV
                   ? reinterpret_cast<const double *>(work + p.nodes_off)
                   : nullptr;
@@ -887,7 +897,7 @@ NV_API nv_status nv_solve_static(int rhs_id, const double *params, double t0, do
 NV_API nv_status nv_get_table(nv_ctx *ctx, int component, void *host_dst, size_t bytes) {
     if (!ctx) return fail(NV_ERR_INVALID_ARG, "ctx is NULL");
     if (!ctx->built) return fail(NV_ERR_NOT_BUILT, "no table before a successful build");
-    if (component < 0 || component >= ctx->plan.dim || !host_dst)
+    if (component < 0 || component >= ctx->plan.components || !host_dst)
         return fail(NV_ERR_INVALID_ARG, "bad component or NULL destination");
     const size_t need = size_t(ctx->plan.M) * size_t(ctx->n_slices) * ctx->plan.elem;
     if (bytes < need) return fail(NV_ERR_BUFFER_TOO_SMALL, "need %zu bytes", need);
@@ -901,7 +911,7 @@ NV_API nv_status nv_get_table(nv_ctx *ctx, int component, void *host_dst, size_t
 NV_API nv_status nv_table_device_ptr(nv_ctx *ctx, int component, void **dev_ptr) {
     if (!ctx || !dev_ptr) return fail(NV_ERR_INVALID_ARG, "NULL argument");
     if (!ctx->built) return fail(NV_ERR_NOT_BUILT, "no table before a successful build");
-    if (component < 0 || component >= ctx->plan.dim)
+    if (component < 0 || component >= ctx->plan.components)
         return fail(NV_ERR_INVALID_ARG, "bad component %d", component);
     *dev_ptr = static_cast<char *>(ctx->tables) + component * ctx->plan.comp_bytes;
     return NV_OK;

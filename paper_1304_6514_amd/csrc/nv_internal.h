@@ -17,7 +17,7 @@ constexpr int kNumXcd = 8;         // MI355X: 8 XCDs, workgroups dispatched roun
 // Arguments of the ensemble-integration kernel (one launch = the whole build).
 struct BuildArgs {
     void *tab0;               // component 0 table, [n_slices][M] of the working type
-    void *tab1;               // component 1 table (2-D problems) or null
+    void *tab1;               // component 1 table (2-D problems, or the slopes) or null
     const void *forcing;      // [n_slices][2*steps+1] forcing values, or null
     uint32_t *nonfinite;      // single-problem build: [n_slices][tiles_per_slice] counts, one
                               // per tile, stored; batch: [n_slices] counters, added to
@@ -44,6 +44,8 @@ struct BuildConfig {
     int precision;            // nv_precision
     int compensated;          // FP32 only: 0 plain, 1 Kahan, 2 blocked summation
     int traj_per_lane;        // 1, 2, 4
+    int slopes;               // 1: also integrate the derivative with respect to the
+                              // grid point and store it as component 1 (1-D problems)
 };
 
 // Status the composition kernel leaves in device memory.
@@ -67,6 +69,7 @@ struct ComposeArgs {
     int n0, n1;
     double lo0, inv0, lo1, inv1;   // inv = (n-1)/(hi-lo), computed on the host
     double hi0;                    // Chebyshev: the interval's upper end
+    double dxi0;                   // stored slopes: the grid spacing (hi - lo)/(n - 1)
     const double *nodes;           // Chebyshev nodes (Lagrange lookup), or null
     double y00, y01;
 };

@@ -28,13 +28,15 @@ NV_RHS_LINEAR, NV_RHS_LOGISTIC, NV_RHS_FORCED_CUBIC, NV_RHS_VDP, NV_RHS_SQUARE =
 NV_SCHEME_RK4, NV_SCHEME_EULER, NV_SCHEME_BACKWARD_EULER = 0, 1, 2
 NV_FP64, NV_FP32 = 0, 1
 NV_INTERP_LINEAR, NV_INTERP_HERMITE, NV_INTERP_BILINEAR, NV_INTERP_CHEBYSHEV = 0, 1, 2, 3
+NV_INTERP_HERMITE_SLOPES = 4
 
 RHS_IDS = {"linear": NV_RHS_LINEAR, "logistic": NV_RHS_LOGISTIC,
            "forced_cubic": NV_RHS_FORCED_CUBIC, "vdp": NV_RHS_VDP, "square": NV_RHS_SQUARE}
 SCHEMES = {"rk4": NV_SCHEME_RK4, "euler": NV_SCHEME_EULER, "be": NV_SCHEME_BACKWARD_EULER}
 PRECISIONS = {"fp64": NV_FP64, "fp32": NV_FP32}
 INTERPS = {"linear": NV_INTERP_LINEAR, "hermite": NV_INTERP_HERMITE,
-           "bilinear": NV_INTERP_BILINEAR, "chebyshev": NV_INTERP_CHEBYSHEV}
+           "bilinear": NV_INTERP_BILINEAR, "chebyshev": NV_INTERP_CHEBYSHEV,
+           "hermite_slopes": NV_INTERP_HERMITE_SLOPES}
 
 
 class nv_ic_grid(ctypes.Structure):

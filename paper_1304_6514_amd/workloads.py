@@ -32,7 +32,7 @@ class Workload:
     steps_per_slice: int
     y0: tuple
     precision: str          # "fp64" or "fp32" (the table build's arithmetic)
-    interp: str             # "linear", "hermite", "bilinear" or "chebyshev"
+    interp: str             # "linear", "hermite", "hermite_slopes", "bilinear" or "chebyshev"
     scheme: str = "rk4"     # "rk4", "euler" or "be" (backward Euler)
     dt: float = 0.0         # > 0: fixed step dt per slice (plus a shorter last step)
 

@@ -73,6 +73,29 @@ def test_required_bytes_layout(nvmod):
     tb3, _ = nvmod.nv_required_bytes(nvmod.NV_RHS_LOGISTIC, 64, _grid(nvmod), 1000,
                                      nvmod.make_options("rk4", "fp64"))
     assert tb3 == 64 * 256 * 8
+    # stored slopes: a second table of the same size
+    gs = _grid(nvmod, (4096,), (-3.0,), (3.0,), "hermite_slopes")
+    tb4, wb4 = nvmod.nv_required_bytes(nvmod.NV_RHS_FORCED_CUBIC, 4096, gs, 2000, o)
+    assert tb4 == 2 * tb and wb4 == wb
+
+
+def test_slopes_configurations_need_no_gpu(nvmod):
+    # a 2-D problem or a 2-D grid has no stored-slope lookup
+    g2 = _grid(nvmod, (8, 8), (0.0, 0.0), (1.0, 1.0), "hermite_slopes")
+    with pytest.raises(nvmod.NvError) as e:
+        nvmod.nv_required_bytes(nvmod.NV_RHS_VDP, 4, g2, 10)
+    assert e.value.status == nvmod.NV_ERR_INVALID_ARG
+    g1 = _grid(nvmod, (8,), (0.0,), (1.0,), "hermite_slopes")
+    with pytest.raises(nvmod.NvError) as e:
+        nvmod.nv_required_bytes(nvmod.NV_RHS_VDP, 4, g1, 10)
+    assert e.value.status == nvmod.NV_ERR_INVALID_ARG
+    # the slopes are integrated with RK4 or forward Euler only
+    with pytest.raises(nvmod.NvError) as e:
+        nvmod.nv_required_bytes(nvmod.NV_RHS_SQUARE, 4, g1, 10, nvmod.make_options("be", "fp64"))
+    assert e.value.status == nvmod.NV_ERR_UNSUPPORTED
+    tb, _ = nvmod.nv_required_bytes(nvmod.NV_RHS_SQUARE, 4, g1, 10,
+                                    nvmod.make_options("euler", "fp64"))
+    assert tb == 2 * 256            # two tables of 4 x 8 doubles, each aligned to 256 bytes
 
 
 @pytest.mark.parametrize("case", [
@@ -206,6 +229,11 @@ def test_batch_argument_errors_need_no_gpu(nvmod):
         with pytest.raises(nvmod.NvError) as e:
             nvmod.nv_batch_create(ctx, [good, good, bad])
         assert e.value.status == nvmod.NV_ERR_INVALID_ARG and "problem 2" in str(e.value)
+        slopes = nvmod.make_problem("logistic", [], 0.0, 10.0, 64,
+                                    _grid(nvmod, interp="hermite_slopes"), 100, [0.1])
+        with pytest.raises(nvmod.NvError) as e:
+            nvmod.nv_batch_create(ctx, [good, slopes])
+        assert e.value.status == nvmod.NV_ERR_UNSUPPORTED and "problem 1" in str(e.value)
         lib = nvmod.load()
         assert lib.nv_batch_create(ctx, None, 0, None) == nvmod.NV_ERR_INVALID_ARG
         assert lib.nv_batch_destroy(None) == 0

@@ -37,6 +37,9 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 # algorithmic FLOPs per trajectory-step (FMA = 2): RK4 = 12*dim + 4*c_f with c_f
 # the right-hand side's cost; the compensated FP32 update adds 3 per component
 RHS_FLOPS = {"linear": 1, "logistic": 2, "forced_cubic": 3, "vdp": 5, "square": 1}
+# the variational term df/dy * v of a 1-D right-hand side, given the value's own
+# intermediates (y^2 of the cubic): p v; (1 - 2 y) v; (-3 y^2) v; (2 y) v
+TANGENT_FLOPS = {"linear": 1, "logistic": 3, "forced_cubic": 2, "square": 2}
 
 WORKLOADS = {"forced_cubic": W.FORCED_CUBIC_FP32, "logistic": W.LOGISTIC_FP64,
              "vdp": W.VDP_FP32}
@@ -73,18 +76,27 @@ def kernel_source_sha1() -> str:
 def algorithmic_bytes(w: W.Workload) -> float:
     """Table write plus the per-slice forcing rows read (non-autonomous only)."""
     elem = 4 if w.precision == "fp32" else 8
-    tables = w.dim * w.n_slices * w.points_per_slice * elem
+    comps = w.dim + (1 if w.interp == "hermite_slopes" else 0)     # the slope table
+    tables = comps * w.n_slices * w.points_per_slice * elem
     forcing = (2 * w.steps_per_slice + 1) * w.n_slices * elem if w.rhs == "forced_cubic" else 0
     return float(tables + forcing)
 
 
 def flops_per_step(w: W.Workload, compensated: bool) -> int:
+    """Algorithmic FLOPs of one trajectory-step: the scheme's stage and
+    combination arithmetic per state component plus its right-hand side
+    evaluations; with stored slopes, the same for the derivative v."""
+    comps = w.dim + (1 if w.interp == "hermite_slopes" else 0)
     if w.scheme == "rk4":
-        f = 12 * w.dim + 4 * RHS_FLOPS[w.rhs]
+        f = 12 * comps + 4 * RHS_FLOPS[w.rhs]
+        if w.interp == "hermite_slopes":
+            f += 4 * TANGENT_FLOPS[w.rhs]
     else:
-        f = 2 * w.dim + RHS_FLOPS[w.rhs]
+        f = 2 * comps + RHS_FLOPS[w.rhs]
+        if w.interp == "hermite_slopes":
+            f += TANGENT_FLOPS[w.rhs]
     if w.precision == "fp32" and compensated:
-        f += 3 * w.dim
+        f += 3 * comps
     return f
 
 
@@ -132,8 +144,9 @@ def cpu_baseline(w: W.Workload, threads: int, steps_per_thread: float = 1.5e8):
         sl = np.repeat(np.arange(i * per_thread, (i + 1) * per_thread, dtype=np.int64),
                        w.points_per_slice)
         pt = np.tile(np.arange(w.points_per_slice, dtype=np.int64), per_thread)
-        oracle.table_entries(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, g,
-                             w.steps_per_slice, sl, pt)
+        entries = (oracle.table_entries_slopes if w.interp == "hermite_slopes"
+                   else oracle.table_entries)
+        entries(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, g, w.steps_per_slice, sl, pt)
 
     with ThreadPoolExecutor(max_workers=threads) as ex:
         t = time.perf_counter()
@@ -153,6 +166,8 @@ def cpu_parallel_build(w: W.Workload, threads: int, slices_per_thread: int = 64)
     FP64 and FP32 on a bounded number of the workload's slices."""
     import oracle
 
+    if w.interp == "hermite_slopes":
+        return {"what": "not built: the OpenMP CPU build integrates values only"}
     ns = min(w.n_slices, threads * slices_per_thread)
     out = {"threads": threads, "slices": ns,
            "what": "table build of the first slices, OpenMP over host threads, 64 "
@@ -744,6 +759,9 @@ def main():
     ap.add_argument("--traj-per-lane", type=int, default=0)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default=None,
                     help="override the workload's build precision")
+    ap.add_argument("--interp", choices=["linear", "hermite", "hermite_slopes"], default=None,
+                    help="override the interpolation of a 1-D workload (hermite_slopes: the "
+                         "build also stores each entry's slope)")
     ap.add_argument("--compensated", type=int, default=2, choices=[0, 1, 2],
                     help="FP32 state accumulation: 0 plain, 1 Kahan, 2 blocked summation")
     ap.add_argument("--two-phase", action="store_true",
@@ -795,6 +813,13 @@ def main():
     w = WORKLOADS[args.workload]
     if args.precision:
         w = w.with_(precision=args.precision)
+    if args.interp:
+        if w.dim != 1:
+            print(f"--interp applies to 1-D workloads; {w.name} is {w.dim}-D", file=sys.stderr)
+            sys.exit(2)
+        w = w.with_(interp=args.interp)
+        if args.interp != WORKLOADS[args.workload].interp:
+            w = w.with_(name=f"{w.name}-{args.interp}")
     dev = torch.device("cuda:0")
     prop = Propagator(dev, traj_per_lane=args.traj_per_lane, compensated=args.compensated,
                       solve_chunks=args.solve_chunks)

@@ -23,6 +23,11 @@ struct RhsLinear {              // y' = p y
     static constexpr int rhs_id = 0;
     __device__ static void f(R, R p, const R *y, R *k) { k[0] = p * y[0]; }
     __device__ static R df(R, R p, R) { return p; }
+    // f and (df/dy) v together (the variational term of slope builds)
+    __device__ static void fjv(R, R p, R y, R v, R &k, R &kv) {
+        k = p * y;
+        kv = p * v;
+    }
 };
 
 template <class R>
@@ -33,6 +38,10 @@ struct RhsLogistic {            // y' = y (1 - y)
     static constexpr int rhs_id = 1;
     __device__ static void f(R, R, const R *y, R *k) { k[0] = y[0] - y[0] * y[0]; }
     __device__ static R df(R, R, R y) { return R(1) - R(2) * y; }
+    __device__ static void fjv(R, R, R y, R v, R &k, R &kv) {
+        k = y - y * y;
+        kv = (R(1) - R(2) * y) * v;
+    }
 };
 
 template <class R>
@@ -46,6 +55,12 @@ struct RhsForcedCubic {         // y' = sin(3t) - y^3, F = sin(3t)
         k[0] = F - y2 * y[0];
     }
     __device__ static R df(R, R, R y) { return R(-3) * y * y; }
+    // the square serves both terms: -3 y^2 is formed from it
+    __device__ static void fjv(R F, R, R y, R v, R &k, R &kv) {
+        const R y2 = y * y;
+        k = F - y2 * y;
+        kv = (R(-3) * y2) * v;
+    }
 };
 
 template <class R>
@@ -69,6 +84,10 @@ struct RhsSquare {              // y' = y^2
     static constexpr int rhs_id = 4;
     __device__ static void f(R, R, const R *y, R *k) { k[0] = y[0] * y[0]; }
     __device__ static R df(R, R, R y) { return R(2) * y; }
+    __device__ static void fjv(R, R, R y, R v, R &k, R &kv) {
+        k = y * y;
+        kv = (R(2) * y) * v;
+    }
 };
 
 // A one-dimensional right-hand side together with its variational equation:
@@ -84,10 +103,8 @@ struct RhsTangent {
     static constexpr bool forced = Base<R>::forced;
     static constexpr bool tangent = true;
     static constexpr int rhs_id = Base<R>::rhs_id;
-    __device__ static void f(R F, R p, const R *y, R *k) {
-        Base<R>::f(F, p, y, k);
-        k[1] = Base<R>::df(F, p, y[0]) * y[1];
-    }
+    // k[0] by the operations of Base::f, k[1] = df/dy(y[0]) y[1]
+    __device__ static void f(R F, R p, const R *y, R *k) { Base<R>::fjv(F, p, y[0], y[1], k[0], k[1]); }
 };
 
 // The forcing function of non-autonomous right-hand sides.

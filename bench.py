@@ -51,7 +51,9 @@ WORKLOADS = {"forced_cubic": W.FORCED_CUBIC_FP32, "logistic": W.LOGISTIC_FP64,
 # sources they were taken with; any other source gives traffic = null.
 MEASURED_TRAFFIC = {
     ("forced-cubic-fp32-4096sl-4096pt-2000st", "blocked", "solve", 32,
-     "e03ec79969c5e4534c83aee7e785134af2500475"): (64800.0 + 65664.0) * 1024,
+     "2817d67987a3ebf0d40700824662c511d2349657"): (64688.0 + 65664.0) * 1024,
+    ("forced-cubic-fp32-4096sl-4096pt-2000st-hermite_slopes", "blocked", "solve", 32,
+     "2817d67987a3ebf0d40700824662c511d2349657"): (64976.0 + 131200.0) * 1024,
 }
 
 # dependent floating-point operations on the critical path of one RK4 step of

@@ -51,16 +51,16 @@ WORKLOADS = {"forced_cubic": W.FORCED_CUBIC_FP32, "logistic": W.LOGISTIC_FP64,
 # sources they were taken with; any other source gives traffic = null.
 MEASURED_TRAFFIC = {
     ("forced-cubic-fp32-4096sl-4096pt-2000st", "blocked", "solve", 32,
-     "2817d67987a3ebf0d40700824662c511d2349657"): (64688.0 + 65664.0) * 1024,
+     "98008abf8d2484d4722438ee50dceda6b18ec554"): (64800.0 + 65664.0) * 1024,
     ("forced-cubic-fp32-4096sl-4096pt-2000st-hermite_slopes", "blocked", "solve", 32,
-     "2817d67987a3ebf0d40700824662c511d2349657"): (64976.0 + 131200.0) * 1024,
+     "98008abf8d2484d4722438ee50dceda6b18ec554"): (64752.0 + 131200.0) * 1024,
 }
 
-# dependent floating-point operations on the critical path of one RK4 step of
-# the builds bound by that chain (read off the compiled loop): FP64 logistic:
-# k1, the stage value, k2, the stage value, k3, the stage value, k4, k1 + k4,
-# + 2 (k2 + k3), y + (h/6) (...)
-CHAIN_OPS = {"logistic-fp64-64sl-256pt-1000st": 10}
+# builds too small to fill the chip (one wave per SIMD): per RK4 step, the FP64
+# VALU instructions of the compiled loop and the dependent operations on its
+# critical path (FP64 logistic: k1..k4 as fma(-u, u, u), three stage values,
+# four FMAs adding the weighted stages into the state, the last after k4)
+SINGLE_WAVE_STEP = {"logistic-fp64-64sl-256pt-1000st": {"valu": 11, "dependent": 8}}
 
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1304_6514_amd", "csrc", f)
                   for f in ("integrate.h", "build_kernels.hip")]
@@ -906,20 +906,30 @@ def main():
         "trajectory_steps_per_span": w.trajectory_steps,
         "single_launch_ms": round(avg_single_ms, 4),
     }
-    if w.name in CHAIN_OPS:
-        # too few trajectories to fill the chip: bound by each trajectory's
-        # chain of dependent operations (S x critical path x dependent latency)
-        ns_op, cyc_op = nv.nv_probe_fma_latency(w.precision, 1 << 22,
-                                                prop.stream.cuda_stream)
-        ops = CHAIN_OPS[w.name]
-        bound_ms = w.steps_per_slice * ops * ns_op * 1e-6
-        roofline["chain_bound"] = {
-            "dependent_ops_per_step": ops, "ns_per_dependent_fma": round(ns_op, 4),
-            "clock_ticks_per_dependent_fma": round(cyc_op, 3),
+    if w.name in SINGLE_WAVE_STEP:
+        # too few trajectories to fill the chip: each wave runs alone on its
+        # SIMD, so a step takes the longer of its instructions' issue and its
+        # dependent chain, both measured for one wave by the FMA probe
+        st = SINGLE_WAVE_STEP[w.name]
+        ns_lat, cyc_lat = nv.nv_probe_fma_chains(w.precision, 1 << 22, 1,
+                                                 prop.stream.cuda_stream)
+        ns_iss, cyc_iss = nv.nv_probe_fma_chains(w.precision, 1 << 22, 4,
+                                                 prop.stream.cuda_stream)
+        issue_ms = w.steps_per_slice * st["valu"] * ns_iss * 1e-6
+        chain_ms = w.steps_per_slice * st["dependent"] * ns_lat * 1e-6
+        bound_ms = max(issue_ms, chain_ms)
+        roofline["single_wave_bound"] = {
+            "valu_per_step": st["valu"], "dependent_ops_per_step": st["dependent"],
+            "ns_per_fma_independent": round(ns_iss, 4),
+            "ns_per_fma_dependent": round(ns_lat, 4),
+            "clock_ticks_per_fma": [round(cyc_iss, 3), round(cyc_lat, 3)],
+            "issue_bound_ms": round(issue_ms, 5), "chain_bound_ms": round(chain_ms, 5),
             "bound_ms": round(bound_ms, 5), "frac": round(bound_ms / avg_span_ms, 4),
-            "what": "steps x dependent FP operations on one RK4 step's critical path x the "
-                    "measured dependent-FMA latency (every trajectory is one such chain; "
-                    "the build has one wave per SIMD on a quarter of the CUs)"}
+            "what": "steps x max(VALU instructions per step x one wave's time per "
+                    "independent FMA, dependent operations per step x its time per "
+                    "dependent FMA): every trajectory is one lane of a wave that runs "
+                    "alone on its SIMD (64 workgroups on 64 CUs), and one wave issues an "
+                    "FP64 FMA every ~2.1 ns whether or not it waits on the last"}
 
     value = w.trajectory_steps * args.steps / elapsed
     out = {

@@ -123,6 +123,8 @@ _SIGNATURES = {
     "nv_batch_get_boundary": [_P, ctypes.c_int, _P, ctypes.c_size_t],
     "nv_probe_fma_latency": [ctypes.c_int, ctypes.c_longlong, _P,
                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+    "nv_probe_fma_chains": [ctypes.c_int, ctypes.c_longlong, ctypes.c_int, _P,
+                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "nv_last_error": [],
     "nv_status_string": [ctypes.c_int],
 }
@@ -325,6 +327,15 @@ def nv_probe_fma_latency(precision="fp64", ops=1 << 22, stream=None):
     ns, cyc = ctypes.c_double(), ctypes.c_double()
     _check(load().nv_probe_fma_latency(PRECISIONS.get(precision, precision), int(ops), stream,
                                        ctypes.byref(ns), ctypes.byref(cyc)))
+    return ns.value, cyc.value
+
+
+def nv_probe_fma_chains(precision="fp64", ops=1 << 22, chains=4, stream=None):
+    """(ns, shader-clock cycles) per FMA of one wave running `chains`
+    independent chains of `ops` dependent FMAs per lane."""
+    ns, cyc = ctypes.c_double(), ctypes.c_double()
+    _check(load().nv_probe_fma_chains(PRECISIONS.get(precision, precision), int(ops),
+                                      int(chains), stream, ctypes.byref(ns), ctypes.byref(cyc)))
     return ns.value, cyc.value
 
 

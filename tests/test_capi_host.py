@@ -313,3 +313,14 @@ def test_linear_argument_errors_need_no_gpu(nvmod):
     assert lib.nv_lin_compose_many(None, None, 4, None, None) == nvmod.NV_ERR_INVALID_ARG
     assert lib.nv_lin_get_tables(None, None, None) == nvmod.NV_ERR_INVALID_ARG
     assert lib.nv_lin_last_timing(None, None, None) == nvmod.NV_ERR_INVALID_ARG
+
+
+def test_probe_argument_errors_need_no_gpu(nvmod):
+    lib = nvmod.load()
+    ns, cyc = ctypes.c_double(), ctypes.c_double()
+    for prec, ops, chains in [(nvmod.NV_FP64, 1000, 1), (nvmod.NV_FP64, 1 << 20, 3),
+                              (7, 1 << 20, 1), (nvmod.NV_FP32, 1 << 20, 0)]:
+        assert lib.nv_probe_fma_chains(prec, ops, chains, None, ctypes.byref(ns),
+                                       ctypes.byref(cyc)) == nvmod.NV_ERR_INVALID_ARG
+    assert lib.nv_probe_fma_chains(nvmod.NV_FP64, 1 << 20, 1, None, None,
+                                   ctypes.byref(cyc)) == nvmod.NV_ERR_INVALID_ARG

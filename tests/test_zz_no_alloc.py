@@ -40,6 +40,11 @@ def _grid(w):
     return nv.make_grid(w.grid_n, w.grid_lo, w.grid_hi, w.interp)
 
 
+def components(w):
+    """Tables of a build: one per state component, plus the slopes."""
+    return w.dim + (1 if w.interp == "hermite_slopes" else 0)
+
+
 def solve_static(torch, w, sentinel=-7.0):
     """Tables (one tensor per component), boundary (N+1, dim) and the status
     of one nv_solve_static call; every output starts filled with a sentinel."""
@@ -61,7 +66,7 @@ def solve_static(torch, w, sentinel=-7.0):
     comp = (n * elem + 255) // 256 * 256
     dt = torch.float64 if w.precision == "fp64" else torch.float32
     tabs = [tables[c * comp:c * comp + n * elem].view(dt).view(w.n_slices, w.points_per_slice)
-            for c in range(w.dim)]
+            for c in range(components(w))]
     st = status.cpu().numpy()
     n_oog = int(st[0])
     bad_slice, done = (int(v) for v in st[1:2].view(np.int32))
@@ -80,11 +85,12 @@ def solve_ctx(torch, w):
 # consecutive calls, each smaller than the one before: the full forced-cubic
 # workload (its forcing rows precomputed into the static scratch), a small
 # forced build whose workgroups form their rows in LDS, a ragged 2-D Van der
-# Pol build, a 1-D FP64 logistic build
+# Pol build, a forced build with stored slopes, a 1-D FP64 logistic build
 SEQUENCE = [
     W.FORCED_CUBIC_FP32,
     W.small(W.FORCED_CUBIC_FP32, 64, (1000,), 30),
     W.small(W.VDP_FP32, 16, (37, 29), 20),
+    W.small(W.FORCED_CUBIC_FP32, 12, (700,), 25).with_(interp="hermite_slopes"),
     W.small(W.LOGISTIC_FP64, 8, (301,), 40),
 ]
 
@@ -96,7 +102,7 @@ def test_static_solve_equals_solve_on_shrinking_calls(torch):
             assert ref.status == nv.NV_OK
             tabs, boundary, (n_oog, bad_slice, done) = solve_static(torch, w)
             iv = torch.int64 if w.precision == "fp64" else torch.int32
-            for c in range(w.dim):
+            for c in range(components(w)):
                 # bit for bit, NaN patterns included
                 assert torch.equal(tabs[c].view(iv), p.table_tensor(c).view(iv)), \
                     f"{w.name}: component {c} table differs"

@@ -71,18 +71,24 @@ __device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 // Mathematical Functions, formula 7.1.26 (absolute error below 1.5e-7, the
 // size of an FP32 rounding of Phi): for x >= 0, with t = 1 / (1 + p x),
 //     erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),
-// and erf(-x) = -erf(x).  With x = |z| / sqrt 2, exp(-x^2) = exp(-z^2 / 2) is
-// also the factor of the density, so one exponential serves both.
+// and erf(-x) = -erf(x), at x = |z| / sqrt 2.  The constants are folded so
+// that one exponential gives the density itself: with u = |z| sqrt(log2(e)/2),
+// phi(z) = 2^(L - u^2), L = log2(1/sqrt(2 pi)); t = 1 / (1 + (p / sqrt(log2 e)) u);
+// and with b_k = a_k sqrt(2 pi) / 2, t (b1 + t (b2 + ...)) phi(z) is
+// (1 - erf(|z|/sqrt 2)) / 2, the tail 1 - Phi(|z|).
 __device__ inline float gelu_d(float z, float &d) {
-    constexpr float p = 0.3275911f, a1 = 0.254829592f, a2 = -0.284496736f,
-                    a3 = 1.421413741f, a4 = -1.453152027f, a5 = 1.061405429f;
-    const float x = fabsf(z) * 0.70710678118654752f;
-    const float t = __builtin_amdgcn_rcpf(fmaf(p, x, 1.0f));
-    const float e = __expf(-0.5f * z * z);
-    const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, a5, a4), a3), a2), a1);
-    const float erfc_half = 0.5f * poly * e;             // (1 - erf(x)) / 2
-    const float P = z >= 0.0f ? 1.0f - erfc_half : erfc_half;
-    d = fmaf(z, 0.39894228040143268f * e, P);
+    constexpr float c = 0.84932180028801904f;    // sqrt(log2(e) / 2)
+    constexpr float pq = 0.27273748087922250f;   // 0.3275911 / sqrt(log2 e)
+    constexpr float L = -1.32574806473615920f;   // log2(1 / sqrt(2 pi))
+    constexpr float b1 = 0.31938153025994087f, b2 = -0.35656378124891560f,
+                    b3 = 1.78147793656981280f, b4 = -1.82125597910777540f,
+                    b5 = 1.33027442958912310f;   // a_k sqrt(2 pi) / 2
+    const float u = fabsf(z) * c;
+    const float t = __builtin_amdgcn_rcpf(fmaf(pq, u, 1.0f));
+    const float phi = __builtin_amdgcn_exp2f(fmaf(-u, u, L));
+    const float tail = (t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, b5, b4), b3), b2), b1)) * phi;
+    const float P = z >= 0.0f ? 1.0f - tail : tail;
+    d = fmaf(z, phi, P);
     return z * P;
 }
 

@@ -78,7 +78,8 @@ NV_API nv_status nv_lin_compose(nv_lin *lin, const double *y0, double *yT, doubl
  * `linearreconstruct`, applied to count independent initial values): the
  * chains lambda^q_{j+1} = c_j + G_j lambda^q_j, q = 0..count-1, evaluated as
  * FP64 matrix products G_j [lambda^q ... lambda^{q+15}] on the matrix cores,
- * 16 chains per workgroup.  Each component's sum c_i + sum_k G_ik l_k is
+ * 16 chains per workgroup (32, sharing the workgroup's table reads, when
+ * count fills two such workgroups per compute unit and M <= 116).  Each component's sum c_i + sum_k G_ik l_k is
  * formed by the matrix cores in an order this interface does not fix (so
  * results are within the FP64 inner-product rounding bound of any order, not
  * bit-equal to nv_lin_compose).

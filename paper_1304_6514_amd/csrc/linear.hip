@@ -448,14 +448,17 @@ const LinChainTable lin_chain;
 // ---- many initial values: the chain as FP64 matrix products -------------
 //
 // Q chains lambda^q_{j+1} = c_j + G_j lambda^q_j are independent, so workgroup
-// b carries the 16 chains q = 16 b .. 16 b + 15 through every slice alone (no
-// synchronisation between workgroups): per slice the product G_j Lambda_j of
-// the M x M table with the M x 16 block of states, on the matrix cores
-// (v_mfma_f64_16x16x4f64: wave w forms rows 16 w .. 16 w + 15 of the product,
-// k = 0 .. 4 KP - 1 in steps of four), then c_j added.  Lambda_j lives in LDS,
-// double buffered (rows k >= M are zero), one barrier per slice; every wave
-// holds the A fragments of its rows of G_{j+1} in registers while it computes
-// slice j.
+// b carries the 16 CB chains q = 16 CB b .. 16 CB b + 16 CB - 1 through every
+// slice alone (no synchronisation between workgroups): per slice the product
+// G_j Lambda_j of the M x M table with the M x 16 CB block of states, on the
+// matrix cores (v_mfma_f64_16x16x4f64: wave w forms rows 16 w .. 16 w + 15 of
+// the product, k = 0 .. 4 KP - 1 in steps of four, each A fragment of G
+// multiplied with the CB 16-column blocks of states), then c_j added.
+// Lambda_j lives in LDS, double buffered (rows k >= M are zero), one barrier
+// per slice; every wave holds the A fragments of its rows of G_{j+1} in
+// registers while it computes slice j.  Every workgroup reads all N tables, so
+// the tables' traffic from the caches is (Q / 16 CB) x N x M (M + 1) doubles:
+// CB = 2 halves it for large Q.
 struct ManyArgs {
     const double *T;            // [N][Ms (M + 1)]
     const double *y0;           // [Q][M]
@@ -468,18 +471,19 @@ struct ManyArgs {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <int KP>
+template <int KP, int CB>
 __global__ __launch_bounds__(512) void lin_many_kernel(ManyArgs a) {
 #pragma clang fp contract(off)
     constexpr int K = 4 * KP;                    // rows of Lambda in LDS (M <= K)
-    __shared__ double lam[2][K][16];
+    constexpr int C = 16 * CB;                   // chains of the workgroup
+    __shared__ double lam[2][K][C];
     const int tid = int(threadIdx.x), lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int M = a.M, N = a.N, Ms = lin_stride(M), per = Ms * (M + 1);
     const int col = lane & 15, kq = lane >> 4;
-    const long long q0 = (long long)blockIdx.x * 16;
-    for (int e = tid; e < 2 * K * 16; e += 512) {
-        const int buf = e / (K * 16), k = (e / 16) % K, c = e % 16;
+    const long long q0 = (long long)blockIdx.x * C;
+    for (int e = tid; e < 2 * K * C; e += 512) {
+        const int buf = e / (K * C), k = (e / C) % K, c = e % C;
         const long long qq = q0 + c < a.Q ? q0 + c : a.Q - 1;
         lam[buf][k][c] = (buf == 0 && k < M) ? a.y0[qq * M + k] : 0.0;
         if (a.boundary && buf == 0 && k < M && q0 + c < a.Q)
@@ -489,11 +493,16 @@ __global__ __launch_bounds__(512) void lin_many_kernel(ManyArgs a) {
     // lane i + 16 k), B[k][j] in lane j + 16 k; the FP64 16 x 16 accumulator
     // interleaves its rows: lane l holds D[4 i + l/16][l % 16] (i = 0..3,
     // measured on the device), so the lane's outputs are rows 16 w + 4 i + kq
-    // of chain column col
+    // of chain column col of each column block
     const int arow = 16 * w + col;
     const bool active = 16 * w < M;
-    const long long q = q0 + col;
-    const bool live = q < a.Q;
+    bool live[CB];
+    long long q[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        q[cb] = q0 + 16 * cb + col;
+        live[cb] = q[cb] < a.Q;
+    }
     // the A fragments and the c values of a slice, loaded unconditionally from
     // clamped (in-block) addresses, with no select after the load (which would
     // wait for it): a column k >= M meets the zero row k of Lambda, a row
@@ -502,7 +511,7 @@ __global__ __launch_bounds__(512) void lin_many_kernel(ManyArgs a) {
     // waits for the prefetch.  (A non-finite table value in column M - 1 thus
     // also reaches the padded terms; it makes its row non-finite in the exact
     // sum as well.)
-    double ga[KP], gb[KP], ca[4], cb[4];
+    double ga[KP], gb[KP], ca[4], cb4[4];
 #define NV_LIN_LOAD(g, cv, j)                                                            \
     do {                                                                                 \
         const double *Tj_ = a.T + (long long)(j) * per;                                  \
@@ -517,28 +526,38 @@ __global__ __launch_bounds__(512) void lin_many_kernel(ManyArgs a) {
         }                                                                                \
     } while (0)
     // one slice: the product on the matrix cores (even and odd k-steps in two
-    // accumulators), c added, the new states to LDS (and the boundary), barrier
+    // accumulators per column block), c added, the new states to LDS (and the
+    // boundary), barrier
 #define NV_LIN_SLICE(g, cv, j)                                                           \
     do {                                                                                 \
         if (active) {                                                                    \
-            v4d acc = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};                 \
-            _Pragma("unroll") for (int kk = 0; kk < KP; ++kk) {                          \
-                if (kk % 2 == 0)                                                         \
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(                          \
-                        g[kk], lam[cur][4 * kk + kq][col], acc, 0, 0, 0);                \
-                else                                                                     \
-                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(                         \
-                        g[kk], lam[cur][4 * kk + kq][col], acc1, 0, 0, 0);               \
+            v4d acc[CB], acc1[CB];                                                       \
+            _Pragma("unroll") for (int cb = 0; cb < CB; ++cb) {                          \
+                acc[cb] = v4d{0.0, 0.0, 0.0, 0.0};                                       \
+                acc1[cb] = v4d{0.0, 0.0, 0.0, 0.0};                                      \
             }                                                                            \
-            acc = acc + acc1;                                                            \
-            _Pragma("unroll") for (int i = 0; i < 4; ++i) {                              \
-                const int r = 16 * w + 4 * i + kq;                                       \
-                const double v = cv[i] + acc[i];                                         \
-                if (r < M) {                                                             \
-                    lam[cur ^ 1][r][col] = v;                                            \
-                    if (live && a.boundary)                                              \
-                        a.boundary[(q * (N + 1) + (j) + 1) * (long long)M + r] = v;      \
-                    if (live && !isfinite(v) && (j) < bad) bad = (j);                    \
+            _Pragma("unroll") for (int kk = 0; kk < KP; ++kk) {                          \
+                _Pragma("unroll") for (int cb = 0; cb < CB; ++cb) {                      \
+                    const double b_ = lam[cur][4 * kk + kq][16 * cb + col];              \
+                    if (kk % 2 == 0)                                                     \
+                        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[kk], b_, acc[cb],   \
+                                                                       0, 0, 0);         \
+                    else                                                                 \
+                        acc1[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[kk], b_, acc1[cb], \
+                                                                        0, 0, 0);        \
+                }                                                                        \
+            }                                                                            \
+            _Pragma("unroll") for (int cb = 0; cb < CB; ++cb) {                          \
+                const v4d s_ = acc[cb] + acc1[cb];                                       \
+                _Pragma("unroll") for (int i = 0; i < 4; ++i) {                          \
+                    const int r = 16 * w + 4 * i + kq;                                   \
+                    const double v = cv[i] + s_[i];                                      \
+                    if (r < M) {                                                         \
+                        lam[cur ^ 1][r][16 * cb + col] = v;                              \
+                        if (live[cb] && a.boundary)                                      \
+                            a.boundary[(q[cb] * (N + 1) + (j) + 1) * (long long)M + r] = v;  \
+                        if (live[cb] && !isfinite(v) && (j) < bad) bad = (j);            \
+                    }                                                                    \
                 }                                                                        \
             }                                                                            \
         }                                                                                \
@@ -549,28 +568,43 @@ __global__ __launch_bounds__(512) void lin_many_kernel(ManyArgs a) {
     if (active) NV_LIN_LOAD(ga, ca, 0);
     __syncthreads();
     for (int j = 0; j < N; j += 2) {
-        if (active) NV_LIN_LOAD(gb, cb, j + 1 < N ? j + 1 : N - 1);
+        if (active) NV_LIN_LOAD(gb, cb4, j + 1 < N ? j + 1 : N - 1);
         NV_LIN_SLICE(ga, ca, j);
         if (j + 1 >= N) break;
         if (active) NV_LIN_LOAD(ga, ca, j + 2 < N ? j + 2 : N - 1);
-        NV_LIN_SLICE(gb, cb, j + 1);
+        NV_LIN_SLICE(gb, cb4, j + 1);
     }
 #undef NV_LIN_LOAD
 #undef NV_LIN_SLICE
-    for (int e = tid; e < M * 16; e += 512) {
-        const int k = e / 16, c = e % 16;
+    for (int e = tid; e < M * C; e += 512) {
+        const int k = e / C, c = e % C;
         if (q0 + c < a.Q) a.yT[(q0 + c) * M + k] = lam[cur][k][c];
     }
     if (bad != 0x7fffffff) atomicMin(a.bad, bad);
 }
 
+// With enough chains for two workgroups of two column blocks on every CU, a
+// workgroup carries two blocks that share its table reads; fewer chains keep
+// one block per workgroup, for more workgroups (measured at M = 99, N = 1024:
+// 16,384 chains 9.1 -> 7.4 ms paired, 4096 chains 2.5 -> 3.7 ms).  Two blocks
+// need more registers: up to KP = 29 (M <= 116) the kernel holds them without
+// spilling.
+constexpr int kManyPairMaxKP = 29;
+
 template <int KP>
-void lin_launch_many(const ManyArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL((lin_many_kernel<KP>), dim3(unsigned((a.Q + 15) / 16)), dim3(512), 0, st,
-                       a);
+void lin_launch_many(const ManyArgs &a, long long pair_from, hipStream_t st) {
+    if constexpr (KP <= kManyPairMaxKP) {
+        if (a.Q >= pair_from) {
+            hipLaunchKernelGGL((lin_many_kernel<KP, 2>), dim3(unsigned((a.Q + 31) / 32)),
+                               dim3(512), 0, st, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((lin_many_kernel<KP, 1>), dim3(unsigned((a.Q + 15) / 16)), dim3(512), 0,
+                       st, a);
 }
 
-using ManyLaunch = void (*)(const ManyArgs &, hipStream_t);
+using ManyLaunch = void (*)(const ManyArgs &, long long, hipStream_t);
 template <int... K>
 constexpr void many_fill(ManyLaunch *t, std::integer_sequence<int, K...>) {
     ((t[K] = &lin_launch_many<K + 1>), ...);
@@ -833,7 +867,12 @@ NV_API nv_status nv_lin_compose_many(nv_lin *l, const double *y0_dev, long long 
     NV_HIP(hipMemcpyAsync(l->bad, &init, sizeof(int), hipMemcpyHostToDevice, l->stream));
     NV_HIP(hipEventRecord(l->e2, l->stream));
     ManyArgs a{l->T, y0_dev, yT_dev, boundary_dev, l->bad, count, M, N};
-    lin_many.f[(M + 3) / 4 - 1](a, l->stream);
+    int dev = 0, n_cu = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n_cu < 1)
+        n_cu = 256;
+    lin_many.f[(M + 3) / 4 - 1](a, 2LL * n_cu * 32, l->stream);
     NV_HIP(hipGetLastError());
     NV_HIP(hipEventRecord(l->e3, l->stream));
     int bad = init;

@@ -211,6 +211,37 @@ def test_compose_many_within_rounding_bound_of_oracle(lin, w):
     assert st == nv.NV_OK and np.array_equal(yT2.cpu().numpy(), yT)
 
 
+@pytest.mark.parametrize("w", [HeatWorkload("heat-M19-N30", 19, 0.001, 30, T=0.3),
+                               HeatWorkload("heat-M99-N12", 99, 0.0005, 12, T=0.12),
+                               HeatWorkload("heat-M120-N8", 120, 0.0005, 8, T=0.08)],
+                         ids=lambda w: w.name)
+def test_compose_many_large_counts_equal_small_ones(lin, w):
+    """With chains enough for two workgroups per CU (16,384 on 256 CUs), a
+    workgroup carries two blocks of 16 chains that share its table reads
+    (M <= 116; M = 120 keeps one block): every chain's states are those of the
+    same chain in a small run, to the bit, and within the rounding bound of the
+    oracle's chain."""
+    import torch
+    say("linear many, large count", w.name)
+    lin.build(w)
+    G, c = lin.tables()
+    Q = 16384 + 37
+    rng = np.random.default_rng(72)
+    y0 = rng.normal(0.0, 1.0, (Q, w.M))
+    st, yT, bnd = lin.compose_many(y0, want_boundary=True)
+    torch.cuda.synchronize()
+    assert st == nv.NV_OK
+    yT, bnd = yT.cpu().numpy(), bnd.cpu().numpy()
+    assert np.array_equal(yT, bnd[:, -1]) and np.array_equal(bnd[:, 0], y0)
+    pick = [0, 15, 16, 31, 32, 33, 47, 8191, 16383, 16384, 16399, 16400, Q - 1]
+    st, yT_s, bnd_s = lin.compose_many(y0[pick], want_boundary=True)
+    torch.cuda.synchronize()
+    assert st == nv.NV_OK
+    assert np.array_equal(bnd_s.cpu().numpy().view(np.int64), bnd[pick].view(np.int64))
+    for q in (0, 31, 16383, Q - 1):
+        check_chain(G, c, bnd[q], lo.compose(G, c, y0[q]), f"{w.name} chain {q}")
+
+
 def test_compose_many_reports_a_nonfinite_chain(lin):
     import torch
     w = HeatWorkload("heat-M9-nan-many", 9, 0.01, 5, T=0.5)

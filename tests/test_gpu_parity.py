@@ -661,3 +661,43 @@ def test_failed_chunked_solve_then_compose_and_solve(orc, torch):
         assert o.status == 0 and res.status == nv.NV_OK
         assert np.array_equal(res.boundary.view(np.int64), o.boundary.view(np.int64))
         assert res.n_out_of_grid == o.n_out_of_grid
+
+
+def test_more_than_2_to_the_32_table_entries(orc, torch):
+    """The largest build here: 2048 slices x 2,097,155 points (ragged), about
+    4.3e9 FP64 entries, a 34 GB table, so that every table offset, tile and
+    count needs more than 32 bits: sampled entries (the last ones included)
+    against the oracle, the composition against the oracle's lazily
+    integrated method, and the chunked nv_solve equal to build + compose."""
+    from paper_1304_6514_amd.propagator import Propagator
+    w = W.Workload("logistic-fp64-2048sl-2097155pt-3st", "logistic", (), 0.0, 1.0, 2048,
+                   (2097155,), (-0.1,), (1.2,), 3, (0.1,), "fp64", "linear")
+    entries = w.n_slices * w.points_per_slice
+    assert entries > 1 << 32
+    say("largest build", w.name, entries, "entries")
+    with Propagator("cuda:0") as p:
+        p.build(w)
+        assert np.all(p.nonfinite_counts() == 0)
+        sl, pt = W.sample_entries(w, 4096, seed=13)
+        sl = np.concatenate([sl, [w.n_slices - 1] * 3, [0]])
+        pt = np.concatenate([pt, [w.points_per_slice - 1, w.points_per_slice - 2, 0],
+                             [w.points_per_slice - 1]])
+        got = p.table_tensor(0)[torch.from_numpy(sl).cuda(), torch.from_numpy(pt).cuda()]
+        ref = orc.table_entries(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, ogrid(orc, w),
+                                w.steps_per_slice, sl, pt)
+        err = mixed_err(got.cpu().numpy(), ref[0])
+        say("largest build sampled error", err)
+        assert err <= TOL["fp64"]
+        g = p.compose()
+        lazy = orc.method_lazy(w.rhs, w.params, w.scheme, w.t0, w.T, w.n_slices, ogrid(orc, w),
+                               w.steps_per_slice, w.interp, w.y0)
+        assert g.status == nv.NV_OK and lazy.status == 0
+        assert g.n_out_of_grid == lazy.n_out_of_grid
+        diff = float(np.max(np.abs(g.boundary - lazy.boundary)))
+        say("largest build: composition against the lazy oracle method", diff)
+        assert diff <= 1e-12
+        r = p.solve(w)
+        say("largest build: nv_solve in", r.n_chunks, "chunks")
+        assert r.status == nv.NV_OK and r.n_chunks > 1
+        assert np.array_equal(r.boundary.view(np.int64), g.boundary.view(np.int64))
+    torch.cuda.empty_cache()

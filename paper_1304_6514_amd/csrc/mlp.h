@@ -139,26 +139,58 @@ struct SmallParams {
     float b4[kOut];
 };
 
-__device__ inline void load_small(SmallParams &sp, const float *params, int tid, int nthreads) {
-    for (int i = tid; i < kWidth * kIn; i += nthreads) sp.w1[i] = params[kW1 + i];
-    for (int i = tid; i < kWidth; i += nthreads) {
-        sp.b1[i] = params[kB1 + i];
-        sp.b2[i] = params[kB2 + i];
-        sp.b3[i] = params[kB3 + i];
+// The small parameters into LDS: every thread's loads are issued before the
+// first store to LDS (a store right after each load would make each thread
+// wait for its loads one at a time).
+template <int kThreads>
+__device__ inline void load_small(SmallParams &sp, const float *params, int tid) {
+    constexpr int kN = kWidth * kIn + 3 * kWidth + kOut * kWidth + kOut;   // 1154 values
+    constexpr int kIter = (kN + kThreads - 1) / kThreads;
+    static_assert(sizeof(SmallParams) == kN * sizeof(float), "SmallParams is the flat list");
+    // SmallParams holds w1, b1, b2, b3, w4, b4; in the flat parameter vector
+    // the matrices W2, W3 sit between them
+    float v[kIter];
+#pragma unroll
+    for (int i = 0; i < kIter; ++i) {
+        int e = tid + i * kThreads;
+        e = e < kN ? e : kN - 1;                   // in bounds, no select after the load
+        const int b1 = kWidth * kIn, b2 = b1 + kWidth, b3 = b2 + kWidth, w4 = b3 + kWidth;
+        const int src = e < b1   ? kW1 + e
+                        : e < b2 ? kB1 + (e - b1)
+                        : e < b3 ? kB2 + (e - b2)
+                        : e < w4 ? kB3 + (e - b3)
+                                 : kW4 + (e - w4);   // W4 then b4, adjacent in both
+        v[i] = params[src];
     }
-    for (int i = tid; i < kOut * kWidth; i += nthreads) sp.w4[i] = params[kW4 + i];
-    if (tid < kOut) sp.b4[tid] = params[kB4 + tid];
+    float *dst = reinterpret_cast<float *>(&sp);
+#pragma unroll
+    for (int i = 0; i < kIter; ++i) {
+        const int e = tid + i * kThreads;
+        if (e < kN) dst[e] = v[i];
+    }
 }
 
-// Copy n_mat permuted bf16 matrices from global memory into padded LDS rows.
-__device__ inline void load_mats(__bf16 *lds, const __bf16 *src, int n_mat, int tid,
-                                 int nthreads) {
-    const int chunks = n_mat * kWidth * (kWidth / 8);      // 16-byte chunks
-    for (int c = tid; c < chunks; c += nthreads) {
-        const int m = c / (kWidth * 16), rem = c - m * kWidth * 16;
-        const int row = rem >> 4, col = (rem & 15) * 8;
-        *reinterpret_cast<bf16x8 *>(lds + (m * kWidth + row) * kLdsRow + col) =
-            *reinterpret_cast<const bf16x8 *>(src + m * kMat + row * kWidth + col);
+// Copy kMats permuted bf16 matrices from global memory into padded LDS rows,
+// every thread's 16-byte loads issued before its first store to LDS.
+template <int kMats, int kThreads>
+__device__ inline void load_mats(__bf16 *lds, const __bf16 *src, int tid) {
+    constexpr int kChunks = kMats * kWidth * (kWidth / 8);      // 16-byte chunks
+    constexpr int kIter = (kChunks + kThreads - 1) / kThreads;
+    bf16x8 v[kIter];
+#pragma unroll
+    for (int i = 0; i < kIter; ++i) {
+        int c = tid + i * kThreads;
+        c = c < kChunks ? c : kChunks - 1;         // in bounds, no select after the load
+        v[i] = *reinterpret_cast<const bf16x8 *>(src + size_t(c) * 8);
+    }
+#pragma unroll
+    for (int i = 0; i < kIter; ++i) {
+        const int c = tid + i * kThreads;
+        if (c < kChunks) {
+            const int m = c / (kWidth * 16), rem = c - m * kWidth * 16;
+            const int row = rem >> 4, col = (rem & 15) * 8;
+            *reinterpret_cast<bf16x8 *>(lds + (m * kWidth + row) * kLdsRow + col) = v[i];
+        }
     }
 }
 

@@ -381,8 +381,8 @@ struct ForwardArgs {
 __global__ __launch_bounds__(kInferThreads) void sur_forward_kernel(ForwardArgs a) {
     __shared__ InferLds L;
     const int tid = int(threadIdx.x);
-    load_mats(L.w, a.shadow, 2, tid, kInferThreads);
-    load_small(L.sp, a.params, tid, kInferThreads);
+    load_mats<2, kInferThreads>(L.w, a.shadow, tid);
+    load_small<kInferThreads>(L.sp, a.params, tid);
     __syncthreads();
     const int lane = tid & 63, s = lane & 15, g = lane >> 4;
     const long long n = ((long long)blockIdx.x * (kInferThreads / 64) + (tid >> 6)) * 16 + s;
@@ -558,8 +558,8 @@ __global__ __launch_bounds__(kInferThreads) void sur_chain_kernel(ChainArgs a) {
 #pragma clang fp contract(off)
     __shared__ ChainLds L;
     const int tid = int(threadIdx.x);
-    load_mats(L.w, a.shadow, 2, tid, kInferThreads);
-    load_small(L.sp, a.params, tid, kInferThreads);
+    load_mats<2, kInferThreads>(L.w, a.shadow, tid);
+    load_small<kInferThreads>(L.sp, a.params, tid);
     __syncthreads();
     const int lane = tid & 63, w = tid >> 6, s = lane & 15, g = lane >> 4;
     const long long q = (long long)blockIdx.x * 16 + s;        // the 4 waves share 16 chains
@@ -850,8 +850,8 @@ __device__ inline void train_tile(const TrainArgs &a, TrainLds &L, long long til
 __global__ __launch_bounds__(kTrainThreads) void sur_train_kernel(TrainArgs a) {
     __shared__ TrainLds L;
     const int tid = int(threadIdx.x);
-    load_mats(L.w, a.shadow, 4, tid, kTrainThreads);
-    load_small(L.sp, a.params, tid, kTrainThreads);
+    load_mats<4, kTrainThreads>(L.w, a.shadow, tid);
+    load_small<kTrainThreads>(L.sp, a.params, tid);
     const int lane = tid & 63;
     const int gi = __builtin_amdgcn_readfirstlane(tid >> 8);        // group
     const int w = __builtin_amdgcn_readfirstlane((tid >> 6) & 3);   // wave in the group

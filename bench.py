@@ -48,7 +48,8 @@ WORKLOADS = {"forced_cubic": W.FORCED_CUBIC_FP32, "logistic": W.LOGISTIC_FP64,
 # WRITE_SIZE (raw counters, summed over the step's build dispatches; the
 # profile files under profiles/ give the commands).  Keyed by workload,
 # accumulation, mode, build launches per step and the SHA-1 of the kernel
-# sources they were taken with; any other source gives traffic = null.
+# sources and build flags they were taken with; any other source gives
+# traffic = null.
 MEASURED_TRAFFIC = {
     ("forced-cubic-fp32-4096sl-4096pt-2000st", "blocked", "solve", 32,
      "98008abf8d2484d4722438ee50dceda6b18ec554"): (64800.0 + 65664.0) * 1024,
@@ -62,8 +63,8 @@ MEASURED_TRAFFIC = {
 # four FMAs adding the weighted stages into the state, the last after k4)
 SINGLE_WAVE_STEP = {"logistic-fp64-64sl-256pt-1000st": {"valu": 11, "dependent": 8}}
 
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1304_6514_amd", "csrc", f)
-                  for f in ("integrate.h", "build_kernels.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1304_6514_amd", f)
+                  for f in ("csrc/integrate.h", "csrc/build_kernels.hip", "_build.py")]
 
 
 def kernel_source_sha1() -> str:

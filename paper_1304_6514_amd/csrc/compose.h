@@ -288,6 +288,28 @@ struct PfShared {
     int done;                      // the chain has ended
 };
 
+// The value of the wave's first active lane, held in scalar registers.  The
+// chain computes the same values in every lane; taking them from one lane
+// tells the compiler so, and its branches then test scalar conditions instead
+// of saving, masking and restoring the execution mask around each one (a lone
+// wave pays an issue slot for every instruction it runs).
+__device__ inline double uniform_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(b & 0xffffffffLL)));
+    const unsigned hi = unsigned(__builtin_amdgcn_readfirstlane(int(b >> 32)));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ inline long long uniform_i64(long long v) {
+    const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(v & 0xffffffffLL)));
+    const unsigned hi = unsigned(__builtin_amdgcn_readfirstlane(int(v >> 32)));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ inline bool uniform_bool(bool v) {
+    return __builtin_amdgcn_readfirstlane(v ? 1 : 0) != 0;
+}
+
 __device__ inline double pf_read(const double *w, unsigned k) {
     return __hip_atomic_load(w + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -304,77 +326,98 @@ __device__ inline void pf_chain(const ComposeArgs &a, PfShared &sh) {
     const int n = a.n0;
     double lam = 0.0, unused = 0.0;
     if (!range_begin<1>(a, lane, lam, unused)) return;    // an earlier range already failed
-    long long oog = 0;
+    int oog = 0;
     int bad_slice = -1;
     double keep = 0.0;
     int jb = a.j_begin;
     int j = a.j_begin;
     // nodes the interpolant reads: i0-1 .. i0+2 (Hermite) or i0 .. i0+1 (linear)
     constexpr int kBelow = Interp == 1 ? 1 : 0, kSpan = Interp == 1 ? 4 : 2;
-    for (; j < a.j_end; ++j) {
-        if (!finite(lam)) {
-            bad_slice = j;
-            break;
-        }
-        // the slot's tag, read while the cell is located; the window's values
-        // are read after it, at addresses that depend on it
-        const unsigned slot = unsigned(j) % kPfSlots;
-        const long long tg =
-            __hip_atomic_load(&sh.tag[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        // the slot's slice and first cell (-1 and -1 for an empty slot)
-        const int tag_slice = int(tg >> 32), base = int(tg & 0xffffffffLL);
-        const double *win = sh.win[slot];
-        long long i0;
-        double w0;
-        oog += locate(a.lo0, a.inv0, n, lam, i0, w0);
-        const int i = int(i0);
-        // a hit needs nodes i-kBelow .. i-kBelow+kSpan-1 inside the window and,
-        // for the Hermite form, a cell away from the row's ends (1 <= i <= n-3),
-        // where both slopes are central; every other case reads global memory
-        const unsigned o = unsigned(i - kBelow - base);
-        const bool hit = tag_slice == j && o <= unsigned(kPfWin - kSpan) &&
-                         (Interp == 0 || i <= n - 3);
-        double next;
-        bool ok;
-        if (hit) {
-            // offsets into the slot; atomic reads keep them LDS reads (a
-            // pointer chosen between LDS and global memory would make them
-            // flat loads)
-            if constexpr (Interp == 1) {
-                const double tm = pf_read(win, o), ta = pf_read(win, o + 1);
-                const double tb = pf_read(win, o + 2), tp = pf_read(win, o + 3);
-                // the weights do not depend on the table: formed while the
-                // reads are in flight (the empty asm keeps them there)
-                HermiteBasis hb = hermite_basis(w0);
-                asm volatile("" : "+v"(hb.h00), "+v"(hb.h10), "+v"(hb.h01), "+v"(hb.h11));
-                const double da = 0.5 * (tb - tm), db = 0.5 * (tp - ta);
-                next = ((hb.h00 * ta + hb.h10 * da) + hb.h01 * tb) + hb.h11 * db;
-                ok = finite(ta) & finite(tb) & finite(da) & finite(db);
+    // A state that is not finite fails the slice that starts from it.  Inside
+    // the loop one test of the interpolated value stands for both checks: an
+    // entry that is not finite (or a slope formed from one) makes the value
+    // not finite (a product with zero gives NaN), so a finite value has finite
+    // entries and is itself the next slice's finite start.  The loop leaves
+    // at the first value that is not finite, and the code after it tells the
+    // two cases apart.
+    double next = 0.0;
+    bool ok = true;
+    if (j < a.j_end && !finite(lam)) {
+        bad_slice = j;
+    } else {
+        for (; j < a.j_end; ++j) {
+            // the slot's tag, read while the cell is located; the window's
+            // values are read after it, at addresses that depend on it
+            const unsigned slot = unsigned(j) % kPfSlots;
+            const long long tg = uniform_i64(__hip_atomic_load(
+                &sh.tag[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+            // the slot's slice and first cell (-1 and -1 for an empty slot)
+            const int tag_slice = int(tg >> 32), base = int(tg & 0xffffffffLL);
+            const double *win = sh.win[slot];
+            long long i0;
+            double w0;
+            oog += locate(a.lo0, a.inv0, n, lam, i0, w0);
+            const int i = int(i0);
+            // a hit needs nodes i-kBelow .. i-kBelow+kSpan-1 inside the window
+            // and, for the Hermite form, a cell away from the row's ends
+            // (1 <= i <= n-3), where both slopes are central; every other case
+            // reads global memory
+            const unsigned o = unsigned(i - kBelow - base);
+            const bool hit = tag_slice == j && o <= unsigned(kPfWin - kSpan) &&
+                             (Interp == 0 || i <= n - 3);
+            if (hit) {
+                // offsets into the slot; atomic reads keep them LDS reads (a
+                // pointer chosen between LDS and global memory would make them
+                // flat loads)
+                if constexpr (Interp == 1) {
+                    const double tm = pf_read(win, o), ta = pf_read(win, o + 1);
+                    const double tb = pf_read(win, o + 2), tp = pf_read(win, o + 3);
+                    // the weights do not depend on the table: formed while the
+                    // reads are in flight (the empty asm keeps them there)
+                    HermiteBasis hb = hermite_basis(w0);
+                    asm volatile("" : "+v"(hb.h00), "+v"(hb.h10), "+v"(hb.h01), "+v"(hb.h11));
+                    const double da = 0.5 * (tb - tm), db = 0.5 * (tp - ta);
+                    next = ((hb.h00 * ta + hb.h10 * da) + hb.h01 * tb) + hb.h11 * db;
+                    ok = finite(ta) & finite(tb) & finite(da) & finite(db);
+                } else {
+                    const double ta = pf_read(win, o), tb = pf_read(win, o + 1);
+                    next = ta + w0 * (tb - ta);
+                    ok = finite(ta) & finite(tb);
+                }
             } else {
-                const double ta = pf_read(win, o), tb = pf_read(win, o + 1);
-                next = ta + w0 * (tb - ta);
-                ok = finite(ta) & finite(tb);
+                const T *row = tab0 + (long long)j * a.M;
+                ok = interp_1d<Interp>([row](long long k) { return double(row[k]); }, i0, w0,
+                                       n, next);
             }
-        } else {
-            const T *row = tab0 + (long long)j * a.M;
-            ok = interp_1d<Interp>([row](long long k) { return double(row[k]); }, i0, w0, n,
-                                   next);
+            asm volatile("" : "+v"(next));   // formed before the branch, not after it
+            next = uniform_f64(next);
+            if (!finite(next)) break;
+            lam = next;
+            // slice j is done.  Its slot is reused for slice j + kPfSlots, which
+            // no helper fetches before the chain is past slice j + kPfSlots -
+            // kPfAhead.
+            if (lane == 0)
+                __hip_atomic_store(&sh.hist[j & 1], pf_pack(j, i0), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (lane == j - jb) keep = lam;
+            if (j - jb == 63) {
+                a.boundary[jb + lane + 1] = keep;
+                jb += 64;
+            }
         }
-        asm volatile("" : "+v"(next));   // formed before the branch, not after it
-        if (!ok) {
-            bad_slice = j;
-            break;
-        }
-        lam = next;
-        // slice j is done.  Its slot is reused for slice j + kPfSlots, which no
-        // helper fetches before the chain is past slice j + kPfSlots - kPfAhead.
-        if (lane == 0)
-            __hip_atomic_store(&sh.hist[j & 1], pf_pack(j, i0), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (lane == j - jb) keep = lam;
-        if (j - jb == 63) {
-            a.boundary[jb + lane + 1] = keep;
-            jb += 64;
+        if (j < a.j_end) {               // slice j gave a value that is not finite
+            if (!uniform_bool(ok)) {     // from an entry that is not finite: j fails
+                bad_slice = j;
+            } else {                     // a state that is not finite: j + 1 fails
+                lam = next;
+                if (lane == j - jb) keep = lam;
+                if (j - jb == 63) {
+                    a.boundary[jb + lane + 1] = keep;
+                    jb += 64;
+                }
+                ++j;
+                if (j < a.j_end) bad_slice = j;
+            }
         }
     }
     if (lane < j - jb) a.boundary[jb + lane + 1] = keep;

@@ -510,6 +510,56 @@ def test_chain_failure_after_several_blocks_of_states(orc, torch, interp, precis
         assert np.array_equal(r.boundary[:n].view(np.int64), o.boundary[:n].view(np.int64))
 
 
+@pytest.mark.parametrize("interp", ["linear", "hermite"])
+@pytest.mark.parametrize("precision,steps,n_slices", [("fp64", 100, 6), ("fp64", 100, 2),
+                                                      ("fp32", 12, 24)])
+def test_chain_state_overflows_from_finite_entries(orc, torch, interp, precision, steps,
+                                                   n_slices):
+    """y' = 7.5 y with one RK4 step of h = 1 multiplies by 238.7, so each slice's
+    table is finite (up to ~1e238 in FP64, ~1e29 in FP32) while the chain,
+    extrapolating far outside the grid, multiplies its state by the slice
+    factor until the interpolated value overflows with every entry finite.
+    The slice after that starts from a non-finite state and fails; when the
+    overflow happens in the last slice the composition ends normally with a
+    non-finite y(T) (the written rule, as in the oracle).  Also through the
+    chunked solve, where the non-finite state crosses from one range of slices
+    to the next."""
+    from paper_1304_6514_amd.propagator import Propagator
+    w = W.Workload(f"linear-overflow-{interp}-{precision}-{n_slices}", "linear", (7.5,), 0.0,
+                   float(steps * n_slices), n_slices, (5,), (-2.0,), (2.0,), steps, (0.5,),
+                   precision, interp)
+    say("overflow from finite entries", w.name)
+    with Propagator("cuda:0") as a:
+        a.build(w)
+        tab = gpu_tables(a, w)
+        assert np.all(np.isfinite(tab))
+        ra = a.compose()
+    o = orc.compose_tables(ogrid(orc, w), w.interp, tab, w.y0)
+    n = (o.bad_slice if o.status != 0 else n_slices) + 1
+    assert not np.isfinite(o.boundary[n - 1, 0])
+    if n_slices == 2:
+        assert o.status == 0                         # the last slice overflows
+    else:
+        assert o.status == orc.NONFINITE and o.bad_slice < n_slices
+    with Propagator("cuda:0", solve_chunks=n_slices) as b:
+        rb = b.solve(w)
+        assert np.array_equal(gpu_tables(b, w), tab)
+    def same(g, e):
+        # finite states to the bit; a NaN's sign and payload are the hardware's own
+        fin = np.isfinite(e)
+        assert np.array_equal(np.isfinite(g), fin)
+        assert np.array_equal(g[fin].view(np.int64), e[fin].view(np.int64))
+        assert np.array_equal(g[~fin], e[~fin], equal_nan=True)
+
+    for r in (ra, rb):
+        assert r.status == (nv.NV_OK if o.status == 0 else nv.NV_ERR_NONFINITE)
+        assert r.bad_slice == o.bad_slice
+        assert r.n_out_of_grid == o.n_out_of_grid
+        same(r.boundary[:n], o.boundary[:n])
+        if o.status == 0:
+            same(r.yT, o.yT)
+
+
 def test_fp32_accumulation_modes_full_size(orc, torch):
     # plain FP32 accumulation of the state misses the FP32 bar on this workload
     # (one rounding of y + dy per step over 2000 steps); Kahan-compensated and

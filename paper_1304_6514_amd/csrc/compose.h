@@ -190,6 +190,7 @@ __device__ inline bool hermite_slopes_values(double ta, double tb, double ma, do
 template <class T, int Interp>
 __device__ inline void compose_range(const ComposeArgs &a, double *final_out = nullptr) {
 #pragma clang fp contract(off)
+    static_assert(Interp != 4, "stored slopes compose through the staged chain");
     constexpr int D = Interp == 2 ? 2 : 1;
     const int lane = int(threadIdx.x) & 63;
     const T *tab0 = static_cast<const T *>(a.tab0);
@@ -215,11 +216,6 @@ __device__ inline void compose_range(const ComposeArgs &a, double *final_out = n
         if constexpr (Interp == 0 || Interp == 1) {
             bad = !interp_1d<Interp>([row0](long long k) { return double(row0[k]); }, i0, w0,
                                      a.n0, next0);
-        } else if constexpr (Interp == 4) {
-            const T *row1 = tab1 + (long long)j * a.M;
-            const double ta = double(row0[i0]), tb = double(row0[i0 + 1]);
-            const double ma = double(row1[i0]), mb = double(row1[i0 + 1]);
-            bad = !hermite_slopes_values(ta, tb, ma, mb, a.dxi0, hermite_basis(w0), next0);
         } else {
             oog += locate(a.lo1, a.inv1, a.n1, lam1, i1, w1);
             const long long c00 = i0 * a.n1 + i1, c10 = (i0 + 1) * a.n1 + i1;
@@ -280,13 +276,19 @@ constexpr int kPfWin = 256;        // table values per window
 constexpr int kPfAhead = 8;        // a window is fetched this many slices ahead
 constexpr int kPfSpinMax = 1 << 20;
 
-struct PfShared {
-    double win[kPfSlots][kPfWin];
+// C = 2 for cubic Hermite with stored slopes: a slot holds the window of the
+// value row (component 0) and the same window of the slope row (component 1).
+template <int C>
+struct PfSharedC {
+    double win[C][kPfSlots][kPfWin];
     long long tag[kPfSlots];       // (slice << 32) | first cell of the window; -1 empty
     long long hist[2];             // (slice << 32) | cell, of the last two slices the chain
                                    // finished (slice j in hist[j & 1])
     int done;                      // the chain has ended
 };
+
+template <int Interp>
+using PfShared = PfSharedC<Interp == 4 ? 2 : 1>;
 
 // The value of the wave's first active lane, held in scalar registers.  The
 // chain computes the same values in every lane; taking them from one lane
@@ -319,10 +321,11 @@ __device__ inline long long pf_pack(int hi, long long lo) {
 }
 
 template <class T, int Interp>
-__device__ inline void pf_chain(const ComposeArgs &a, PfShared &sh) {
+__device__ inline void pf_chain(const ComposeArgs &a, PfShared<Interp> &sh) {
 #pragma clang fp contract(off)
     const int lane = int(threadIdx.x) & 63;
     const T *tab0 = static_cast<const T *>(a.tab0);
+    const T *tab1 = static_cast<const T *>(a.tab1);
     const int n = a.n0;
     double lam = 0.0, unused = 0.0;
     if (!range_begin<1>(a, lane, lam, unused)) return;    // an earlier range already failed
@@ -331,7 +334,8 @@ __device__ inline void pf_chain(const ComposeArgs &a, PfShared &sh) {
     double keep = 0.0;
     int jb = a.j_begin;
     int j = a.j_begin;
-    // nodes the interpolant reads: i0-1 .. i0+2 (Hermite) or i0 .. i0+1 (linear)
+    // nodes the interpolant reads: i0-1 .. i0+2 (Hermite on differences) or
+    // i0 .. i0+1 (linear, Hermite on stored slopes)
     constexpr int kBelow = Interp == 1 ? 1 : 0, kSpan = Interp == 1 ? 4 : 2;
     // A state that is not finite fails the slice that starts from it.  Inside
     // the loop one test of the interpolated value stands for both checks: an
@@ -353,18 +357,18 @@ __device__ inline void pf_chain(const ComposeArgs &a, PfShared &sh) {
                 &sh.tag[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
             // the slot's slice and first cell (-1 and -1 for an empty slot)
             const int tag_slice = int(tg >> 32), base = int(tg & 0xffffffffLL);
-            const double *win = sh.win[slot];
+            const double *win = sh.win[0][slot];
             long long i0;
             double w0;
             oog += locate(a.lo0, a.inv0, n, lam, i0, w0);
             const int i = int(i0);
             // a hit needs nodes i-kBelow .. i-kBelow+kSpan-1 inside the window
-            // and, for the Hermite form, a cell away from the row's ends
-            // (1 <= i <= n-3), where both slopes are central; every other case
-            // reads global memory
+            // and, for the Hermite form on differences, a cell away from the
+            // row's ends (1 <= i <= n-3), where both slopes are central; every
+            // other case reads global memory
             const unsigned o = unsigned(i - kBelow - base);
             const bool hit = tag_slice == j && o <= unsigned(kPfWin - kSpan) &&
-                             (Interp == 0 || i <= n - 3);
+                             (Interp != 1 || i <= n - 3);
             if (hit) {
                 // offsets into the slot; atomic reads keep them LDS reads (a
                 // pointer chosen between LDS and global memory would make them
@@ -379,11 +383,23 @@ __device__ inline void pf_chain(const ComposeArgs &a, PfShared &sh) {
                     const double da = 0.5 * (tb - tm), db = 0.5 * (tp - ta);
                     next = ((hb.h00 * ta + hb.h10 * da) + hb.h01 * tb) + hb.h11 * db;
                     ok = finite(ta) & finite(tb) & finite(da) & finite(db);
+                } else if constexpr (Interp == 4) {
+                    const double *win1 = sh.win[Interp == 4 ? 1 : 0][slot];
+                    const double ta = pf_read(win, o), tb = pf_read(win, o + 1);
+                    const double ma = pf_read(win1, o), mb = pf_read(win1, o + 1);
+                    HermiteBasis hb = hermite_basis(w0);
+                    asm volatile("" : "+v"(hb.h00), "+v"(hb.h10), "+v"(hb.h01), "+v"(hb.h11));
+                    ok = hermite_slopes_values(ta, tb, ma, mb, a.dxi0, hb, next);
                 } else {
                     const double ta = pf_read(win, o), tb = pf_read(win, o + 1);
                     next = ta + w0 * (tb - ta);
                     ok = finite(ta) & finite(tb);
                 }
+            } else if constexpr (Interp == 4) {
+                const T *row0 = tab0 + (long long)j * a.M, *row1 = tab1 + (long long)j * a.M;
+                const double ta = double(row0[i0]), tb = double(row0[i0 + 1]);
+                const double ma = double(row1[i0]), mb = double(row1[i0 + 1]);
+                ok = hermite_slopes_values(ta, tb, ma, mb, a.dxi0, hermite_basis(w0), next);
             } else {
                 const T *row = tab0 + (long long)j * a.M;
                 ok = interp_1d<Interp>([row](long long k) { return double(row[k]); }, i0, w0,
@@ -425,10 +441,11 @@ __device__ inline void pf_chain(const ComposeArgs &a, PfShared &sh) {
 }
 
 // Helper wave r (1..kPfHelpers) stages slices j_begin + r, j_begin + r + kPfHelpers, ...
-template <class T>
-__device__ inline void pf_helper(const ComposeArgs &a, PfShared &sh, int r) {
+template <class T, int C>
+__device__ inline void pf_helper(const ComposeArgs &a, PfSharedC<C> &sh, int r) {
     const int lane = int(threadIdx.x) & 63;
     const T *tab0 = static_cast<const T *>(a.tab0);
+    const T *tab1 = static_cast<const T *>(a.tab1);
     const int n = a.n0;
     const long long top = n > kPfWin ? n - kPfWin : 0;
     for (int s = a.j_begin + r; s < a.j_end; s += kPfHelpers) {
@@ -458,14 +475,17 @@ __device__ inline void pf_helper(const ComposeArgs &a, PfShared &sh, int r) {
         const long long rate = jn - jo == 1 ? in - io : 0;
         long long base = in + rate * ((long long)s - jn) - kPfWin / 2;
         base = base < 0 ? 0 : (base > top ? top : base);
-        const T *row = tab0 + (long long)s * a.M;
         const int slot = s % kPfSlots;
 #pragma unroll
-        for (int q = 0; q < kPfWin / 64; ++q) {
-            // past the row's end (a row shorter than a window) the last value
-            // is read again; the chain never uses those entries
-            const long long k = base + q * 64 + lane;
-            sh.win[slot][q * 64 + lane] = double(row[k < n ? k : n - 1]);
+        for (int c = 0; c < C; ++c) {
+            const T *row = (c == 0 ? tab0 : tab1) + (long long)s * a.M;
+#pragma unroll
+            for (int q = 0; q < kPfWin / 64; ++q) {
+                // past the row's end (a row shorter than a window) the last
+                // value is read again; the chain never uses those entries
+                const long long k = base + q * 64 + lane;
+                sh.win[c][slot][q * 64 + lane] = double(row[k < n ? k : n - 1]);
+            }
         }
         __builtin_amdgcn_wave_barrier();
         if (lane == 0)
@@ -477,7 +497,7 @@ __device__ inline void pf_helper(const ComposeArgs &a, PfShared &sh, int r) {
 // The whole 1-D composition of a range: wave 0 runs the chain, waves
 // 1..kPfHelpers stage windows for it.
 template <class T, int Interp>
-__device__ inline void compose_range_staged(const ComposeArgs &a, PfShared &sh) {
+__device__ inline void compose_range_staged(const ComposeArgs &a, PfShared<Interp> &sh) {
     const int wave = int(threadIdx.x) >> 6;
     if (threadIdx.x < kPfSlots) sh.tag[threadIdx.x] = -1;
     if (threadIdx.x == 0) {

@@ -32,7 +32,7 @@ __global__ void compose_kernel(ComposeArgs a) {
 // workgroup of 1 + kPfHelpers waves.
 template <class T, int Interp>
 __global__ __launch_bounds__(64 * (1 + kPfHelpers)) void compose_staged_kernel(ComposeArgs a) {
-    __shared__ PfShared sh;
+    __shared__ PfShared<Interp> sh;
     if (blockIdx.x != 0) return;
     compose_range_staged<T, Interp>(a, sh);
 }
@@ -74,7 +74,7 @@ hipError_t launch_compose(int interp, int precision, const ComposeArgs &a, hipSt
                 hipLaunchKernelGGL((compose_kernel<double, 2>), grid, block, 0, s, a);
             break;
         case 3: hipLaunchKernelGGL((compose_kernel<double, 3>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((compose_kernel<double, 4>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((compose_staged_kernel<double, 4>), grid, staged, 0, s, a); break;
         default: return hipErrorInvalidValue;
         }
     } else {
@@ -88,7 +88,7 @@ hipError_t launch_compose(int interp, int precision, const ComposeArgs &a, hipSt
                 hipLaunchKernelGGL((compose_kernel<float, 2>), grid, block, 0, s, a);
             break;
         case 3: hipLaunchKernelGGL((compose_kernel<float, 3>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((compose_kernel<float, 4>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((compose_staged_kernel<float, 4>), grid, staged, 0, s, a); break;
         default: return hipErrorInvalidValue;
         }
     }

@@ -552,76 +552,99 @@ __device__ inline void pf2_chain(const ComposeArgs &a, PfShared2 &sh) {
     const T *tab1 = static_cast<const T *>(a.tab1);
     double lam0 = 0.0, lam1 = 0.0;
     if (!range_begin<2>(a, lane, lam0, lam1)) return;     // an earlier range already failed
-    long long oog = 0;
+    int oog = 0;
     int bad_slice = -1;
     double keep0 = 0.0, keep1 = 0.0;
     int jb = a.j_begin;
     int j = a.j_begin;
-    for (; j < a.j_end; ++j) {
-        if (!finite(lam0) || !finite(lam1)) {
-            bad_slice = j;
-            break;
+    // As in the 1-D chain: inside the loop one test of the two interpolated
+    // values stands for the corners' tests and the next slice's start test (a
+    // corner that is not finite makes its component's value not finite), and
+    // the slice at which the loop leaves is told apart after it.
+    double next0 = 0.0, next1 = 0.0;
+    bool bad = false;
+    if (j < a.j_end && (!finite(lam0) || !finite(lam1))) {
+        bad_slice = j;
+    } else {
+        for (; j < a.j_end; ++j) {
+            const unsigned slot = unsigned(j) % kPf2Slots;
+            const long long tg = uniform_i64(__hip_atomic_load(
+                &sh.tag[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+            const int tag_slice = int(tg >> 32);
+            const int b0 = int((tg >> 16) & 0xffff), b1 = int(tg & 0xffff);
+            long long i0, i1;
+            double w0, w1;
+            oog += locate(a.lo0, a.inv0, a.n0, lam0, i0, w0);
+            oog += locate(a.lo1, a.inv1, a.n1, lam1, i1, w1);
+            // a hit needs cells i0, i0+1 and i1, i1+1 inside the window
+            const unsigned o0 = unsigned(int(i0) - b0), o1 = unsigned(int(i1) - b1);
+            const bool hit = tag_slice == j && o0 <= unsigned(kPf2Side - 2) &&
+                             o1 <= unsigned(kPf2Side - 2);
+            double p00, p01, p10, p11, q00, q01, q10, q11;
+            if (hit) {
+                const double *u = sh.win[slot][0], *v = sh.win[slot][1];
+                const unsigned e = o0 * kPf2Side + o1;
+                p00 = pf_read(u, e);
+                p01 = pf_read(u, e + 1);
+                p10 = pf_read(u, e + kPf2Side);
+                p11 = pf_read(u, e + kPf2Side + 1);
+                q00 = pf_read(v, e);
+                q01 = pf_read(v, e + 1);
+                q10 = pf_read(v, e + kPf2Side);
+                q11 = pf_read(v, e + kPf2Side + 1);
+            } else {
+                const long long c00 = i0 * a.n1 + i1, c10 = (i0 + 1) * a.n1 + i1;
+                const T *row0 = tab0 + (long long)j * a.M, *row1 = tab1 + (long long)j * a.M;
+                p00 = double(row0[c00]);
+                p01 = double(row0[c00 + 1]);
+                p10 = double(row0[c10]);
+                p11 = double(row0[c10 + 1]);
+                q00 = double(row1[c00]);
+                q01 = double(row1[c00 + 1]);
+                q10 = double(row1[c10]);
+                q11 = double(row1[c10 + 1]);
+            }
+            bad = bilinear_values(p00, p01, p10, p11, q00, q01, q10, q11, w0, w1, next0, next1);
+            asm volatile("" : "+v"(next0), "+v"(next1));   // formed before the branch
+            next0 = uniform_f64(next0);
+            next1 = uniform_f64(next1);
+            if (!finite(next0) || !finite(next1)) break;
+            lam0 = next0;
+            lam1 = next1;
+            // slice j is done (its slot is reused for slice j + kPf2Slots, which
+            // no helper fetches before the chain is past slice j + kPf2Slots -
+            // kPf2Ahead)
+            if (lane == 0)
+                __hip_atomic_store(&sh.hist[j & 1], pf_pack(j, (i0 << 16) | i1),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (lane == j - jb) {
+                keep0 = lam0;
+                keep1 = lam1;
+            }
+            if (j - jb == 63) {
+                a.boundary[(long long)(jb + lane + 1) * 2] = keep0;
+                a.boundary[(long long)(jb + lane + 1) * 2 + 1] = keep1;
+                jb += 64;
+            }
         }
-        const unsigned slot = unsigned(j) % kPf2Slots;
-        const long long tg =
-            __hip_atomic_load(&sh.tag[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        const int tag_slice = int(tg >> 32);
-        const int b0 = int((tg >> 16) & 0xffff), b1 = int(tg & 0xffff);
-        long long i0, i1;
-        double w0, w1;
-        oog += locate(a.lo0, a.inv0, a.n0, lam0, i0, w0);
-        oog += locate(a.lo1, a.inv1, a.n1, lam1, i1, w1);
-        // a hit needs cells i0, i0+1 and i1, i1+1 inside the window
-        const unsigned o0 = unsigned(int(i0) - b0), o1 = unsigned(int(i1) - b1);
-        const bool hit = tag_slice == j && o0 <= unsigned(kPf2Side - 2) &&
-                         o1 <= unsigned(kPf2Side - 2);
-        double p00, p01, p10, p11, q00, q01, q10, q11;
-        if (hit) {
-            const double *u = sh.win[slot][0], *v = sh.win[slot][1];
-            const unsigned e = o0 * kPf2Side + o1;
-            p00 = pf_read(u, e);
-            p01 = pf_read(u, e + 1);
-            p10 = pf_read(u, e + kPf2Side);
-            p11 = pf_read(u, e + kPf2Side + 1);
-            q00 = pf_read(v, e);
-            q01 = pf_read(v, e + 1);
-            q10 = pf_read(v, e + kPf2Side);
-            q11 = pf_read(v, e + kPf2Side + 1);
-        } else {
-            const long long c00 = i0 * a.n1 + i1, c10 = (i0 + 1) * a.n1 + i1;
-            const T *row0 = tab0 + (long long)j * a.M, *row1 = tab1 + (long long)j * a.M;
-            p00 = double(row0[c00]);
-            p01 = double(row0[c00 + 1]);
-            p10 = double(row0[c10]);
-            p11 = double(row0[c10 + 1]);
-            q00 = double(row1[c00]);
-            q01 = double(row1[c00 + 1]);
-            q10 = double(row1[c10]);
-            q11 = double(row1[c10 + 1]);
-        }
-        double next0, next1;
-        const bool bad =
-            bilinear_values(p00, p01, p10, p11, q00, q01, q10, q11, w0, w1, next0, next1);
-        asm volatile("" : "+v"(next0), "+v"(next1));   // formed before the branch
-        if (bad) {
-            bad_slice = j;
-            break;
-        }
-        lam0 = next0;
-        lam1 = next1;
-        // slice j is done (its slot is reused for slice j + kPf2Slots, which no
-        // helper fetches before the chain is past slice j + kPf2Slots - kPf2Ahead)
-        if (lane == 0)
-            __hip_atomic_store(&sh.hist[j & 1], pf_pack(j, (i0 << 16) | i1), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (lane == j - jb) {
-            keep0 = lam0;
-            keep1 = lam1;
-        }
-        if (j - jb == 63) {
-            a.boundary[(long long)(jb + lane + 1) * 2] = keep0;
-            a.boundary[(long long)(jb + lane + 1) * 2 + 1] = keep1;
-            jb += 64;
+        if (j < a.j_end) {               // slice j gave a value that is not finite
+            if (bad) {                   // from a corner that is not finite: j fails
+                bad_slice = j;
+            } else {                     // a state that is not finite: j + 1 fails
+                lam0 = next0;
+                lam1 = next1;
+                if (lane == j - jb) {
+                    keep0 = lam0;
+                    keep1 = lam1;
+                }
+                if (j - jb == 63) {
+                    a.boundary[(long long)(jb + lane + 1) * 2] = keep0;
+                    a.boundary[(long long)(jb + lane + 1) * 2 + 1] = keep1;
+                    jb += 64;
+                }
+                ++j;
+                if (j < a.j_end) bad_slice = j;
+            }
         }
     }
     if (lane < j - jb) {

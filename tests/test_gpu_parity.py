@@ -560,6 +560,45 @@ def test_chain_state_overflows_from_finite_entries(orc, torch, interp, precision
             same(r.yT, o.yT)
 
 
+@pytest.mark.parametrize("case", ["overflow", "overflow-last", "corner", "start"])
+def test_bilinear_chain_nonfinite_cases(orc, torch, case):
+    """The 2-D chain's failure rules on tables written by hand into the
+    context's buffer (then composed by the GPU and by the oracle): every slice
+    maps (y1, y2) to F (y1, y2) with F = 1e200, so from y0 = (0.5, -0.25) the
+    second lookup's value overflows although every corner is finite (the
+    third slice fails; with two slices the chain ends with a non-finite y(T));
+    a non-finite corner in the first lookup's cell fails the first slice; a
+    non-finite y0 fails it before any lookup."""
+    from paper_1304_6514_amd.propagator import Propagator
+    n_slices = 2 if case == "overflow-last" else 7
+    w = W.Workload(f"vdp-{case}", "vdp", (1.0,), 0.0, 1.0, n_slices, (9, 7), (-2.0, -3.0),
+                   (2.0, 3.0), 5, (0.5, -0.25), "fp64", "bilinear")
+    y0 = (float("nan"), 0.1) if case == "start" else w.y0
+    say("bilinear chain", case)
+    with Propagator("cuda:0") as p:
+        p.build(w)
+        x1 = np.linspace(-2.0, 2.0, 9)[:, None] * np.ones((1, 7))
+        x2 = np.ones((9, 1)) * np.linspace(-3.0, 3.0, 7)[None, :]
+        tab = np.stack([np.broadcast_to(1e200 * x1.reshape(-1), (n_slices, 63)),
+                        np.broadcast_to(1e200 * x2.reshape(-1), (n_slices, 63))]).copy()
+        if case == "corner":
+            tab[1, 0, 5 * 7 + 2] = np.inf          # corner (5, 2) of the cell y0 falls in
+        for c in range(2):
+            p.table_tensor(c).copy_(torch.from_numpy(tab[c]))
+        assert np.array_equal(gpu_tables(p, w), tab)
+        r = p.compose(y0)
+    o = orc.compose_tables(ogrid(orc, w), w.interp, tab, y0)
+    want_bad = {"overflow": 2, "overflow-last": -1, "corner": 0, "start": 0}[case]
+    assert o.bad_slice == want_bad and (o.status == 0) == (want_bad < 0)
+    assert r.status == (nv.NV_OK if o.status == 0 else nv.NV_ERR_NONFINITE)
+    assert r.bad_slice == o.bad_slice and r.n_out_of_grid == o.n_out_of_grid
+    n = (o.bad_slice if o.status != 0 else n_slices) + 1
+    got, exp = r.boundary[:n], o.boundary[:n]
+    fin = np.isfinite(exp)
+    assert np.array_equal(np.isfinite(got), fin)
+    assert np.array_equal(got[fin].view(np.int64), exp[fin].view(np.int64))
+
+
 def test_fp32_accumulation_modes_full_size(orc, torch):
     # plain FP32 accumulation of the state misses the FP32 bar on this workload
     # (one rounding of y + dy per step over 2000 steps); Kahan-compensated and

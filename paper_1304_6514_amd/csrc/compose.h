@@ -30,6 +30,15 @@ __device__ inline int locate(double lo, double inv, int n, double x, long long &
 
 __device__ inline bool finite(double v) { return isfinite(v); }
 
+// Every argument finite; the tests are combined without short-circuit
+// branches (as integers), so they issue side by side.
+__device__ inline bool all_finite(double a, double b) {
+    return (int(finite(a)) & int(finite(b))) != 0;
+}
+__device__ inline bool all_finite(double a, double b, double c, double d) {
+    return (int(finite(a)) & int(finite(b)) & int(finite(c)) & int(finite(d))) != 0;
+}
+
 // The lanes of the wave on which v is not finite (one class test, its result
 // left in a scalar register pair).
 __device__ inline unsigned long long any_nonfinite(double v) {
@@ -69,7 +78,7 @@ __device__ inline bool interp_1d_values(double tm, double ta, double tb, double 
 #pragma clang fp contract(off)
     if constexpr (Interp == 0) {
         next = ta + w0 * (tb - ta);
-        return finite(ta) & finite(tb);
+        return all_finite(ta, tb);
     } else {
         // node i0 (never the last): one-sided at the first node, else central;
         // node i0+1 (never the first): one-sided at the last node, else central.
@@ -79,7 +88,7 @@ __device__ inline bool interp_1d_values(double tm, double ta, double tb, double 
         const double da = i0 == 0 ? da_end : da_in;
         const double db = i0 + 1 == n - 1 ? db_end : db_in;
         next = ((hb.h00 * ta + hb.h10 * da) + hb.h01 * tb) + hb.h11 * db;
-        return finite(ta) & finite(tb) & finite(da) & finite(db);
+        return all_finite(ta, tb, da, db);
     }
 }
 
@@ -184,7 +193,7 @@ __device__ inline bool hermite_slopes_values(double ta, double tb, double ma, do
 #pragma clang fp contract(off)
     const double da = dxi * ma, db = dxi * mb;
     next = ((hb.h00 * ta + hb.h10 * da) + hb.h01 * tb) + hb.h11 * db;
-    return finite(ta) & finite(tb) & finite(da) & finite(db);
+    return all_finite(ta, tb, da, db);
 }
 
 template <class T, int Interp>
@@ -382,7 +391,7 @@ __device__ inline void pf_chain(const ComposeArgs &a, PfShared<Interp> &sh) {
                     asm volatile("" : "+v"(hb.h00), "+v"(hb.h10), "+v"(hb.h01), "+v"(hb.h11));
                     const double da = 0.5 * (tb - tm), db = 0.5 * (tp - ta);
                     next = ((hb.h00 * ta + hb.h10 * da) + hb.h01 * tb) + hb.h11 * db;
-                    ok = finite(ta) & finite(tb) & finite(da) & finite(db);
+                    ok = all_finite(ta, tb, da, db);
                 } else if constexpr (Interp == 4) {
                     const double *win1 = sh.win[Interp == 4 ? 1 : 0][slot];
                     const double ta = pf_read(win, o), tb = pf_read(win, o + 1);
@@ -393,7 +402,7 @@ __device__ inline void pf_chain(const ComposeArgs &a, PfShared<Interp> &sh) {
                 } else {
                     const double ta = pf_read(win, o), tb = pf_read(win, o + 1);
                     next = ta + w0 * (tb - ta);
-                    ok = finite(ta) & finite(tb);
+                    ok = all_finite(ta, tb);
                 }
             } else if constexpr (Interp == 4) {
                 const T *row0 = tab0 + (long long)j * a.M, *row1 = tab1 + (long long)j * a.M;

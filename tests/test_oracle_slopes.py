@@ -4,7 +4,7 @@ The slope table holds, for every entry, the derivative of the slice's
 discrete map with respect to the grid point (the derivative of the RK4 or
 Euler map that produced the entry, carried through every stage by the chain
 rule).  The paper's computation phase tabulates values only; the slopes are
-the optional second table of the survey's reading of cubic Hermite lookup.
+an optional second table for cubic Hermite lookup, which the paper leaves out.
 Pins, each independent of the oracle's tangent code:
   - y' = lambda y: the derivative of S steps is the one-step factor to the
     power S, for every grid point, and equals value / grid point;

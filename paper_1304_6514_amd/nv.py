@@ -272,6 +272,43 @@ def nv_solve(ctx, rhs_id, params, t0, T, n_slices, grid: nv_ic_grid, steps_per_s
     return st, yT, boundary, info
 
 
+class SolveCall:
+    """nv_solve's arguments for one problem, marshalled once.  Repeated solves
+    of the same problem (a serving loop, the benchmark) then pay for the
+    foreign call and the copies of the outputs only, not for building the
+    argument arrays and pointers again.  Call it with the context and y0;
+    it returns what nv_solve returns, the outputs copied out of its buffers."""
+
+    def __init__(self, rhs_id, params, t0, T, n_slices, grid: nv_ic_grid, steps_per_slice,
+                 dim, want_boundary=True):
+        p = np.ascontiguousarray(np.asarray(params if params is not None else [0.0],
+                                            dtype=np.float64).reshape(-1))
+        self._p = p if p.size else np.zeros(1)
+        self._grid = grid
+        self._y0 = np.zeros(dim)
+        self._yT = np.full(dim, np.nan)
+        self._boundary = np.full((n_slices + 1, dim), np.nan) if want_boundary else None
+        self._info = nv_compose_info()
+        self._args = (int(rhs_id), _ptr(self._p), float(t0), float(T), int(n_slices),
+                      ctypes.byref(grid), int(steps_per_slice), _ptr(self._y0), _ptr(self._yT),
+                      _ptr(self._boundary) if self._boundary is not None else None,
+                      ctypes.byref(self._info))
+        self._fn = load().nv_solve
+
+    def __call__(self, ctx, y0):
+        self._y0[:] = y0
+        st = self._fn(ctx, *self._args)
+        if st not in (NV_OK, NV_ERR_NONFINITE):
+            _check(st)
+        info = nv_compose_info.from_buffer_copy(self._info)
+        b = None
+        if self._boundary is not None:
+            b = self._boundary.copy()
+            if st != NV_OK:             # rows past the failing slice were not written
+                b[info.bad_slice + 1:] = np.nan
+        return st, self._yT.copy(), b, info
+
+
 def nv_solve_static(rhs_id, params, t0, T, n_slices, grid: nv_ic_grid, steps_per_slice,
                     opt: nv_options, tables_dev, table_bytes, y0, boundary_dev, status_dev):
     """Queues the build and the composition on opt.stream with the library's

@@ -37,6 +37,7 @@ class Propagator:
         self.traj_per_lane = traj_per_lane
         self.compensated = compensated
         self.solve_chunks = solve_chunks
+        self._solve_calls, self._solve_for = {}, None
         self.ctx = nv.nv_ctx_create()
         self._tables = None
         self._work = None
@@ -105,9 +106,19 @@ class Propagator:
         """Both phases, the composition pipelined behind the build (synchronous)."""
         g, rhs = self._prepare(w)
         self.workload = None
-        st, yT, b, info = nv.nv_solve(self.ctx, rhs, params if params is not None else w.params,
-                                      w.t0, w.T, w.n_slices, g, w.steps_per_slice,
-                                      w.y0 if y0 is None else y0, w.dim, want_boundary)
+        params = params if params is not None else w.params
+        # the call's arguments are marshalled once per workload, parameters and
+        # boundary choice (the binding's share of a small solve's latency)
+        key = (params if isinstance(params, tuple)
+               else tuple(np.asarray(params, dtype=np.float64).reshape(-1)), bool(want_boundary))
+        call = self._solve_calls.get(key) if self._solve_for is w else None
+        if call is None:
+            if self._solve_for is not w:
+                self._solve_calls, self._solve_for = {}, w
+            call = nv.SolveCall(rhs, params, w.t0, w.T, w.n_slices, g, w.steps_per_slice,
+                                w.dim, want_boundary)
+            self._solve_calls[key] = call
+        st, yT, b, info = call(self.ctx, w.y0 if y0 is None else y0)
         self.workload = w
         return ComposeResult(st, yT, b, info.n_out_of_grid, info.bad_slice, info.n_chunks)
 

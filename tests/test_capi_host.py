@@ -324,3 +324,22 @@ def test_probe_argument_errors_need_no_gpu(nvmod):
                                        ctypes.byref(cyc)) == nvmod.NV_ERR_INVALID_ARG
     assert lib.nv_probe_fma_chains(nvmod.NV_FP64, 1 << 20, 1, None, None,
                                    ctypes.byref(cyc)) == nvmod.NV_ERR_INVALID_ARG
+
+
+def test_prepared_solve_call_marshals_once_and_reports_errors(nvmod):
+    # nv_solve's arguments marshalled once (no GPU needed: a NULL context is
+    # rejected before any HIP call, and the error is raised like nv_solve's)
+    from paper_1304_6514_amd import workloads as W
+    nv = nvmod
+    w = W.LOGISTIC_FP64
+    g = nv.make_grid(w.grid_n, w.grid_lo, w.grid_hi, w.interp)
+    call = nv.SolveCall(nv.RHS_IDS[w.rhs], w.params, w.t0, w.T, w.n_slices, g,
+                        w.steps_per_slice, w.dim)
+    assert call._boundary.shape == (w.n_slices + 1, w.dim)
+    for _ in range(2):
+        with pytest.raises(nv.NvError) as e:
+            call(None, w.y0)
+        assert e.value.status == nv.NV_ERR_INVALID_ARG
+    assert np.array_equal(call._y0, np.asarray(w.y0))
+    assert nv.SolveCall(nv.RHS_IDS[w.rhs], w.params, w.t0, w.T, w.n_slices, g,
+                        w.steps_per_slice, w.dim, want_boundary=False)._boundary is None

@@ -277,7 +277,8 @@ class SolveCall:
     of the same problem (a serving loop, the benchmark) then pay for the
     foreign call and the copies of the outputs only, not for building the
     argument arrays and pointers again.  Call it with the context and y0;
-    it returns what nv_solve returns, the outputs copied out of its buffers."""
+    it returns what nv_solve returns, the outputs copied out of its buffers.
+    One call at a time: concurrent calls of one SolveCall share its buffers."""
 
     def __init__(self, rhs_id, params, t0, T, n_slices, grid: nv_ic_grid, steps_per_slice,
                  dim, want_boundary=True):

@@ -272,33 +272,19 @@ def nv_solve(ctx, rhs_id, params, t0, T, n_slices, grid: nv_ic_grid, steps_per_s
     return st, yT, boundary, info
 
 
-class SolveCall:
-    """nv_solve's arguments for one problem, marshalled once.  Repeated solves
-    of the same problem (a serving loop, the benchmark) then pay for the
-    foreign call and the copies of the outputs only, not for building the
-    argument arrays and pointers again.  Call it with the context and y0;
-    it returns what nv_solve returns, the outputs copied out of its buffers.
-    One call at a time: concurrent calls of one SolveCall share its buffers."""
+class _Outputs:
+    """y0, yT, boundary and info buffers of one prepared composition call."""
 
-    def __init__(self, rhs_id, params, t0, T, n_slices, grid: nv_ic_grid, steps_per_slice,
-                 dim, want_boundary=True):
-        p = np.ascontiguousarray(np.asarray(params if params is not None else [0.0],
-                                            dtype=np.float64).reshape(-1))
-        self._p = p if p.size else np.zeros(1)
-        self._grid = grid
+    def __init__(self, n_slices, dim, want_boundary):
         self._y0 = np.zeros(dim)
         self._yT = np.full(dim, np.nan)
         self._boundary = np.full((n_slices + 1, dim), np.nan) if want_boundary else None
         self._info = nv_compose_info()
-        self._args = (int(rhs_id), _ptr(self._p), float(t0), float(T), int(n_slices),
-                      ctypes.byref(grid), int(steps_per_slice), _ptr(self._y0), _ptr(self._yT),
-                      _ptr(self._boundary) if self._boundary is not None else None,
-                      ctypes.byref(self._info))
-        self._fn = load().nv_solve
+        self._out = (_ptr(self._y0), _ptr(self._yT),
+                     _ptr(self._boundary) if self._boundary is not None else None,
+                     ctypes.byref(self._info))
 
-    def __call__(self, ctx, y0):
-        self._y0[:] = y0
-        st = self._fn(ctx, *self._args)
+    def _finish(self, st):
         if st not in (NV_OK, NV_ERR_NONFINITE):
             _check(st)
         info = nv_compose_info.from_buffer_copy(self._info)
@@ -308,6 +294,45 @@ class SolveCall:
             if st != NV_OK:             # rows past the failing slice were not written
                 b[info.bad_slice + 1:] = np.nan
         return st, self._yT.copy(), b, info
+
+
+class SolveCall(_Outputs):
+    """nv_solve's arguments for one problem, marshalled once.  Repeated solves
+    of the same problem (a serving loop, the benchmark) then pay for the
+    foreign call and the copies of the outputs only, not for building the
+    argument arrays and pointers again.  Call it with the context and y0;
+    it returns what nv_solve returns, the outputs copied out of its buffers.
+    One call at a time: concurrent calls of one SolveCall share its buffers."""
+
+    def __init__(self, rhs_id, params, t0, T, n_slices, grid: nv_ic_grid, steps_per_slice,
+                 dim, want_boundary=True):
+        super().__init__(n_slices, dim, want_boundary)
+        p = np.ascontiguousarray(np.asarray(params if params is not None else [0.0],
+                                            dtype=np.float64).reshape(-1))
+        self._p = p if p.size else np.zeros(1)
+        self._grid = grid
+        y0, yT, b, info = self._out
+        self._args = (int(rhs_id), _ptr(self._p), float(t0), float(T), int(n_slices),
+                      ctypes.byref(grid), int(steps_per_slice), y0, yT, b, info)
+        self._fn = load().nv_solve
+
+    def __call__(self, ctx, y0):
+        self._y0[:] = y0
+        return self._finish(self._fn(ctx, *self._args))
+
+
+class ComposeCall(_Outputs):
+    """nv_compose's arguments for one built problem, marshalled once (many
+    initial values queried one after another through the same tables).  The
+    same contract as SolveCall."""
+
+    def __init__(self, n_slices, dim, want_boundary=True):
+        super().__init__(n_slices, dim, want_boundary)
+        self._fn = load().nv_compose
+
+    def __call__(self, ctx, y0):
+        self._y0[:] = y0
+        return self._finish(self._fn(ctx, *self._out))
 
 
 def nv_solve_static(rhs_id, params, t0, T, n_slices, grid: nv_ic_grid, steps_per_slice,

@@ -38,6 +38,7 @@ class Propagator:
         self.compensated = compensated
         self.solve_chunks = solve_chunks
         self._solve_calls, self._solve_for = {}, None
+        self._compose_calls = {}
         self.ctx = nv.nv_ctx_create()
         self._tables = None
         self._work = None
@@ -125,8 +126,11 @@ class Propagator:
     def compose(self, y0=None, want_boundary=True) -> ComposeResult:
         """Communication phase (synchronous)."""
         w = self.workload
-        st, yT, b, info = nv.nv_compose(self.ctx, w.y0 if y0 is None else y0, w.dim,
-                                        w.n_slices, want_boundary)
+        key = (w.n_slices, w.dim, bool(want_boundary))
+        call = self._compose_calls.get(key)
+        if call is None:
+            call = self._compose_calls[key] = nv.ComposeCall(w.n_slices, w.dim, want_boundary)
+        st, yT, b, info = call(self.ctx, w.y0 if y0 is None else y0)
         return ComposeResult(st, yT, b, info.n_out_of_grid, info.bad_slice, info.n_chunks)
 
     # -- inspection ------------------------------------------------------------

@@ -343,3 +343,7 @@ def test_prepared_solve_call_marshals_once_and_reports_errors(nvmod):
     assert np.array_equal(call._y0, np.asarray(w.y0))
     assert nv.SolveCall(nv.RHS_IDS[w.rhs], w.params, w.t0, w.T, w.n_slices, g,
                         w.steps_per_slice, w.dim, want_boundary=False)._boundary is None
+    comp = nv.ComposeCall(w.n_slices, w.dim)
+    with pytest.raises(nv.NvError) as e:
+        comp(None, w.y0)
+    assert e.value.status == nv.NV_ERR_INVALID_ARG

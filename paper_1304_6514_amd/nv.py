@@ -321,6 +321,23 @@ class SolveCall(_Outputs):
         return self._finish(self._fn(ctx, *self._args))
 
 
+class BuildCall:
+    """nv_build_propagators' arguments for one problem, marshalled once (the
+    same contract as SolveCall); call it with the context."""
+
+    def __init__(self, rhs_id, params, t0, T, n_slices, grid: nv_ic_grid, steps_per_slice):
+        p = np.ascontiguousarray(np.asarray(params if params is not None else [0.0],
+                                            dtype=np.float64).reshape(-1))
+        self._p = p if p.size else np.zeros(1)
+        self._grid = grid
+        self._args = (int(rhs_id), _ptr(self._p), float(t0), float(T), int(n_slices),
+                      ctypes.byref(grid), int(steps_per_slice))
+        self._fn = load().nv_build_propagators
+
+    def __call__(self, ctx):
+        return _check(self._fn(ctx, *self._args))
+
+
 class ComposeCall(_Outputs):
     """nv_compose's arguments for one built problem, marshalled once (many
     initial values queried one after another through the same tables).  The

@@ -37,7 +37,7 @@ class Propagator:
         self.traj_per_lane = traj_per_lane
         self.compensated = compensated
         self.solve_chunks = solve_chunks
-        self._solve_calls, self._solve_for = {}, None
+        self._calls, self._calls_for = {}, None
         self._compose_calls = {}
         self.ctx = nv.nv_ctx_create()
         self._tables = None
@@ -96,11 +96,23 @@ class Propagator:
         self._prepared_for, self._prepared = w, (g, rhs)
         return g, rhs
 
+    def _key(self, w: Workload, params, *extra):
+        # per workload (its identity) and parameters: the calls marshalled for it
+        if self._calls_for is not w:
+            self._calls, self._calls_for = {}, w
+        return (params if isinstance(params, tuple)
+                else tuple(np.asarray(params, dtype=np.float64).reshape(-1)),) + extra
+
     def build(self, w: Workload, params=None):
         """Computation phase: tables of every slice (asynchronous on the stream)."""
         g, rhs = self._prepare(w)
-        nv.nv_build_propagators(self.ctx, rhs, params if params is not None else w.params,
-                                w.t0, w.T, w.n_slices, g, w.steps_per_slice)
+        params = params if params is not None else w.params
+        key = ("build",) + self._key(w, params)
+        call = self._calls.get(key)
+        if call is None:
+            call = self._calls[key] = nv.BuildCall(rhs, params, w.t0, w.T, w.n_slices, g,
+                                                   w.steps_per_slice)
+        call(self.ctx)
         self.workload = w
 
     def solve(self, w: Workload, y0=None, params=None, want_boundary=True) -> ComposeResult:
@@ -110,15 +122,11 @@ class Propagator:
         params = params if params is not None else w.params
         # the call's arguments are marshalled once per workload, parameters and
         # boundary choice (the binding's share of a small solve's latency)
-        key = (params if isinstance(params, tuple)
-               else tuple(np.asarray(params, dtype=np.float64).reshape(-1)), bool(want_boundary))
-        call = self._solve_calls.get(key) if self._solve_for is w else None
+        key = ("solve",) + self._key(w, params, bool(want_boundary))
+        call = self._calls.get(key)
         if call is None:
-            if self._solve_for is not w:
-                self._solve_calls, self._solve_for = {}, w
-            call = nv.SolveCall(rhs, params, w.t0, w.T, w.n_slices, g, w.steps_per_slice,
-                                w.dim, want_boundary)
-            self._solve_calls[key] = call
+            call = self._calls[key] = nv.SolveCall(rhs, params, w.t0, w.T, w.n_slices, g,
+                                                   w.steps_per_slice, w.dim, want_boundary)
         st, yT, b, info = call(self.ctx, w.y0 if y0 is None else y0)
         self.workload = w
         return ComposeResult(st, yT, b, info.n_out_of_grid, info.bad_slice, info.n_chunks)

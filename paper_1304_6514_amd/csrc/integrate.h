@@ -282,10 +282,10 @@ __device__ inline unsigned build_tile_rows(const BuildArgs &a, int j, int tile,
     // Builds small enough to leave one wave per SIMD are bound by that wave's
     // own instruction stream, in which the loop's counter, compare and branch
     // take issue slots; large builds hide them behind other waves.  Unrolling
-    // 8 FP64 or 4 FP32 steps (with the loop aligned to the instruction cache
-    // line, a build flag of the files that include this one) measured
-    // fastest for the small builds and equal for the large ones.
-    constexpr int kUnroll = sizeof(R) == 8 ? 8 : 4;
+    // 8 steps (with the loop aligned to the instruction cache line, a build
+    // flag of the files that include this one) measured fastest for the small
+    // builds and equal for the large ones.
+    constexpr int kUnroll = 8;
     for (int s0 = 0; s0 < S; s0 += kSumBlock) {
         const int s1 = min(s0 + kSumBlock, S);
 #pragma unroll kUnroll

@@ -25,7 +25,7 @@ from paper_1304_6514_amd import nv
 from paper_1304_6514_amd import workloads as W
 
 TOL = {"fp64": 1e-12, "fp32": 1e-5}
-N_CASES = 48
+N_CASES = 96
 
 
 def say(*a):
